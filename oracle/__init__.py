@@ -1,0 +1,274 @@
+"""CPU oracle for the Sample-Align-D data-parallel core -- TEST INFRASTRUCTURE.
+
+A ctypes wrapper over ``sad_oracle.c`` (plain single-threaded C written from
+the paper's definitions).  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the HIP library never calls it and
+shares no code with it.
+
+Parity status per step (what pins it, in ``tests/test_oracle_*.py``):
+  k-mer lists, c_ij, F          brute force (collections.Counter, Fraction)
+  local/global rank, samples    order-statistic and sum properties, sorted()
+  pivots, buckets               Y order statistics, pivot ranges, paper bound
+  UPGMA                         scipy average linkage (tie-free), crafted ties
+  profile alignment             exhaustive enumeration of alignments (score
+                                and tie-broken path), textbook pairwise Gotoh,
+                                numpy column scores, score recomputation
+  progressive / refine / glue   replay invariants (degapped rows, restriction,
+                                no all-gap columns, recomputed merge scores)
+The whole pipeline has no printed example in the paper: end to end it is pinned
+only through those invariants.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sad_oracle.c")
+_LIB = os.path.join(_HERE, "libsad_oracle.so")
+
+OP_M, OP_X, OP_Y = 0, 1, 2
+OK, E_INVAL, E_CAPACITY, E_OVERFLOW = 0, -1, -2, -3
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: status {code}")
+        self.code = code
+
+
+def build(force: bool = False) -> str:
+    """Compiles the oracle with gcc (plain -O2, portable code)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-Wno-unused-function", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+P = ctypes.c_void_p
+I32, I64 = ctypes.c_int32, ctypes.c_int64
+
+
+def _declare(L):
+    L.sadref_kmer_list.argtypes = [P, I64, ctypes.c_int, ctypes.c_int, P, P, P]
+    L.sadref_common_kmers.argtypes = [P, I64, P, I64, ctypes.c_int, ctypes.c_int]
+    L.sadref_common_kmers.restype = I64
+    L.sadref_fhat.argtypes = [P, I64, P, I64, ctypes.c_int, ctypes.c_int]
+    L.sadref_fhat.restype = ctypes.c_uint32
+    L.sadref_kmer_rank.argtypes = [I32, I32, P, P, I32, I32, I32, P, P, I32, P]
+    L.sadref_partition.argtypes = [I32, P, I32, P, P, P, P, P]
+    L.sadref_upgma.argtypes = [I32, P, P]
+    L.sadref_profile_align.argtypes = [P, I32, I32, P, I32, I32, I32, P, I32, I32, P, P, P]
+    L.sadref_align_buckets.argtypes = [I32, I32, P, P, I32, P, P, I32, P, I32, I32,
+                                       P, P, P, P, P, P, P, I64, P]
+    L.sadref_consensus.argtypes = [P, I32, I32, I32, P, P]
+    L.sadref_refine.argtypes = [I32, I32, P, P, I32, P, P, P, P, I32, P, I32, I32,
+                                P, I32, P, P, P, P, P, P, P, P]
+    for f in ("sadref_kmer_list", "sadref_kmer_rank", "sadref_partition", "sadref_upgma",
+              "sadref_profile_align", "sadref_align_buckets", "sadref_consensus",
+              "sadref_refine"):
+        getattr(L, f).restype = ctypes.c_int
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _check(st, what):
+    if st != OK:
+        raise OracleError(st, what)
+
+
+# --------------------------------------------------------------------------
+# k-mers
+# --------------------------------------------------------------------------
+
+def kmer_list(x, A: int, k: int):
+    x = _c(x, np.uint8)
+    m = max(len(x) - k + 1, 1)
+    taus = np.zeros(m, np.int32)
+    cnts = np.zeros(m, np.int32)
+    nu = np.zeros(1, np.int64)
+    _check(lib().sadref_kmer_list(_p(x), len(x), A, k, _p(taus), _p(cnts), _p(nu)), "kmer_list")
+    u = int(nu[0])
+    return taus[:u].copy(), cnts[:u].copy()
+
+
+def common_kmers(xi, xj, A: int, k: int) -> int:
+    xi, xj = _c(xi, np.uint8), _c(xj, np.uint8)
+    return int(lib().sadref_common_kmers(_p(xi), len(xi), _p(xj), len(xj), A, k))
+
+
+def fhat(xi, xj, A: int, k: int) -> int:
+    xi, xj = _c(xi, np.uint8), _c(xj, np.uint8)
+    return int(lib().sadref_fhat(_p(xi), len(xi), _p(xj), len(xj), A, k))
+
+
+# --------------------------------------------------------------------------
+# rank and partition
+# --------------------------------------------------------------------------
+
+def kmer_rank(codes, offsets, A: int, k: int, p: int, s_max: int = 1024):
+    codes, offsets = _c(codes, np.uint8), _c(offsets, np.int64)
+    n = len(offsets) - 1
+    key = np.zeros(max(n, 1), np.uint64)
+    cap = max(s_max, p) + p
+    sid = np.zeros(cap, np.int32)
+    ns = np.zeros(1, np.int32)
+    st = lib().sadref_kmer_rank(n, A, _p(codes), _p(offsets), k, p, s_max, _p(key), _p(sid),
+                                cap, _p(ns))
+    _check(st, "kmer_rank")
+    return key[:n].copy(), sid[:int(ns[0])].copy()
+
+
+def partition(key, p: int):
+    key = _c(key, np.uint64)
+    n = len(key)
+    pk = np.zeros(max(p - 1, 1), np.uint64)
+    pid = np.zeros(max(p - 1, 1), np.int32)
+    bucket = np.zeros(max(n, 1), np.int32)
+    boff = np.zeros(p + 1, np.int32)
+    mem = np.zeros(max(n, 1), np.int32)
+    st = lib().sadref_partition(n, _p(key), p, _p(pk), _p(pid), _p(bucket), _p(boff), _p(mem))
+    _check(st, "partition")
+    return dict(pivot_key=pk[:p - 1].copy(), pivot_id=pid[:p - 1].copy(),
+                bucket=bucket[:n].copy(), bucket_off=boff, members=mem[:n].copy())
+
+
+# --------------------------------------------------------------------------
+# alignment pieces
+# --------------------------------------------------------------------------
+
+def upgma(F):
+    F = _c(F, np.uint32)
+    n = F.shape[0]
+    merges = np.zeros(max(2 * (n - 1), 2), np.int32)
+    _check(lib().sadref_upgma(n, _p(F), _p(merges)), "upgma")
+    return merges[:2 * max(n - 1, 0)].reshape(-1, 2).copy()
+
+
+def profile_align(C1, n1: int, C2, n2: int, S, go: int, ge: int):
+    """Returns (ops, score); C1: W1 x A, C2: W2 x A counts."""
+    S = _c(S, np.int8)
+    A = S.shape[0]
+    C1 = _c(np.asarray(C1).reshape(-1, A), np.uint16)
+    C2 = _c(np.asarray(C2).reshape(-1, A), np.uint16)
+    W1, W2 = C1.shape[0], C2.shape[0]
+    ops = np.zeros(max(W1 + W2, 1), np.uint8)
+    nops = np.zeros(1, np.int32)
+    score = np.zeros(1, np.int64)
+    st = lib().sadref_profile_align(_p(C1), W1, n1, _p(C2), W2, n2, A, _p(S), go, ge,
+                                    _p(ops), _p(nops), _p(score))
+    _check(st, "profile_align")
+    return ops[:int(nops[0])].copy(), int(score[0])
+
+
+def consensus(counts, n: int):
+    counts = _c(counts, np.uint16)
+    W, A = counts.shape
+    out = np.zeros(max(W, 1), np.uint8)
+    ln = np.zeros(1, np.int32)
+    _check(lib().sadref_consensus(_p(counts), W, n, A, _p(out), _p(ln)), "consensus")
+    return out[:int(ln[0])].copy()
+
+
+def align_buckets(codes, offsets, A: int, bucket_off, members, k: int, S, go: int, ge: int,
+                  want_ops: bool = False):
+    codes, offsets = _c(codes, np.uint8), _c(offsets, np.int64)
+    boff, mem, S = _c(bucket_off, np.int32), _c(members, np.int32), _c(S, np.int8)
+    n = len(offsets) - 1
+    p = len(boff) - 1
+    colmap = np.zeros(max(len(codes), 1), np.int32)
+    width = np.zeros(p, np.int32)
+    mscore = np.zeros(max(n, 1), np.int64)
+    mlist = np.full(max(2 * n, 2), -1, np.int32)
+    mcells = np.zeros(max(n, 1), np.int64)
+    cells = np.zeros(1, np.int64)
+    if want_ops:
+        cap = int(2 * len(codes) * max(1, int(np.log2(max(n, 2)))) + 16)
+        while True:
+            ops = np.zeros(cap, np.uint8)
+            ops_off = np.zeros(n + 1, np.int64)
+            st = lib().sadref_align_buckets(n, A, _p(codes), _p(offsets), p, _p(boff), _p(mem),
+                                            k, _p(S), go, ge, _p(colmap), _p(width), _p(mscore),
+                                            _p(mlist), _p(mcells), _p(cells), _p(ops), cap,
+                                            _p(ops_off))
+            if st == E_CAPACITY:
+                cap *= 4
+                continue
+            break
+    else:
+        ops = ops_off = None
+        st = lib().sadref_align_buckets(n, A, _p(codes), _p(offsets), p, _p(boff), _p(mem),
+                                        k, _p(S), go, ge, _p(colmap), _p(width), _p(mscore),
+                                        _p(mlist), _p(mcells), _p(cells), None, 0, None)
+    _check(st, "align_buckets")
+    out = dict(colmap=colmap[:len(codes)].copy(), width=width, merge_score=mscore[:n].copy(),
+               merge_list=mlist[:2 * n].reshape(-1, 2).copy(), merge_cells=mcells[:n].copy(),
+               cells=int(cells[0]))
+    if want_ops:
+        out["ops"] = ops
+        out["ops_off"] = ops_off
+    return out
+
+
+def refine(codes, offsets, A: int, bucket_off, members, colmap_b, width_b, k: int, S,
+           go: int, ge: int):
+    codes, offsets = _c(codes, np.uint8), _c(offsets, np.int64)
+    boff, mem, S = _c(bucket_off, np.int32), _c(members, np.int32), _c(S, np.int8)
+    cb, wb = _c(colmap_b, np.int32), _c(width_b, np.int32)
+    n = len(offsets) - 1
+    p = len(boff) - 1
+    # the ancestors' alignment is at most as wide as all ancestors together
+    ga_cap = max(int(wb.astype(np.int64).sum()), 1)
+    ga = np.zeros(ga_cap, np.uint8)
+    ga_len = np.zeros(1, np.int32)
+    cg = np.zeros(max(len(codes), 1), np.int32)
+    wg = np.zeros(1, np.int32)
+    ms = np.zeros(2 * p, np.int64)
+    ml = np.zeros(4 * p, np.int32)
+    mc = np.zeros(2 * p, np.int64)
+    nm = np.zeros(1, np.int32)
+    cells = np.zeros(1, np.int64)
+    st = lib().sadref_refine(n, A, _p(codes), _p(offsets), p, _p(boff), _p(mem), _p(cb), _p(wb),
+                             k, _p(S), go, ge, _p(ga), ga_cap, _p(ga_len), _p(cg), _p(wg),
+                             _p(ms), _p(ml), _p(mc), _p(nm), _p(cells))
+    _check(st, "refine")
+    m = int(nm[0])
+    return dict(ga=ga[:int(ga_len[0])].copy(), colmap=cg[:len(codes)].copy(), width=int(wg[0]),
+                merge_score=ms[:m].copy(), merge_list=ml[:2 * m].reshape(-1, 2).copy(),
+                merge_cells=mc[:m].copy(), cells=int(cells[0]))
+
+
+def run_pipeline(codes, offsets, A: int, k: int, p: int, S, go: int, ge: int,
+                 s_max: int = 1024, want_ops: bool = False):
+    """All four steps in order, as the HIP library's calls chain them."""
+    key, samples = kmer_rank(codes, offsets, A, k, p, s_max)
+    part = partition(key, p)
+    al = align_buckets(codes, offsets, A, part["bucket_off"], part["members"], k, S, go, ge,
+                       want_ops=want_ops)
+    rf = refine(codes, offsets, A, part["bucket_off"], part["members"], al["colmap"],
+                al["width"], k, S, go, ge)
+    return dict(key=key, samples=samples, part=part, align=al, refine=rf)

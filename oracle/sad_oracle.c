@@ -1,0 +1,912 @@
+/*
+ * CPU oracle for the Sample-Align-D data-parallel core (Saeed & Khokhar,
+ * arXiv 0901.2742).  TEST INFRASTRUCTURE ONLY -- see sad_oracle.h.
+ *
+ * Plain, single-threaded C.  Each function follows one step of the method in
+ * the order the paper states it; where the paper leaves a choice open, the
+ * reading used is stated next to the code.  All arithmetic is integer: scores
+ * in int64, k-mer similarities as exact rationals c/d turned into the fixed
+ * point floor(c * 2^31 / d).
+ */
+#include "sad_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+#define NEG_INF (INT64_MIN / 4)
+
+/* ------------------------------------------------------------------ */
+/* input validation                                                    */
+/* ------------------------------------------------------------------ */
+
+/* A^k, or -1 if it exceeds 2^16 (k-mer codes are kept below 2^16). */
+static int64_t kmer_space(int A, int k) {
+  int64_t v = 1;
+  for (int u = 0; u < k; ++u) {
+    v *= A;
+    if (v > 65536) return -1;
+  }
+  return v;
+}
+
+static int validate_seqs(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                         int32_t k) {
+  if (n < 0 || (A != 4 && A != 20) || k < 1 || kmer_space(A, k) < 0) return SADREF_E_INVAL;
+  if (!offsets || offsets[0] != 0) return SADREF_E_INVAL;
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t L = offsets[i + 1] - offsets[i];
+    if (L < k) return SADREF_E_INVAL;
+    for (int64_t t = offsets[i]; t < offsets[i + 1]; ++t)
+      if (codes[t] >= A) return SADREF_E_INVAL;
+  }
+  return SADREF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* k-mer counts and the fractional common k-mer similarity (Section 2)  */
+/* ------------------------------------------------------------------ */
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+int sadref_kmer_list(const uint8_t* x, int64_t L, int A, int k,
+                     int32_t* taus, int32_t* counts, int64_t* n_unique) {
+  *n_unique = 0;
+  if (L < k) return SADREF_OK;
+  int64_t m = L - k + 1;
+  int32_t* all = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  for (int64_t t = 0; t < m; ++t) {
+    int32_t tau = 0;
+    for (int u = 0; u < k; ++u) tau = tau * A + x[t + u];
+    all[t] = tau;
+  }
+  qsort(all, (size_t)m, sizeof(int32_t), cmp_i32);
+  int64_t u = 0;
+  for (int64_t t = 0; t < m; ++t) {
+    if (u > 0 && taus[u - 1] == all[t]) {
+      counts[u - 1] += 1;
+    } else {
+      taus[u] = all[t];
+      counts[u] = 1;
+      ++u;
+    }
+  }
+  free(all);
+  *n_unique = u;
+  return SADREF_OK;
+}
+
+typedef struct {
+  int64_t len;      /* sequence length */
+  int64_t nu;       /* unique k-mers */
+  int32_t* tau;
+  int32_t* cnt;
+} kmer_list_t;
+
+static void build_list(kmer_list_t* kl, const uint8_t* x, int64_t L, int A, int k) {
+  int64_t m = L >= k ? L - k + 1 : 1;
+  kl->len = L;
+  kl->tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  kl->cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  sadref_kmer_list(x, L, A, k, kl->tau, kl->cnt, &kl->nu);
+}
+
+static void free_list(kmer_list_t* kl) {
+  free(kl->tau);
+  free(kl->cnt);
+}
+
+/* sum_tau min(n_i(tau), n_j(tau)) by a merge of two sorted lists */
+static int64_t common_lists(const kmer_list_t* a, const kmer_list_t* b) {
+  int64_t c = 0, u = 0, v = 0;
+  while (u < a->nu && v < b->nu) {
+    if (a->tau[u] < b->tau[v]) {
+      ++u;
+    } else if (a->tau[u] > b->tau[v]) {
+      ++v;
+    } else {
+      c += a->cnt[u] < b->cnt[v] ? a->cnt[u] : b->cnt[v];
+      ++u;
+      ++v;
+    }
+  }
+  return c;
+}
+
+/* Reading of the garbled r_ij formula: the leading "tau ." is dropped, so
+ * r_ij = c_ij / d_ij with d_ij = min(|x_i|, |x_j|) - k + 1, a similarity in
+ * [0, 1].  Its fixed point is floor(c * 2^31 / d). */
+static uint32_t fhat_lists(const kmer_list_t* a, const kmer_list_t* b, int k) {
+  int64_t L = a->len < b->len ? a->len : b->len;
+  if (L < k) return 0;
+  int64_t d = L - k + 1;
+  int64_t c = common_lists(a, b);
+  return (uint32_t)(((uint64_t)c << 31) / (uint64_t)d);
+}
+
+int64_t sadref_common_kmers(const uint8_t* xi, int64_t Li, const uint8_t* xj, int64_t Lj,
+                            int A, int k) {
+  kmer_list_t a, b;
+  build_list(&a, xi, Li, A, k);
+  build_list(&b, xj, Lj, A, k);
+  int64_t c = common_lists(&a, &b);
+  free_list(&a);
+  free_list(&b);
+  return c;
+}
+
+uint32_t sadref_fhat(const uint8_t* xi, int64_t Li, const uint8_t* xj, int64_t Lj, int A, int k) {
+  kmer_list_t a, b;
+  build_list(&a, xi, Li, A, k);
+  build_list(&b, xj, Lj, A, k);
+  uint32_t f = fhat_lists(&a, &b, k);
+  free_list(&a);
+  free_list(&b);
+  return f;
+}
+
+/* ------------------------------------------------------------------ */
+/* composite keys (K_i, i) and chunks                                  */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  uint64_t key;
+  int32_t id;
+} ckey_t;
+
+static int cmp_ckey(const void* a, const void* b) {
+  const ckey_t* x = (const ckey_t*)a;
+  const ckey_t* y = (const ckey_t*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return (x->id > y->id) - (x->id < y->id);
+}
+
+static int ckey_less(ckey_t a, ckey_t b) { return cmp_ckey(&a, &b) < 0; }
+
+/* The paper places N/p sequences on each of p processors; here processor c
+ * holds the contiguous chunk [floor(c N / p), floor((c+1) N / p)). */
+static int32_t chunk_lo(int32_t n, int32_t p, int32_t c) {
+  return (int32_t)(((int64_t)c * n) / p);
+}
+
+/* ------------------------------------------------------------------ */
+/* Step 1: local rank, samples, globalised rank (Sections 2, 2.3.1)     */
+/* ------------------------------------------------------------------ */
+
+int sadref_kmer_rank(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                     int32_t kmer_k, int32_t p, int32_t s_max,
+                     uint64_t* key, int32_t* sample_ids, int32_t sample_cap,
+                     int32_t* n_samples) {
+  int st = validate_seqs(n, A, codes, offsets, kmer_k);
+  if (st) return st;
+  if (p < 1 || s_max < 1 || n < 2 * p) return SADREF_E_INVAL;
+
+  kmer_list_t* kl = (kmer_list_t*)malloc(sizeof(kmer_list_t) * (size_t)(n > 0 ? n : 1));
+  for (int32_t i = 0; i < n; ++i)
+    build_list(&kl[i], codes + offsets[i], offsets[i + 1] - offsets[i], A, kmer_k);
+
+  /* samples per processor: k = p - 1 as in Section 2.3.2, capped so that the
+   * whole sample stays within s_max and each chunk keeps a non-sampled item */
+  int32_t w_min = n;
+  for (int32_t c = 0; c < p; ++c) {
+    int32_t w = chunk_lo(n, p, c + 1) - chunk_lo(n, p, c);
+    if (w < w_min) w_min = w;
+  }
+  int32_t ks = p - 1;
+  int32_t cap = s_max / p;
+  if (cap < 1) cap = 1;
+  if (ks > cap) ks = cap;
+  if (ks > w_min - 1) ks = w_min - 1;
+  int32_t S = p * ks;
+  *n_samples = S;
+  if (S > sample_cap) {
+    for (int32_t i = 0; i < n; ++i) free_list(&kl[i]);
+    free(kl);
+    return SADREF_E_CAPACITY;
+  }
+
+  /* local k-mer rank: K_loc(i) = sum over j in i's chunk (self included) of
+   * F(i, j); the chunk is sorted by (K_loc, i) and ks evenly spaced items are
+   * sampled at positions floor(t w / (ks + 1)), t = 1..ks */
+  ckey_t* buf = (ckey_t*)malloc(sizeof(ckey_t) * (size_t)(n > 0 ? n : 1));
+  for (int32_t c = 0; c < p; ++c) {
+    int32_t lo = chunk_lo(n, p, c), hi = chunk_lo(n, p, c + 1), w = hi - lo;
+    for (int32_t i = lo; i < hi; ++i) {
+      uint64_t s = 0;
+      for (int32_t j = lo; j < hi; ++j) s += fhat_lists(&kl[i], &kl[j], kmer_k);
+      buf[i - lo].key = s;
+      buf[i - lo].id = i;
+    }
+    qsort(buf, (size_t)w, sizeof(ckey_t), cmp_ckey);
+    for (int32_t t = 1; t <= ks; ++t)
+      sample_ids[c * ks + (t - 1)] = buf[((int64_t)t * w) / (ks + 1)].id;
+  }
+
+  /* globalised rank: every sequence against all k*p samples (self included
+   * when the sequence is itself a sample) */
+  for (int32_t i = 0; i < n; ++i) {
+    uint64_t s = 0;
+    for (int32_t t = 0; t < S; ++t) s += fhat_lists(&kl[i], &kl[sample_ids[t]], kmer_k);
+    key[i] = s;
+  }
+
+  free(buf);
+  for (int32_t i = 0; i < n; ++i) free_list(&kl[i]);
+  free(kl);
+  return SADREF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Regular sampling, pivots and buckets (Section 2.3.2)                 */
+/* ------------------------------------------------------------------ */
+
+int sadref_partition(int32_t n, const uint64_t* key, int32_t p,
+                     uint64_t* pivot_key, int32_t* pivot_id,
+                     int32_t* bucket, int32_t* bucket_off, int32_t* members) {
+  if (p < 1 || n < 2 * p) return SADREF_E_INVAL;
+  int64_t ny = (int64_t)p * (p - 1);
+  ckey_t* Y = (ckey_t*)malloc(sizeof(ckey_t) * (size_t)(ny > 0 ? ny : 1));
+  ckey_t* buf = (ckey_t*)malloc(sizeof(ckey_t) * (size_t)n);
+
+  /* each chunk sorted by (K_i, i); p - 1 evenly spaced keys at positions
+   * floor(t w / p), t = 1..p-1 (repeats allowed when w < p) */
+  for (int32_t c = 0; c < p; ++c) {
+    int32_t lo = chunk_lo(n, p, c), hi = chunk_lo(n, p, c + 1), w = hi - lo;
+    for (int32_t i = lo; i < hi; ++i) {
+      buf[i - lo].key = key[i];
+      buf[i - lo].id = i;
+    }
+    qsort(buf, (size_t)w, sizeof(ckey_t), cmp_ckey);
+    for (int32_t t = 1; t <= p - 1; ++t)
+      Y[(int64_t)c * (p - 1) + (t - 1)] = buf[((int64_t)t * w) / p];
+  }
+
+  /* sort the p(p-1) gathered keys; pivots Y_{p/2}, Y_{p+p/2}, ...,
+   * Y_{(p-2)p+p/2} (1-based) -- p - 1 of them */
+  qsort(Y, (size_t)ny, sizeof(ckey_t), cmp_ckey);
+  for (int32_t t = 1; t <= p - 1; ++t) {
+    ckey_t y = Y[p / 2 + (int64_t)(t - 1) * p - 1];
+    pivot_key[t - 1] = y.key;
+    pivot_id[t - 1] = y.id;
+  }
+
+  /* bucket(i) = number of pivots strictly below (K_i, i): a key equal to a
+   * pivot stays in the lower bucket */
+  for (int32_t b = 0; b <= p; ++b) bucket_off[b] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    ckey_t me = {key[i], i};
+    int32_t b = 0;
+    for (int32_t t = 0; t < p - 1; ++t) {
+      ckey_t y = {pivot_key[t], pivot_id[t]};
+      if (ckey_less(y, me)) ++b;
+    }
+    bucket[i] = b;
+    bucket_off[b + 1] += 1;
+  }
+  for (int32_t b = 0; b < p; ++b) bucket_off[b + 1] += bucket_off[b];
+  int32_t* fill = (int32_t*)calloc((size_t)p, sizeof(int32_t));
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t b = bucket[i];
+    members[bucket_off[b] + fill[b]++] = i;
+  }
+  free(fill);
+  free(buf);
+  free(Y);
+  return SADREF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* UPGMA guide tree on the fixed-point similarities                    */
+/* ------------------------------------------------------------------ */
+
+/* Pick the active pair with the largest average similarity
+ * S_AB / (|A| |B|); compared exactly by cross-multiplication in 128 bits;
+ * ties go to the lexicographically smallest (min id, max id). */
+int sadref_upgma(int32_t n, const uint32_t* F, int32_t* merges) {
+  if (n <= 1) return SADREF_OK;
+  uint64_t* S = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n * (size_t)n);
+  int32_t* id = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int64_t* sz = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  char* active = (char*)malloc((size_t)n);
+  for (int32_t a = 0; a < n; ++a) {
+    for (int32_t b = 0; b < n; ++b) S[(size_t)a * n + b] = F[(size_t)a * n + b];
+    id[a] = a;
+    sz[a] = 1;
+    active[a] = 1;
+  }
+  for (int32_t step = 0; step < n - 1; ++step) {
+    int32_t ba = -1, bb = -1;
+    for (int32_t a = 0; a < n; ++a) {
+      if (!active[a]) continue;
+      for (int32_t b = a + 1; b < n; ++b) {
+        if (!active[b]) continue;
+        if (ba < 0) {
+          ba = a;
+          bb = b;
+          continue;
+        }
+        unsigned __int128 lhs = (unsigned __int128)S[(size_t)a * n + b] *
+                                (unsigned __int128)(sz[ba] * sz[bb]);
+        unsigned __int128 rhs = (unsigned __int128)S[(size_t)ba * n + bb] *
+                                (unsigned __int128)(sz[a] * sz[b]);
+        int better = lhs > rhs;
+        if (lhs == rhs) {
+          int32_t lo1 = id[a] < id[b] ? id[a] : id[b], hi1 = id[a] < id[b] ? id[b] : id[a];
+          int32_t lo2 = id[ba] < id[bb] ? id[ba] : id[bb], hi2 = id[ba] < id[bb] ? id[bb] : id[ba];
+          better = lo1 < lo2 || (lo1 == lo2 && hi1 < hi2);
+        }
+        if (better) {
+          ba = a;
+          bb = b;
+        }
+      }
+    }
+    int32_t ia = id[ba], ib = id[bb];
+    merges[2 * step] = ia < ib ? ia : ib;
+    merges[2 * step + 1] = ia < ib ? ib : ia;
+    /* the union takes slot ba: S(new, C) = S(A, C) + S(B, C) */
+    for (int32_t c = 0; c < n; ++c) {
+      if (!active[c] || c == ba || c == bb) continue;
+      uint64_t v = S[(size_t)ba * n + c] + S[(size_t)bb * n + c];
+      S[(size_t)ba * n + c] = v;
+      S[(size_t)c * n + ba] = v;
+    }
+    sz[ba] += sz[bb];
+    id[ba] = n + step;
+    active[bb] = 0;
+  }
+  free(S);
+  free(id);
+  free(sz);
+  free(active);
+  return SADREF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Profile-profile affine-gap alignment (Section 2.3.3)                */
+/* ------------------------------------------------------------------ */
+
+/* Tie bits recorded per cell: which ops attain H, and which predecessor
+ * attains X and Y. */
+#define B_HM 1
+#define B_HX 2
+#define B_HY 4
+#define B_XO 8
+#define B_XE 16
+#define B_YO 32
+#define B_YE 64
+
+static int64_t max2(int64_t a, int64_t b) { return a > b ? a : b; }
+
+/* Column score s(i, j) = sum_a sum_b C1[i][a] S[a][b] C2[j][b]: every pair of
+ * rows (one from each profile) with residues in both columns contributes its
+ * substitution score.  U = C1 * S is formed first (a plain matrix product). */
+static int64_t* column_scores(const uint16_t* C1, int32_t W1, const uint16_t* C2, int32_t W2,
+                              int32_t A, const int8_t* S) {
+  int64_t* U = (int64_t*)malloc(sizeof(int64_t) * (size_t)(W1 > 0 ? W1 : 1) * (size_t)A);
+  for (int32_t i = 0; i < W1; ++i)
+    for (int32_t b = 0; b < A; ++b) {
+      int64_t u = 0;
+      for (int32_t a = 0; a < A; ++a) u += (int64_t)C1[(size_t)i * A + a] * S[a * A + b];
+      U[(size_t)i * A + b] = u;
+    }
+  int64_t* sc = (int64_t*)malloc(sizeof(int64_t) * (size_t)(W1 > 0 ? W1 : 1) *
+                                 (size_t)(W2 > 0 ? W2 : 1));
+  for (int32_t i = 0; i < W1; ++i)
+    for (int32_t j = 0; j < W2; ++j) {
+      int64_t s = 0;
+      for (int32_t b = 0; b < A; ++b) s += U[(size_t)i * A + b] * C2[(size_t)j * A + b];
+      sc[(size_t)i * W2 + j] = s;
+    }
+  free(U);
+  return sc;
+}
+
+/* Reading of the profile gap model (the paper only names the method of its
+ * reference [12]): affine run cost g(l) = o + (l - 1) e with o = n1 n2 go and
+ * e = n1 n2 ge, terminal gaps charged like internal ones.  Recurrences
+ * (Gotoh):
+ *   M(i,j) = H(i-1,j-1) + s(i,j)
+ *   X(i,j) = max(X(i-1,j) - e, H(i-1,j) - o)      column i of P1 vs a gap
+ *   Y(i,j) = max(Y(i,j-1) - e, H(i,j-1) - o)      column j of P2 vs a gap
+ *   H(i,j) = max(M, X, Y)
+ * Among optimal alignments the one returned has the lexicographically smallest
+ * op string read backwards from (W1, W2), with M < X < Y. */
+int sadref_profile_align(const uint16_t* C1, int32_t W1, int32_t n1,
+                         const uint16_t* C2, int32_t W2, int32_t n2,
+                         int32_t A, const int8_t* S, int32_t go, int32_t ge,
+                         uint8_t* ops, int32_t* n_ops, int64_t* score) {
+  if (W1 < 0 || W2 < 0 || n1 < 0 || n2 < 0 || go < ge || ge < 0) return SADREF_E_INVAL;
+  int64_t G = (int64_t)n1 * n2;
+  int64_t o = G * go, e = G * ge;
+  int64_t smax = 1;
+  for (int32_t a = 0; a < A * A; ++a) {
+    int64_t v = S[a] < 0 ? -(int64_t)S[a] : S[a];
+    if (v > smax) smax = v;
+  }
+  int64_t unit = smax > go ? smax : go;
+  /* static bound of every DP value: (W1 + W2 + 2) * G * max(|S|, go) */
+  if ((double)(W1 + W2 + 2) * (double)G * (double)unit >= 2.0e18) return SADREF_E_OVERFLOW;
+
+  int64_t* sc = column_scores(C1, W1, C2, W2, A, S);
+  size_t R = (size_t)W1 + 1, C = (size_t)W2 + 1;
+  int64_t* H = (int64_t*)malloc(sizeof(int64_t) * R * C);
+  int64_t* X = (int64_t*)malloc(sizeof(int64_t) * R * C);
+  int64_t* Y = (int64_t*)malloc(sizeof(int64_t) * R * C);
+  uint8_t* bits = (uint8_t*)calloc(R * C, 1);
+#define AT(M_, i_, j_) M_[(size_t)(i_) * C + (size_t)(j_)]
+
+  AT(H, 0, 0) = 0;
+  AT(X, 0, 0) = NEG_INF;
+  AT(Y, 0, 0) = NEG_INF;
+  for (int32_t i = 1; i <= W1; ++i) {
+    AT(H, i, 0) = -(o + (int64_t)(i - 1) * e);
+    AT(X, i, 0) = AT(H, i, 0);
+    AT(Y, i, 0) = NEG_INF;
+  }
+  for (int32_t j = 1; j <= W2; ++j) {
+    AT(H, 0, j) = -(o + (int64_t)(j - 1) * e);
+    AT(Y, 0, j) = AT(H, 0, j);
+    AT(X, 0, j) = NEG_INF;
+  }
+  for (int32_t i = 1; i <= W1; ++i) {
+    for (int32_t j = 1; j <= W2; ++j) {
+      int64_t m = AT(H, i - 1, j - 1) + sc[(size_t)(i - 1) * W2 + (j - 1)];
+      int64_t xo = AT(H, i - 1, j) - o;
+      int64_t xe = AT(X, i - 1, j) - e;
+      int64_t x = max2(xo, xe);
+      int64_t yo = AT(H, i, j - 1) - o;
+      int64_t ye = AT(Y, i, j - 1) - e;
+      int64_t y = max2(yo, ye);
+      int64_t h = max2(m, max2(x, y));
+      uint8_t bt = 0;
+      if (m == h) bt |= B_HM;
+      if (x == h) bt |= B_HX;
+      if (y == h) bt |= B_HY;
+      if (xo == x) bt |= B_XO;
+      if (xe == x) bt |= B_XE;
+      if (yo == y) bt |= B_YO;
+      if (ye == y) bt |= B_YE;
+      AT(H, i, j) = h;
+      AT(X, i, j) = x;
+      AT(Y, i, j) = y;
+      AT(bits, i, j) = bt;
+    }
+  }
+  *score = AT(H, W1, W2);
+
+  /* Traceback, greedy from the end: at every step the next op back is the
+   * smallest one that still admits an optimal completion.  In state H the
+   * candidates are the ops attaining H; in state X the run either extends
+   * (xExt) or was opened from H(i-1, j), whose attaining ops then follow
+   * (an X never directly precedes an opened X run unless o == e, in which
+   * case the extension covers it); likewise for Y. */
+  int32_t i = W1, j = W2, k = 0;
+  int state = 0; /* 0 = H, 1 = X, 2 = Y */
+  uint8_t* rev = (uint8_t*)malloc((size_t)W1 + (size_t)W2 + 1);
+  while (i > 0 && j > 0) {
+    uint8_t bt = AT(bits, i, j);
+    if (state == 0) {
+      if (bt & B_HM) {
+        rev[k++] = SADREF_OP_M;
+        --i;
+        --j;
+      } else if (bt & B_HX) {
+        state = 1;
+      } else {
+        state = 2;
+      }
+    } else if (state == 1) {
+      rev[k++] = SADREF_OP_X;
+      --i;
+      int prev_m = (i > 0 && j > 0) ? (AT(bits, i, j) & B_HM) != 0 : 0;
+      if ((bt & B_XO) && prev_m) state = 0;
+      else if (bt & B_XE) state = 1;
+      else state = 0;
+    } else {
+      rev[k++] = SADREF_OP_Y;
+      --j;
+      int prev_mx = (i > 0 && j > 0) ? (AT(bits, i, j) & (B_HM | B_HX)) != 0 : 0;
+      if ((bt & B_YO) && prev_mx) state = 0;
+      else if (bt & B_YE) state = 2;
+      else state = 0;
+    }
+  }
+  /* on the border the rest of the path is forced */
+  while (i > 0) {
+    rev[k++] = SADREF_OP_X;
+    --i;
+  }
+  while (j > 0) {
+    rev[k++] = SADREF_OP_Y;
+    --j;
+  }
+  for (int32_t t = 0; t < k; ++t) ops[t] = rev[k - 1 - t];
+  *n_ops = k;
+#undef AT
+  free(rev);
+  free(sc);
+  free(H);
+  free(X);
+  free(Y);
+  free(bits);
+  return SADREF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Progressive alignment along the guide tree                          */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t W;        /* columns */
+  int32_t n;        /* rows */
+  uint16_t* cnt;    /* W x A counts */
+  int32_t* up;      /* column in the parent, W entries (NULL for the root) */
+  int32_t parent;
+} node_t;
+
+static int check_count(int64_t v) { return v <= 65535; }
+
+/* Aligns n leaf sequences progressively along the UPGMA tree of their
+ * k-mer similarities.  Outputs: root node index, per-merge scores, cells, op
+ * strings.  nodes[] must hold 2n - 1 entries. */
+static int progressive(int32_t n, const uint8_t* const* seq, const int64_t* len, int32_t A,
+                       int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge,
+                       node_t* nodes, int32_t* merges, int64_t* mscore, int64_t* mcells,
+                       uint8_t* ops_out, int64_t ops_cap, int64_t* ops_off, int64_t* ops_pos) {
+  /* leaves: one-row profiles */
+  for (int32_t a = 0; a < n; ++a) {
+    node_t* nd = &nodes[a];
+    nd->W = (int32_t)len[a];
+    nd->n = 1;
+    nd->cnt = (uint16_t*)calloc((size_t)(nd->W > 0 ? nd->W : 1) * (size_t)A, sizeof(uint16_t));
+    for (int32_t c = 0; c < nd->W; ++c) nd->cnt[(size_t)c * A + seq[a][c]] = 1;
+    nd->up = NULL;
+    nd->parent = -1;
+  }
+  if (n <= 1) return SADREF_OK;
+
+  /* pairwise fixed-point similarities, then UPGMA */
+  kmer_list_t* kl = (kmer_list_t*)malloc(sizeof(kmer_list_t) * (size_t)n);
+  for (int32_t a = 0; a < n; ++a) build_list(&kl[a], seq[a], len[a], A, kmer_k);
+  uint32_t* F = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n * (size_t)n);
+  for (int32_t a = 0; a < n; ++a)
+    for (int32_t b = 0; b < n; ++b) F[(size_t)a * n + b] = fhat_lists(&kl[a], &kl[b], kmer_k);
+  for (int32_t a = 0; a < n; ++a) free_list(&kl[a]);
+  free(kl);
+  sadref_upgma(n, F, merges);
+  free(F);
+
+  int st = SADREF_OK;
+  for (int32_t t = 0; t < n - 1 && st == SADREF_OK; ++t) {
+    /* P1 = the child with the smaller id */
+    node_t* p1 = &nodes[merges[2 * t]];
+    node_t* p2 = &nodes[merges[2 * t + 1]];
+    node_t* nd = &nodes[n + t];
+    int32_t cap = p1->W + p2->W;
+    uint8_t* ops = (uint8_t*)malloc((size_t)(cap > 0 ? cap : 1));
+    int32_t nops = 0;
+    int64_t sc = 0;
+    st = sadref_profile_align(p1->cnt, p1->W, p1->n, p2->cnt, p2->W, p2->n, A, S, go, ge,
+                              ops, &nops, &sc);
+    if (st) {
+      free(ops);
+      break;
+    }
+    mscore[t] = sc;
+    mcells[t] = (int64_t)p1->W * p2->W;
+    if (ops_out) {
+      ops_off[t] = *ops_pos;
+      if (*ops_pos + nops > ops_cap) {
+        st = SADREF_E_CAPACITY;
+      } else {
+        memcpy(ops_out + *ops_pos, ops, (size_t)nops);
+        *ops_pos += nops;
+      }
+    }
+    /* merged alignment: P1's rows then P2's rows; column counts add */
+    nd->W = nops;
+    nd->n = p1->n + p2->n;
+    nd->cnt = (uint16_t*)calloc((size_t)(nops > 0 ? nops : 1) * (size_t)A, sizeof(uint16_t));
+    nd->up = NULL;
+    nd->parent = -1;
+    p1->up = (int32_t*)malloc(sizeof(int32_t) * (size_t)(p1->W > 0 ? p1->W : 1));
+    p2->up = (int32_t*)malloc(sizeof(int32_t) * (size_t)(p2->W > 0 ? p2->W : 1));
+    p1->parent = n + t;
+    p2->parent = n + t;
+    int32_t i = 0, j = 0;
+    for (int32_t c = 0; c < nops; ++c) {
+      if (ops[c] != SADREF_OP_Y) {
+        for (int32_t a = 0; a < A; ++a) {
+          int64_t v = (int64_t)nd->cnt[(size_t)c * A + a] + p1->cnt[(size_t)i * A + a];
+          if (!check_count(v)) st = SADREF_E_OVERFLOW;
+          nd->cnt[(size_t)c * A + a] = (uint16_t)v;
+        }
+        p1->up[i++] = c;
+      }
+      if (ops[c] != SADREF_OP_X) {
+        for (int32_t a = 0; a < A; ++a) {
+          int64_t v = (int64_t)nd->cnt[(size_t)c * A + a] + p2->cnt[(size_t)j * A + a];
+          if (!check_count(v)) st = SADREF_E_OVERFLOW;
+          nd->cnt[(size_t)c * A + a] = (uint16_t)v;
+        }
+        p2->up[j++] = c;
+      }
+    }
+    free(ops);
+  }
+  return st;
+}
+
+static void free_nodes(node_t* nodes, int32_t m) {
+  for (int32_t a = 0; a < m; ++a) {
+    free(nodes[a].cnt);
+    free(nodes[a].up);
+  }
+}
+
+/* column of residue r of leaf a in the root's alignment */
+static int32_t root_column(const node_t* nodes, int32_t a, int32_t r) {
+  int32_t c = r;
+  while (nodes[a].parent >= 0) {
+    c = nodes[a].up[c];
+    a = nodes[a].parent;
+  }
+  return c;
+}
+
+int sadref_align_buckets(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                         int32_t p, const int32_t* bucket_off, const int32_t* members,
+                         int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge,
+                         int32_t* colmap, int32_t* width, int64_t* merge_score,
+                         int32_t* merge_list, int64_t* merge_cells, int64_t* cells,
+                         uint8_t* ops, int64_t ops_cap, int64_t* ops_off) {
+  int st = validate_seqs(n, A, codes, offsets, kmer_k);
+  if (st) return st;
+  if (p < 1 || go < ge || ge < 0) return SADREF_E_INVAL;
+  if (bucket_off[0] != 0 || bucket_off[p] != n) return SADREF_E_INVAL;
+  *cells = 0;
+  int64_t ops_pos = 0;
+  for (int32_t b = 0; b < p && st == SADREF_OK; ++b) {
+    int32_t lo = bucket_off[b], nb = bucket_off[b + 1] - lo;
+    if (nb < 0) return SADREF_E_INVAL;
+    if (nb == 0) {
+      width[b] = 0;
+      continue;
+    }
+    const uint8_t** seq = (const uint8_t**)malloc(sizeof(uint8_t*) * (size_t)nb);
+    int64_t* len = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
+    for (int32_t a = 0; a < nb; ++a) {
+      int32_t id = members[lo + a];
+      seq[a] = codes + offsets[id];
+      len[a] = offsets[id + 1] - offsets[id];
+    }
+    node_t* nodes = (node_t*)calloc((size_t)(2 * nb - 1), sizeof(node_t));
+    st = progressive(nb, seq, len, A, kmer_k, S, go, ge, nodes, merge_list + 2 * (int64_t)lo,
+                     merge_score + lo, merge_cells + lo, ops, ops_cap,
+                     ops ? ops_off + lo : NULL, &ops_pos);
+    /* the bucket's last slot holds no merge: its offset closes the previous
+     * op string, so merge t always ends at ops_off[t + 1] */
+    if (ops && st == SADREF_OK) ops_off[lo + nb - 1] = ops_pos;
+    if (st == SADREF_OK) {
+      int32_t root = 2 * nb - 2;
+      width[b] = nodes[root].W;
+      for (int32_t t = 0; t < nb - 1; ++t) *cells += merge_cells[lo + t];
+      for (int32_t a = 0; a < nb; ++a) {
+        int32_t id = members[lo + a];
+        for (int64_t r = 0; r < len[a]; ++r)
+          colmap[offsets[id] + r] = root_column(nodes, a, (int32_t)r);
+      }
+    }
+    free_nodes(nodes, 2 * nb - 1);
+    free(nodes);
+    free(seq);
+    free(len);
+  }
+  if (ops && st == SADREF_OK) ops_off[n] = ops_pos;
+  return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Ancestors, global ancestor, refinement and glue (Section 2.3.3)      */
+/* ------------------------------------------------------------------ */
+
+/* Reading of "local ancestor": the majority consensus of the alignment. */
+int sadref_consensus(const uint16_t* counts, int32_t W, int32_t n, int32_t A,
+                     uint8_t* out, int32_t* out_len) {
+  int32_t m = 0;
+  for (int32_t c = 0; c < W; ++c) {
+    int64_t tot = 0;
+    int32_t best = 0;
+    for (int32_t a = 0; a < A; ++a) {
+      tot += counts[(size_t)c * A + a];
+      if (counts[(size_t)c * A + a] > counts[(size_t)c * A + best]) best = a;
+    }
+    if (2 * tot >= n) out[m++] = (uint8_t)best;
+  }
+  *out_len = m;
+  return SADREF_OK;
+}
+
+int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                  int32_t p, const int32_t* bucket_off, const int32_t* members,
+                  const int32_t* colmap_b, const int32_t* width_b,
+                  int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge,
+                  uint8_t* ga, int32_t ga_cap, int32_t* ga_len,
+                  int32_t* colmap_g, int32_t* width_g,
+                  int64_t* merge_score_g, int32_t* merge_list_g, int64_t* merge_cells_g,
+                  int32_t* n_merges_g, int64_t* cells) {
+  int st = validate_seqs(n, A, codes, offsets, kmer_k);
+  if (st) return st;
+  if (p < 1 || go < ge || ge < 0) return SADREF_E_INVAL;
+  if (bucket_off[0] != 0 || bucket_off[p] != n) return SADREF_E_INVAL;
+
+  /* bucket alignments as column-count profiles */
+  int32_t q = 0;
+  int32_t* nonempty = (int32_t*)malloc(sizeof(int32_t) * (size_t)p);
+  uint16_t** prof = (uint16_t**)calloc((size_t)p, sizeof(uint16_t*));
+  for (int32_t b = 0; b < p; ++b) {
+    int32_t lo = bucket_off[b], nb = bucket_off[b + 1] - lo;
+    if (nb <= 0) continue;
+    nonempty[q++] = b;
+    int32_t W = width_b[b];
+    prof[b] = (uint16_t*)calloc((size_t)(W > 0 ? W : 1) * (size_t)A, sizeof(uint16_t));
+    for (int32_t a = 0; a < nb; ++a) {
+      int32_t id = members[lo + a];
+      for (int64_t r = offsets[id]; r < offsets[id + 1]; ++r) {
+        int32_t c = colmap_b[r];
+        if (c < 0 || c >= W) {
+          st = SADREF_E_INVAL;
+          continue;
+        }
+        prof[b][(size_t)c * A + codes[r]] += 1;
+      }
+    }
+  }
+
+  /* local ancestors */
+  uint8_t** anc = (uint8_t**)calloc((size_t)(q > 0 ? q : 1), sizeof(uint8_t*));
+  int64_t* anc_len = (int64_t*)calloc((size_t)(q > 0 ? q : 1), sizeof(int64_t));
+  for (int32_t u = 0; u < q && st == SADREF_OK; ++u) {
+    int32_t b = nonempty[u];
+    int32_t W = width_b[b], len = 0;
+    anc[u] = (uint8_t*)malloc((size_t)(W > 0 ? W : 1));
+    sadref_consensus(prof[b], W, bucket_off[b + 1] - bucket_off[b], A, anc[u], &len);
+    anc_len[u] = len;
+  }
+
+  /* global ancestor: the consensus of the ancestors aligned along their own
+   * guide tree (leaves in bucket order) */
+  int32_t nm = 0;
+  *cells = 0;
+  uint8_t* GA = NULL;
+  int32_t GL = 0;
+  if (st == SADREF_OK) {
+    if (q == 1) {
+      GL = (int32_t)anc_len[0];
+      GA = (uint8_t*)malloc((size_t)(GL > 0 ? GL : 1));
+      memcpy(GA, anc[0], (size_t)GL);
+    } else {
+      node_t* nodes = (node_t*)calloc((size_t)(2 * q - 1), sizeof(node_t));
+      st = progressive(q, (const uint8_t* const*)anc, anc_len, A, kmer_k, S, go, ge, nodes,
+                       merge_list_g, merge_score_g, merge_cells_g, NULL, 0, NULL, NULL);
+      if (st == SADREF_OK) {
+        node_t* root = &nodes[2 * q - 2];
+        GA = (uint8_t*)malloc((size_t)(root->W > 0 ? root->W : 1));
+        sadref_consensus(root->cnt, root->W, root->n, A, GA, &GL);
+        nm = q - 1;
+        for (int32_t t = 0; t < nm; ++t) *cells += merge_cells_g[t];
+      }
+      free_nodes(nodes, 2 * q - 1);
+      free(nodes);
+    }
+  }
+  if (st == SADREF_OK) {
+    *ga_len = GL;
+    if (GL > ga_cap) st = SADREF_E_CAPACITY;
+    else memcpy(ga, GA, (size_t)GL);
+  }
+
+  /* refinement: every bucket alignment against GA as a one-row profile; the
+   * bucket's own columns stay together (only all-gap columns are inserted) */
+  uint8_t** bops = (uint8_t**)calloc((size_t)(q > 0 ? q : 1), sizeof(uint8_t*));
+  int32_t* bnops = (int32_t*)calloc((size_t)(q > 0 ? q : 1), sizeof(int32_t));
+  uint16_t* gap_prof = NULL;
+  if (st == SADREF_OK) {
+    gap_prof = (uint16_t*)calloc((size_t)(GL > 0 ? GL : 1) * (size_t)A, sizeof(uint16_t));
+    for (int32_t c = 0; c < GL; ++c) gap_prof[(size_t)c * A + GA[c]] = 1;
+    for (int32_t u = 0; u < q && st == SADREF_OK; ++u) {
+      int32_t b = nonempty[u];
+      int32_t W = width_b[b], nb = bucket_off[b + 1] - bucket_off[b];
+      bops[u] = (uint8_t*)malloc((size_t)(W + GL > 0 ? W + GL : 1));
+      int64_t sc = 0;
+      st = sadref_profile_align(prof[b], W, nb, gap_prof, GL, 1, A, S, go, ge, bops[u],
+                                &bnops[u], &sc);
+      merge_score_g[nm + u] = sc;
+      merge_cells_g[nm + u] = (int64_t)W * GL;
+      merge_list_g[2 * (nm + u)] = b;
+      merge_list_g[2 * (nm + u) + 1] = -1;
+      *cells += (int64_t)W * GL;
+    }
+  }
+
+  /* glue: before GA position j (and after the last one) an insert slot holds
+   * the bucket columns aligned to gaps there -- bucket by bucket, each in its
+   * own order -- then comes the shared column j; all-gap columns are dropped */
+  if (st == SADREF_OK) {
+    int64_t slots = (int64_t)GL + 1;
+    int64_t* ins = (int64_t*)calloc((size_t)(q * slots > 0 ? q * slots : 1), sizeof(int64_t));
+    char* shared_used = (char*)calloc((size_t)(GL > 0 ? GL : 1), 1);
+    for (int32_t u = 0; u < q; ++u) {
+      int32_t j = 0;
+      for (int32_t t = 0; t < bnops[u]; ++t) {
+        if (bops[u][t] == SADREF_OP_X) ins[(int64_t)u * slots + j] += 1;
+        else {
+          if (bops[u][t] == SADREF_OP_M) shared_used[j] = 1;
+          ++j;
+        }
+      }
+    }
+    /* start index of each (slot, bucket) block and each kept shared column */
+    int64_t* blk = (int64_t*)malloc(sizeof(int64_t) * (size_t)(q * slots > 0 ? q * slots : 1));
+    int64_t* shared_at = (int64_t*)malloc(sizeof(int64_t) * (size_t)(GL > 0 ? GL : 1));
+    int64_t pos = 0;
+    for (int64_t j = 0; j < slots; ++j) {
+      for (int32_t u = 0; u < q; ++u) {
+        blk[(int64_t)u * slots + j] = pos;
+        pos += ins[(int64_t)u * slots + j];
+      }
+      if (j < GL) {
+        shared_at[j] = shared_used[j] ? pos : -1;
+        if (shared_used[j]) ++pos;
+      }
+    }
+    *width_g = (int32_t)pos;
+    for (int32_t u = 0; u < q; ++u) {
+      int32_t b = nonempty[u];
+      int32_t W = width_b[b];
+      int32_t* to_g = (int32_t*)malloc(sizeof(int32_t) * (size_t)(W > 0 ? W : 1));
+      int32_t i = 0, j = 0;
+      int64_t k_in = 0;
+      for (int32_t t = 0; t < bnops[u]; ++t) {
+        uint8_t op = bops[u][t];
+        if (op == SADREF_OP_X) {
+          to_g[i++] = (int32_t)(blk[(int64_t)u * slots + j] + k_in);
+          ++k_in;
+        } else {
+          if (op == SADREF_OP_M) to_g[i++] = (int32_t)shared_at[j];
+          ++j;
+          k_in = 0;
+        }
+      }
+      int32_t lo = bucket_off[b], nb = bucket_off[b + 1] - lo;
+      for (int32_t a = 0; a < nb; ++a) {
+        int32_t id = members[lo + a];
+        for (int64_t r = offsets[id]; r < offsets[id + 1]; ++r) colmap_g[r] = to_g[colmap_b[r]];
+      }
+      free(to_g);
+    }
+    free(ins);
+    free(shared_used);
+    free(blk);
+    free(shared_at);
+  }
+  *n_merges_g = nm + q;
+
+  for (int32_t u = 0; u < q; ++u) {
+    free(anc[u]);
+    free(bops[u]);
+  }
+  for (int32_t b = 0; b < p; ++b) free(prof[b]);
+  free(prof);
+  free(anc);
+  free(anc_len);
+  free(bops);
+  free(bnops);
+  free(gap_prof);
+  free(GA);
+  free(nonempty);
+  return st;
+}
