@@ -1,0 +1,176 @@
+/*
+ * sad.h -- C-ABI of the MI355X (gfx950) library for the data-parallel core of
+ * Sample-Align-D (F. Saeed, A. Khokhar, "Sample-Align-D: A High Performance
+ * Multiple Sequence Alignment System using Phylogenetic Sampling and Domain
+ * Decomposition", arXiv 0901.2742).
+ *
+ * Problem statement (Section 2, algorithm box; Section 2.2): given N
+ * sequences, insert gaps so that all rows have equal length and the sum-of-
+ * pairs score of the result is high.  The method sample-sorts the sequences
+ * into p buckets by k-mer rank, aligns every bucket independently, and glues
+ * the bucket alignments through a global ancestor.  The four calls below are
+ * the four stages of that pipeline, in order.
+ *
+ * Conventions for every call
+ *  - Pointers named d_* are device pointers (HBM of the current HIP device);
+ *    everything else is host memory.  All arrays are owned by the caller; the
+ *    library never frees or keeps them.  Inputs are read-only.
+ *  - The library allocates its own transient device workspace (grown on
+ *    demand, kept per device until sad_release()).
+ *  - Work is enqueued on `stream`; each call synchronises that stream before
+ *    it returns so that it can report device-side errors in its status.
+ *  - Residue codes are 0..A-1 (A = 20 proteins, A = 4 DNA).  A k-mer tau of
+ *    a sequence x at position t is sum_u x[t+u] * A^(k-1-u); A^k <= 65536.
+ *  - Limits: sequence length <= 8192; profile width <= 4096 columns;
+ *    DP values must stay within the 32-bit bound described at
+ *    sad_align_buckets (otherwise SAD_E_OVERFLOW).
+ *  - Status codes are returned; no exception crosses the ABI.  On error the
+ *    contents of the outputs are unspecified.  sad_last_error() gives a
+ *    message for the calling thread's last failure.
+ */
+#ifndef SAD_H
+#define SAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SAD_OK 0
+#define SAD_E_INVAL (-1)        /* bad code, L < k, N < 2p, go < ge, bad alphabet, bad k */
+#define SAD_E_CAPACITY (-2)     /* a caller capacity or a library limit is too small */
+#define SAD_E_OVERFLOW (-3)     /* a DP value bound exceeds the 32-bit range */
+#define SAD_E_DEVICE (-4)       /* HIP runtime failure */
+#define SAD_E_UNIMPLEMENTED (-5)
+
+/* mode flags (sad_params.mode) */
+#define SAD_PLAIN 0u            /* column scores on the vector ALUs */
+#define SAD_BATCHED_MFMA 1u     /* column scores on int8 matrix cores (same results) */
+
+/* N sequences: residue codes of sequence i are d_codes[d_offsets[i] ..
+ * d_offsets[i+1]).  total_len must equal d_offsets[n]; max_len must be >= every
+ * length (both are checked on the device). */
+typedef struct sad_seqs {
+  int32_t n;
+  int32_t alphabet;            /* 20 or 4 */
+  const uint8_t* d_codes;      /* [total_len] */
+  const int64_t* d_offsets;    /* [n + 1], d_offsets[0] == 0 */
+  int64_t total_len;
+  int32_t max_len;
+} sad_seqs;
+
+/* Method parameters.  subst is a host pointer to the A x A int8 substitution
+ * matrix (row-major, symmetric).  Gap runs of length l cost
+ * gap_open + (l - 1) * gap_extend (gap_open >= gap_extend >= 0). */
+typedef struct sad_params {
+  int32_t kmer_k;              /* k-mer length of the similarity (Section 2) */
+  int32_t p;                   /* number of buckets ("processors") */
+  int32_t s_max;               /* cap on the number of global samples (1024) */
+  const int8_t* subst;         /* host, A x A */
+  int32_t gap_open;
+  int32_t gap_extend;
+  uint32_t mode;               /* SAD_PLAIN or SAD_BATCHED_MFMA */
+} sad_params;
+
+/* Alignment results (device arrays, caller-allocated). */
+typedef struct sad_msa {
+  int32_t* d_colmap;           /* [total_len]: column of each residue */
+  int32_t* d_width;            /* per bucket [p] (bucket alignments) or [1] (glued) */
+  int64_t* d_merge_score;      /* per alignment step (see each call) */
+  int32_t* d_merge_list;       /* pairs of cluster ids per alignment step */
+  int64_t* d_merge_cells;      /* DP cells W1 * W2 per alignment step */
+  int64_t* d_cells;            /* [1]: total DP cells */
+} sad_msa;
+
+/*
+ * Stage 1 -- k-mer rank (Section 2 "k-mer Rank", Section 2.3.1, steps 1-6 of
+ * the algorithm box).  Processor c of the paper holds the contiguous chunk
+ * [floor(c N / p), floor((c+1) N / p)).  With F(i,j) = floor(c_ij 2^31 / d_ij),
+ * c_ij = sum_tau min(n_i(tau), n_j(tau)) and d_ij = min(L_i, L_j) - k + 1:
+ *   local rank  K_loc(i) = sum_{j in chunk(i)} F(i,j)  (self included);
+ *   each chunk is sorted by (K_loc(i), i) and k_s = min(p-1, max(1, s_max/p),
+ *   w_min - 1) samples are taken at positions floor(t w / (k_s+1)), t=1..k_s;
+ *   globalised rank d_key[i] = sum over all p k_s samples s of F(i,s).
+ * Outputs: d_key[n] (uint64), d_sample_ids[p k_s] (chunk-major), *n_samples
+ * (host).  SAD_E_CAPACITY (with *n_samples set) if p k_s > sample_cap.
+ */
+int32_t sad_kmer_rank(const sad_seqs* seqs, const sad_params* prm, uint64_t* d_key,
+                      int32_t* d_sample_ids, int32_t sample_cap, int32_t* n_samples,
+                      hipStream_t stream);
+
+/*
+ * Stage 2 -- regular-sampling partition (Section 2.3.2, steps 7-10).  Each chunk
+ * is sorted by the composite key (key_i, i); p-1 keys are taken at positions
+ * floor(t w / p), t = 1..p-1; the p(p-1) gathered keys Y are sorted and the
+ * pivots are Y at 1-based positions floor(p/2) + (t-1) p, t = 1..p-1.
+ * bucket(i) = number of pivots strictly below (key_i, i).
+ * Outputs (device): d_pivot_key/d_pivot_id[p-1], d_bucket[n],
+ * d_bucket_off[p+1] (exclusive prefix of bucket sizes), d_members[n] (ids of
+ * each bucket, ascending).
+ */
+int32_t sad_partition(const sad_seqs* seqs, const uint64_t* d_key, const sad_params* prm,
+                      uint64_t* d_pivot_key, int32_t* d_pivot_id, int32_t* d_bucket,
+                      int32_t* d_bucket_off, int32_t* d_members, hipStream_t stream);
+
+/*
+ * Stage 3 -- independent alignment of every bucket (Section 2.3.3, step 11; the
+ * sequential aligner is k-mer similarity + UPGMA + progressive profile-profile
+ * alignment):
+ *   - UPGMA on F among the bucket's members (leaves in d_members order) merges
+ *     the active pair with the largest average similarity, compared exactly;
+ *     ties go to the smallest (min id, max id); cluster t gets id n_b + t;
+ *   - each merge aligns P1 = child with the smaller id against P2 with affine
+ *     gaps: column score s(i,j) = sum_ab C1[i][a] S[a][b] C2[j][b]; a gap run
+ *     of length l costs G (go + (l-1) ge), G = n1 n2; terminal gaps charged;
+ *     among optimal alignments the one whose op string read backwards is
+ *     lexicographically smallest (M < X < Y) is taken; rows of P1 then P2.
+ * Outputs (device, out): d_colmap[total_len]: column of each residue in its
+ * bucket's alignment; d_width[p]; bucket b's merges occupy slots
+ * [d_bucket_off[b], d_bucket_off[b] + n_b - 1) of d_merge_score[n],
+ * d_merge_cells[n] and d_merge_list[2n] (local cluster ids); d_cells[1].
+ * 32-bit bound: every merge needs (W1 + W2 + 2) n1 n2 max(|S|, go) < 2^29.
+ */
+int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                          const int32_t* d_members, const sad_params* prm, sad_msa* out,
+                          hipStream_t stream);
+
+/*
+ * Stage 4 -- global ancestor, ancestor-constrained refinement and glue
+ * (Section 2.3.3, steps 12-15).  The local ancestor of a bucket is the
+ * majority consensus of its alignment (column kept iff 2 residues >= rows;
+ * most frequent residue, smallest code on ties).  The q non-empty buckets'
+ * ancestors are aligned like a bucket (leaves in bucket order); GA is the
+ * consensus of that alignment (GA = the ancestor when q = 1).  Each bucket
+ * alignment is then aligned against GA as a one-row profile (G = n_b); its own
+ * columns stay together.  Glue: before GA position j (and after the last) an
+ * insert slot holds the bucket columns aligned to gaps there, bucket by
+ * bucket; then the shared column j; all-gap columns are dropped.
+ * Inputs: the stage-3 outputs d_colmap/d_width of `buckets`.
+ * Outputs: d_ga[ga_cap] and *ga_len (host; SAD_E_CAPACITY if too small);
+ * global_out: d_colmap[total_len], d_width[1]; d_merge_score/d_merge_cells
+ * [2p] and d_merge_list[4p]: the q-1 ancestor merges then the q refinement
+ * alignments (pairs (bucket, -1)); *n_steps (host) = 2q - 1; d_cells[1].
+ */
+int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off, const int32_t* d_members,
+                   const sad_msa* buckets, const sad_params* prm, uint8_t* d_ga,
+                   int32_t ga_cap, int32_t* ga_len, sad_msa* global_out, int32_t* n_steps,
+                   hipStream_t stream);
+
+/* Message for the calling thread's last non-OK status (static storage). */
+const char* sad_last_error(void);
+
+/* Frees the library's device workspaces on every device. */
+void sad_release(void);
+
+/* Library version string. */
+const char* sad_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAD_H */

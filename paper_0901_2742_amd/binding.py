@@ -1,0 +1,233 @@
+"""ctypes binding of libsad.so (include/sad.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the method runs in the library's gfx950 kernels.  If the
+library is not built this module raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsad.so")
+
+SAD_OK = 0
+SAD_E_INVAL = -1
+SAD_E_CAPACITY = -2
+SAD_E_OVERFLOW = -3
+SAD_E_DEVICE = -4
+SAD_E_UNIMPLEMENTED = -5
+SAD_PLAIN = 0
+SAD_BATCHED_MFMA = 1
+
+# the functions include/sad.h declares
+EXPORTS = ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine",
+           "sad_last_error", "sad_release", "sad_version")
+
+
+class SadError(RuntimeError):
+    def __init__(self, code: int, call: str, msg: str):
+        super().__init__(f"{call} failed with status {code}: {msg}")
+        self.code = code
+
+
+class SadSeqs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("alphabet", ctypes.c_int32),
+                ("d_codes", ctypes.c_void_p), ("d_offsets", ctypes.c_void_p),
+                ("total_len", ctypes.c_int64), ("max_len", ctypes.c_int32)]
+
+
+class SadParams(ctypes.Structure):
+    _fields_ = [("kmer_k", ctypes.c_int32), ("p", ctypes.c_int32), ("s_max", ctypes.c_int32),
+                ("subst", ctypes.c_void_p), ("gap_open", ctypes.c_int32),
+                ("gap_extend", ctypes.c_int32), ("mode", ctypes.c_uint32)]
+
+
+class SadMsa(ctypes.Structure):
+    _fields_ = [("d_colmap", ctypes.c_void_p), ("d_width", ctypes.c_void_p),
+                ("d_merge_score", ctypes.c_void_p), ("d_merge_list", ctypes.c_void_p),
+                ("d_merge_cells", ctypes.c_void_p), ("d_cells", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libsad.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_0901_2742_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I32 = ctypes.c_int32
+        L.sad_kmer_rank.argtypes = [P, P, P, P, I32, P, P]
+        L.sad_partition.argtypes = [P, P, P, P, P, P, P, P, P]
+        L.sad_align_buckets.argtypes = [P, P, P, P, P, P]
+        L.sad_refine.argtypes = [P, P, P, P, P, P, I32, P, P, P, P]
+        for f in ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine"):
+            getattr(L, f).restype = I32
+        L.sad_last_error.restype = ctypes.c_char_p
+        L.sad_version.restype = ctypes.c_char_p
+        L.sad_release.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(code: int, call: str):
+    if code != SAD_OK:
+        raise SadError(code, call, lib().sad_last_error().decode(errors="replace"))
+
+
+@dataclasses.dataclass
+class DeviceSeqs:
+    """Sequences resident in HBM (uint8 codes, int64 offsets)."""
+    n: int
+    alphabet: int
+    codes: torch.Tensor
+    offsets: torch.Tensor
+    total_len: int
+    max_len: int
+
+    @classmethod
+    def from_numpy(cls, codes: np.ndarray, offsets: np.ndarray, alphabet: int,
+                   device: str = "cuda") -> "DeviceSeqs":
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        n = len(offsets) - 1
+        lens = np.diff(offsets)
+        c = torch.from_numpy(codes if len(codes) else np.zeros(1, np.uint8)).to(device)
+        o = torch.from_numpy(offsets).to(device)
+        return cls(n, alphabet, c, o, int(offsets[-1]), int(lens.max()) if n else 0)
+
+    def c_struct(self) -> SadSeqs:
+        return SadSeqs(self.n, self.alphabet, self.codes.data_ptr(), self.offsets.data_ptr(),
+                       self.total_len, self.max_len)
+
+
+@dataclasses.dataclass
+class Params:
+    kmer_k: int
+    p: int
+    subst: np.ndarray
+    gap_open: int
+    gap_extend: int
+    s_max: int = 1024
+    mode: int = SAD_BATCHED_MFMA
+
+    def c_struct(self) -> SadParams:
+        self._s = np.ascontiguousarray(self.subst, dtype=np.int8)  # keep alive
+        return SadParams(self.kmer_k, self.p, self.s_max,
+                         self._s.ctypes.data_as(ctypes.c_void_p).value, self.gap_open,
+                         self.gap_extend, self.mode)
+
+
+def sad_kmer_rank(seqs: DeviceSeqs, prm: Params):
+    """Stage 1: globalised k-mer rank.  Returns (key[n] uint64 as int64 tensor,
+    sample_ids int32 tensor)."""
+    dev = seqs.codes.device
+    key = torch.empty(max(seqs.n, 1), dtype=torch.int64, device=dev)
+    cap = max(prm.s_max, prm.p) + prm.p
+    sid = torch.empty(cap, dtype=torch.int32, device=dev)
+    ns = ctypes.c_int32(0)
+    s, p = seqs.c_struct(), prm.c_struct()
+    code = lib().sad_kmer_rank(ctypes.byref(s), ctypes.byref(p), _ptr(key), _ptr(sid), cap,
+                               ctypes.byref(ns), _stream())
+    _check(code, "sad_kmer_rank")
+    return key[:seqs.n], sid[:ns.value]
+
+
+def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params):
+    """Stage 2: pivots and buckets.  Returns a dict of device tensors."""
+    dev = key.device
+    n, p = seqs.n, prm.p
+    out = dict(pivot_key=torch.empty(max(p - 1, 1), dtype=torch.int64, device=dev),
+               pivot_id=torch.empty(max(p - 1, 1), dtype=torch.int32, device=dev),
+               bucket=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+               bucket_off=torch.empty(p + 1, dtype=torch.int32, device=dev),
+               members=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
+    s, pp = seqs.c_struct(), prm.c_struct()
+    code = lib().sad_partition(ctypes.byref(s), _ptr(key), ctypes.byref(pp),
+                               _ptr(out["pivot_key"]), _ptr(out["pivot_id"]), _ptr(out["bucket"]),
+                               _ptr(out["bucket_off"]), _ptr(out["members"]), _stream())
+    _check(code, "sad_partition")
+    out["pivot_key"] = out["pivot_key"][:p - 1]
+    out["pivot_id"] = out["pivot_id"][:p - 1]
+    out["bucket"] = out["bucket"][:n]
+    out["members"] = out["members"][:n]
+    return out
+
+
+def _msa_tensors(n_res: int, n_width: int, n_steps: int, dev):
+    return dict(colmap=torch.empty(max(n_res, 1), dtype=torch.int32, device=dev),
+                width=torch.empty(max(n_width, 1), dtype=torch.int32, device=dev),
+                merge_score=torch.empty(max(n_steps, 1), dtype=torch.int64, device=dev),
+                merge_list=torch.empty(max(2 * n_steps, 2), dtype=torch.int32, device=dev),
+                merge_cells=torch.empty(max(n_steps, 1), dtype=torch.int64, device=dev),
+                cells=torch.empty(1, dtype=torch.int64, device=dev))
+
+
+def _msa_struct(m: dict) -> SadMsa:
+    return SadMsa(m["colmap"].data_ptr(), m["width"].data_ptr(), m["merge_score"].data_ptr(),
+                  m["merge_list"].data_ptr(), m["merge_cells"].data_ptr(), m["cells"].data_ptr())
+
+
+def sad_align_buckets(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor,
+                      prm: Params, out: dict | None = None):
+    """Stage 3: align every bucket.  Returns a dict of device tensors."""
+    dev = seqs.codes.device
+    if out is None:
+        out = _msa_tensors(seqs.total_len, prm.p, seqs.n, dev)
+    s, pp, m = seqs.c_struct(), prm.c_struct(), _msa_struct(out)
+    code = lib().sad_align_buckets(ctypes.byref(s), _ptr(bucket_off), _ptr(members),
+                                   ctypes.byref(pp), ctypes.byref(m), _stream())
+    _check(code, "sad_align_buckets")
+    return out
+
+
+def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, buckets: dict,
+               prm: Params, out: dict | None = None, ga_cap: int | None = None):
+    """Stage 4: global ancestor, refinement and glue.  Returns a dict of device
+    tensors plus ``ga_len`` and ``n_steps``."""
+    dev = seqs.codes.device
+    if out is None:
+        out = _msa_tensors(seqs.total_len, 1, 2 * prm.p, dev)
+    if ga_cap is None:
+        ga_cap = max(int(buckets["width"][:prm.p].sum().item()), 1)
+    ga = out.get("ga")
+    if ga is None or ga.numel() < ga_cap:
+        ga = torch.empty(max(ga_cap, 1), dtype=torch.uint8, device=dev)
+        out["ga"] = ga
+    gl = ctypes.c_int32(0)
+    nst = ctypes.c_int32(0)
+    s, pp = seqs.c_struct(), prm.c_struct()
+    mb, mg = _msa_struct(buckets), _msa_struct(out)
+    code = lib().sad_refine(ctypes.byref(s), _ptr(bucket_off), _ptr(members), ctypes.byref(mb),
+                            ctypes.byref(pp), _ptr(ga), ga_cap, ctypes.byref(gl), ctypes.byref(mg),
+                            ctypes.byref(nst), _stream())
+    _check(code, "sad_refine")
+    out["ga_len"] = gl.value
+    out["n_steps"] = nst.value
+    return out
+
+
+def sad_version() -> str:
+    return lib().sad_version().decode()
+
+
+def sad_release() -> None:
+    lib().sad_release()

@@ -1,0 +1,948 @@
+// Host side of the C-ABI (include/sad.h): argument checks, workspace
+// planning, kernel sequencing, device status readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sad_internal.h"
+
+namespace sad {
+
+// ------------------------------------------------------------------ state
+struct DeviceCtx {
+  char* arena = nullptr;      // per-step workspace (engine, k-mer lists, ...)
+  size_t cap = 0;
+  char* keep = nullptr;       // buffers that live across engine runs in one call
+  size_t keep_cap = 0;
+  DevStatus* st = nullptr;    // device status word
+  DevStatus* h_st = nullptr;  // pinned host copy
+  int64_t* h_small = nullptr; // pinned host scratch for small readbacks
+  size_t h_small_cap = 0;
+};
+
+static std::mutex g_mu;
+static std::vector<DeviceCtx> g_ctx;
+static thread_local std::string g_err;
+
+static int32_t fail(int32_t code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(SAD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+static int32_t get_ctx(DeviceCtx** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1);
+  DeviceCtx& c = g_ctx[dev];
+  if (!c.st) {
+    HIPCHK(hipMalloc(&c.st, sizeof(DevStatus)));
+    HIPCHK(hipHostMalloc(&c.h_st, sizeof(DevStatus), hipHostMallocDefault));
+  }
+  *out = &c;
+  return SAD_OK;
+}
+
+static int32_t ensure_host_small(DeviceCtx* c, size_t count) {
+  if (count <= c->h_small_cap) return SAD_OK;
+  if (c->h_small) HIPCHK(hipHostFree(c->h_small));
+  c->h_small = nullptr;
+  size_t n = std::max(count, (size_t)4096);
+  HIPCHK(hipHostMalloc(&c->h_small, n * sizeof(int64_t), hipHostMallocDefault));
+  c->h_small_cap = n;
+  return SAD_OK;
+}
+
+// Plans a set of device buffers, then carves them from the grow-only arena.
+struct Carver {
+  struct Req {
+    void** ptr;
+    size_t bytes;
+  };
+  std::vector<Req> reqs;
+  template <class T>
+  void add(T*& p, size_t count) {
+    reqs.push_back({reinterpret_cast<void**>(&p), count * sizeof(T)});
+  }
+  size_t total() const {
+    size_t t = 0;
+    for (auto& r : reqs) t += (r.bytes + 255) & ~size_t(255);
+    return t + 256;
+  }
+  int32_t carve_into(char** base, size_t* cap) {
+    size_t need = total();
+    if (need > *cap) {
+      if (*base) HIPCHK(hipFree(*base));
+      *base = nullptr;
+      *cap = 0;
+      hipError_t e = hipMalloc(base, need);
+      if (e != hipSuccess) {
+        *base = nullptr;
+        return fail(SAD_E_DEVICE, "workspace of " + std::to_string(need) +
+                                      " bytes: " + hipGetErrorString(e));
+      }
+      *cap = need;
+    }
+    size_t off = 0;
+    for (auto& r : reqs) {
+      *r.ptr = *base + off;
+      off += (r.bytes + 255) & ~size_t(255);
+    }
+    return SAD_OK;
+  }
+  int32_t carve(DeviceCtx* c) { return carve_into(&c->arena, &c->cap); }
+  int32_t carve_keep(DeviceCtx* c) { return carve_into(&c->keep, &c->keep_cap); }
+};
+
+static const char* where_name(int32_t w) {
+  switch (w) {
+    case W_VALIDATE: return "input validation";
+    case W_KMER: return "k-mer lists";
+    case W_RANK: return "rank";
+    case W_PART: return "partition";
+    case W_UPGMA: return "guide tree";
+    case W_ENGINE: return "alignment engine (row count)";
+    case W_ENGINE_POOL: return "alignment engine (profile pool)";
+    case W_ENGINE_TB: return "alignment engine (traceback scratch)";
+    case W_ENGINE_WIDTH: return "alignment engine (profile width limit)";
+    case W_ENGINE_BOUND: return "alignment engine (32-bit score bound)";
+    case W_ENGINE_WAIT: return "alignment engine (queue wait limit)";
+    case W_REFINE: return "refine";
+    default: return "device";
+  }
+}
+
+static int32_t reset_status(DeviceCtx* c, hipStream_t s) {
+  HIPCHK(hipMemsetAsync(c->st, 0, sizeof(DevStatus), s));
+  return SAD_OK;
+}
+
+// Copies the status word back (synchronising the stream).
+static int32_t read_status(DeviceCtx* c, hipStream_t s, DevStatus* out) {
+  HIPCHK(hipMemcpyAsync(c->h_st, c->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  *out = *c->h_st;
+  return SAD_OK;
+}
+
+static int32_t status_to_code(const DevStatus& d) {
+  if (d.code == 0) return SAD_OK;
+  int64_t detail = ((int64_t)d.detail_hi << 32) | (uint32_t)d.detail_lo;
+  return fail(d.code, std::string(where_name(d.where)) + ": status " + std::to_string(d.code) +
+                          ", detail " + std::to_string(detail));
+}
+
+static int32_t finish(DeviceCtx* c, hipStream_t s) {
+  DevStatus d{};
+  int32_t r = read_status(c, s, &d);
+  if (r) return r;
+  return status_to_code(d);
+}
+
+template <class T>
+static int32_t d2h(DeviceCtx* c, const T* dptr, size_t count, std::vector<T>& out, hipStream_t s) {
+  size_t words = (count * sizeof(T) + 7) / 8;
+  int32_t r = ensure_host_small(c, words);
+  if (r) return r;
+  HIPCHK(hipMemcpyAsync(c->h_small, dptr, count * sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out.resize(count);
+  std::memcpy(out.data(), c->h_small, count * sizeof(T));
+  return SAD_OK;
+}
+
+template <class T>
+static int32_t h2d(const std::vector<T>& in, T* dptr, hipStream_t s) {
+  if (in.empty()) return SAD_OK;
+  HIPCHK(hipMemcpyAsync(dptr, in.data(), in.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return SAD_OK;
+}
+
+// ------------------------------------------------------------------ checks
+
+static int64_t kmer_space(int A, int k) {
+  int64_t v = 1;
+  for (int u = 0; u < k; ++u) {
+    v *= A;
+    if (v > 65536) return -1;
+  }
+  return v;
+}
+
+static int32_t check_seqs(const sad_seqs* s, int k) {
+  if (!s) return fail(SAD_E_INVAL, "null sequences");
+  if (s->n < 0) return fail(SAD_E_INVAL, "negative sequence count");
+  if (s->alphabet != 4 && s->alphabet != 20) return fail(SAD_E_INVAL, "alphabet must be 4 or 20");
+  if (k < 1 || kmer_space(s->alphabet, k) < 0) return fail(SAD_E_INVAL, "k-mer length out of range");
+  if (s->n > 0 && (!s->d_codes || !s->d_offsets)) return fail(SAD_E_INVAL, "null device arrays");
+  if (s->total_len < 0) return fail(SAD_E_INVAL, "negative total length");
+  if (s->max_len > kMaxLen) return fail(SAD_E_INVAL, "sequence longer than the library limit");
+  if (s->n > 0 && s->max_len < k) return fail(SAD_E_INVAL, "sequences shorter than k");
+  return SAD_OK;
+}
+
+static int32_t check_params(const sad_params* p, int A, bool need_scoring) {
+  if (!p) return fail(SAD_E_INVAL, "null params");
+  if (p->p < 1) return fail(SAD_E_INVAL, "p must be >= 1");
+  if (p->s_max < 1) return fail(SAD_E_INVAL, "s_max must be >= 1");
+  if (need_scoring) {
+    if (!p->subst) return fail(SAD_E_INVAL, "null substitution matrix");
+    if (p->gap_extend < 0 || p->gap_open < p->gap_extend)
+      return fail(SAD_E_INVAL, "gaps must satisfy gap_open >= gap_extend >= 0");
+    for (int a = 0; a < A; ++a)
+      for (int b = 0; b < A; ++b)
+        if (p->subst[a * A + b] != p->subst[b * A + a])
+          return fail(SAD_E_INVAL, "substitution matrix must be symmetric");
+  }
+  return SAD_OK;
+}
+
+static int32_t validate_on_device(DeviceCtx* c, const sad_seqs* s, int k, hipStream_t stream) {
+  int32_t r = reset_status(c, stream);
+  if (r) return r;
+  launch_validate(*s, k, c->st, stream);
+  return finish(c, stream);
+}
+
+static void chunk_sizes(int n, int p, int* w_min) {
+  int m = n;
+  for (int c = 0; c < p; ++c) {
+    int w = (int)(((int64_t)(c + 1) * n) / p) - (int)(((int64_t)c * n) / p);
+    m = std::min(m, w);
+  }
+  *w_min = m;
+}
+
+// ------------------------------------------------------------------ engine driver
+
+struct TreeSet {
+  // groups of leaves: group g = leaf nodes group_off[g] .. group_off[g+1]
+  int ngroups;
+  int nleaves;
+  const int32_t* d_group_off;      // device [ngroups + 1]
+  std::vector<int32_t> h_group_off;
+  const uint8_t* d_codes;          // leaf sequences
+  const int64_t* d_offsets;
+  const int32_t* d_ids;            // leaf r = sequence d_ids[r] (or r if null)
+  int64_t total_len;               // residues addressed by offsets
+  int max_len;
+  int kmer_k;
+};
+
+struct EngineBuffers {
+  int32_t *node_W, *node_n, *node_parent;
+  int64_t *node_prof, *node_up;
+  int32_t *job_a, *job_b, *job_out, *job_next, *job_pending;
+  int64_t *job_score, *job_cells, *job_ops_off;
+  int32_t *queue, *queue_flag, *qctl;
+  unsigned long long* tops;
+  uint16_t* prof_pool;
+  int32_t* up_pool;
+  uint32_t* tb;
+  int32_t* bnd;
+  int64_t prof_cap, up_cap, tb_words;
+  int nwg;
+};
+
+static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, int njobs,
+                        int64_t prof_cap, int64_t up_cap, int64_t tb_words) {
+  e.nwg = std::max(1, std::min(njobs, engine_workgroups()));
+  e.prof_cap = prof_cap;
+  e.up_cap = up_cap;
+  e.tb_words = tb_words;
+  cv.add(e.node_W, nnodes);
+  cv.add(e.node_n, nnodes);
+  cv.add(e.node_parent, nnodes);
+  cv.add(e.node_prof, nnodes);
+  cv.add(e.node_up, nnodes);
+  cv.add(e.job_a, nslots);
+  cv.add(e.job_b, nslots);
+  cv.add(e.job_out, nslots);
+  cv.add(e.job_next, nslots);
+  cv.add(e.job_pending, nslots);
+  cv.add(e.job_score, nslots);
+  cv.add(e.job_cells, nslots);
+  cv.add(e.job_ops_off, nslots);
+  cv.add(e.queue, std::max(njobs, 1));
+  cv.add(e.queue_flag, std::max(njobs, 1));
+  cv.add(e.qctl, 4);
+  cv.add(e.tops, 2);
+  cv.add(e.prof_pool, (size_t)prof_cap);
+  cv.add(e.up_pool, (size_t)up_cap);
+  cv.add(e.tb, (size_t)e.nwg * (size_t)tb_words);
+  cv.add(e.bnd, (size_t)e.nwg * 2 * (kMaxWidth + 1));
+}
+
+static int64_t tb_words_for(int wcap) {
+  int64_t strips = (wcap + 63) / 64;
+  int64_t t4 = (wcap + 63 + 3) / 4;
+  return strips * t4 * 64;
+}
+
+static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const int8_t* S, int go,
+                              int ge, uint32_t mode, uint8_t* ops_out, DevStatus* st) {
+  EngineArgs a{};
+  a.node_W = e.node_W;
+  a.node_n = e.node_n;
+  a.node_prof = e.node_prof;
+  a.node_up = e.node_up;
+  a.node_parent = e.node_parent;
+  a.prof_pool = e.prof_pool;
+  a.up_pool = e.up_pool;
+  a.prof_top = e.tops;
+  a.up_top = e.tops + 1;
+  a.prof_cap = e.prof_cap;
+  a.up_cap = e.up_cap;
+  a.njobs = njobs;
+  a.job_a = e.job_a;
+  a.job_b = e.job_b;
+  a.job_out = e.job_out;
+  a.job_next = e.job_next;
+  a.job_pending = e.job_pending;
+  a.job_score = e.job_score;
+  a.job_cells = e.job_cells;
+  a.job_ops_off = e.job_ops_off;
+  a.ops_out = ops_out;
+  a.queue = e.queue;
+  a.queue_flag = e.queue_flag;
+  a.queue_head = e.qctl;
+  a.queue_tail = e.qctl + 1;
+  a.tb = e.tb;
+  a.tb_words_per_wg = e.tb_words;
+  a.bnd = e.bnd;
+  a.A = A;
+  int smax = 0;
+  for (int q = 0; q < A * A; ++q) {
+    a.S[q] = S[q];
+    smax = std::max(smax, std::abs((int)S[q]));
+  }
+  a.smax = smax;
+  a.go = go;
+  a.ge = ge;
+  a.mode = mode;
+  a.st = st;
+  // queue waits end after 20 s of wall clock (a malformed DAG cannot hang)
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  a.wait_ticks = (int64_t)khz * 1000 * 20;
+  return a;
+}
+
+// Uploads tops (prof_top, up_top) and resets the queue control words.
+__global__ void init_engine_ctl_kernel(unsigned long long* tops, unsigned long long prof0,
+                                       unsigned long long up0, int32_t* qctl) {
+  tops[0] = prof0;
+  tops[1] = up0;
+  qctl[0] = 0;
+  qctl[1] = 0;
+  qctl[2] = 0;
+  qctl[3] = 0;
+}
+
+// Progressive alignment of every group of leaves along its UPGMA tree.
+// Merge lists (local ids) must already be in d_merges at slots of
+// h_group_off.  Outputs per slot: score/cells; colmap of every leaf residue;
+// width per group.
+struct TreeOutputs {
+  int32_t* d_colmap;
+  int32_t* d_width;
+  int64_t* d_score;
+  int64_t* d_cells;
+  int64_t* d_cells_total;
+  bool keep_engine;   // leave engine buffers for the caller to read nodes
+};
+
+static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
+                         const sad_params* prm, int A, Carver& base_cv, EngineBuffers& e,
+                         const TreeOutputs& out, hipStream_t stream) {
+  const int N = ts.nleaves;
+  int njobs = 0;
+  for (int g = 0; g < ts.ngroups; ++g)
+    njobs += std::max(0, ts.h_group_off[g + 1] - ts.h_group_off[g] - 1);
+  int wcap = std::min(kMaxWidth, std::max(2 * ts.max_len + 64, 128));
+  int64_t tbw = tb_words_for(wcap);
+  int64_t prof_cap = (int64_t)A * (ts.total_len * 6 + 4096);
+  int64_t up_cap = ts.total_len * 6 + 4096;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    Carver cv = base_cv;
+    plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, prof_cap, up_cap, tbw);
+    int32_t r = cv.carve(c);
+    if (r) return r;
+    r = reset_status(c, stream);
+    if (r) return r;
+    launch_fill_i32(e.node_parent, -1, 2 * (int64_t)std::max(N, 1), stream);
+    launch_fill_i32(e.job_next, -1, std::max(N, 1), stream);
+    launch_fill_i32(e.job_a, -1, std::max(N, 1), stream);
+    launch_fill_i32(e.queue_flag, 0, std::max(njobs, 1), stream);
+    launch_fill_i32(reinterpret_cast<int32_t*>(e.job_ops_off), -1, 2 * (int64_t)std::max(N, 1),
+                    stream);
+    init_engine_ctl_kernel<<<1, 1, 0, stream>>>(e.tops, (unsigned long long)ts.total_len * A,
+                                                (unsigned long long)ts.total_len, e.qctl);
+    launch_make_leaves(ts.d_codes, ts.d_offsets, ts.d_ids, N, A, 0, e.node_W, e.node_n,
+                       e.node_prof, e.node_up, e.node_parent, e.prof_pool, ts.total_len, stream);
+    launch_make_jobs(d_merges, ts.d_group_off, ts.ngroups, N, N, e.node_parent, e.job_a, e.job_b,
+                     e.job_out, e.job_next, e.job_pending, e.queue, e.queue_flag, e.qctl + 1,
+                     stream);
+    EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
+                               nullptr, c->st);
+    launch_engine(a, e.nwg, stream);
+    DevStatus d{};
+    r = read_status(c, stream, &d);
+    if (r) return r;
+    if (d.code == SAD_E_CAPACITY && (d.where == W_ENGINE_POOL || d.where == W_ENGINE_TB)) {
+      int64_t need = ((int64_t)d.detail_hi << 32) | (uint32_t)d.detail_lo;
+      if (d.where == W_ENGINE_TB) tbw = std::max(tbw * 2, need);
+      else {
+        prof_cap *= 2;
+        up_cap *= 2;
+      }
+      continue;
+    }
+    if (d.code) return status_to_code(d);
+    // results
+    r = reset_status(c, stream);
+    if (r) return r;
+    if (out.d_colmap)
+      launch_colmap(ts.d_offsets, ts.d_ids, N, e.node_parent, e.node_up, e.up_pool, out.d_colmap,
+                    c->st, stream);
+    if (out.d_width) launch_widths(ts.d_group_off, ts.ngroups, N, e.node_W, out.d_width, stream);
+    if (out.d_cells_total)
+      launch_fill_i32(reinterpret_cast<int32_t*>(out.d_cells_total), 0, 2, stream);
+    if (out.d_score)
+      launch_job_results(e.job_a, e.job_score, e.job_cells, N, out.d_score, out.d_cells,
+                         out.d_cells_total, stream);
+    return finish(c, stream);
+  }
+  return fail(SAD_E_CAPACITY, "alignment engine workspace did not converge");
+}
+
+}  // namespace sad
+
+// ====================================================================== C-ABI
+
+using namespace sad;
+
+extern "C" int32_t sad_kmer_rank(const sad_seqs* seqs, const sad_params* prm, uint64_t* d_key,
+                                 int32_t* d_sample_ids, int32_t sample_cap, int32_t* n_samples,
+                                 hipStream_t stream) {
+  if (!prm) return fail(SAD_E_INVAL, "null params");
+  int32_t r = check_seqs(seqs, prm->kmer_k);
+  if (r) return r;
+  r = check_params(prm, seqs->alphabet, false);
+  if (r) return r;
+  const int n = seqs->n, p = prm->p, A = seqs->alphabet, k = prm->kmer_k;
+  if (n < 2 * p) return fail(SAD_E_INVAL, "need N >= 2p");
+  if (!d_key || !n_samples || (!d_sample_ids && sample_cap > 0))
+    return fail(SAD_E_INVAL, "null output");
+  int w_min = 0;
+  chunk_sizes(n, p, &w_min);
+  int ks = std::min(p - 1, std::min(std::max(1, prm->s_max / p), w_min - 1));
+  const int S = p * ks;
+  *n_samples = S;
+  if (S > sample_cap) return fail(SAD_E_CAPACITY, "sample capacity too small");
+  DeviceCtx* c = nullptr;
+  r = get_ctx(&c);
+  if (r) return r;
+  r = validate_on_device(c, seqs, k, stream);
+  if (r) return r;
+  const int kspace = (int)kmer_space(A, k);
+  uint32_t* entries;
+  int32_t *nu, *sorted;
+  uint64_t* kloc;
+  Carver cv;
+  cv.add(entries, (size_t)std::max<int64_t>(seqs->total_len, 1));
+  cv.add(nu, std::max(n, 1));
+  cv.add(kloc, std::max(n, 1));
+  cv.add(sorted, std::max(n, 1));
+  r = cv.carve(c);
+  if (r) return r;
+  r = reset_status(c, stream);
+  if (r) return r;
+  launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st, stream);
+  KmerLists kl{entries, seqs->d_offsets, nu, seqs->d_offsets};
+  launch_rowsum_chunk(kl, n, p, k, kspace, kloc, stream);
+  launch_chunk_sort(kloc, n, p, sorted, stream);
+  launch_pick_samples(sorted, n, p, ks, d_sample_ids, stream);
+  launch_rowsum_list(kl, n, d_sample_ids, S, k, kspace, d_key, stream);
+  return finish(c, stream);
+}
+
+extern "C" int32_t sad_partition(const sad_seqs* seqs, const uint64_t* d_key, const sad_params* prm,
+                                 uint64_t* d_pivot_key, int32_t* d_pivot_id, int32_t* d_bucket,
+                                 int32_t* d_bucket_off, int32_t* d_members, hipStream_t stream) {
+  if (!seqs || !prm) return fail(SAD_E_INVAL, "null argument");
+  int32_t r = check_params(prm, seqs->alphabet, false);
+  if (r) return r;
+  const int n = seqs->n, p = prm->p;
+  if (n < 2 * p) return fail(SAD_E_INVAL, "need N >= 2p");
+  if (!d_key || !d_bucket || !d_bucket_off || !d_members || (p > 1 && (!d_pivot_key || !d_pivot_id)))
+    return fail(SAD_E_INVAL, "null device array");
+  DeviceCtx* c = nullptr;
+  r = get_ctx(&c);
+  if (r) return r;
+  const int ny = p * (p - 1);
+  const int nblk = (n + 255) / 256;
+  int32_t *sorted, *Yi, *Ysi, *blk, *total;
+  uint64_t *Yk, *Ysk;
+  Carver cv;
+  cv.add(sorted, std::max(n, 1));
+  cv.add(Yk, std::max(ny, 1));
+  cv.add(Yi, std::max(ny, 1));
+  cv.add(Ysk, std::max(ny, 1));
+  cv.add(Ysi, std::max(ny, 1));
+  cv.add(blk, (size_t)std::max(nblk, 1) * p);
+  cv.add(total, p);
+  r = cv.carve(c);
+  if (r) return r;
+  r = reset_status(c, stream);
+  if (r) return r;
+  launch_chunk_sort(d_key, n, p, sorted, stream);
+  launch_partition(d_key, n, p, sorted, Yk, Yi, Ysk, Ysi, d_pivot_key, d_pivot_id, d_bucket, blk,
+                   total, d_bucket_off, d_members, stream);
+  return finish(c, stream);
+}
+
+extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                                     const int32_t* d_members, const sad_params* prm, sad_msa* out,
+                                     hipStream_t stream) {
+  if (!prm || !out) return fail(SAD_E_INVAL, "null argument");
+  int32_t r = check_seqs(seqs, prm->kmer_k);
+  if (r) return r;
+  r = check_params(prm, seqs->alphabet, true);
+  if (r) return r;
+  if (!d_bucket_off || !d_members || !out->d_colmap || !out->d_width || !out->d_merge_score ||
+      !out->d_merge_list || !out->d_merge_cells || !out->d_cells)
+    return fail(SAD_E_INVAL, "null device array");
+  const int n = seqs->n, p = prm->p, A = seqs->alphabet, k = prm->kmer_k;
+  DeviceCtx* c = nullptr;
+  r = get_ctx(&c);
+  if (r) return r;
+  r = validate_on_device(c, seqs, k, stream);
+  if (r) return r;
+  std::vector<int32_t> off;
+  r = d2h(c, d_bucket_off, (size_t)p + 1, off, stream);
+  if (r) return r;
+  if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
+  int64_t fm_total = 0;
+  int max_n = 0;
+  std::vector<int64_t> fm_off(p);
+  for (int b = 0; b < p; ++b) {
+    int nb = off[b + 1] - off[b];
+    if (nb < 0) return fail(SAD_E_INVAL, "bucket offsets must be non-decreasing");
+    fm_off[b] = fm_total;
+    fm_total += (int64_t)nb * nb;
+    max_n = std::max(max_n, nb);
+  }
+  const int kspace = (int)kmer_space(A, k);
+  uint32_t *entries, *F;
+  int32_t* nu;
+  int64_t* d_fm_off;
+  uint64_t* Sw;
+  Carver cv;
+  cv.add(entries, (size_t)std::max<int64_t>(seqs->total_len, 1));
+  cv.add(nu, std::max(n, 1));
+  cv.add(d_fm_off, std::max(p, 1));
+  cv.add(F, (size_t)std::max<int64_t>(fm_total, 1));
+  cv.add(Sw, (size_t)std::max<int64_t>(fm_total, 1));
+  r = cv.carve(c);
+  if (r) return r;
+  r = h2d(fm_off, d_fm_off, stream);
+  if (r) return r;
+  r = reset_status(c, stream);
+  if (r) return r;
+  launch_fill_i32(out->d_merge_list, -1, 2 * (int64_t)n, stream);
+  launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_score), 0, 2 * (int64_t)n, stream);
+  launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_cells), 0, 2 * (int64_t)n, stream);
+  launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st, stream);
+  KmerLists kl{entries, seqs->d_offsets, nu, seqs->d_offsets};
+  launch_fmatrix_groups(kl, d_bucket_off, d_members, p, n, d_fm_off, k, kspace, F, stream);
+  launch_upgma(F, d_fm_off, d_bucket_off, p, max_n, Sw, out->d_merge_list, d_bucket_off, c->st,
+               stream);
+  r = finish(c, stream);
+  if (r) return r;
+
+  TreeSet ts;
+  ts.ngroups = p;
+  ts.nleaves = n;
+  ts.d_group_off = d_bucket_off;
+  ts.h_group_off = off;
+  ts.d_codes = seqs->d_codes;
+  ts.d_offsets = seqs->d_offsets;
+  ts.d_ids = d_members;
+  ts.total_len = seqs->total_len;
+  ts.max_len = seqs->max_len;
+  ts.kmer_k = k;
+  EngineBuffers e{};
+  TreeOutputs to{out->d_colmap, out->d_width, out->d_merge_score, out->d_merge_cells,
+                 out->d_cells, false};
+  // the engine's workspace follows the k-mer/UPGMA buffers (merge lists are
+  // in the caller's array, so those buffers are no longer needed)
+  Carver base;
+  return run_trees(c, ts, out->d_merge_list, prm, A, base, e, to, stream);
+}
+
+namespace sad {
+
+__global__ void iota_kernel(int32_t* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+__global__ void group_one_kernel(int32_t* goff, int q, int32_t* list, int32_t root) {
+  goff[0] = 0;
+  goff[1] = q;
+  list[0] = root;
+}
+
+// Refinement outputs: ancestor merges (slots 0..q-2) then the q refinement
+// alignments; pairs of the refinement steps are (bucket, -1).
+__global__ void refine_results_kernel(int q, const int64_t* __restrict__ ga_score,
+                                      const int64_t* __restrict__ ga_cells,
+                                      const int32_t* __restrict__ ga_merges,
+                                      const int64_t* __restrict__ rf_score,
+                                      const int64_t* __restrict__ rf_cells,
+                                      const int32_t* __restrict__ bucket_of_u, int64_t* score,
+                                      int32_t* list, int64_t* cells, int64_t* total) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int64_t tot = 0;
+  int m = 0;
+  for (int t = 0; t < q - 1; ++t, ++m) {
+    score[m] = ga_score[t];
+    cells[m] = ga_cells[t];
+    list[2 * m] = ga_merges[2 * t];
+    list[2 * m + 1] = ga_merges[2 * t + 1];
+    tot += ga_cells[t];
+  }
+  for (int u = 0; u < q; ++u, ++m) {
+    score[m] = rf_score[u];
+    cells[m] = rf_cells[u];
+    list[2 * m] = bucket_of_u[u];
+    list[2 * m + 1] = -1;
+    tot += rf_cells[u];
+  }
+  *total = tot;
+}
+
+__global__ void init_refine_ctl_kernel(unsigned long long* tops, unsigned long long prof0,
+                                       unsigned long long up0, int32_t* qctl) {
+  tops[0] = prof0;
+  tops[1] = up0;
+  qctl[0] = 0;
+  qctl[1] = 0;
+}
+
+}  // namespace sad
+
+extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                              const int32_t* d_members, const sad_msa* buckets,
+                              const sad_params* prm, uint8_t* d_ga, int32_t ga_cap,
+                              int32_t* ga_len, sad_msa* gout, int32_t* n_steps,
+                              hipStream_t stream) {
+  if (!prm || !buckets || !gout || !ga_len || !n_steps) return fail(SAD_E_INVAL, "null argument");
+  int32_t r = check_seqs(seqs, prm->kmer_k);
+  if (r) return r;
+  r = check_params(prm, seqs->alphabet, true);
+  if (r) return r;
+  if (!d_bucket_off || !d_members || !buckets->d_colmap || !buckets->d_width || !gout->d_colmap ||
+      !gout->d_width || !gout->d_merge_score || !gout->d_merge_list || !gout->d_merge_cells ||
+      !gout->d_cells || (!d_ga && ga_cap > 0))
+    return fail(SAD_E_INVAL, "null device array");
+  const int n = seqs->n, p = prm->p, A = seqs->alphabet, k = prm->kmer_k;
+  DeviceCtx* c = nullptr;
+  r = get_ctx(&c);
+  if (r) return r;
+  r = validate_on_device(c, seqs, k, stream);
+  if (r) return r;
+  std::vector<int32_t> off, wid;
+  r = d2h(c, d_bucket_off, (size_t)p + 1, off, stream);
+  if (r) return r;
+  r = d2h(c, buckets->d_width, (size_t)p, wid, stream);
+  if (r) return r;
+  if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
+
+  // non-empty buckets u = 0..q-1 in bucket order; their columns at wo[u]
+  std::vector<int32_t> uidx(p, -1), bucket_of_u, width_u, rows_u;
+  std::vector<int64_t> wo;
+  int64_t Wtot = 0;
+  int maxW = 0;
+  for (int b = 0; b < p; ++b) {
+    const int nb = off[b + 1] - off[b];
+    if (nb < 0) return fail(SAD_E_INVAL, "bucket offsets must be non-decreasing");
+    if (nb == 0) continue;
+    if (wid[b] < 0 || wid[b] > kMaxWidth) return fail(SAD_E_INVAL, "bucket width out of range");
+    uidx[b] = (int)bucket_of_u.size();
+    bucket_of_u.push_back(b);
+    width_u.push_back(wid[b]);
+    rows_u.push_back(nb);
+    wo.push_back(Wtot);
+    Wtot += wid[b];
+    maxW = std::max(maxW, wid[b]);
+  }
+  const int q = (int)bucket_of_u.size();
+  wo.push_back(Wtot);
+  if (q == 0) return fail(SAD_E_INVAL, "no sequences");
+
+  // ---- stage buffers that live across the engine runs
+  int32_t *d_uidx, *d_bucket_of_u, *d_width_u, *d_rows_u, *anc_len, *cons_list, *ga_goff,
+      *ga_merges, *ga_list, *ga_len_d, *ins, *used, *slot_total, *slot_start, *shared_at, *to_g;
+  int64_t *d_wo, *anc_off, *stage_off, *ga_score, *ga_cells, *ga_cells_tot, *rf_ops_off, *ga_off0;
+  uint32_t* cnt32;
+  uint16_t* prof16;
+  uint8_t *anc_stage, *anc_codes, *ga_stage, *rf_ops;
+  int32_t* cnode_W;
+  int32_t* cnode_n;
+  int64_t* cnode_prof;
+  const int64_t Wt1 = std::max<int64_t>(Wtot, 1);
+  Carver kv;
+  kv.add(d_uidx, p);
+  kv.add(d_bucket_of_u, q);
+  kv.add(d_width_u, q);
+  kv.add(d_rows_u, q);
+  kv.add(d_wo, q + 1);
+  kv.add(cnt32, (size_t)Wt1 * A);
+  kv.add(prof16, (size_t)Wt1 * A);
+  kv.add(cnode_W, q);
+  kv.add(cnode_n, q);
+  kv.add(cnode_prof, q);
+  kv.add(cons_list, q);
+  kv.add(anc_stage, (size_t)Wt1);
+  kv.add(anc_len, q);
+  kv.add(anc_off, q + 1);
+  kv.add(stage_off, q + 1);
+  kv.add(anc_codes, (size_t)Wt1);
+  kv.add(ga_goff, 2);
+  kv.add(ga_list, 1);
+  kv.add(ga_merges, 2 * std::max(q, 1));
+  kv.add(ga_score, std::max(q, 1));
+  kv.add(ga_cells, std::max(q, 1));
+  kv.add(ga_cells_tot, 1);
+  kv.add(ga_stage, (size_t)Wt1 + 1);
+  kv.add(ga_len_d, 1);
+  kv.add(ga_off0, 2);
+  kv.add(to_g, (size_t)Wt1);
+  r = kv.carve_keep(c);
+  if (r) return r;
+  r = h2d(uidx, d_uidx, stream);
+  if (!r) r = h2d(bucket_of_u, d_bucket_of_u, stream);
+  if (!r) r = h2d(width_u, d_width_u, stream);
+  if (!r) r = h2d(rows_u, d_rows_u, stream);
+  if (!r) r = h2d(wo, d_wo, stream);
+  if (!r) r = h2d(wo, stage_off, stream);
+  if (r) return r;
+  std::vector<int64_t> prof_offs(q);
+  for (int u = 0; u < q; ++u) prof_offs[u] = wo[u] * A;
+  r = h2d(prof_offs, cnode_prof, stream);
+  if (!r) r = h2d(width_u, cnode_W, stream);
+  if (!r) r = h2d(rows_u, cnode_n, stream);
+  if (r) return r;
+
+  // ---- bucket profiles and local ancestors
+  r = reset_status(c, stream);
+  if (r) return r;
+  launch_fill_i32(reinterpret_cast<int32_t*>(cnt32), 0, Wt1 * A, stream);
+  launch_rebuild_profiles(seqs->d_codes, seqs->d_offsets, d_members, d_bucket_off, p, n,
+                          buckets->d_colmap, d_uidx, d_wo, buckets->d_width, A, cnt32, Wt1 * A,
+                          prof16, c->st, stream);
+  iota_kernel<<<(q + 255) / 256, 256, 0, stream>>>(cons_list, q);
+  launch_consensus(cons_list, q, cnode_W, cnode_n, cnode_prof, prof16, A, anc_stage, stage_off,
+                   anc_len, stream);
+  launch_compact(anc_stage, stage_off, anc_len, q, anc_off, anc_codes, stream);
+  r = finish(c, stream);
+  if (r) return r;
+  std::vector<int64_t> h_anc_off;
+  r = d2h(c, anc_off, (size_t)q + 1, h_anc_off, stream);
+  if (r) return r;
+  int max_anc = 0;
+  for (int u = 0; u < q; ++u) max_anc = std::max<int>(max_anc, (int)(h_anc_off[u + 1] - h_anc_off[u]));
+
+  // ---- global ancestor
+  int GL = 0;
+  if (q == 1) {
+    GL = (int)h_anc_off[1];
+    HIPCHK(hipMemcpyAsync(ga_stage, anc_codes, (size_t)std::max(GL, 0), hipMemcpyDeviceToDevice,
+                          stream));
+  } else {
+    const int kspace = (int)kmer_space(A, k);
+    uint32_t *entries, *F;
+    int32_t *nu, *ids;
+    int64_t* fm0;
+    uint64_t* Sw;
+    Carver cv;
+    cv.add(entries, (size_t)std::max<int64_t>(h_anc_off[q], 1));
+    cv.add(nu, q);
+    cv.add(ids, q);
+    cv.add(fm0, 1);
+    cv.add(F, (size_t)q * q);
+    cv.add(Sw, (size_t)q * q);
+    r = cv.carve(c);
+    if (r) return r;
+    r = reset_status(c, stream);
+    if (r) return r;
+    group_one_kernel<<<1, 1, 0, stream>>>(ga_goff, q, ga_list, q + (q - 2));
+    iota_kernel<<<(q + 255) / 256, 256, 0, stream>>>(ids, q);
+    launch_fill_i32(reinterpret_cast<int32_t*>(fm0), 0, 2, stream);
+    launch_fill_i32(reinterpret_cast<int32_t*>(ga_off0), 0, 4, stream);
+    launch_kmer_lists(anc_codes, anc_off, q, A, k, entries, nullptr, nu, c->st, stream);
+    KmerLists kl{entries, anc_off, nu, anc_off};
+    launch_fmatrix_groups(kl, ga_goff, ids, 1, q, fm0, k, kspace, F, stream);
+    launch_upgma(F, fm0, ga_goff, 1, q, Sw, ga_merges, reinterpret_cast<int32_t*>(ga_off0), c->st,
+                 stream);
+    r = finish(c, stream);
+    if (r) return r;
+    TreeSet ts;
+    ts.ngroups = 1;
+    ts.nleaves = q;
+    ts.d_group_off = ga_goff;
+    ts.h_group_off = {0, q};
+    ts.d_codes = anc_codes;
+    ts.d_offsets = anc_off;
+    ts.d_ids = nullptr;
+    ts.total_len = h_anc_off[q];
+    ts.max_len = max_anc;
+    ts.kmer_k = k;
+    EngineBuffers e{};
+    TreeOutputs to{nullptr, nullptr, ga_score, ga_cells, ga_cells_tot, true};
+    Carver base;
+    r = run_trees(c, ts, ga_merges, prm, A, base, e, to, stream);
+    if (r) return r;
+    r = reset_status(c, stream);
+    if (r) return r;
+    launch_consensus(ga_list, 1, e.node_W, e.node_n, e.node_prof, e.prof_pool, A, ga_stage,
+                     ga_off0, ga_len_d, stream);
+    r = finish(c, stream);
+    if (r) return r;
+    std::vector<int32_t> gl;
+    r = d2h(c, ga_len_d, 1, gl, stream);
+    if (r) return r;
+    GL = gl[0];
+  }
+  *ga_len = GL;
+  if (GL > ga_cap) return fail(SAD_E_CAPACITY, "GA capacity too small");
+  if (GL > kMaxWidth) return fail(SAD_E_CAPACITY, "global ancestor wider than the library limit");
+  if (GL > 0) HIPCHK(hipMemcpyAsync(d_ga, ga_stage, (size_t)GL, hipMemcpyDeviceToDevice, stream));
+  {
+    std::vector<int32_t> gl{GL};
+    r = h2d(gl, ga_len_d, stream);
+    if (r) return r;
+  }
+
+  // ---- refinement: every bucket alignment against GA (one-row profile)
+  std::vector<int64_t> ops_off(q + 1);
+  int64_t ops_tot = 0;
+  for (int u = 0; u < q; ++u) {
+    ops_off[u] = ops_tot;
+    ops_tot += width_u[u] + GL;
+  }
+  ops_off[q] = ops_tot;
+  {
+    Carver kv2 = kv;
+    kv2.add(rf_ops, (size_t)std::max<int64_t>(ops_tot, 1));
+    kv2.add(rf_ops_off, q + 1);
+    kv2.add(ins, (size_t)q * (GL + 1));
+    kv2.add(used, std::max(GL, 1));
+    kv2.add(slot_total, GL + 1);
+    kv2.add(slot_start, GL + 1);
+    kv2.add(shared_at, std::max(GL, 1));
+    // same prefix as kv: earlier buffers keep their addresses and contents
+    if (kv2.total() > c->keep_cap) {
+      // grow while preserving: copy the prefix out through the work arena
+      size_t keep_bytes = kv.total();
+      char* tmp = nullptr;
+      HIPCHK(hipMalloc(&tmp, keep_bytes));
+      HIPCHK(hipMemcpyAsync(tmp, c->keep, keep_bytes, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      r = kv2.carve_keep(c);
+      if (r) {
+        hipFree(tmp);
+        return r;
+      }
+      HIPCHK(hipMemcpyAsync(c->keep, tmp, keep_bytes, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      HIPCHK(hipFree(tmp));
+    } else {
+      r = kv2.carve_keep(c);
+      if (r) return r;
+    }
+  }
+  r = h2d(ops_off, rf_ops_off, stream);
+  if (r) return r;
+  int64_t tbw = 0;
+  for (int u = 0; u < q; ++u) {
+    int64_t strips = (width_u[u] + 63) / 64, t4 = (GL + 63 + 3) / 4;
+    tbw = std::max(tbw, strips * t4 * 64);
+  }
+  tbw = std::max<int64_t>(tbw, 64);
+  const int64_t prof_fixed = (Wtot + GL) * A;
+  const int64_t prof_cap = prof_fixed + (ops_tot + 1) * A;
+  const int64_t up_cap = Wtot + GL + ops_tot + 1;
+  EngineBuffers e{};
+  Carver cv;
+  plan_engine(cv, e, 2 * q + 1, q, q, prof_cap, up_cap, tbw);
+  r = cv.carve(c);
+  if (r) return r;
+  r = reset_status(c, stream);
+  if (r) return r;
+  HIPCHK(hipMemcpyAsync(e.prof_pool, prof16, (size_t)Wtot * A * sizeof(uint16_t),
+                        hipMemcpyDeviceToDevice, stream));
+  launch_onehot_seq(ga_stage, ga_len_d, std::max(GL, 1), A, e.prof_pool + Wtot * A, stream);
+  launch_fill_i32(e.node_parent, -1, 2 * q + 1, stream);
+  launch_fill_i32(e.queue_flag, 0, q, stream);
+  init_refine_ctl_kernel<<<1, 1, 0, stream>>>(e.tops, (unsigned long long)prof_fixed,
+                                              (unsigned long long)(Wtot + GL), e.qctl);
+  launch_refine_nodes(q, d_wo, d_width_u, d_rows_u, Wtot * A, Wtot, ga_len_d, A, 0, e.node_W,
+                      e.node_n, e.node_prof, e.node_up, stream);
+  launch_refine_jobs(q, rf_ops_off, e.job_a, e.job_b, e.job_out, e.job_next, e.job_pending,
+                     e.job_ops_off, e.queue, e.queue_flag, e.qctl + 1, e.node_parent, stream);
+  EngineArgs a = engine_args(e, q, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
+                             rf_ops, c->st);
+  launch_engine(a, e.nwg, stream);
+  r = finish(c, stream);
+  if (r) return r;
+
+  // ---- glue
+  r = reset_status(c, stream);
+  if (r) return r;
+  launch_fill_i32(ins, 0, (int64_t)q * (GL + 1), stream);
+  launch_fill_i32(used, 0, std::max(GL, 1), stream);
+  launch_glue(rf_ops, rf_ops_off, e.node_W + q + 1, q, GL, ins, used, slot_total, slot_start,
+              shared_at, gout->d_width, d_wo, to_g, seqs->d_offsets, d_members, d_bucket_off, p, n,
+              d_uidx, buckets->d_colmap, gout->d_colmap, stream);
+  refine_results_kernel<<<1, 1, 0, stream>>>(q, ga_score, ga_cells, ga_merges, e.job_score,
+                                             e.job_cells, d_bucket_of_u, gout->d_merge_score,
+                                             gout->d_merge_list, gout->d_merge_cells,
+                                             gout->d_cells);
+  *n_steps = 2 * q - 1;
+  return finish(c, stream);
+}
+
+extern "C" const char* sad_last_error(void) { return g_err.c_str(); }
+
+extern "C" void sad_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& c : g_ctx) {
+    if (c.arena) hipFree(c.arena);
+    if (c.keep) hipFree(c.keep);
+    if (c.st) hipFree(c.st);
+    if (c.h_st) hipHostFree(c.h_st);
+    if (c.h_small) hipHostFree(c.h_small);
+    c = DeviceCtx{};
+  }
+}
+
+extern "C" const char* sad_version(void) { return "sad-gfx950 0.1"; }

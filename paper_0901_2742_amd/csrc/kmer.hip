@@ -1,0 +1,349 @@
+// k-mer stage kernels (paper Section 2 "k-mer Rank" and Section 2.3.1):
+// input validation, per-sequence sorted k-mer lists, pair sums
+// c_ij = sum_tau min(n_i(tau), n_j(tau)) against an LDS-resident histogram,
+// the fixed point F = floor(c 2^31 / d), and the per-chunk rank sort.
+#include "sad_internal.h"
+
+namespace sad {
+
+// ------------------------------------------------------------------ validation
+
+__global__ void validate_lengths_kernel(const int64_t* __restrict__ off, int n, int64_t total,
+                                        int max_len, int k, DevStatus* st) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    if (off[0] != 0 || off[n] != total) raise_error(st, SAD_E_INVAL, off[n], W_VALIDATE);
+  }
+  if (i >= n) return;
+  int64_t L = off[i + 1] - off[i];
+  if (L < k || L > max_len || L > kMaxLen) raise_error(st, SAD_E_INVAL, i, W_VALIDATE);
+}
+
+__global__ void validate_codes_kernel(const uint8_t* __restrict__ codes, int64_t total, int A,
+                                      DevStatus* st) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride)
+    if (codes[t] >= A) raise_error(st, SAD_E_INVAL, t, W_VALIDATE);
+}
+
+void launch_validate(const sad_seqs& s, int k, DevStatus* st, hipStream_t stream) {
+  int n = s.n;
+  validate_lengths_kernel<<<(n + 256) / 256, 256, 0, stream>>>(s.d_offsets, n, s.total_len,
+                                                              s.max_len, k, st);
+  int64_t blocks = (s.total_len + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  validate_codes_kernel<<<(int)blocks, 256, 0, stream>>>(s.d_codes, s.total_len, s.alphabet, st);
+}
+
+// ------------------------------------------------------------------ k-mer lists
+// One 256-thread workgroup per sequence: k-mer codes into LDS, bitonic sort,
+// run-length compaction to (tau << 16 | count) entries in ascending tau.
+
+constexpr int kListThreads = 256;
+
+__global__ __launch_bounds__(kListThreads) void kmer_list_kernel(
+    const uint8_t* __restrict__ codes, const int64_t* __restrict__ off, int A, int k,
+    uint32_t* __restrict__ entries, int32_t* __restrict__ nu) {
+  __shared__ uint32_t keys[kMaxLen];
+  __shared__ int32_t seg_base[kListThreads + 1];
+  const int seq = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t base = off[seq];
+  const int L = (int)(off[seq + 1] - base);
+  const int m = L - k + 1;
+  if (m <= 0) {
+    if (tid == 0) nu[seq] = 0;
+    return;
+  }
+  int P = 1;
+  while (P < m) P <<= 1;
+  for (int t = tid; t < P; t += kListThreads) {
+    uint32_t tau = 0xffffffffu;
+    if (t < m) {
+      tau = 0;
+      for (int u = 0; u < k; ++u) tau = tau * (uint32_t)A + codes[base + t + u];
+    }
+    keys[t] = tau;
+  }
+  __syncthreads();
+  // bitonic sort of keys[0..P)
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < P / 2; t += kListThreads) {
+        int lo = 2 * t - (t & (stride - 1));
+        int hi = lo + stride;
+        bool up = ((lo & size) == 0);
+        uint32_t a = keys[lo], b = keys[hi];
+        if ((a > b) == up) {
+          keys[lo] = b;
+          keys[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // run starts: each thread owns a contiguous segment of positions
+  const int per = (m + kListThreads - 1) / kListThreads;
+  const int s0 = tid * per;
+  const int s1 = min(m, s0 + per);
+  int cnt = 0;
+  for (int t = s0; t < s1; ++t)
+    if (t == 0 || keys[t] != keys[t - 1]) ++cnt;
+  seg_base[tid] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int w = 0; w < kListThreads; ++w) {
+      int c = seg_base[w];
+      seg_base[w] = acc;
+      acc += c;
+    }
+    seg_base[kListThreads] = acc;
+    nu[seq] = acc;
+  }
+  __syncthreads();
+  int u = seg_base[tid];
+  for (int t = s0; t < s1; ++t) {
+    if (t == 0 || keys[t] != keys[t - 1]) {
+      int e = t + 1;
+      while (e < m && keys[e] == keys[t]) ++e;
+      entries[base + u] = (keys[t] << 16) | (uint32_t)(e - t);
+      ++u;
+    }
+  }
+}
+
+void launch_kmer_lists(const uint8_t* codes, const int64_t* offsets, int n, int A, int k,
+                       uint32_t* entries, int64_t* /*kl_off*/, int32_t* nu, DevStatus* /*st*/,
+                       hipStream_t stream) {
+  if (n <= 0) return;
+  kmer_list_kernel<<<n, kListThreads, 0, stream>>>(codes, offsets, A, k, entries, nu);
+}
+
+// ------------------------------------------------------------------ pair sums
+// One 256-thread workgroup per row sequence r: its counts go to a dense u16
+// histogram in LDS; each wave streams one column sequence's list at a time
+// (64 consecutive entries per load) and sums min(count, H[tau]).
+
+constexpr int kPairThreads = 256;
+
+__device__ inline uint32_t fhat_of(int64_t c, int64_t Li, int64_t Lj, int k) {
+  int64_t L = Li < Lj ? Li : Lj;
+  if (L < k) return 0u;
+  uint64_t d = (uint64_t)(L - k + 1);
+  return (uint32_t)(((uint64_t)c << 31) / d);
+}
+
+__device__ inline int64_t wave_sum64(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Loads row r's list into the histogram (hist must be zero).
+__device__ inline void hist_load(uint16_t* hist, const KmerLists& kl, int r) {
+  const uint32_t* e = kl.entries + kl.off[r];
+  const int nr = kl.nu[r];
+  for (int t = threadIdx.x; t < nr; t += blockDim.x) {
+    uint32_t v = e[t];
+    hist[v >> 16] = (uint16_t)(v & 0xffff);
+  }
+}
+
+__device__ inline void hist_clear(uint16_t* hist, int kspace) {
+  uint32_t* h32 = reinterpret_cast<uint32_t*>(hist);
+  for (int t = threadIdx.x; t < (kspace + 1) / 2; t += blockDim.x) h32[t] = 0;
+}
+
+// c between the histogram's row and column sequence c (wave-wide)
+__device__ inline int64_t wave_common(const uint16_t* hist, const KmerLists& kl, int c) {
+  const uint32_t* e = kl.entries + kl.off[c];
+  const int nc = kl.nu[c];
+  const int lane = threadIdx.x & 63;
+  int64_t acc = 0;
+  for (int t = lane; t < nc; t += 64) {
+    uint32_t v = e[t];
+    uint32_t h = hist[v >> 16];
+    uint32_t cnt = v & 0xffff;
+    acc += cnt < h ? cnt : h;
+  }
+  return wave_sum64(acc);
+}
+
+__device__ inline int64_t seq_len(const KmerLists& kl, int i) {
+  return kl.seq_off[i + 1] - kl.seq_off[i];
+}
+
+// Block reduction of per-wave partial sums held by lane 0 of each wave.
+__device__ inline uint64_t block_sum_waves(uint64_t v, uint64_t* red) {
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  uint64_t s = 0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+  return s;
+}
+
+// K_loc(r) = sum over j in chunk(r) of F(r, j)
+__global__ __launch_bounds__(kPairThreads) void rowsum_chunk_kernel(KmerLists kl, int n, int p,
+                                                                     int k, int kspace,
+                                                                     uint64_t* __restrict__ out) {
+  extern __shared__ uint16_t hist[];
+  __shared__ uint64_t red[kPairThreads / 64];
+  const int r = blockIdx.x;
+  int c = (int)(((int64_t)r * p) / n);
+  while (c + 1 <= p && (((int64_t)(c + 1) * n) / p) <= r) ++c;
+  while ((((int64_t)c * n) / p) > r) --c;
+  const int lo = (int)(((int64_t)c * n) / p), hi = (int)(((int64_t)(c + 1) * n) / p);
+  hist_clear(hist, kspace);
+  __syncthreads();
+  hist_load(hist, kl, r);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t Lr = seq_len(kl, r);
+  uint64_t part = 0;
+  for (int j = lo + wave; j < hi; j += nw) {
+    int64_t cc = wave_common(hist, kl, j);
+    part += fhat_of(cc, Lr, seq_len(kl, j), k);
+  }
+  uint64_t s = block_sum_waves(part, red);
+  if (threadIdx.x == 0) out[r] = s;
+}
+
+// out(r) = sum over the listed columns of F(r, col)
+__global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl,
+                                                                    const int32_t* __restrict__ cols,
+                                                                    int ncols, int k, int kspace,
+                                                                    uint64_t* __restrict__ out) {
+  extern __shared__ uint16_t hist[];
+  __shared__ uint64_t red[kPairThreads / 64];
+  const int r = blockIdx.x;
+  hist_clear(hist, kspace);
+  __syncthreads();
+  hist_load(hist, kl, r);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t Lr = seq_len(kl, r);
+  uint64_t part = 0;
+  for (int q = wave; q < ncols; q += nw) {
+    int j = cols[q];
+    int64_t cc = wave_common(hist, kl, j);
+    part += fhat_of(cc, Lr, seq_len(kl, j), k);
+  }
+  uint64_t s = block_sum_waves(part, red);
+  if (threadIdx.x == 0) out[r] = s;
+}
+
+// F rows inside groups: row index g_row in [0, total_rows) of the ids array;
+// its group's members are ids[group_off[g] .. group_off[g+1]); the group's
+// matrix starts at fm_off[g] (n_g x n_g, row-major).
+__global__ __launch_bounds__(kPairThreads) void fmatrix_kernel(KmerLists kl,
+                                                                const int32_t* __restrict__ group_off,
+                                                                const int32_t* __restrict__ ids,
+                                                                int ngroups,
+                                                                const int64_t* __restrict__ fm_off,
+                                                                int k, int kspace,
+                                                                uint32_t* __restrict__ F) {
+  extern __shared__ uint16_t hist[];
+  const int row = blockIdx.x;
+  int lo = 0, hi = ngroups;  // find g with group_off[g] <= row < group_off[g+1]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (group_off[mid] <= row) lo = mid;
+    else hi = mid;
+  }
+  const int g = lo;
+  const int g0 = group_off[g], ng = group_off[g + 1] - g0;
+  const int a = row - g0;
+  const int r = ids[row];
+  hist_clear(hist, kspace);
+  __syncthreads();
+  hist_load(hist, kl, r);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t Lr = seq_len(kl, r);
+  uint32_t* Frow = F + fm_off[g] + (int64_t)a * ng;
+  for (int b = wave; b < ng; b += nw) {
+    int j = ids[g0 + b];
+    int64_t cc = wave_common(hist, kl, j);
+    if ((threadIdx.x & 63) == 0) Frow[b] = fhat_of(cc, Lr, seq_len(kl, j), k);
+  }
+}
+
+static size_t hist_bytes(int kspace) { return (size_t)((kspace + 1) / 2) * 4; }
+
+// Histograms above 64 KB (4^8 k-mers) need the larger dynamic-LDS limit.
+static void allow_lds(const void* fn, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+void launch_rowsum_chunk(const KmerLists& kl, int n, int p, int k, int kspace, uint64_t* out,
+                         hipStream_t stream) {
+  if (n <= 0) return;
+  allow_lds((const void*)rowsum_chunk_kernel, hist_bytes(kspace));
+  rowsum_chunk_kernel<<<n, kPairThreads, hist_bytes(kspace), stream>>>(kl, n, p, k, kspace, out);
+}
+
+void launch_rowsum_list(const KmerLists& kl, int n, const int32_t* cols, int ncols, int k,
+                        int kspace, uint64_t* out, hipStream_t stream) {
+  if (n <= 0) return;
+  allow_lds((const void*)rowsum_list_kernel, hist_bytes(kspace));
+  rowsum_list_kernel<<<n, kPairThreads, hist_bytes(kspace), stream>>>(kl, cols, ncols, k, kspace,
+                                                                      out);
+}
+
+void launch_fmatrix_groups(const KmerLists& kl, const int32_t* group_off, const int32_t* ids,
+                           int ngroups, int64_t total_rows, const int64_t* fm_off, int k,
+                           int kspace, uint32_t* F, hipStream_t stream) {
+  if (total_rows <= 0) return;
+  allow_lds((const void*)fmatrix_kernel, hist_bytes(kspace));
+  fmatrix_kernel<<<(unsigned)total_rows, kPairThreads, hist_bytes(kspace), stream>>>(
+      kl, group_off, ids, ngroups, fm_off, k, kspace, F);
+}
+
+// ------------------------------------------------------------------ chunk sort
+// sorted[lo(c) + rank] = i, rank = #{j in chunk(i) : (key_j, j) < (key_i, i)}.
+
+__global__ void chunk_rank_kernel(const uint64_t* __restrict__ key, int n, int p,
+                                  int32_t* __restrict__ sorted) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = (int)(((int64_t)i * p) / n);
+  while (c + 1 <= p && (((int64_t)(c + 1) * n) / p) <= i) ++c;
+  while ((((int64_t)c * n) / p) > i) --c;
+  const int lo = (int)(((int64_t)c * n) / p), hi = (int)(((int64_t)(c + 1) * n) / p);
+  const uint64_t ki = key[i];
+  int rank = 0;
+  for (int j = lo; j < hi; ++j) {
+    uint64_t kj = key[j];
+    rank += (kj < ki) || (kj == ki && j < i);
+  }
+  sorted[lo + rank] = i;
+}
+
+void launch_chunk_sort(const uint64_t* key, int n, int p, int32_t* sorted, hipStream_t stream) {
+  if (n <= 0) return;
+  chunk_rank_kernel<<<(n + 255) / 256, 256, 0, stream>>>(key, n, p, sorted);
+}
+
+// sample t (1..ks) of chunk c: sorted[lo + floor(t w / (ks + 1))]
+__global__ void pick_samples_kernel(const int32_t* __restrict__ sorted, int n, int p, int ks,
+                                    int32_t* __restrict__ sample_ids) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= p * ks) return;
+  int c = q / ks, t = q % ks + 1;
+  int lo = (int)(((int64_t)c * n) / p), hi = (int)(((int64_t)(c + 1) * n) / p);
+  int w = hi - lo;
+  sample_ids[q] = sorted[lo + (int)(((int64_t)t * w) / (ks + 1))];
+}
+
+void launch_pick_samples(const int32_t* sorted, int n, int p, int ks, int32_t* sample_ids,
+                         hipStream_t stream) {
+  int tot = p * ks;
+  if (tot <= 0) return;
+  pick_samples_kernel<<<(tot + 255) / 256, 256, 0, stream>>>(sorted, n, p, ks, sample_ids);
+}
+
+}  // namespace sad

@@ -1,0 +1,154 @@
+// Regular-sampling partition (paper Section 2.3.2): per-chunk picks of p-1
+// composite keys (K_i, i), a stable merge of the p sorted runs into Y, the
+// pivots Y_{p/2 + (t-1)p}, bucket ids by binary search over the pivots, and a
+// stable scatter of ids into buckets.
+#include "sad_internal.h"
+
+namespace sad {
+
+__device__ inline bool ck_less(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+// Y[c (p-1) + t - 1] = key of sorted chunk c at floor(t w / p)
+__global__ void y_pick_kernel(const uint64_t* __restrict__ key, const int32_t* __restrict__ sorted,
+                              int n, int p, uint64_t* __restrict__ Yk, int32_t* __restrict__ Yi) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= p * (p - 1)) return;
+  int c = q / (p - 1), t = q % (p - 1) + 1;
+  int lo = (int)(((int64_t)c * n) / p), hi = (int)(((int64_t)(c + 1) * n) / p);
+  int id = sorted[lo + (int)(((int64_t)t * (hi - lo)) / p)];
+  Yk[q] = key[id];
+  Yi[q] = id;
+}
+
+// number of entries of run [r0, r0 + len) strictly below (k, i) / at most (k, i)
+__device__ inline int run_lower(const uint64_t* Yk, const int32_t* Yi, int r0, int len, uint64_t k,
+                                int32_t i) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (ck_less(Yk[r0 + mid], Yi[r0 + mid], k, i)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+__device__ inline int run_upper(const uint64_t* Yk, const int32_t* Yi, int r0, int len, uint64_t k,
+                                int32_t i) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (!ck_less(k, i, Yk[r0 + mid], Yi[r0 + mid])) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Stable rank of each Y entry among all runs (equal entries ordered by run,
+// then position), scattered into sorted order.
+__global__ void y_merge_kernel(const uint64_t* __restrict__ Yk, const int32_t* __restrict__ Yi,
+                               int p, uint64_t* __restrict__ Sk, int32_t* __restrict__ Si) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int len = p - 1;
+  if (q >= p * len) return;
+  const int c = q / len, pos = q % len;
+  const uint64_t k = Yk[q];
+  const int32_t i = Yi[q];
+  int rank = pos;
+  for (int r = 0; r < p; ++r) {
+    if (r == c) continue;
+    rank += (r < c) ? run_upper(Yk, Yi, r * len, len, k, i) : run_lower(Yk, Yi, r * len, len, k, i);
+  }
+  Sk[rank] = k;
+  Si[rank] = i;
+}
+
+__global__ void pivot_kernel(const uint64_t* __restrict__ Sk, const int32_t* __restrict__ Si, int p,
+                             uint64_t* __restrict__ pk, int32_t* __restrict__ pi) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  if (t > p - 1) return;
+  int idx = p / 2 + (t - 1) * p - 1;
+  pk[t - 1] = Sk[idx];
+  pi[t - 1] = Si[idx];
+}
+
+constexpr int kScatterBlock = 256;
+
+// bucket(i) = #pivots strictly below (K_i, i); per-block bucket counts.
+__global__ __launch_bounds__(kScatterBlock) void bucket_kernel(
+    const uint64_t* __restrict__ key, int n, int p, const uint64_t* __restrict__ pk,
+    const int32_t* __restrict__ pi, int32_t* __restrict__ bucket, int32_t* __restrict__ blk_cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = key[i];
+  int lo = 0, hi = p - 1;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (ck_less(pk[mid], pi[mid], k, i)) lo = mid + 1;
+    else hi = mid;
+  }
+  bucket[i] = lo;
+  atomicAdd(&blk_cnt[(int64_t)blockIdx.x * p + lo], 1);
+}
+
+// per bucket: exclusive prefix over blocks (in place) and total
+__global__ void bucket_scan_blocks_kernel(int32_t* __restrict__ blk_cnt, int nblk, int p,
+                                          int32_t* __restrict__ total) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p) return;
+  int acc = 0;
+  for (int q = 0; q < nblk; ++q) {
+    int v = blk_cnt[(int64_t)q * p + b];
+    blk_cnt[(int64_t)q * p + b] = acc;
+    acc += v;
+  }
+  total[b] = acc;
+}
+
+__global__ void bucket_offsets_kernel(const int32_t* __restrict__ total, int p,
+                                      int32_t* __restrict__ off) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int acc = 0;
+  for (int b = 0; b < p; ++b) {
+    off[b] = acc;
+    acc += total[b];
+  }
+  off[p] = acc;
+}
+
+__global__ __launch_bounds__(kScatterBlock) void bucket_scatter_kernel(
+    const int32_t* __restrict__ bucket, int n, int p, const int32_t* __restrict__ blk_cnt,
+    const int32_t* __restrict__ off, int32_t* __restrict__ members) {
+  __shared__ int32_t bk[kScatterBlock];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = i < n ? bucket[i] : -1;
+  bk[threadIdx.x] = b;
+  __syncthreads();
+  if (i >= n) return;
+  int before = 0;
+  for (int t = 0; t < (int)threadIdx.x; ++t) before += (bk[t] == b);
+  members[off[b] + blk_cnt[(int64_t)blockIdx.x * p + b] + before] = i;
+}
+
+void launch_partition(const uint64_t* key, int n, int p, const int32_t* sorted, uint64_t* Ykey,
+                      int32_t* Yid, uint64_t* Ysorted_key, int32_t* Ysorted_id,
+                      uint64_t* pivot_key, int32_t* pivot_id, int32_t* bucket, int32_t* blk_cnt,
+                      int32_t* total, int32_t* bucket_off, int32_t* members, hipStream_t stream) {
+  const int ny = p * (p - 1);
+  if (ny > 0) {
+    y_pick_kernel<<<(ny + 255) / 256, 256, 0, stream>>>(key, sorted, n, p, Ykey, Yid);
+    y_merge_kernel<<<(ny + 255) / 256, 256, 0, stream>>>(Ykey, Yid, p, Ysorted_key, Ysorted_id);
+    pivot_kernel<<<(p - 1 + 255) / 256, 256, 0, stream>>>(Ysorted_key, Ysorted_id, p, pivot_key,
+                                                          pivot_id);
+  }
+  const int nblk = (n + kScatterBlock - 1) / kScatterBlock;
+  hipMemsetAsync(blk_cnt, 0, sizeof(int32_t) * (size_t)nblk * p, stream);
+  bucket_kernel<<<nblk, kScatterBlock, 0, stream>>>(key, n, p, pivot_key, pivot_id, bucket,
+                                                    blk_cnt);
+  bucket_scan_blocks_kernel<<<(p + 255) / 256, 256, 0, stream>>>(blk_cnt, nblk, p, total);
+  bucket_offsets_kernel<<<1, 1, 0, stream>>>(total, p, bucket_off);
+  bucket_scatter_kernel<<<nblk, kScatterBlock, 0, stream>>>(bucket, n, p, blk_cnt, bucket_off,
+                                                            members);
+}
+
+}  // namespace sad

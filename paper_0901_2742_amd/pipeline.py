@@ -1,0 +1,53 @@
+"""Chains the four C-ABI calls on one HIP stream (the paper's algorithm box:
+rank, partition, per-bucket alignment, ancestor refinement + glue)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def to_device(codes, offsets, alphabet: int) -> B.DeviceSeqs:
+    return B.DeviceSeqs.from_numpy(codes, offsets, alphabet)
+
+
+def run_device(seqs: B.DeviceSeqs, prm: B.Params) -> dict:
+    """All four stages; results stay on the device."""
+    key, samples = B.sad_kmer_rank(seqs, prm)
+    part = B.sad_partition(seqs, key, prm)
+    al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm)
+    rf = B.sad_refine(seqs, part["bucket_off"], part["members"], al, prm)
+    return dict(key=key, samples=samples, part=part, align=al, refine=rf)
+
+
+def to_host(res: dict, n: int, p: int, total_len: int) -> dict:
+    """Copies the device results into numpy arrays shaped like the oracle's."""
+    def h(t):
+        return t.detach().cpu().numpy()
+
+    part = {k: h(v) for k, v in res["part"].items()}
+    part["pivot_key"] = part["pivot_key"].view(np.uint64)
+    al = res["align"]
+    rf = res["refine"]
+    m = int(rf["n_steps"])
+    return dict(
+        key=h(res["key"]).view(np.uint64),
+        samples=h(res["samples"]),
+        part=part,
+        align=dict(colmap=h(al["colmap"])[:total_len], width=h(al["width"])[:p],
+                   merge_score=h(al["merge_score"])[:n],
+                   merge_list=h(al["merge_list"])[:2 * n].reshape(-1, 2),
+                   merge_cells=h(al["merge_cells"])[:n], cells=int(h(al["cells"])[0])),
+        refine=dict(ga=h(rf["ga"])[:rf["ga_len"]], colmap=h(rf["colmap"])[:total_len],
+                    width=int(h(rf["width"])[0]), merge_score=h(rf["merge_score"])[:m],
+                    merge_list=h(rf["merge_list"])[:2 * m].reshape(-1, 2),
+                    merge_cells=h(rf["merge_cells"])[:m], cells=int(h(rf["cells"])[0])),
+    )
+
+
+def run(codes, offsets, alphabet: int, prm: B.Params) -> dict:
+    seqs = to_device(codes, offsets, alphabet)
+    res = run_device(seqs, prm)
+    torch.cuda.synchronize()
+    return to_host(res, seqs.n, prm.p, seqs.total_len)

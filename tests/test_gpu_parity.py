@@ -1,0 +1,152 @@
+"""Parity of the HIP library (through the C-ABI) with the CPU oracle.
+
+Every output is integer, so the bar is bit-exact: rank keys, samples, pivots,
+buckets, per-merge scores/cells/merge lists, column maps, widths, the global
+ancestor and the glued column map.  Inputs are the seeded workloads (full size
+for the two smaller ones) plus small edge cases (p = 1, empty buckets,
+DNA with k = 8, tiny buckets)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import CONFIGS, dna_matrix, generate, make_inputs, protein_matrix
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hip():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0901_2742_amd import binding as B
+    from paper_0901_2742_amd import pipeline
+    B.lib()
+    return B, pipeline
+
+
+def compare(got, ref, what=""):
+    assert np.array_equal(got["key"], ref["key"]), f"{what}: keys"
+    assert np.array_equal(got["samples"], ref["samples"]), f"{what}: samples"
+    for k in ("pivot_key", "pivot_id", "bucket", "bucket_off", "members"):
+        assert np.array_equal(np.asarray(got["part"][k]), np.asarray(ref["part"][k])), f"{what}: {k}"
+    boff = ref["part"]["bucket_off"]
+    ga, ra = got["align"], ref["align"]
+    assert np.array_equal(ga["width"], ra["width"]), f"{what}: widths"
+    p = len(boff) - 1
+    for b in range(p):
+        lo, nb = boff[b], boff[b + 1] - boff[b]
+        sl = slice(lo, lo + max(nb - 1, 0))
+        assert np.array_equal(ga["merge_list"][sl], ra["merge_list"][sl]), f"{what}: merges {b}"
+        assert np.array_equal(ga["merge_score"][sl], ra["merge_score"][sl]), f"{what}: scores {b}"
+        assert np.array_equal(ga["merge_cells"][sl], ra["merge_cells"][sl]), f"{what}: cells {b}"
+    assert ga["cells"] == ra["cells"], f"{what}: total cells"
+    assert np.array_equal(ga["colmap"], ra["colmap"]), f"{what}: bucket column maps"
+    gr, rr = got["refine"], ref["refine"]
+    assert np.array_equal(gr["ga"], rr["ga"]), f"{what}: global ancestor"
+    assert np.array_equal(gr["merge_list"], rr["merge_list"]), f"{what}: ancestor merges"
+    assert np.array_equal(gr["merge_score"], rr["merge_score"]), f"{what}: refine scores"
+    assert np.array_equal(gr["merge_cells"], rr["merge_cells"]), f"{what}: refine cells"
+    assert gr["cells"] == rr["cells"]
+    assert gr["width"] == rr["width"], f"{what}: glued width"
+    assert np.array_equal(gr["colmap"], rr["colmap"]), f"{what}: glued column map"
+
+
+def run_both(B, pipeline, s, k, p, S, go, ge, mode, s_max=1024):
+    prm = B.Params(k, p, S, go, ge, s_max, mode)
+    got = pipeline.run(s.codes, s.offsets, s.alphabet, prm)
+    ref = oracle.run_pipeline(s.codes, s.offsets, s.alphabet, k, p, S, go, ge, s_max)
+    return got, ref
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_prot64_full(hip, mode):
+    B, pipeline = hip
+    w = CONFIGS["prot64"]
+    _say(f"case prot64 mode={mode}")
+    s = make_inputs("prot64")
+    got, ref = run_both(B, pipeline, s, w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, mode)
+    compare(got, ref, "prot64")
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 7])
+def test_small_protein_sets(hip, p):
+    B, pipeline = hip
+    _say(f"case small protein p={p}")
+    s = generate(4242 + p, 30, 20, 3, {"kind": "fixed", "value": 70}, 0.15, 0.04, 3)
+    got, ref = run_both(B, pipeline, s, 3, p, protein_matrix(), 10, 1, 1)
+    compare(got, ref, f"p={p}")
+
+
+def test_small_dna_k8(hip):
+    B, pipeline = hip
+    _say("case small dna k=8")
+    s = generate(808, 40, 4, 4, {"kind": "uniform_int", "lo": 90, "hi": 140}, 0.05, 0.01, 8)
+    got, ref = run_both(B, pipeline, s, 8, 4, dna_matrix(), 5, 2, 1)
+    compare(got, ref, "dna")
+
+
+def test_long_sequences_multi_strip(hip):
+    """Profiles wider than several 64-row strips and the 256-column ring."""
+    B, pipeline = hip
+    _say("case long sequences")
+    s = generate(31, 12, 20, 2, {"kind": "fixed", "value": 700}, 0.1, 0.02, 3)
+    got, ref = run_both(B, pipeline, s, 3, 2, protein_matrix(), 10, 1, 1)
+    compare(got, ref, "long")
+
+
+def test_gap_models(hip):
+    """o == e and free extension: many tied optima exercise the tie rule."""
+    B, pipeline = hip
+    s = generate(77, 16, 20, 2, {"kind": "fixed", "value": 50}, 0.3, 0.05, 3)
+    for go, ge in [(3, 3), (6, 0), (0, 0)]:
+        _say(f"case gaps {go}/{ge}")
+        got, ref = run_both(B, pipeline, s, 3, 2, protein_matrix(), go, ge, 1)
+        compare(got, ref, f"gaps {go}/{ge}")
+
+
+def test_prot2000_full(hip):
+    B, pipeline = hip
+    w = CONFIGS["prot2000"]
+    _say("case prot2000")
+    s = make_inputs("prot2000")
+    got, ref = run_both(B, pipeline, s, w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, 1)
+    compare(got, ref, "prot2000")
+
+
+def test_repeat_runs_identical(hip):
+    B, pipeline = hip
+    _say("case determinism")
+    w = CONFIGS["prot64"]
+    s = make_inputs("prot64")
+    prm = B.Params(w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, w.s_max, 1)
+    a = pipeline.run(s.codes, s.offsets, s.alphabet, prm)
+    b = pipeline.run(s.codes, s.offsets, s.alphabet, prm)
+    assert np.array_equal(a["refine"]["colmap"], b["refine"]["colmap"])
+    assert np.array_equal(a["align"]["merge_score"], b["align"]["merge_score"])
+
+
+def test_error_paths(hip):
+    B, pipeline = hip
+    _say("case error paths")
+    s = make_inputs("prot64")
+    seqs = pipeline.to_device(s.codes, s.offsets, 20)
+    with pytest.raises(B.SadError) as e:
+        B.sad_kmer_rank(seqs, B.Params(3, 40, protein_matrix(), 10, 1))   # N < 2p
+    assert e.value.code == B.SAD_E_INVAL
+    bad = s.codes.copy()
+    bad[5] = 25
+    seqs_bad = pipeline.to_device(bad, s.offsets, 20)
+    with pytest.raises(B.SadError) as e:
+        B.sad_kmer_rank(seqs_bad, B.Params(3, 4, protein_matrix(), 10, 1))
+    assert e.value.code == B.SAD_E_INVAL
+    with pytest.raises(B.SadError) as e:
+        B.sad_kmer_rank(seqs, B.Params(4, 4, protein_matrix(), 10, 1))    # 20^4 > 2^16
+    assert e.value.code == B.SAD_E_INVAL
