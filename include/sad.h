@@ -161,6 +161,14 @@ int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off, const int3
                    int32_t ga_cap, int32_t* ga_len, sad_msa* global_out, int32_t* n_steps,
                    hipStream_t stream);
 
+/* Kernel timing for measurement tools.  While enabled, every launch of the
+ * alignment engine kernel (the DP + traceback + merge kernel that dominates
+ * stages 3 and 4) is bracketed by HIP events on the call's stream; the
+ * accumulated time and launch count are read (and optionally reset) with
+ * sad_profile_read.  Disabled by default; enabling adds no device work. */
+int32_t sad_profile_enable(int32_t on);
+int32_t sad_profile_read(double* engine_ms, int64_t* engine_launches, int32_t reset);
+
 /* Message for the calling thread's last non-OK status (static storage). */
 const char* sad_last_error(void);
 

@@ -27,7 +27,8 @@ SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
 EXPORTS = ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine",
-           "sad_last_error", "sad_release", "sad_version")
+           "sad_profile_enable", "sad_profile_read", "sad_last_error", "sad_release",
+           "sad_version")
 
 
 class SadError(RuntimeError):
@@ -73,6 +74,10 @@ def lib():
         L.sad_refine.argtypes = [P, P, P, P, P, P, I32, P, P, P, P]
         for f in ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine"):
             getattr(L, f).restype = I32
+        L.sad_profile_enable.argtypes = [I32]
+        L.sad_profile_enable.restype = I32
+        L.sad_profile_read.argtypes = [P, P, I32]
+        L.sad_profile_read.restype = I32
         L.sad_last_error.restype = ctypes.c_char_p
         L.sad_version.restype = ctypes.c_char_p
         L.sad_release.restype = None
@@ -223,6 +228,18 @@ def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor
     out["ga_len"] = gl.value
     out["n_steps"] = nst.value
     return out
+
+
+def sad_profile_enable(on: bool) -> None:
+    lib().sad_profile_enable(1 if on else 0)
+
+
+def sad_profile_read(reset: bool = False):
+    """(engine kernel milliseconds, engine launches) accumulated while enabled."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    lib().sad_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0)
+    return ms.value, n.value
 
 
 def sad_version() -> str:

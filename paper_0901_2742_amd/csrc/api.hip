@@ -29,6 +29,46 @@ static std::mutex g_mu;
 static std::vector<DeviceCtx> g_ctx;
 static thread_local std::string g_err;
 
+// engine-kernel timing (sad_profile_enable / sad_profile_read)
+static bool g_prof_on = false;
+static double g_prof_ms = 0.0;
+static int64_t g_prof_launches = 0;
+
+struct EngineTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit EngineTimer(hipStream_t st) : s(st) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, s);
+  }
+  void stop() {
+    if (a) (void)hipEventRecord(b, s);
+  }
+  // call after the stream has been synchronised
+  void collect() {
+    if (!a) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_prof_ms += ms;
+      g_prof_launches += 1;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    a = b = nullptr;
+  }
+  ~EngineTimer() {
+    if (a) {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  }
+};
+
 static int32_t fail(int32_t code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -120,6 +160,7 @@ static const char* where_name(int32_t w) {
     case W_ENGINE_BOUND: return "alignment engine (32-bit score bound)";
     case W_ENGINE_WAIT: return "alignment engine (queue wait limit)";
     case W_REFINE: return "refine";
+    case W_ENGINE_LINK: return "alignment engine (strip boundary scratch)";
     default: return "device";
   }
 }
@@ -254,16 +295,27 @@ struct EngineBuffers {
   int32_t* up_pool;
   uint32_t* tb;
   int32_t* bnd;
-  int64_t prof_cap, up_cap, tb_words;
+  int64_t prof_cap, up_cap, tb_words, link_words;
+  int link_rows, link_stride;
   int nwg;
 };
 
+// Engine scratch sized for profiles up to wcap columns.
+static int64_t tb_words_for(int wcap) {
+  int64_t strips = (wcap + 63) / 64;
+  int64_t chunks = (wcap + 63 + 63) / 64;
+  return strips * chunks * 16 * 64;
+}
+
 static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, int njobs,
-                        int64_t prof_cap, int64_t up_cap, int64_t tb_words) {
+                        int64_t prof_cap, int64_t up_cap, int wcap) {
   e.nwg = std::max(1, std::min(njobs, engine_workgroups()));
   e.prof_cap = prof_cap;
   e.up_cap = up_cap;
-  e.tb_words = tb_words;
+  e.tb_words = tb_words_for(wcap);
+  e.link_rows = std::max(1, (wcap + 63) / 64 - 1);
+  e.link_stride = wcap + 1;
+  e.link_words = (int64_t)e.link_rows * 2 * e.link_stride;
   cv.add(e.node_W, nnodes);
   cv.add(e.node_n, nnodes);
   cv.add(e.node_parent, nnodes);
@@ -283,14 +335,8 @@ static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, in
   cv.add(e.tops, 2);
   cv.add(e.prof_pool, (size_t)prof_cap);
   cv.add(e.up_pool, (size_t)up_cap);
-  cv.add(e.tb, (size_t)e.nwg * (size_t)tb_words);
-  cv.add(e.bnd, (size_t)e.nwg * 2 * (kMaxWidth + 1));
-}
-
-static int64_t tb_words_for(int wcap) {
-  int64_t strips = (wcap + 63) / 64;
-  int64_t t4 = (wcap + 63 + 3) / 4;
-  return strips * t4 * 64;
+  cv.add(e.tb, (size_t)e.nwg * (size_t)e.tb_words);
+  cv.add(e.bnd, (size_t)e.nwg * (size_t)e.link_words);
 }
 
 static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const int8_t* S, int go,
@@ -324,6 +370,9 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
   a.tb = e.tb;
   a.tb_words_per_wg = e.tb_words;
   a.bnd = e.bnd;
+  a.link_words_per_wg = e.link_words;
+  a.link_rows = e.link_rows;
+  a.link_stride = e.link_stride;
   a.A = A;
   int smax = 0;
   for (int q = 0; q < A * A; ++q) {
@@ -376,12 +425,11 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
   for (int g = 0; g < ts.ngroups; ++g)
     njobs += std::max(0, ts.h_group_off[g + 1] - ts.h_group_off[g] - 1);
   int wcap = std::min(kMaxWidth, std::max(2 * ts.max_len + 64, 128));
-  int64_t tbw = tb_words_for(wcap);
   int64_t prof_cap = (int64_t)A * (ts.total_len * 6 + 4096);
   int64_t up_cap = ts.total_len * 6 + 4096;
   for (int attempt = 0; attempt < 8; ++attempt) {
     Carver cv = base_cv;
-    plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, prof_cap, up_cap, tbw);
+    plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, prof_cap, up_cap, wcap);
     int32_t r = cv.carve(c);
     if (r) return r;
     r = reset_status(c, stream);
@@ -401,16 +449,21 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                      stream);
     EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                                nullptr, c->st);
+    EngineTimer timer(stream);
     launch_engine(a, e.nwg, stream);
+    timer.stop();
     DevStatus d{};
     r = read_status(c, stream, &d);
     if (r) return r;
-    if (d.code == SAD_E_CAPACITY && (d.where == W_ENGINE_POOL || d.where == W_ENGINE_TB)) {
-      int64_t need = ((int64_t)d.detail_hi << 32) | (uint32_t)d.detail_lo;
-      if (d.where == W_ENGINE_TB) tbw = std::max(tbw * 2, need);
-      else {
+    if (njobs > 0) timer.collect();
+    if (d.code == SAD_E_CAPACITY &&
+        (d.where == W_ENGINE_POOL ||
+         ((d.where == W_ENGINE_TB || d.where == W_ENGINE_LINK) && wcap < kMaxWidth))) {
+      if (d.where == W_ENGINE_POOL) {
         prof_cap *= 2;
         up_cap *= 2;
+      } else {
+        wcap = std::min(kMaxWidth, 2 * wcap);
       }
       continue;
     }
@@ -882,18 +935,13 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   }
   r = h2d(ops_off, rf_ops_off, stream);
   if (r) return r;
-  int64_t tbw = 0;
-  for (int u = 0; u < q; ++u) {
-    int64_t strips = (width_u[u] + 63) / 64, t4 = (GL + 63 + 3) / 4;
-    tbw = std::max(tbw, strips * t4 * 64);
-  }
-  tbw = std::max<int64_t>(tbw, 64);
+  const int rwcap = std::max(64, std::max(maxW, GL));
   const int64_t prof_fixed = (Wtot + GL) * A;
   const int64_t prof_cap = prof_fixed + (ops_tot + 1) * A;
   const int64_t up_cap = Wtot + GL + ops_tot + 1;
   EngineBuffers e{};
   Carver cv;
-  plan_engine(cv, e, 2 * q + 1, q, q, prof_cap, up_cap, tbw);
+  plan_engine(cv, e, 2 * q + 1, q, q, prof_cap, up_cap, rwcap);
   r = cv.carve(c);
   if (r) return r;
   r = reset_status(c, stream);
@@ -911,9 +959,12 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                      e.job_ops_off, e.queue, e.queue_flag, e.qctl + 1, e.node_parent, stream);
   EngineArgs a = engine_args(e, q, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                              rf_ops, c->st);
+  EngineTimer timer(stream);
   launch_engine(a, e.nwg, stream);
+  timer.stop();
   r = finish(c, stream);
   if (r) return r;
+  timer.collect();
 
   // ---- glue
   r = reset_status(c, stream);
@@ -929,6 +980,23 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                                              gout->d_cells);
   *n_steps = 2 * q - 1;
   return finish(c, stream);
+}
+
+extern "C" int32_t sad_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof_on = on != 0;
+  return SAD_OK;
+}
+
+extern "C" int32_t sad_profile_read(double* engine_ms, int64_t* engine_launches, int32_t reset) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (engine_ms) *engine_ms = g_prof_ms;
+  if (engine_launches) *engine_launches = g_prof_launches;
+  if (reset) {
+    g_prof_ms = 0.0;
+    g_prof_launches = 0;
+  }
+  return SAD_OK;
 }
 
 extern "C" const char* sad_last_error(void) { return g_err.c_str(); }

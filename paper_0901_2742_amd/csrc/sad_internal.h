@@ -40,7 +40,7 @@ __device__ inline void raise_error(DevStatus* st, int32_t code, int64_t detail, 
 enum Where : int32_t {
   W_VALIDATE = 1, W_KMER = 2, W_RANK = 3, W_PART = 4, W_UPGMA = 5, W_ENGINE = 6,
   W_ENGINE_POOL = 7, W_ENGINE_TB = 8, W_ENGINE_WIDTH = 9, W_ENGINE_BOUND = 10,
-  W_ENGINE_WAIT = 11, W_REFINE = 12,
+  W_ENGINE_WAIT = 11, W_REFINE = 12, W_ENGINE_LINK = 13,
 };
 
 // ------------------------------------------------------------------ arena
@@ -132,9 +132,12 @@ struct EngineArgs {
   int32_t* queue_head;
   int32_t* queue_tail;
   // DP scratch (per workgroup)
-  uint32_t* tb;           // traceback words
+  uint32_t* tb;           // tie bytes, packed four per word
   int64_t tb_words_per_wg;
-  int32_t* bnd;           // boundary rows: 4 * (kMaxWidth + 1) ints per workgroup
+  int32_t* bnd;           // strip boundary rows: link_rows x {H, X} x link_stride ints
+  int64_t link_words_per_wg;
+  int32_t link_rows;
+  int32_t link_stride;
   // scoring
   int32_t A;
   int8_t S[kMaxAlpha * kMaxAlpha];
