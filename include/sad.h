@@ -21,8 +21,9 @@
  *    it returns so that it can report device-side errors in its status.
  *  - Residue codes are 0..A-1 (A = 20 proteins, A = 4 DNA).  A k-mer tau of
  *    a sequence x at position t is sum_u x[t+u] * A^(k-1-u); A^k <= 65536.
- *  - Limits: sequence length <= 8192; profile width <= 4096 columns;
- *    DP values must stay within the 32-bit bound described at
+ *  - Limits: sequence length <= 8192; profile width <= 4096 columns; at most
+ *    8000 sequences per bucket and 8000 buckets; DP values must stay within
+ *    the 32-bit bound described at
  *    sad_align_buckets (otherwise SAD_E_OVERFLOW).
  *  - Status codes are returned; no exception crosses the ABI.  On error the
  *    contents of the outputs are unspecified.  sad_last_error() gives a
@@ -168,6 +169,11 @@ int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off, const int3
  * sad_profile_read.  Disabled by default; enabling adds no device work. */
 int32_t sad_profile_enable(int32_t on);
 int32_t sad_profile_read(double* engine_ms, int64_t* engine_launches, int32_t reset);
+/* Per-job phase times of the alignment engine while profiling is enabled,
+ * summed over jobs (milliseconds): ms_out[0] waiting for a ready job,
+ * [1] DP, [2] traceback, [3] merge, [4] publication (device-scope fence and
+ * queue hand-off); *jobs = jobs timed.  ms_out needs 5 entries. */
+int32_t sad_profile_phases(double* ms_out, int64_t* jobs, int32_t reset);
 
 /* Message for the calling thread's last non-OK status (static storage). */
 const char* sad_last_error(void);

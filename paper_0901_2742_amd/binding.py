@@ -27,7 +27,8 @@ SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
 EXPORTS = ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine",
-           "sad_profile_enable", "sad_profile_read", "sad_last_error", "sad_release",
+           "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_last_error",
+           "sad_release",
            "sad_version")
 
 
@@ -78,6 +79,8 @@ def lib():
         L.sad_profile_enable.restype = I32
         L.sad_profile_read.argtypes = [P, P, I32]
         L.sad_profile_read.restype = I32
+        L.sad_profile_phases.argtypes = [P, P, I32]
+        L.sad_profile_phases.restype = I32
         L.sad_last_error.restype = ctypes.c_char_p
         L.sad_version.restype = ctypes.c_char_p
         L.sad_release.restype = None
@@ -240,6 +243,16 @@ def sad_profile_read(reset: bool = False):
     n = ctypes.c_int64(0)
     lib().sad_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0)
     return ms.value, n.value
+
+
+def sad_profile_phases(reset: bool = False):
+    """Engine job phases (ms summed over jobs): wait, dp, traceback, merge, publish;
+    and the number of jobs."""
+    out = (ctypes.c_double * 5)()
+    n = ctypes.c_int64(0)
+    lib().sad_profile_phases(out, ctypes.byref(n), 1 if reset else 0)
+    return dict(wait=out[0], dp=out[1], traceback=out[2], merge=out[3], publish=out[4],
+                jobs=n.value)
 
 
 def sad_version() -> str:

@@ -23,6 +23,7 @@ struct DeviceCtx {
   DevStatus* h_st = nullptr;  // pinned host copy
   int64_t* h_small = nullptr; // pinned host scratch for small readbacks
   size_t h_small_cap = 0;
+  unsigned long long* phase = nullptr;  // engine phase ticks (profiling)
 };
 
 static std::mutex g_mu;
@@ -33,6 +34,8 @@ static thread_local std::string g_err;
 static bool g_prof_on = false;
 static double g_prof_ms = 0.0;
 static int64_t g_prof_launches = 0;
+static unsigned long long g_phase[6] = {0, 0, 0, 0, 0, 0};
+static double g_tick_khz = 0.0;
 
 struct EngineTimer {
   hipEvent_t a = nullptr, b = nullptr;
@@ -390,7 +393,28 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
       hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
     khz = 100000;
   a.wait_ticks = (int64_t)khz * 1000 * 20;
+  g_tick_khz = khz;
   return a;
+}
+
+// Per-phase tick accumulation of the engine kernel while profiling is on.
+static int32_t attach_phases(DeviceCtx* c, EngineArgs& a, hipStream_t s) {
+  a.phase_acc = nullptr;
+  if (!g_prof_on) return SAD_OK;
+  if (!c->phase) HIPCHK(hipMalloc(&c->phase, 8 * sizeof(unsigned long long)));
+  HIPCHK(hipMemsetAsync(c->phase, 0, 8 * sizeof(unsigned long long), s));
+  a.phase_acc = c->phase;
+  return SAD_OK;
+}
+
+static int32_t collect_phases(DeviceCtx* c, const EngineArgs& a, hipStream_t s) {
+  if (!a.phase_acc) return SAD_OK;
+  unsigned long long h[8];
+  HIPCHK(hipMemcpyAsync(h, c->phase, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int q = 0; q < 6; ++q) g_phase[q] += h[q];
+  return SAD_OK;
 }
 
 // Uploads tops (prof_top, up_top) and resets the queue control words.
@@ -449,6 +473,8 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                      stream);
     EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                                nullptr, c->st);
+    r = attach_phases(c, a, stream);
+    if (r) return r;
     EngineTimer timer(stream);
     launch_engine(a, e.nwg, stream);
     timer.stop();
@@ -456,6 +482,8 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     r = read_status(c, stream, &d);
     if (r) return r;
     if (njobs > 0) timer.collect();
+    r = collect_phases(c, a, stream);
+    if (r) return r;
     if (d.code == SAD_E_CAPACITY &&
         (d.where == W_ENGINE_POOL ||
          ((d.where == W_ENGINE_TB || d.where == W_ENGINE_LINK) && wcap < kMaxWidth))) {
@@ -602,6 +630,7 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
     fm_total += (int64_t)nb * nb;
     max_n = std::max(max_n, nb);
   }
+  if (max_n > kMaxGroup) return fail(SAD_E_CAPACITY, "bucket larger than the library limit");
   const int kspace = (int)kmer_space(A, k);
   uint32_t *entries, *F;
   int32_t* nu;
@@ -750,6 +779,7 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   const int q = (int)bucket_of_u.size();
   wo.push_back(Wtot);
   if (q == 0) return fail(SAD_E_INVAL, "no sequences");
+  if (q > kMaxGroup) return fail(SAD_E_CAPACITY, "too many buckets for the ancestor tree");
 
   // ---- stage buffers that live across the engine runs
   int32_t *d_uidx, *d_bucket_of_u, *d_width_u, *d_rows_u, *anc_len, *cons_list, *ga_goff,
@@ -959,12 +989,16 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                      e.job_ops_off, e.queue, e.queue_flag, e.qctl + 1, e.node_parent, stream);
   EngineArgs a = engine_args(e, q, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                              rf_ops, c->st);
+  r = attach_phases(c, a, stream);
+  if (r) return r;
   EngineTimer timer(stream);
   launch_engine(a, e.nwg, stream);
   timer.stop();
   r = finish(c, stream);
   if (r) return r;
   timer.collect();
+  r = collect_phases(c, a, stream);
+  if (r) return r;
 
   // ---- glue
   r = reset_status(c, stream);
@@ -999,6 +1033,19 @@ extern "C" int32_t sad_profile_read(double* engine_ms, int64_t* engine_launches,
   return SAD_OK;
 }
 
+extern "C" int32_t sad_profile_phases(double* ms_out, int64_t* jobs, int32_t reset) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const double per_ms = g_tick_khz > 0 ? 1.0 / g_tick_khz : 0.0;
+  if (ms_out) {
+    for (int q = 0; q < 4; ++q) ms_out[q] = (double)g_phase[q] * per_ms;
+    ms_out[4] = (double)g_phase[5] * per_ms;
+  }
+  if (jobs) *jobs = (int64_t)g_phase[4];
+  if (reset)
+    for (int q = 0; q < 6; ++q) g_phase[q] = 0;
+  return SAD_OK;
+}
+
 extern "C" const char* sad_last_error(void) { return g_err.c_str(); }
 
 extern "C" void sad_release(void) {
@@ -1009,6 +1056,7 @@ extern "C" void sad_release(void) {
     if (c.st) hipFree(c.st);
     if (c.h_st) hipHostFree(c.h_st);
     if (c.h_small) hipHostFree(c.h_small);
+    if (c.phase) hipFree(c.phase);
     c = DeviceCtx{};
   }
 }

@@ -26,6 +26,8 @@
 // Memory layout: node profiles are W x A uint16 counts in one pool; column
 // maps (node column -> parent column) are W int32 in another.  Internal nodes
 // are bump-allocated with W1 + W2 columns.
+#include <cstdlib>
+
 #include "sad_internal.h"
 
 namespace sad {
@@ -33,9 +35,9 @@ namespace sad {
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kColRing = 128;   // staged P2 columns per wave (power of two)
-constexpr int kStageT4 = 16;    // traceback staging: 16 x 64 words
+constexpr int kStageT4 = 16;    // traceback staging: 16 x 64 words (64 steps of a strip)
 constexpr int kMaxStrips = kMaxWidth / 64;
-constexpr int kEngineWGPerCU = 3;
+constexpr int kEngineWGPerCU = 1;
 
 // 32-bit words per staged P2 column: counts as packed u16 pairs, padded so a
 // protein column is three 16-byte LDS reads
@@ -52,13 +54,17 @@ __device__ inline int32_t shl1(int32_t old_lane63, int32_t v) {
   // lane l receives lane l+1's v; lane 63 keeps old_lane63
   return __builtin_amdgcn_update_dpp(old_lane63, v, 0x130, 0xf, 0xf, false);
 }
-// Scratch that a workgroup rewrites job after job is read past the vector L1
-// (agent-scope loads), so no line cached by an earlier job can be returned.
-__device__ inline int32_t load_l2(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline uint32_t load_l2(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Per-workgroup scratch (tie words, strip boundary rows) is written and read
+// by the waves of one workgroup, i.e. one CU, whose vector L1 is write-through
+// and sees its own stores: plain loads after workgroup-scope synchronisation.
+__device__ inline int32_t load_wg(const int32_t* p) { return *p; }
+__device__ inline uint32_t load_wg(const uint32_t* p) { return *p; }
+
+// -1, 0 or 1 for d < 0, d == 0, d > 0 (one v_med3_i32)
+__device__ inline int32_t sign3(int32_t d) {
+  int32_t r;
+  asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(d));
+  return r;
 }
 
 __device__ inline int32_t dot2(uint32_t a, uint32_t b, int32_t c) {
@@ -152,8 +158,9 @@ __device__ inline void dp_chunk(int t0, int lane, int W2, int32_t o, int32_t e,
     const int32_t t2 = max(Xn, Yn);
     const int32_t Hn = max(M, t2);
     const uint32_t hc = (M >= t2) ? 0u : ((Xn >= Yn) ? 1u : 2u);
-    const uint32_t xc = (uint32_t)(min(max(xo - xe, -1), 1) + 1);  // 0 ext, 1 both, 2 open
-    const uint32_t yc = (uint32_t)(min(max(yo - ye, -1), 1) + 1);
+    // 0 extend only, 1 both, 2 open only (stored as sign + 1)
+    const uint32_t xc = (uint32_t)(sign3(xo - xe) + 1);
+    const uint32_t yc = (uint32_t)(sign3(yo - ye) + 1);
     const uint32_t bits = hc | (xc << 2) | (yc << 4);
     if (!MASK || (j >= 1 && j <= W2)) {
       H = Hn;
@@ -171,7 +178,8 @@ __device__ inline void dp_chunk(int t0, int lane, int W2, int32_t o, int32_t e,
 }
 
 // One strip of the DP (run by one wave).  Returns false if the job aborted.
-template <int A>
+// PACK: U fits in 16 bits, so column scores use packed dot products.
+template <int A, bool PACK>
 __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                          int32_t* prog, uint32_t* tbw, int32_t* links, const int32_t* Ssh,
                          const uint16_t* P1, const uint16_t* P2) {
@@ -180,24 +188,31 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
   const int32_t o = J.o, e = J.e;
   const int i = 64 * s + lane + 1;
   const int ie = min(i, W1);
-  int32_t U[A];
-  uint32_t Up[(A + 1) / 2];
+  int32_t U[PACK ? 1 : A];
+  uint32_t Up[PACK ? (A + 1) / 2 : 1];
   {
-    uint16_t c1[A];
+    // U = C1[i] S, one row of S at a time (keeps few values live)
+    int32_t Uf[A];
 #pragma unroll
-    for (int q = 0; q < A; ++q) c1[q] = (i <= W1) ? P1[(int64_t)(i - 1) * A + q] : (uint16_t)0;
+    for (int b = 0; b < A; ++b) Uf[b] = 0;
+    const uint16_t* crow = P1 + (int64_t)(ie - 1) * A;
+#pragma unroll 1
+    for (int q = 0; q < A; ++q) {
+      const int32_t cq = (i <= W1) ? (int32_t)crow[q] : 0;
+      const int32_t* Srow = Ssh + q * A;
 #pragma unroll
-    for (int b = 0; b < A; ++b) {
-      int32_t u = 0;
-#pragma unroll
-      for (int q = 0; q < A; ++q) u += (int32_t)c1[q] * Ssh[q * A + b];
-      U[b] = u;
+      for (int b = 0; b < A; ++b) Uf[b] += cq * Srow[b];
     }
+    if constexpr (PACK) {
 #pragma unroll
-    for (int m = 0; m < (A + 1) / 2; ++m) {
-      const uint32_t lo = (uint32_t)U[2 * m] & 0xffffu;
-      const uint32_t hi = (2 * m + 1 < A) ? ((uint32_t)U[2 * m + 1] << 16) : 0u;
-      Up[m] = lo | hi;
+      for (int m = 0; m < (A + 1) / 2; ++m) {
+        const uint32_t lo = (uint32_t)Uf[2 * m] & 0xffffu;
+        const uint32_t hi = (2 * m + 1 < A) ? ((uint32_t)Uf[2 * m + 1] << 16) : 0u;
+        Up[m] = lo | hi;
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < A; ++b) U[b] = Uf[b];
     }
   }
   int32_t H = -(o + (ie - 1) * e);
@@ -209,41 +224,67 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
   const int32_t* inX = inH + stride;
   int32_t* outH = links + (int64_t)s * 2 * stride;
   int32_t* outX = outH + stride;
+  // the next chunk's P2 columns and boundary row are loaded during the current
+  // chunk (the boundary only if its producer is already far enough)
+  constexpr int NW = (A + 1) / 2;
+  uint32_t pcol[NW];
+  int32_t pbh = 0, pbx = kNeg32;
+  bool have_link = (s == 0);
+  auto prefetch = [&](int c, bool block) -> bool {
+    const int jn = 64 * c + 1 + lane;
+    if (jn <= W2) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(P2 + (int64_t)(jn - 1) * A);
+#pragma unroll
+      for (int m = 0; m < NW; ++m) pcol[m] = src[m];
+    }
+    if (s == 0) {
+      pbh = jn <= W2 ? -(o + (jn - 1) * e) : 0;
+      pbx = kNeg32;
+      have_link = true;
+      return true;
+    }
+    const int need = min(W2, 64 * c + 64);
+    if (block) {
+      if (!wait_link(a, J, prog, s - 1, need)) return false;
+    } else if (__hip_atomic_load(&prog[s - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <
+               need) {
+      have_link = false;
+      return true;
+    }
+    if (jn <= W2) {
+      pbh = load_wg(inH + jn);
+      pbx = load_wg(inX + jn);
+    }
+    have_link = true;
+    return true;
+  };
+  if (!prefetch(0, true)) return false;
   for (int c = 0; c < nchunks; ++c) {
     const int t0 = 64 * c;
     const int jn = t0 + 1 + lane;
-    int32_t bh = 0, bx = kNeg32;
-    if (s == 0) {
-      if (jn <= W2) bh = -(o + (jn - 1) * e);
-    } else {
+    if (!have_link) {
       if (!wait_link(a, J, prog, s - 1, min(W2, t0 + 64))) return false;
       if (jn <= W2) {
-        bh = load_l2(inH + jn);
-        bx = load_l2(inX + jn);
+        pbh = load_wg(inH + jn);
+        pbx = load_wg(inX + jn);
       }
     }
+    const int32_t bh = pbh, bx = pbx;
     if (jn <= W2) {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(P2 + (int64_t)(jn - 1) * A);
       uint32_t* dst = ring + ((jn - 1) & (kColRing - 1)) * CW;
 #pragma unroll
-      for (int m = 0; m < (A + 1) / 2; ++m) dst[m] = src[m];
+      for (int m = 0; m < NW; ++m) dst[m] = pcol[m];
 #pragma unroll
-      for (int m = (A + 1) / 2; m < CW; ++m) dst[m] = 0u;
+      for (int m = NW; m < CW; ++m) dst[m] = 0u;
     }
     __threadfence_block();
+    if (c + 1 < nchunks) prefetch(c + 1, false);
     int32_t oh = 0, ox = 0;
     const bool mask = (c == 0) || (t0 + 64 > W2);
-    if (J.packed) {
-      if (mask)
-        dp_chunk<A, true, true>(t0, lane, W2, o, e, ring, Up, U, H, X, Y, Hprev, bh, bx, oh, ox, tbs);
-      else
-        dp_chunk<A, true, false>(t0, lane, W2, o, e, ring, Up, U, H, X, Y, Hprev, bh, bx, oh, ox, tbs);
-    } else {
-      if (mask)
-        dp_chunk<A, false, true>(t0, lane, W2, o, e, ring, Up, U, H, X, Y, Hprev, bh, bx, oh, ox, tbs);
-      else
-        dp_chunk<A, false, false>(t0, lane, W2, o, e, ring, Up, U, H, X, Y, Hprev, bh, bx, oh, ox, tbs);
-    }
+    if (mask)
+      dp_chunk<A, PACK, true>(t0, lane, W2, o, e, ring, Up, U, H, X, Y, Hprev, bh, bx, oh, ox, tbs);
+    else
+      dp_chunk<A, PACK, false>(t0, lane, W2, o, e, ring, Up, U, H, X, Y, Hprev, bh, bx, oh, ox, tbs);
     if (s + 1 < nstrips) {
       // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
       const int jo = t0 + lane - 62;
@@ -261,73 +302,141 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
 }
 
 // ---------------------------------------------------------------- traceback
+// The path visits strips from the last to the first and, inside a strip,
+// steps t = j - 1 + l that decrease by one or two per op: a staged block of
+// 16 x 64 tie words in LDS serves about 30 ops before it is reloaded.
 struct Stage {
   int s, t4a;
 };
 
-__device__ inline uint32_t tb_fetch(const uint32_t* tbw, uint32_t* tbst, Stage& st, int stride_s,
-                                    int T4, int lane, int i, int j) {
-  const int s = (i - 1) >> 6, l = (i - 1) & 63, t = j - 1 + l, t4 = t >> 2;
-  if (s != st.s || t4 < st.t4a || t4 >= st.t4a + kStageT4) {
-    st.s = s;
-    st.t4a = max(0, t4 - (kStageT4 - 1));
-    __builtin_amdgcn_wave_barrier();
-    __threadfence_block();
+// Makes the staged block of strip s cover tie words t4lo..t4hi (t4hi - t4lo
+// < kStageT4); the block is placed with t4hi at its top because the path
+// moves towards smaller t.
+__device__ inline void stage_cover(const uint32_t* tbw, uint32_t* tbst, Stage& st, int stride_s,
+                                   int T4, int lane, int s, int t4lo, int t4hi) {
+  if (s == st.s && t4lo >= st.t4a && t4hi < st.t4a + kStageT4) return;
+  const int t4a = max(0, t4hi - (kStageT4 - 1));
+  __builtin_amdgcn_wave_barrier();
+  __threadfence_block();
+  // all loads in flight before the first LDS store (addresses clamped to the
+  // strip, out-of-strip words zeroed afterwards)
+  const uint32_t* base = tbw + (int64_t)s * stride_s + lane;
+  uint32_t v[kStageT4];
 #pragma unroll
-    for (int r = 0; r < kStageT4; ++r) {
-      const int tt = st.t4a + r;
-      tbst[r * 64 + lane] =
-          (tt < T4) ? load_l2(tbw + (int64_t)s * stride_s + (int64_t)tt * 64 + lane) : 0u;
-    }
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-  }
-  const uint32_t w = tbst[(t4 - st.t4a) * 64 + l];
-  return (w >> (8 * (t & 3))) & 0xffu;
+  for (int r = 0; r < kStageT4; ++r) v[r] = load_wg(base + (int64_t)min(t4a + r, T4 - 1) * 64);
+#pragma unroll
+  for (int r = 0; r < kStageT4; ++r) tbst[r * 64 + lane] = (t4a + r < T4) ? v[r] : 0u;
+  st.s = s;
+  st.t4a = t4a;
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
 }
 
-// Writes the op string to ops[cap - n .. cap) (lane 0 stores); returns n.
-__device__ int traceback(const uint32_t* tbw, uint32_t* tbst, uint8_t* ops, int W1, int W2,
-                         int nchunks, int lane) {
-  Stage st{-1, 0};
+// 8 x 8 window of tie bytes held one per lane: lane q is cell
+// (wi - q / 8, wj - q % 8), restricted to the strip of row wi.  The path is
+// followed with v_readlane instead of LDS round trips; the window is rebuilt
+// from the staged block when the path leaves it.
+struct Window {
+  int wi, wj, wlo;
+  uint32_t v;
+};
+
+__device__ inline void window_load(const uint32_t* tbw, uint32_t* tbst, Stage& st, Window& w,
+                                   int stride_s, int T4, int lane, int i, int j) {
+  const int s = (i - 1) >> 6;
+  const int lo = 64 * s + 1;
+  const int ilow = max(lo, i - 7);
+  const int t_hi = j - 1 + ((i - 1) & 63);
+  const int t_lo = max(0, j - 8) + ((ilow - 1) & 63);
+  stage_cover(tbw, tbst, st, stride_s, T4, lane, s, t_lo >> 2, t_hi >> 2);
+  w.wi = i;
+  w.wj = j;
+  w.wlo = lo;
+  const int ci = i - (lane >> 3), cj = j - (lane & 7);
+  uint32_t byte = 0;
+  if (ci >= lo && cj >= 1) {
+    const int l = (ci - 1) & 63, t = cj - 1 + l;
+    const uint32_t word = tbst[((t >> 2) - st.t4a) * 64 + l];
+    byte = (word >> (8 * (t & 3))) & 0xffu;
+  }
+  w.v = byte;
+}
+
+__device__ inline uint32_t window_get(const uint32_t* tbw, uint32_t* tbst, Stage& st, Window& w,
+                                      int stride_s, int T4, int lane, int i, int j) {
+  int di = w.wi - i, dj = w.wj - j;
+  if (di < 0 || di > 7 || dj < 0 || dj > 7 || i < w.wlo) {
+    window_load(tbw, tbst, st, w, stride_s, T4, lane, i, j);
+    di = 0;
+    dj = 0;
+  }
+  return (uint32_t)__builtin_amdgcn_readlane((int)w.v, di * 8 + dj);
+}
+
+// Ops are shifted into a register one per step (the newest in lane 63) and
+// stored 64 at a time; op q (q-th from the end) goes to ops[cap - 1 - q].
+struct OpSink {
+  int32_t v;
+  int k;
+};
+
+__device__ inline void op_emit(OpSink& o, uint8_t* ops, int cap, int lane, int op) {
+  o.v = __builtin_amdgcn_update_dpp(op, o.v, 0x130, 0xf, 0xf, false);
+  ++o.k;
+  if ((o.k & 63) == 0) ops[cap - 1 - (o.k - 64 + lane)] = (uint8_t)o.v;
+}
+
+__device__ inline void op_flush(OpSink& o, uint8_t* ops, int cap, int lane) {
+  const int r = o.k & 63;
+  if (r && lane >= 64 - r) ops[cap - 1 - (o.k - 64 + lane)] = (uint8_t)o.v;
+}
+
+// Writes the op string to ops[cap - n .. cap); returns n.  Whole wave.
+__device__ __forceinline__ int traceback(const uint32_t* tbw, uint32_t* tbst, uint8_t* ops, int W1,
+                                         int W2, int nchunks, int lane) {
+  Stage st;
+  st.s = -1;
+  st.t4a = 0;
+  Window w;
+  w.wi = -100;
+  w.wj = -100;
+  w.wlo = 0;
+  w.v = 0;
+  OpSink os{0, 0};
   const int stride_s = nchunks * 16 * 64, T4 = nchunks * 16;
   const int cap = W1 + W2;
-  int i = W1, j = W2, state = 0, k = 0;
+  int i = W1, j = W2, state = 0;
   while (i > 0 && j > 0) {
-    const uint32_t b = tb_fetch(tbw, tbst, st, stride_s, T4, lane, i, j);
+    const uint32_t b = window_get(tbw, tbst, st, w, stride_s, T4, lane, i, j);
     if (state == 0) {
       const uint32_t hc = b & 3u;
       if (hc == 0) {
-        if (lane == 0) ops[cap - 1 - k] = 0;
-        ++k;
+        op_emit(os, ops, cap, lane, 0);
         --i;
         --j;
       } else {
         state = (int)hc;
       }
     } else if (state == 1) {
-      if (lane == 0) ops[cap - 1 - k] = 1;
-      ++k;
+      op_emit(os, ops, cap, lane, 1);
       const uint32_t xc = (b >> 2) & 3u;  // 0 extend only, 1 both, 2 open only
       --i;
       bool pm = false;
-      if (i > 0) pm = (tb_fetch(tbw, tbst, st, stride_s, T4, lane, i, j) & 3u) == 0;
+      if (i > 0) pm = (window_get(tbw, tbst, st, w, stride_s, T4, lane, i, j) & 3u) == 0;
       state = (xc >= 1 && pm) ? 0 : (xc <= 1 ? 1 : 0);
     } else {
-      if (lane == 0) ops[cap - 1 - k] = 2;
-      ++k;
+      op_emit(os, ops, cap, lane, 2);
       const uint32_t yc = (b >> 4) & 3u;
       --j;
       bool pmx = false;
-      if (j > 0) pmx = (tb_fetch(tbw, tbst, st, stride_s, T4, lane, i, j) & 3u) <= 1u;
+      if (j > 0) pmx = (window_get(tbw, tbst, st, w, stride_s, T4, lane, i, j) & 3u) <= 1u;
       state = (yc >= 1 && pmx) ? 0 : (yc <= 1 ? 2 : 0);
     }
   }
-  for (; i > 0; --i, ++k)
-    if (lane == 0) ops[cap - 1 - k] = 1;
-  for (; j > 0; --j, ++k)
-    if (lane == 0) ops[cap - 1 - k] = 2;
-  return k;
+  for (; i > 0; --i) op_emit(os, ops, cap, lane, 1);
+  for (; j > 0; --j) op_emit(os, ops, cap, lane, 2);
+  op_flush(os, ops, cap, lane);
+  return os.k;
 }
 
 // ---------------------------------------------------------------- merge
@@ -402,9 +511,11 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   uint32_t* myring = ring + wave * kColRing * CW;
   __syncthreads();
 
+  uint64_t tk0 = 0, tk1 = 0, tk2 = 0, tk3 = 0, tk35 = 0;  // phase timestamps (thread 0)
   for (;;) {
     // ---- fetch a ready job (thread 0) and describe it to the workgroup
     if (tid == 0) {
+      tk0 = __builtin_amdgcn_s_memrealtime();
       const int slot = atomicAdd(a.queue_head, 1);
       J.slot = slot;
       J.job = -1;
@@ -488,6 +599,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
     __syncthreads();
     const int job = J.job;
     if (job < 0) break;
+    if (tid == 0) tk1 = __builtin_amdgcn_s_memrealtime();
     const int na = J.na, nb = J.nb, out = J.out;
     const int W1 = J.W1, W2 = J.W2;
     const uint16_t* P1 = a.prof_pool + a.node_prof[na];
@@ -500,8 +612,13 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       for (int L = tid; L < kMaxStrips; L += kThreads) prog[L] = 0;
       __syncthreads();
       if (W1 > 0 && W2 > 0) {
-        for (int s = wave; s < J.nstrips; s += kWaves)
-          if (!dp_strip<A>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2)) break;
+        if (J.packed) {
+          for (int s = wave; s < J.nstrips; s += kWaves)
+            if (!dp_strip<A, true>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2)) break;
+        } else {
+          for (int s = wave; s < J.nstrips; s += kWaves)
+            if (!dp_strip<A, false>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2)) break;
+        }
       }
       __builtin_amdgcn_s_waitcnt(0);  // tie bytes stored before the barrier
       __threadfence_block();
@@ -511,12 +628,14 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         __syncthreads();
       }
     }
+    if (tid == 0) tk2 = __builtin_amdgcn_s_memrealtime();
     if (!J.err) {
       if (wave == 0) {
         const int n = traceback(tbw, tbst, ops, W1, W2, J.nchunks, lane);
         if (lane == 0) J.nops = n;
       }
       __syncthreads();
+      if (tid == 0) tk3 = __builtin_amdgcn_s_memrealtime();
       const int nops = J.nops;
       const int base = W1 + W2 - nops;
       // jobs that export their op string (refinement) leave the column maps
@@ -553,8 +672,20 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         a.job_cells[job] = (int64_t)W1 * W2;
       }
     }
+    __syncthreads();
+    if (tid == 0) tk35 = __builtin_amdgcn_s_memrealtime();
     __threadfence();
     __syncthreads();
+    if (tid == 0 && a.phase_acc) {
+      const uint64_t tk4 = __builtin_amdgcn_s_memrealtime();
+      if (tk3 < tk2) tk3 = tk2;
+      atomicAdd(&a.phase_acc[0], (unsigned long long)(tk1 - tk0));
+      atomicAdd(&a.phase_acc[1], (unsigned long long)(tk2 - tk1));
+      atomicAdd(&a.phase_acc[2], (unsigned long long)(tk3 - tk2));
+      atomicAdd(&a.phase_acc[3], (unsigned long long)(tk35 - tk3));
+      atomicAdd(&a.phase_acc[4], 1ull);
+      atomicAdd(&a.phase_acc[5], (unsigned long long)(tk4 - tk35));
+    }
     if (tid == 0) {
       const int nx = a.job_next[job];
       if (nx >= 0) {
@@ -573,12 +704,17 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
 }
 
 int engine_workgroups() {
+  int per_cu = kEngineWGPerCU;
+  if (const char* env = getenv("SAD_ENGINE_WGS_PER_CU")) {
+    const int v = atoi(env);
+    if (v >= 1 && v <= 8) per_cu = v;
+  }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
   if (cus <= 0) cus = 256;
-  return cus * kEngineWGPerCU;
+  return cus * per_cu;
 }
 
 void launch_engine(const EngineArgs& a, int nwg, hipStream_t stream) {

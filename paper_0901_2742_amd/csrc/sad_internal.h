@@ -16,6 +16,7 @@ namespace sad {
 constexpr int kMaxLen = 8192;        // longest accepted sequence
 constexpr int kMaxWidth = 4096;      // widest profile a DP accepts
 constexpr int kMaxAlpha = 20;
+constexpr int kMaxGroup = 8000;      // largest bucket (UPGMA keeps 5 ints per member in LDS)
 constexpr int32_t kNeg32 = -(1 << 30);  // "minus infinity" of the 32-bit DP
 
 // ------------------------------------------------------------------ device status
@@ -145,6 +146,7 @@ struct EngineArgs {
   int32_t smax;           // max |S|
   uint32_t mode;
   int64_t wait_ticks;     // queue wait limit in s_memrealtime ticks
+  unsigned long long* phase_acc;  // optional: ticks in queue wait, DP, traceback, merge; jobs
   DevStatus* st;
 };
 void launch_engine(const EngineArgs& a, int nwg, hipStream_t stream);
