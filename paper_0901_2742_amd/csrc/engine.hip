@@ -332,6 +332,28 @@ __device__ inline void stage_cover(const uint32_t* tbw, uint32_t* tbst, Stage& s
   __builtin_amdgcn_wave_barrier();
 }
 
+// The traceback enters a cell in one of 7 states: 0 = H, 1 + c = after an X
+// op whose cell had open/extend code c, 4 + c = after a Y op likewise.  The op
+// taken at the cell depends only on the state and the cell's tie byte:
+//   after X: H if the run was opened (c >= 1) and M attains H here, else X if
+//            it could be extended (c <= 1), else H;
+//   after Y: H if opened and M or X attains H here, else Y if extendable, else H;
+//   in H: the smallest op attaining H.
+// op_table packs the 7 ops (2 bits each) and the cell's X and Y codes (bits
+// 14-15, 16-17) so the walk needs one v_readlane per op.
+__device__ inline uint32_t op_table(uint32_t b) {
+  const uint32_t hc = b & 3u, xc = (b >> 2) & 3u, yc = (b >> 4) & 3u;
+  uint32_t t = hc;
+#pragma unroll
+  for (uint32_t c = 0; c < 3; ++c) {
+    const uint32_t ox = (c >= 1u && hc == 0u) ? hc : (c <= 1u ? 1u : hc);
+    const uint32_t oy = (c >= 1u && hc <= 1u) ? hc : (c <= 1u ? 2u : hc);
+    t |= ox << (2 * (1 + c));
+    t |= oy << (2 * (4 + c));
+  }
+  return t | (xc << 14) | (yc << 16);
+}
+
 // 8 x 8 window of tie bytes held one per lane: lane q is cell
 // (wi - q / 8, wj - q % 8), restricted to the strip of row wi.  The path is
 // followed with v_readlane instead of LDS round trips; the window is rebuilt
@@ -359,7 +381,7 @@ __device__ inline void window_load(const uint32_t* tbw, uint32_t* tbst, Stage& s
     const uint32_t word = tbst[((t >> 2) - st.t4a) * 64 + l];
     byte = (word >> (8 * (t & 3))) & 0xffu;
   }
-  w.v = byte;
+  w.v = op_table(byte);
 }
 
 __device__ inline uint32_t window_get(const uint32_t* tbw, uint32_t* tbst, Stage& st, Window& w,
@@ -405,33 +427,17 @@ __device__ __forceinline__ int traceback(const uint32_t* tbw, uint32_t* tbst, ui
   OpSink os{0, 0};
   const int stride_s = nchunks * 16 * 64, T4 = nchunks * 16;
   const int cap = W1 + W2;
-  int i = W1, j = W2, state = 0;
+  // One op per iteration: the entry state and the cell's packed op table give
+  // the op; the next entry state is H after M, or X/Y with this cell's code.
+  int i = W1, j = W2;
+  uint32_t state = 0;
   while (i > 0 && j > 0) {
-    const uint32_t b = window_get(tbw, tbst, st, w, stride_s, T4, lane, i, j);
-    if (state == 0) {
-      const uint32_t hc = b & 3u;
-      if (hc == 0) {
-        op_emit(os, ops, cap, lane, 0);
-        --i;
-        --j;
-      } else {
-        state = (int)hc;
-      }
-    } else if (state == 1) {
-      op_emit(os, ops, cap, lane, 1);
-      const uint32_t xc = (b >> 2) & 3u;  // 0 extend only, 1 both, 2 open only
-      --i;
-      bool pm = false;
-      if (i > 0) pm = (window_get(tbw, tbst, st, w, stride_s, T4, lane, i, j) & 3u) == 0;
-      state = (xc >= 1 && pm) ? 0 : (xc <= 1 ? 1 : 0);
-    } else {
-      op_emit(os, ops, cap, lane, 2);
-      const uint32_t yc = (b >> 4) & 3u;
-      --j;
-      bool pmx = false;
-      if (j > 0) pmx = (window_get(tbw, tbst, st, w, stride_s, T4, lane, i, j) & 3u) <= 1u;
-      state = (yc >= 1 && pmx) ? 0 : (yc <= 1 ? 2 : 0);
-    }
+    const uint32_t tab = window_get(tbw, tbst, st, w, stride_s, T4, lane, i, j);
+    const uint32_t op = (tab >> (2 * state)) & 3u;
+    op_emit(os, ops, cap, lane, (int)op);
+    state = (op == 0u) ? 0u : (op == 1u ? 1u + ((tab >> 14) & 3u) : 4u + ((tab >> 16) & 3u));
+    i -= (op != 2u);
+    j -= (op != 1u);
   }
   for (; i > 0; --i) op_emit(os, ops, cap, lane, 1);
   for (; j > 0; --j) op_emit(os, ops, cap, lane, 2);
