@@ -339,78 +339,44 @@ __device__ inline void stage_cover(const uint32_t* tbw, uint32_t* tbst, Stage& s
 //            it could be extended (c <= 1), else H;
 //   after Y: H if opened and M or X attains H here, else Y if extendable, else H;
 //   in H: the smallest op attaining H.
-// op_table packs the 7 ops (2 bits each) and the cell's X and Y codes (bits
-// 14-15, 16-17) so the walk needs one v_readlane per op.
-__device__ inline uint32_t op_table(uint32_t b) {
+// The state after the op determines the op (0: M, 1-3: X, 4-6: Y) and, with
+// the cell's X or Y code, the next entry state.  next_table packs, for each of
+// the 7 entry states, the next state in a 4-bit field, so one v_readlane and
+// one bit-field extract advance the walk by one op.
+__device__ inline uint32_t next_table(uint32_t b) {
   const uint32_t hc = b & 3u, xc = (b >> 2) & 3u, yc = (b >> 4) & 3u;
-  uint32_t t = hc;
+  const uint32_t nx = 1u + xc, ny = 4u + yc;
+  const uint32_t n0 = 0u, n1 = nx, n2 = ny;
+  const uint32_t nh = hc == 0u ? n0 : (hc == 1u ? n1 : n2);
+  uint32_t t = nh;
 #pragma unroll
   for (uint32_t c = 0; c < 3; ++c) {
-    const uint32_t ox = (c >= 1u && hc == 0u) ? hc : (c <= 1u ? 1u : hc);
+    const uint32_t ox = (c >= 1u && hc == 0u) ? 0u : (c <= 1u ? 1u : hc);
     const uint32_t oy = (c >= 1u && hc <= 1u) ? hc : (c <= 1u ? 2u : hc);
-    t |= ox << (2 * (1 + c));
-    t |= oy << (2 * (4 + c));
+    const uint32_t sx = ox == 0u ? n0 : (ox == 1u ? n1 : n2);
+    const uint32_t sy = oy == 0u ? n0 : (oy == 1u ? n1 : n2);
+    t |= sx << (4 * (1 + c));
+    t |= sy << (4 * (4 + c));
   }
-  return t | (xc << 14) | (yc << 16);
+  return t;
 }
 
-// 8 x 8 window of tie bytes held one per lane: lane q is cell
-// (wi - q / 8, wj - q % 8), restricted to the strip of row wi.  The path is
-// followed with v_readlane instead of LDS round trips; the window is rebuilt
-// from the staged block when the path leaves it.
-struct Window {
-  int wi, wj, wlo;
-  uint32_t v;
-};
+// Window step per next state: M moves (-1, -1), X (-1, 0), Y (0, -1); in the
+// window's lane numbering (lane q = cell (i - q / 8, j - q % 8)) that is +9,
+// +8 or +1.  One 4-bit field per state.
+constexpr uint32_t kWindowStep = 0x1118889u;
+// Ops per window: after at most 7 ops the offset (di, dj) is still below 8 in
+// both coordinates, so the lane index identifies it and no bound is checked.
+constexpr int kWindowOps = 7;
 
-__device__ inline void window_load(const uint32_t* tbw, uint32_t* tbst, Stage& st, Window& w,
-                                   int stride_s, int T4, int lane, int i, int j) {
-  const int s = (i - 1) >> 6;
-  const int lo = 64 * s + 1;
-  const int ilow = max(lo, i - 7);
-  const int t_hi = j - 1 + ((i - 1) & 63);
-  const int t_lo = max(0, j - 8) + ((ilow - 1) & 63);
-  stage_cover(tbw, tbst, st, stride_s, T4, lane, s, t_lo >> 2, t_hi >> 2);
-  w.wi = i;
-  w.wj = j;
-  w.wlo = lo;
-  const int ci = i - (lane >> 3), cj = j - (lane & 7);
-  uint32_t byte = 0;
-  if (ci >= lo && cj >= 1) {
-    const int l = (ci - 1) & 63, t = cj - 1 + l;
-    const uint32_t word = tbst[((t >> 2) - st.t4a) * 64 + l];
-    byte = (word >> (8 * (t & 3))) & 0xffu;
-  }
-  w.v = op_table(byte);
-}
+__device__ inline int state_op(int sg) { return sg == 0 ? 0 : (sg <= 3 ? 1 : 2); }
 
-__device__ inline uint32_t window_get(const uint32_t* tbw, uint32_t* tbst, Stage& st, Window& w,
-                                      int stride_s, int T4, int lane, int i, int j) {
-  int di = w.wi - i, dj = w.wj - j;
-  if (di < 0 || di > 7 || dj < 0 || dj > 7 || i < w.wlo) {
-    window_load(tbw, tbst, st, w, stride_s, T4, lane, i, j);
-    di = 0;
-    dj = 0;
-  }
-  return (uint32_t)__builtin_amdgcn_readlane((int)w.v, di * 8 + dj);
-}
-
-// Ops are shifted into a register one per step (the newest in lane 63) and
-// stored 64 at a time; op q (q-th from the end) goes to ops[cap - 1 - q].
-struct OpSink {
-  int32_t v;
-  int k;
-};
-
-__device__ inline void op_emit(OpSink& o, uint8_t* ops, int cap, int lane, int op) {
-  o.v = __builtin_amdgcn_update_dpp(op, o.v, 0x130, 0xf, 0xf, false);
-  ++o.k;
-  if ((o.k & 63) == 0) ops[cap - 1 - (o.k - 64 + lane)] = (uint8_t)o.v;
-}
-
-__device__ inline void op_flush(OpSink& o, uint8_t* ops, int cap, int lane) {
-  const int r = o.k & 63;
-  if (r && lane >= 64 - r) ops[cap - 1 - (o.k - 64 + lane)] = (uint8_t)o.v;
+// Entry states are shifted into a register one per op (the newest in lane 63)
+// and stored as ops when 56 or more are pending: the q-th op from the end goes
+// to ops[cap - 1 - q].
+__device__ inline void ops_store(uint8_t* ops, int cap, int lane, int32_t acc, int k, int kst) {
+  const int pend = k - kst;
+  if (lane >= 64 - pend) ops[cap - 1 - (k - 64 + lane)] = (uint8_t)state_op(acc);
 }
 
 // Writes the op string to ops[cap - n .. cap); returns n.  Whole wave.
@@ -419,83 +385,156 @@ __device__ __forceinline__ int traceback(const uint32_t* tbw, uint32_t* tbst, ui
   Stage st;
   st.s = -1;
   st.t4a = 0;
-  Window w;
-  w.wi = -100;
-  w.wj = -100;
-  w.wlo = 0;
-  w.v = 0;
-  OpSink os{0, 0};
   const int stride_s = nchunks * 16 * 64, T4 = nchunks * 16;
   const int cap = W1 + W2;
-  // One op per iteration: the entry state and the cell's packed op table give
-  // the op; the next entry state is H after M, or X/Y with this cell's code.
+  int32_t acc = 0;
+  int k = 0, kst = 0;
   int i = W1, j = W2;
-  uint32_t state = 0;
+  int sg = 0;
+  const int qi = lane >> 3, qj = lane & 7;
   while (i > 0 && j > 0) {
-    const uint32_t tab = window_get(tbw, tbst, st, w, stride_s, T4, lane, i, j);
-    const uint32_t op = (tab >> (2 * state)) & 3u;
-    op_emit(os, ops, cap, lane, (int)op);
-    state = (op == 0u) ? 0u : (op == 1u ? 1u + ((tab >> 14) & 3u) : 4u + ((tab >> 16) & 3u));
-    i -= (op != 2u);
-    j -= (op != 1u);
+    // window of the cells (i - qi, j - qj) of this strip, from the staged block
+    const int s = (i - 1) >> 6;
+    const int lo = 64 * s + 1, l = (i - 1) & 63;
+    const int ilow = max(lo, i - 7);
+    const int t_hi = j - 1 + l;
+    const int t_lo = max(0, j - 8) + ((ilow - 1) & 63);
+    stage_cover(tbw, tbst, st, stride_s, T4, lane, s, t_lo >> 2, t_hi >> 2);
+    const int ci = i - qi, cj = j - qj;
+    uint32_t byte = 0;
+    if (ci >= lo && cj >= 1) {
+      const int lc = (ci - 1) & 63, t = cj - 1 + lc;
+      const uint32_t word = tbst[((t >> 2) - st.t4a) * 64 + lc];
+      byte = (word >> (8 * (t & 3))) & 0xffu;
+    }
+    const int32_t v = (int32_t)next_table(byte);
+    if (k - kst > 64 - kWindowOps) {
+      ops_store(ops, cap, lane, acc, k, kst);
+      kst = k;
+    }
+    // the window's cells outside the strip or left of column 1 are never
+    // reached: at most l + 1 row steps and j column steps
+    const int n = min(kWindowOps, min(l + 1, j));
+    int idx = 0;
+    for (int r = 0; r < n; ++r) {
+      const uint32_t tab = (uint32_t)__builtin_amdgcn_readlane(v, idx);
+      sg = (int)((tab >> (4 * sg)) & 7u);
+      idx += (int)((kWindowStep >> (4 * sg)) & 15u);
+      acc = __builtin_amdgcn_update_dpp(sg, acc, 0x130, 0xf, 0xf, false);
+    }
+    k += n;
+    i -= idx >> 3;
+    j -= idx & 7;
   }
-  for (; i > 0; --i) op_emit(os, ops, cap, lane, 1);
-  for (; j > 0; --j) op_emit(os, ops, cap, lane, 2);
-  op_flush(os, ops, cap, lane);
-  return os.k;
+  for (; i > 0; --i) {
+    if (k - kst == 64) {
+      ops_store(ops, cap, lane, acc, k, kst);
+      kst = k;
+    }
+    acc = __builtin_amdgcn_update_dpp(1, acc, 0x130, 0xf, 0xf, false);
+    ++k;
+  }
+  for (; j > 0; --j) {
+    if (k - kst == 64) {
+      ops_store(ops, cap, lane, acc, k, kst);
+      kst = k;
+    }
+    acc = __builtin_amdgcn_update_dpp(4, acc, 0x130, 0xf, 0xf, false);
+    ++k;
+  }
+  ops_store(ops, cap, lane, acc, k, kst);
+  return k;
 }
 
 // ---------------------------------------------------------------- merge
+// Column q of the new profile is P1[ii] + P2[jj] (the parts its op consumes),
+// where ii and jj count the earlier ops that consume a P1 / P2 column.  The
+// counts come from one ballot per 64 ops and a scan over those groups; then
+// each lane writes one whole column (rows are 8-byte aligned: A u16 counts
+// at a multiple of A elements, A in {4, 20}).
+template <int A>
+struct MergeRow {
+  static constexpr int NW = A / 4;  // uint2 words per column
+  uint2 a[NW], b[NW];
+  int q, ii, jj;
+  bool c1, c2;
+};
+
+template <int A>
+__device__ inline void merge_load(MergeRow<A>& r, const uint8_t* ops, int base, int nops, int g,
+                                  const int32_t* gcnt, const uint2* __restrict__ P1,
+                                  const uint2* __restrict__ P2, int lane) {
+  constexpr int NW = MergeRow<A>::NW;
+  r.q = 64 * g + lane;
+  const bool in = r.q < nops;
+  const int op = in ? ops[base + r.q] : 3;
+  r.c1 = in && op != 2;
+  r.c2 = in && op != 1;
+  const uint64_t b1 = __ballot(r.c1), b2 = __ballot(r.c2);
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int pre = gcnt[g];
+  r.ii = (pre & 0xffff) + __popcll(b1 & below);
+  r.jj = (pre >> 16) + __popcll(b2 & below);
+#pragma unroll
+  for (int m = 0; m < NW; ++m) {
+    r.a[m] = r.c1 ? P1[(int64_t)r.ii * NW + m] : make_uint2(0u, 0u);
+    r.b[m] = r.c2 ? P2[(int64_t)r.jj * NW + m] : make_uint2(0u, 0u);
+  }
+}
+
+template <int A>
+__device__ inline void merge_store(const MergeRow<A>& r, int nops, uint2* __restrict__ Pout,
+                                   int32_t* up1, int32_t* up2) {
+  constexpr int NW = MergeRow<A>::NW;
+  if (r.q < nops) {
+    // counts add per 16-bit half without carries (n1 + n2 < 65536)
+#pragma unroll
+    for (int m = 0; m < NW; ++m)
+      Pout[(int64_t)r.q * NW + m] = make_uint2(r.a[m].x + r.b[m].x, r.a[m].y + r.b[m].y);
+  }
+  if (r.c1 && up1) up1[r.ii] = r.q;
+  if (r.c2 && up2) up2[r.jj] = r.q;
+}
+
 template <int A>
 __device__ void merge(const uint8_t* ops, int base, int nops, const uint16_t* P1,
                       const uint16_t* P2, uint16_t* Pout, int32_t* up1, int32_t* up2,
-                      int32_t* wsum) {
+                      int32_t* gcnt) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int per = (nops + kThreads - 1) / kThreads;
-  const int s0 = min(nops, tid * per), s1 = min(nops, s0 + per);
-  int ci = 0, cj = 0;
-  for (int q = s0; q < s1; ++q) {
-    const uint8_t op = ops[base + q];
-    ci += (op != 2);
-    cj += (op != 1);
-  }
-  // exclusive scan of (ci, cj) over the workgroup
-  int ii = ci, jj = cj;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int vi = __shfl_up(ii, d, 64), vj = __shfl_up(jj, d, 64);
-    if (lane >= d) {
-      ii += vi;
-      jj += vj;
-    }
-  }
-  if (lane == 63) {
-    wsum[2 * wave] = ii;
-    wsum[2 * wave + 1] = jj;
+  const int ng = (nops + 63) >> 6;
+  for (int g = wave; g < ng; g += kWaves) {
+    const int q = 64 * g + lane;
+    const int op = q < nops ? ops[base + q] : 3;
+    const uint64_t b1 = __ballot(q < nops && op != 2), b2 = __ballot(q < nops && op != 1);
+    if (lane == 0) gcnt[g] = __popcll(b1) | (__popcll(b2) << 16);
   }
   __syncthreads();
-  for (int w = 0; w < wave; ++w) {
-    ii += wsum[2 * w];
-    jj += wsum[2 * w + 1];
+  if (wave == 0) {
+    // exclusive scan of the packed (P1, P2) counts; halves stay below 2^16
+    int carry = 0;
+    for (int g0 = 0; g0 < ng; g0 += 64) {
+      const int g = g0 + lane;
+      const int v = g < ng ? gcnt[g] : 0;
+      int x = v;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      if (g < ng) gcnt[g] = carry + x - v;
+      carry += __shfl(x, 63, 64);
+    }
   }
-  ii -= ci;
-  jj -= cj;
-  for (int q = s0; q < s1; ++q) {
-    const uint8_t op = ops[base + q];
-#pragma unroll
-    for (int b = 0; b < A; ++b) {
-      uint32_t v = 0;
-      if (op != 2) v += P1[(int64_t)ii * A + b];
-      if (op != 1) v += P2[(int64_t)jj * A + b];
-      Pout[(int64_t)q * A + b] = (uint16_t)v;
-    }
-    if (op != 2) {
-      if (up1) up1[ii] = q;
-      ++ii;
-    }
-    if (op != 1) {
-      if (up2) up2[jj] = q;
-      ++jj;
-    }
+  __syncthreads();
+  const uint2* p1 = reinterpret_cast<const uint2*>(P1);
+  const uint2* p2 = reinterpret_cast<const uint2*>(P2);
+  uint2* po = reinterpret_cast<uint2*>(Pout);
+  for (int g = wave; g < ng; g += 2 * kWaves) {
+    MergeRow<A> r0, r1;
+    merge_load<A>(r0, ops, base, nops, g, gcnt, p1, p2, lane);
+    const bool two = g + kWaves < ng;
+    if (two) merge_load<A>(r1, ops, base, nops, g + kWaves, gcnt, p1, p2, lane);
+    merge_store<A>(r0, nops, po, up1, up2);
+    if (two) merge_store<A>(r1, nops, po, up1, up2);
   }
 }
 
@@ -508,7 +547,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   __shared__ uint8_t ops[2 * kMaxWidth];
   __shared__ int32_t Ssh[A * A];
   __shared__ int32_t prog[kMaxStrips];
-  __shared__ int32_t wsum[2 * kWaves];
+  __shared__ int32_t gcnt[2 * kMaxWidth / 64];
   __shared__ JobInfo J;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int q = tid; q < A * A; q += kThreads) Ssh[q] = a.S[q];
@@ -647,7 +686,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       // jobs that export their op string (refinement) leave the column maps
       // alone: several of them share the same second node
       merge<A>(ops, base, nops, P1, P2, a.prof_pool + J.prof_off, oo >= 0 ? nullptr : up1,
-               oo >= 0 ? nullptr : up2, wsum);
+               oo >= 0 ? nullptr : up2, gcnt);
       if (oo >= 0)
         for (int q = tid; q < nops; q += kThreads) a.ops_out[oo + q] = ops[base + q];
       if (tid == 0) {
