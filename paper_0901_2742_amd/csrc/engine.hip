@@ -81,6 +81,7 @@ struct JobInfo {
   int32_t err, abort, packed;
   int32_t nstrips, nchunks;
   int32_t final_score, nops;
+  int32_t nd_u, nd_c;  // digits of U and of the counts in the MFMA tile products
   long long prof_off, up_off;
 };
 
@@ -103,14 +104,13 @@ __device__ inline bool wait_link(const EngineArgs& a, JobInfo& J, const int32_t*
 }
 
 // 64 DP steps of one strip.  MASK: some cells of the chunk lie outside
-// 1 <= j <= W2 and must leave H/X/Y untouched.
-template <int A, bool PACK, bool MASK>
-__device__ inline void dp_chunk(int t0, int lane, int W2, int32_t o, int32_t e,
-                                const uint32_t* ring, const uint32_t* Up, const int32_t* U,
-                                int32_t& H, int32_t& X, int32_t& Y, int32_t& Hprev,
-                                int32_t bhv, int32_t bxv, int32_t& oh, int32_t& ox,
-                                uint32_t* tbs) {
-  constexpr int CW = ColWords<A>::value;
+// 1 <= j <= W2 and must leave H/X/Y untouched.  score(k, j) gives s(i, j) of
+// this lane's row at step k.
+template <bool MASK, typename Score>
+__device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, int32_t o, int32_t e,
+                                         Score&& score, int32_t& H, int32_t& X, int32_t& Y,
+                                         int32_t& Hprev, int32_t bhv, int32_t bxv, int32_t& oh,
+                                         int32_t& ox, uint32_t (&tw)[16]) {
   uint32_t word = 0;
 #pragma unroll
   for (int k = 0; k < 64; ++k) {
@@ -121,6 +121,43 @@ __device__ inline void dp_chunk(int t0, int lane, int W2, int32_t o, int32_t e,
     bxv = shl1(bxv, bxv);
     const int32_t Hdiag = Hprev;
     Hprev = Hup;
+    const int32_t sc = score(k, j);
+    const int32_t M = Hdiag + sc;
+    const int32_t xo = Hup - o, xe = Xup - e;
+    const int32_t Xn = max(xo, xe);
+    const int32_t yo = H - o, ye = Y - e;
+    const int32_t Yn = max(yo, ye);
+    const int32_t t2 = max(Xn, Yn);
+    const int32_t Hn = max(M, t2);
+    const uint32_t hc = (M >= t2) ? 0u : ((Xn >= Yn) ? 1u : 2u);
+    // 0 extend only, 1 both, 2 open only (stored as sign + 1)
+    const uint32_t xc = (uint32_t)(sign3(xo - xe) + 1);
+    const uint32_t yc = (uint32_t)(sign3(yo - ye) + 1);
+    const uint32_t bits = hc | (xc << 2) | (yc << 4);
+    if (!MASK || (j >= 1 && j <= W2)) {
+      H = Hn;
+      X = Xn;
+      Y = Yn;
+    }
+    word |= bits << (8 * (k & 3));
+    if ((k & 3) == 3) {
+      tw[k >> 2] = word;
+      word = 0;
+    }
+    oh = shl1(H, oh);
+    ox = shl1(X, ox);
+  }
+}
+
+// Column score from a P2 column staged in the wave's LDS ring: packed 16-bit
+// dot products (PACK) or 32-bit products.
+template <int A, bool PACK>
+struct RingScore {
+  const uint32_t* ring;
+  const uint32_t* Up;
+  const int32_t* U;
+  __device__ __forceinline__ int32_t operator()(int, int j) const {
+    constexpr int CW = ColWords<A>::value;
     const uint32_t* col = ring + ((j - 1) & (kColRing - 1)) * CW;
     int32_t sc = 0;
     if constexpr (PACK) {
@@ -150,32 +187,9 @@ __device__ inline void dp_chunk(int t0, int lane, int W2, int32_t o, int32_t e,
         if (2 * m + 1 < A) sc += U[2 * m + 1] * (int32_t)(w >> 16);
       }
     }
-    const int32_t M = Hdiag + sc;
-    const int32_t xo = Hup - o, xe = Xup - e;
-    const int32_t Xn = max(xo, xe);
-    const int32_t yo = H - o, ye = Y - e;
-    const int32_t Yn = max(yo, ye);
-    const int32_t t2 = max(Xn, Yn);
-    const int32_t Hn = max(M, t2);
-    const uint32_t hc = (M >= t2) ? 0u : ((Xn >= Yn) ? 1u : 2u);
-    // 0 extend only, 1 both, 2 open only (stored as sign + 1)
-    const uint32_t xc = (uint32_t)(sign3(xo - xe) + 1);
-    const uint32_t yc = (uint32_t)(sign3(yo - ye) + 1);
-    const uint32_t bits = hc | (xc << 2) | (yc << 4);
-    if (!MASK || (j >= 1 && j <= W2)) {
-      H = Hn;
-      X = Xn;
-      Y = Yn;
-    }
-    word |= bits << (8 * (k & 3));
-    if ((k & 3) == 3) {
-      tbs[((t0 + k) >> 2) * 64 + lane] = word;
-      word = 0;
-    }
-    oh = shl1(H, oh);
-    ox = shl1(X, ox);
+    return sc;
   }
-}
+};
 
 // One strip of the DP (run by one wave).  Returns false if the job aborted.
 // PACK: U fits in 16 bits, so column scores use packed dot products.
@@ -281,10 +295,12 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
     if (c + 1 < nchunks) prefetch(c + 1, false);
     int32_t oh = 0, ox = 0;
     const bool mask = (c == 0) || (t0 + 64 > W2);
+    const RingScore<A, PACK> score{ring, Up, U};
+    uint32_t tw[16];
     if (mask)
-      dp_chunk<A, PACK, true>(t0, lane, W2, o, e, ring, Up, U, H, X, Y, Hprev, bh, bx, oh, ox, tbs);
+      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
     else
-      dp_chunk<A, PACK, false>(t0, lane, W2, o, e, ring, Up, U, H, X, Y, Hprev, bh, bx, oh, ox, tbs);
+      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
     if (s + 1 < nstrips) {
       // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
       const int jo = t0 + lane - 62;
@@ -296,6 +312,259 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
       __builtin_amdgcn_s_waitcnt(0);  // the link stores have reached L2
       __hip_atomic_store(&prog[s], done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    // tie words after the release, so that the wait above covers only the
+    // link stores (and this chunk's loads)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tbs[(t0 / 4 + q) * 64 + lane] = tw[q];
+  }
+  if (s == ((W1 - 1) >> 6) && lane == ((W1 - 1) & 63)) J.final_score = H;
+  return true;
+}
+
+// ------------------------------------------------- DP strip, MFMA column scores
+// The scores of a 64 x 64 tile (this strip's rows, 64 columns of P2) are one
+// int8 matrix product on the matrix cores: s = U C2^T with U = C1 S.  U is
+// split into signed base-256 digits and the counts into base-128 digits, so
+// every partial product is exact in int32 and s = sum 2^(8a + 7b) U_a C2_b^T
+// (mod 2^32, where s itself fits).  The tile is stored in a per-wave LDS ring
+// skewed along anti-diagonals: cell (row l, column j) sits in row l at slot
+// (l + j - 1) mod 128, so the scores lane l needs during one chunk are 64
+// consecutive words of its row.  Tile c is written before chunk c; chunk c
+// reads tile c for k >= l and tile c - 1 otherwise (its slots were written one
+// chunk earlier and are not overwritten until chunk c + 1).
+constexpr int kScPitch = 129;             // words per ring row (odd: no bank conflicts)
+constexpr int kScWords = 64 * kScPitch;   // per wave
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned v16u __attribute__((ext_vector_type(16)));
+
+template <int A>
+struct Tile {
+  static constexpr int KS = A > 16 ? 2 : 1;  // 16-deep K steps (K padded to 16 KS)
+};
+
+__device__ inline long pack_bytes8(const int32_t (&v)[8]) {
+  uint32_t lo = 0, hi = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    lo |= ((uint32_t)v[e] & 0xffu) << (8 * e);
+    hi |= ((uint32_t)v[4 + e] & 0xffu) << (8 * e);
+  }
+  return (long)(((uint64_t)hi << 32) | lo);
+}
+
+// 8 counts held as four packed u16 pairs -> 8 bytes (bytes 0 and 2 of each word)
+__device__ inline long pack_counts8(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+  const uint32_t lo = __builtin_amdgcn_perm(w1, w0, 0x06040200u);
+  const uint32_t hi = __builtin_amdgcn_perm(w3, w2, 0x06040200u);
+  return (long)(((uint64_t)hi << 32) | lo);
+}
+
+// Raw counts of tile columns for this lane's MFMA B operand: column
+// 64 c + 32 cb + (lane & 31), counts 16 ks + 8 h + 0..7 (h = lane / 32).
+template <int A>
+__device__ inline void tile_load_counts(uint32_t (&bw)[2][Tile<A>::KS][4], const uint16_t* P2,
+                                        int W2, int c, int lane) {
+  const int n = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int col = 64 * c + 32 * cb + n;
+    const bool ok = col < W2;
+    const uint2* src = reinterpret_cast<const uint2*>(P2 + (int64_t)(ok ? col : 0) * A);
+#pragma unroll
+    for (int ks = 0; ks < Tile<A>::KS; ++ks) {
+      // words [8 ks + 4 h, +4) of the column, where they exist
+      const int w0 = 8 * ks + 4 * h;
+      uint2 x = make_uint2(0u, 0u), y = make_uint2(0u, 0u);
+      if (ok && 2 * w0 < A) x = src[w0 / 2];
+      if (ok && 2 * w0 + 4 < A) y = src[w0 / 2 + 1];
+      bw[cb][ks][0] = x.x;
+      bw[cb][ks][1] = x.y;
+      bw[cb][ks][2] = y.x;
+      bw[cb][ks][3] = y.y;
+    }
+  }
+}
+
+// Computes tile c and stores it in the wave's score ring.
+template <int A>
+__device__ inline void tile_scores(const long (&ua)[3][2][Tile<A>::KS],
+                                   const uint32_t (&bw)[2][Tile<A>::KS][4], int nd_u, int nd_c,
+                                   uint32_t* ring, int c, int lane) {
+  constexpr int KS = Tile<A>::KS;
+  const int n = lane & 31, h = lane >> 5;
+  long bd[3][2][KS];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const uint32_t* w = bw[cb][ks];
+      bd[0][cb][ks] = pack_counts8(w[0] & 0x007f007fu, w[1] & 0x007f007fu, w[2] & 0x007f007fu,
+                                   w[3] & 0x007f007fu);
+      bd[1][cb][ks] = pack_counts8((w[0] >> 7) & 0x007f007fu, (w[1] >> 7) & 0x007f007fu,
+                                   (w[2] >> 7) & 0x007f007fu, (w[3] >> 7) & 0x007f007fu);
+      bd[2][cb][ks] = pack_counts8((w[0] >> 14) & 0x00030003u, (w[1] >> 14) & 0x00030003u,
+                                   (w[2] >> 14) & 0x00030003u, (w[3] >> 14) & 0x00030003u);
+    }
+  const int base = 64 * (c & 1);
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      v16u tot = {};
+#pragma unroll
+      for (int ad = 0; ad < 3; ++ad)
+#pragma unroll
+        for (int bdg = 0; bdg < 3; ++bdg) {
+          if (ad >= nd_u || bdg >= nd_c) continue;
+          v16i acc = {};
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks)
+            acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(ua[ad][rb][ks], bd[bdg][cb][ks], acc, 0, 0,
+                                                         0);
+          tot += __builtin_bit_cast(v16u, acc) << (uint32_t)(8 * ad + 7 * bdg);
+        }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * rb + (r & 3) + 8 * (r >> 2) + 4 * h;
+        const int slot = (base + row + 32 * cb + n) & 127;
+        ring[row * kScPitch + slot] = tot[r];
+      }
+    }
+}
+
+// One strip with MFMA tile scores (run by one wave).  Returns false if the
+// job aborted.
+template <int A>
+__device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
+                              int32_t* prog, uint32_t* tbw, int32_t* links, const int32_t* S32,
+                              const uint16_t* P1, const uint16_t* P2) {
+  constexpr int KS = Tile<A>::KS;
+  const int W1 = J.W1, W2 = J.W2, nchunks = J.nchunks, nstrips = J.nstrips;
+  const int nd_u = J.nd_u, nd_c = J.nd_c;
+  const int32_t o = J.o, e = J.e;
+  const int i = 64 * s + lane + 1;
+  const int ie = min(i, W1);
+  // A operands: U rows 64 s + 32 rb + (lane & 31), K entries 16 ks + 8 h + 0..7,
+  // as signed base-256 digits
+  long ua[3][2][KS];
+  {
+    const int m = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const int row = 64 * s + 32 * rb + m;
+      const bool ok = row < W1;
+      const uint16_t* crow = P1 + (int64_t)(ok ? row : 0) * A;
+      int32_t u[KS][8];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) u[ks][q] = 0;
+#pragma unroll 1
+      for (int q = 0; q < A; ++q) {
+        const int32_t cq = ok ? (int32_t)crow[q] : 0;
+        const int32_t* Sq = S32 + q * 32 + 8 * h;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int x = 0; x < 8; ++x) u[ks][x] += cq * Sq[16 * ks + x];
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        int32_t d0[8], d1[8], d2[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+          const int32_t v = u[ks][x];
+          const int32_t a0 = (int32_t)((uint32_t)v << 24) >> 24;
+          const int32_t v1 = (v - a0) >> 8;
+          const int32_t a1 = (int32_t)((uint32_t)v1 << 24) >> 24;
+          d0[x] = a0;
+          d1[x] = a1;
+          d2[x] = (v1 - a1) >> 8;
+        }
+        ua[0][rb][ks] = pack_bytes8(d0);
+        ua[1][rb][ks] = pack_bytes8(d1);
+        ua[2][rb][ks] = pack_bytes8(d2);
+      }
+    }
+  }
+  int32_t H = -(o + (ie - 1) * e);
+  int32_t X = kNeg32, Y = kNeg32;
+  int32_t Hprev = (s == 0) ? 0 : -(o + (64 * s - 1) * e);
+  uint32_t* tbs = tbw + (int64_t)s * nchunks * 16 * 64;
+  const int stride = a.link_stride;
+  const int32_t* inH = links + (int64_t)(s - 1) * 2 * stride;
+  const int32_t* inX = inH + stride;
+  int32_t* outH = links + (int64_t)s * 2 * stride;
+  int32_t* outX = outH + stride;
+  const int ntiles = (W2 + 63) >> 6;
+  uint32_t bw[2][KS][4];
+  int32_t pbh = 0, pbx = kNeg32;
+  bool have_link = (s == 0);
+  auto link_fetch = [&](int c, bool block) -> bool {
+    const int jn = 64 * c + 1 + lane;
+    if (s == 0) {
+      pbh = jn <= W2 ? -(o + (jn - 1) * e) : 0;
+      pbx = kNeg32;
+      have_link = true;
+      return true;
+    }
+    const int need = min(W2, 64 * c + 64);
+    if (block) {
+      if (!wait_link(a, J, prog, s - 1, need)) return false;
+    } else if (__hip_atomic_load(&prog[s - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <
+               need) {
+      have_link = false;
+      return true;
+    }
+    if (jn <= W2) {
+      pbh = load_wg(inH + jn);
+      pbx = load_wg(inX + jn);
+    }
+    have_link = true;
+    return true;
+  };
+  tile_load_counts<A>(bw, P2, W2, 0, lane);
+  if (!link_fetch(0, true)) return false;
+  for (int c = 0; c < nchunks; ++c) {
+    const int t0 = 64 * c;
+    const int jn = t0 + 1 + lane;
+    if (!have_link) {
+      if (!wait_link(a, J, prog, s - 1, min(W2, t0 + 64))) return false;
+      if (jn <= W2) {
+        pbh = load_wg(inH + jn);
+        pbx = load_wg(inX + jn);
+      }
+    }
+    const int32_t bh = pbh, bx = pbx;
+    if (c < ntiles) tile_scores<A>(ua, bw, nd_u, nd_c, ring, c, lane);
+    int32_t scv[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) scv[k] = (int32_t)ring[lane * kScPitch + (t0 & 127) + k];
+    if (c + 1 < ntiles) tile_load_counts<A>(bw, P2, W2, c + 1, lane);
+    if (c + 1 < nchunks) link_fetch(c + 1, false);
+    int32_t oh = 0, ox = 0;
+    const bool mask = (c == 0) || (t0 + 64 > W2);
+    auto score = [&](int k, int) -> int32_t { return scv[k]; };
+    uint32_t tw[16];
+    if (mask)
+      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+    else
+      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+    if (s + 1 < nstrips) {
+      // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
+      const int jo = t0 + lane - 62;
+      if (jo >= 1 && jo <= W2) {
+        outH[jo] = oh;
+        outX[jo] = ox;
+      }
+      const int done = (c + 1 == nchunks) ? W2 : min(W2, t0 + 1);
+      __builtin_amdgcn_s_waitcnt(0);  // the link stores have reached L2
+      __hip_atomic_store(&prog[s], done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    // tie words after the release, so that the wait above covers only the
+    // link stores (and this chunk's loads)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tbs[(t0 / 4 + q) * 64 + lane] = tw[q];
   }
   if (s == ((W1 - 1) >> 6) && lane == ((W1 - 1) & 63)) J.final_score = H;
   return true;
@@ -539,10 +808,12 @@ __device__ void merge(const uint8_t* ops, int base, int nops, const uint16_t* P1
 }
 
 // ---------------------------------------------------------------- kernel
-template <int A>
+template <int A, bool MFMA>
 __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   constexpr int CW = ColWords<A>::value;
-  __shared__ __attribute__((aligned(16))) uint32_t ring[kWaves * kColRing * CW];
+  constexpr int kRingWords = MFMA ? kScWords : kColRing * CW;  // per wave
+  __shared__ __attribute__((aligned(16))) uint32_t ring[kWaves * kRingWords];
+  __shared__ int32_t S32[MFMA ? A * 32 : 1];
   __shared__ uint32_t tbst[kStageT4 * 64];
   __shared__ uint8_t ops[2 * kMaxWidth];
   __shared__ int32_t Ssh[A * A];
@@ -551,9 +822,13 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   __shared__ JobInfo J;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int q = tid; q < A * A; q += kThreads) Ssh[q] = a.S[q];
+  if constexpr (MFMA) {
+    // S with its columns zero-padded to 32 (the K extent of the tile products)
+    for (int q = tid; q < A * 32; q += kThreads) S32[q] = (q % 32) < A ? a.S[(q / 32) * A + q % 32] : 0;
+  }
   uint32_t* tbw = a.tb + (int64_t)blockIdx.x * a.tb_words_per_wg;
   int32_t* links = a.bnd + (int64_t)blockIdx.x * a.link_words_per_wg;
-  uint32_t* myring = ring + wave * kColRing * CW;
+  uint32_t* myring = ring + wave * kRingWords;
   __syncthreads();
 
   uint64_t tk0 = 0, tk1 = 0, tk2 = 0, tk3 = 0, tk35 = 0;  // phase timestamps (thread 0)
@@ -638,6 +913,10 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         J.o = (int32_t)(G * a.go);
         J.e = (int32_t)(G * a.ge);
         J.packed = ((int64_t)n1 * a.smax <= 32767 && n2 <= 32767) ? 1 : 0;
+        // signed base-256 digits of U (|U| <= n1 smax), base-128 digits of counts
+        const int64_t umax = (int64_t)n1 * a.smax;
+        J.nd_u = umax <= 127 ? 1 : (umax <= 32639 ? 2 : 3);
+        J.nd_c = n2 <= 127 ? 1 : (n2 <= 16383 ? 2 : 3);
         J.final_score = 0;
       }
     }
@@ -657,7 +936,10 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       for (int L = tid; L < kMaxStrips; L += kThreads) prog[L] = 0;
       __syncthreads();
       if (W1 > 0 && W2 > 0) {
-        if (J.packed) {
+        if constexpr (MFMA) {
+          for (int s = wave; s < J.nstrips; s += kWaves)
+            if (!dp_strip_mfma<A>(a, J, s, lane, myring, prog, tbw, links, S32, P1, P2)) break;
+        } else if (J.packed) {
           for (int s = wave; s < J.nstrips; s += kWaves)
             if (!dp_strip<A, true>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2)) break;
         } else {
@@ -764,8 +1046,14 @@ int engine_workgroups() {
 
 void launch_engine(const EngineArgs& a, int nwg, hipStream_t stream) {
   if (a.njobs <= 0 || nwg <= 0) return;
-  if (a.A == 20) engine_kernel<20><<<nwg, kThreads, 0, stream>>>(a);
-  else engine_kernel<4><<<nwg, kThreads, 0, stream>>>(a);
+  const bool mfma = a.mode == SAD_BATCHED_MFMA;
+  if (a.A == 20) {
+    if (mfma) engine_kernel<20, true><<<nwg, kThreads, 0, stream>>>(a);
+    else engine_kernel<20, false><<<nwg, kThreads, 0, stream>>>(a);
+  } else {
+    if (mfma) engine_kernel<4, true><<<nwg, kThreads, 0, stream>>>(a);
+    else engine_kernel<4, false><<<nwg, kThreads, 0, stream>>>(a);
+  }
 }
 
 }  // namespace sad
