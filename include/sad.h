@@ -174,6 +174,13 @@ int32_t sad_profile_read(double* engine_ms, int64_t* engine_launches, int32_t re
  * [1] DP, [2] traceback, [3] merge, [4] publication (device-scope fence and
  * queue hand-off); *jobs = jobs timed.  ms_out needs 5 entries. */
 int32_t sad_profile_phases(double* ms_out, int64_t* jobs, int32_t reset);
+/* Per-job records of the most recent engine launch made while profiling was
+ * enabled: 8 int64 per job slot (slots without a job are all zero), {W1, W2, ops, fetch, start, DP end,
+ * traceback end, merge end}, times in nanoseconds from the launch's first job
+ * fetch (fetch = the workgroup asked the queue; start = the job was handed
+ * to it).  Copies min(cap, n) records to host memory `out` (may be NULL);
+ * *njobs = n. */
+int32_t sad_profile_jobs(int64_t* out, int64_t cap, int64_t* njobs);
 
 /* Message for the calling thread's last non-OK status (static storage). */
 const char* sad_last_error(void);

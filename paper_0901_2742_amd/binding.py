@@ -27,7 +27,8 @@ SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
 EXPORTS = ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine",
-           "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_last_error",
+           "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs",
+           "sad_last_error",
            "sad_release",
            "sad_version")
 
@@ -81,6 +82,8 @@ def lib():
         L.sad_profile_read.restype = I32
         L.sad_profile_phases.argtypes = [P, P, I32]
         L.sad_profile_phases.restype = I32
+        L.sad_profile_jobs.argtypes = [P, ctypes.c_int64, P]
+        L.sad_profile_jobs.restype = I32
         L.sad_last_error.restype = ctypes.c_char_p
         L.sad_version.restype = ctypes.c_char_p
         L.sad_release.restype = None
@@ -253,6 +256,18 @@ def sad_profile_phases(reset: bool = False):
     lib().sad_profile_phases(out, ctypes.byref(n), 1 if reset else 0)
     return dict(wait=out[0], dp=out[1], traceback=out[2], merge=out[3], publish=out[4],
                 jobs=n.value)
+
+
+def sad_profile_jobs():
+    """Per-job records of the last profiled engine launch, an (n, 8) int64
+    array: W1, W2, ops, fetch, start, DP end, traceback end, merge end (ns)."""
+    import numpy as np
+    n = ctypes.c_int64(0)
+    lib().sad_profile_jobs(None, 0, ctypes.byref(n))
+    out = np.zeros((n.value, 8), np.int64)
+    if n.value:
+        lib().sad_profile_jobs(out.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n))
+    return out
 
 
 def sad_version() -> str:

@@ -1,5 +1,6 @@
 // Host side of the C-ABI (include/sad.h): argument checks, workspace
 // planning, kernel sequencing, device status readback.
+#include <climits>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +25,8 @@ struct DeviceCtx {
   int64_t* h_small = nullptr; // pinned host scratch for small readbacks
   size_t h_small_cap = 0;
   unsigned long long* phase = nullptr;  // engine phase ticks (profiling)
+  long long* jobrec = nullptr;          // per-job records (profiling)
+  int64_t jobrec_cap = 0;
 };
 
 static std::mutex g_mu;
@@ -35,6 +38,7 @@ static bool g_prof_on = false;
 static double g_prof_ms = 0.0;
 static int64_t g_prof_launches = 0;
 static unsigned long long g_phase[6] = {0, 0, 0, 0, 0, 0};
+static std::vector<long long> g_jobrec;  // records of the last profiled engine launch
 static double g_tick_khz = 0.0;
 
 struct EngineTimer {
@@ -398,12 +402,28 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
 }
 
 // Per-phase tick accumulation of the engine kernel while profiling is on.
-static int32_t attach_phases(DeviceCtx* c, EngineArgs& a, hipStream_t s) {
+// nslots: job ids are below it (slot-indexed jobs may leave unused slots).
+static int32_t attach_phases(DeviceCtx* c, EngineArgs& a, int nslots, hipStream_t s) {
   a.phase_acc = nullptr;
+  a.job_rec = nullptr;
+  a.nrec = 0;
   if (!g_prof_on) return SAD_OK;
   if (!c->phase) HIPCHK(hipMalloc(&c->phase, 8 * sizeof(unsigned long long)));
   HIPCHK(hipMemsetAsync(c->phase, 0, 8 * sizeof(unsigned long long), s));
   a.phase_acc = c->phase;
+  if (nslots > c->jobrec_cap) {
+    if (c->jobrec) HIPCHK(hipFree(c->jobrec));
+    c->jobrec = nullptr;
+    c->jobrec_cap = 0;
+    HIPCHK(hipMalloc(&c->jobrec, (size_t)nslots * 8 * sizeof(long long)));
+    c->jobrec_cap = nslots;
+  }
+  if (nslots > 0) {
+    // unused slots read back as zeros
+    HIPCHK(hipMemsetAsync(c->jobrec, 0, (size_t)nslots * 8 * sizeof(long long), s));
+    a.job_rec = c->jobrec;
+    a.nrec = nslots;
+  }
   return SAD_OK;
 }
 
@@ -414,6 +434,21 @@ static int32_t collect_phases(DeviceCtx* c, const EngineArgs& a, hipStream_t s) 
   HIPCHK(hipStreamSynchronize(s));
   std::lock_guard<std::mutex> lk(g_mu);
   for (int q = 0; q < 6; ++q) g_phase[q] += h[q];
+  if (a.job_rec) {
+    g_jobrec.resize((size_t)a.nrec * 8);
+    HIPCHK(hipMemcpy(g_jobrec.data(), a.job_rec, g_jobrec.size() * sizeof(long long),
+                     hipMemcpyDeviceToHost));
+    // timestamps in nanoseconds from the launch's first job fetch; slots
+    // without a job stay all zero
+    long long t0 = LLONG_MAX;
+    for (int64_t q = 0; q < a.nrec; ++q)
+      if (g_jobrec[q * 8 + 3] != 0) t0 = std::min(t0, g_jobrec[q * 8 + 3]);
+    const double ns = g_tick_khz > 0 ? 1e6 / g_tick_khz : 0.0;
+    for (int64_t q = 0; q < a.nrec; ++q)
+      if (g_jobrec[q * 8 + 3] != 0)
+        for (int f = 3; f < 8; ++f)
+          g_jobrec[q * 8 + f] = (long long)((double)(g_jobrec[q * 8 + f] - t0) * ns);
+  }
   return SAD_OK;
 }
 
@@ -440,6 +475,47 @@ struct TreeOutputs {
   int64_t* d_cells_total;
   bool keep_engine;   // leave engine buffers for the caller to read nodes
 };
+
+// Tree levels for level-by-level launches: a job's level is one more than its
+// children's (leaf-leaf merges are level 0).  Writes the jobs grouped by
+// level into the queue (all flags set) and the level offsets to lvl_off.
+static int32_t plan_levels(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
+                           EngineBuffers& e, int njobs, std::vector<int32_t>* lvl_off,
+                           hipStream_t stream) {
+  const int N = ts.nleaves;
+  std::vector<int32_t> merges(2 * (size_t)N);
+  HIPCHK(hipMemcpyAsync(merges.data(), d_merges, merges.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  std::vector<int32_t> level(N, 0);
+  int maxl = 0;
+  for (int g = 0; g < ts.ngroups; ++g) {
+    const int g0 = ts.h_group_off[g], ng = ts.h_group_off[g + 1] - g0;
+    for (int t = 0; t + 1 < ng; ++t) {
+      int l = 0;
+      for (int q = 0; q < 2; ++q) {
+        const int x = merges[2 * (size_t)(g0 + t) + q];
+        if (x < 0 || x >= 2 * ng - 1) return fail(SAD_E_INVAL, "malformed guide tree");
+        if (x >= ng) l = std::max(l, level[g0 + (x - ng)] + 1);
+      }
+      level[g0 + t] = l;
+      maxl = std::max(maxl, l);
+    }
+  }
+  std::vector<int32_t> cnt(maxl + 2, 0);
+  for (int g = 0; g < ts.ngroups; ++g)
+    for (int t = ts.h_group_off[g]; t + 1 < ts.h_group_off[g + 1]; ++t) ++cnt[level[t] + 1];
+  for (int l = 0; l <= maxl; ++l) cnt[l + 1] += cnt[l];
+  std::vector<int32_t> order(njobs), pos(cnt.begin(), cnt.end() - 1);
+  for (int g = 0; g < ts.ngroups; ++g)
+    for (int t = ts.h_group_off[g]; t + 1 < ts.h_group_off[g + 1]; ++t) order[pos[level[t]]++] = t;
+  HIPCHK(hipMemcpyAsync(e.queue, order.data(), (size_t)njobs * sizeof(int32_t),
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  launch_fill_i32(e.queue_flag, 1, njobs, stream);
+  *lvl_off = std::move(cnt);
+  return SAD_OK;
+}
 
 static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
                          const sad_params* prm, int A, Carver& base_cv, EngineBuffers& e,
@@ -473,10 +549,29 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                      stream);
     EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                                nullptr, c->st);
-    r = attach_phases(c, a, stream);
+    r = attach_phases(c, a, std::max(N, 1), stream);
     if (r) return r;
+    // plain mode: one launch per tree level (jobs of a level are independent)
+    std::vector<int32_t> lvl_off;
+    if (prm->mode == SAD_PLAIN && njobs > 0) {
+      r = plan_levels(c, ts, d_merges, e, njobs, &lvl_off, stream);
+      if (r) return r;
+    }
     EngineTimer timer(stream);
-    launch_engine(a, e.nwg, stream);
+    if (lvl_off.empty()) {
+      launch_engine(a, e.nwg, stream);
+    } else {
+      for (size_t l = 0; l + 1 < lvl_off.size(); ++l) {
+        const int cnt = lvl_off[l + 1] - lvl_off[l];
+        EngineArgs al = a;
+        al.queue = e.queue + lvl_off[l];
+        al.queue_flag = e.queue_flag + lvl_off[l];
+        al.njobs = cnt;
+        al.no_push = 1;
+        launch_fill_i32(e.qctl, 0, 2, stream);
+        launch_engine(al, std::max(1, std::min(cnt, e.nwg)), stream);
+      }
+    }
     timer.stop();
     DevStatus d{};
     r = read_status(c, stream, &d);
@@ -989,7 +1084,7 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                      e.job_ops_off, e.queue, e.queue_flag, e.qctl + 1, e.node_parent, stream);
   EngineArgs a = engine_args(e, q, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                              rf_ops, c->st);
-  r = attach_phases(c, a, stream);
+  r = attach_phases(c, a, q, stream);
   if (r) return r;
   EngineTimer timer(stream);
   launch_engine(a, e.nwg, stream);
@@ -1046,6 +1141,17 @@ extern "C" int32_t sad_profile_phases(double* ms_out, int64_t* jobs, int32_t res
   return SAD_OK;
 }
 
+extern "C" int32_t sad_profile_jobs(int64_t* out, int64_t cap, int64_t* njobs) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int64_t n = (int64_t)g_jobrec.size() / 8;
+  if (njobs) *njobs = n;
+  if (out && cap > 0) {
+    const int64_t m = std::min(n, cap);
+    std::copy(g_jobrec.begin(), g_jobrec.begin() + m * 8, out);
+  }
+  return SAD_OK;
+}
+
 extern "C" const char* sad_last_error(void) { return g_err.c_str(); }
 
 extern "C" void sad_release(void) {
@@ -1057,6 +1163,7 @@ extern "C" void sad_release(void) {
     if (c.h_st) hipHostFree(c.h_st);
     if (c.h_small) hipHostFree(c.h_small);
     if (c.phase) hipFree(c.phase);
+    if (c.jobrec) hipFree(c.jobrec);
     c = DeviceCtx{};
   }
 }

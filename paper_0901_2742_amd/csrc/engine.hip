@@ -1012,8 +1012,19 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       atomicAdd(&a.phase_acc[3], (unsigned long long)(tk35 - tk3));
       atomicAdd(&a.phase_acc[4], 1ull);
       atomicAdd(&a.phase_acc[5], (unsigned long long)(tk4 - tk35));
+      if (a.job_rec && job < a.nrec) {
+        long long* r = a.job_rec + (int64_t)job * 8;
+        r[0] = W1;
+        r[1] = W2;
+        r[2] = J.err ? 0 : J.nops;
+        r[3] = (long long)tk0;
+        r[4] = (long long)tk1;
+        r[5] = (long long)tk2;
+        r[6] = (long long)tk3;
+        r[7] = (long long)tk35;
+      }
     }
-    if (tid == 0) {
+    if (tid == 0 && !a.no_push) {
       const int nx = a.job_next[job];
       if (nx >= 0) {
         const int prev = atomicSub(&a.job_pending[nx], 1);

@@ -147,6 +147,9 @@ struct EngineArgs {
   uint32_t mode;
   int64_t wait_ticks;     // queue wait limit in s_memrealtime ticks
   unsigned long long* phase_acc;  // optional: ticks in queue wait, DP, traceback, merge; jobs
+  long long* job_rec;  // optional: per job slot W1, W2, ops and five phase timestamps (8 words)
+  int32_t nrec;        // job slots in job_rec
+  int32_t no_push;     // 1: finished jobs do not queue their parents (level-by-level launches)
   DevStatus* st;
 };
 void launch_engine(const EngineArgs& a, int nwg, hipStream_t stream);

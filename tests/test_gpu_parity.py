@@ -112,13 +112,16 @@ def test_gap_models(hip):
         compare(got, ref, f"gaps {go}/{ge}")
 
 
-def test_prot2000_full(hip):
+@pytest.mark.parametrize("mode", [1, 0])
+def test_prot2000_full(hip, mode):
+    # mode 1: one persistent launch over all trees, MFMA tile scores;
+    # mode 0: one launch per tree level, VALU column scores
     B, pipeline = hip
     w = CONFIGS["prot2000"]
-    _say("case prot2000")
+    _say(f"case prot2000 mode={mode}")
     s = make_inputs("prot2000")
-    got, ref = run_both(B, pipeline, s, w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, 1)
-    compare(got, ref, "prot2000")
+    got, ref = run_both(B, pipeline, s, w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, mode)
+    compare(got, ref, f"prot2000 mode {mode}")
 
 
 def test_repeat_runs_identical(hip):
