@@ -23,8 +23,7 @@
  *    a sequence x at position t is sum_u x[t+u] * A^(k-1-u); A^k <= 65536.
  *  - Limits: sequence length <= 8192; profile width <= 4096 columns; at most
  *    8000 sequences per bucket and 8000 buckets; DP values must stay within
- *    the 32-bit bound described at
- *    sad_align_buckets (otherwise SAD_E_OVERFLOW).
+ *    the bound described at sad_align_buckets (otherwise SAD_E_OVERFLOW).
  *  - Status codes are returned; no exception crosses the ABI.  On error the
  *    contents of the outputs are unspecified.  sad_last_error() gives a
  *    message for the calling thread's last failure.
@@ -45,7 +44,7 @@ extern "C" {
 #define SAD_OK 0
 #define SAD_E_INVAL (-1)        /* bad code, L < k, N < 2p, go < ge, bad alphabet, bad k */
 #define SAD_E_CAPACITY (-2)     /* a caller capacity or a library limit is too small */
-#define SAD_E_OVERFLOW (-3)     /* a DP value bound exceeds the 32-bit range */
+#define SAD_E_OVERFLOW (-3)     /* a DP value bound exceeds the 64-bit DP's range */
 #define SAD_E_DEVICE (-4)       /* HIP runtime failure */
 #define SAD_E_UNIMPLEMENTED (-5)
 
@@ -134,7 +133,10 @@ int32_t sad_partition(const sad_seqs* seqs, const uint64_t* d_key, const sad_par
  * bucket's alignment; d_width[p]; bucket b's merges occupy slots
  * [d_bucket_off[b], d_bucket_off[b] + n_b - 1) of d_merge_score[n],
  * d_merge_cells[n] and d_merge_list[2n] (local cluster ids); d_cells[1].
- * 32-bit bound: every merge needs (W1 + W2 + 2) n1 n2 max(|S|, go) < 2^29.
+ * Value bound: a merge whose (W1 + W2 + 2) n1 n2 max(|S|, go) is below 2^29
+ * runs the 32-bit DP, up to 2 * 10^18 the 64-bit DP (same results); beyond
+ * that, or if n1 n2 max|S| reaches 2^31 (column scores are 32-bit), the call
+ * fails with SAD_E_OVERFLOW.
  */
 int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_bucket_off,
                           const int32_t* d_members, const sad_params* prm, sad_msa* out,

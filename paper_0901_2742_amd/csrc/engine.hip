@@ -54,11 +54,40 @@ __device__ inline int32_t shl1(int32_t old_lane63, int32_t v) {
   // lane l receives lane l+1's v; lane 63 keeps old_lane63
   return __builtin_amdgcn_update_dpp(old_lane63, v, 0x130, 0xf, 0xf, false);
 }
+// 64-bit DP values (merges whose score bound does not fit 32 bits) move
+// between lanes as two 32-bit halves.
+__device__ inline int64_t shr1(int64_t old_lane0, int64_t v) {
+  const int32_t lo = shr1((int32_t)(uint32_t)old_lane0, (int32_t)(uint32_t)v);
+  const int32_t hi = shr1((int32_t)(old_lane0 >> 32), (int32_t)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ inline int64_t shl1(int64_t old_lane63, int64_t v) {
+  const int32_t lo = shl1((int32_t)(uint32_t)old_lane63, (int32_t)(uint32_t)v);
+  const int32_t hi = shl1((int32_t)(old_lane63 >> 32), (int32_t)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// "minus infinity" of the DP in each value type: far enough below every
+// reachable value that subtracting gap costs cannot wrap
+template <typename T>
+struct DpNeg;
+template <>
+struct DpNeg<int32_t> {
+  static constexpr int32_t value = kNeg32;
+};
+template <>
+struct DpNeg<int64_t> {
+  static constexpr int64_t value = -(1ll << 62);
+};
+// Largest static bound of a 64-bit merge (the same limit as the CPU oracle's).
+constexpr int64_t kBound64 = 2000000000000000000ll;
+
 // Per-workgroup scratch (tie words, strip boundary rows) is written and read
 // by the waves of one workgroup, i.e. one CU, whose vector L1 is write-through
 // and sees its own stores: plain loads after workgroup-scope synchronisation.
-__device__ inline int32_t load_wg(const int32_t* p) { return *p; }
-__device__ inline uint32_t load_wg(const uint32_t* p) { return *p; }
+template <typename V>
+__device__ inline V load_wg(const V* p) {
+  return *p;
+}
 
 // -1, 0 or 1 for d < 0, d == 0, d > 0 (one v_med3_i32)
 __device__ inline int32_t sign3(int32_t d) {
@@ -66,6 +95,7 @@ __device__ inline int32_t sign3(int32_t d) {
   asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(d));
   return r;
 }
+__device__ inline int32_t sign3(int64_t d) { return (int32_t)(d > 0) - (int32_t)(d < 0); }
 
 __device__ inline int32_t dot2(uint32_t a, uint32_t b, int32_t c) {
   typedef short v2s __attribute__((ext_vector_type(2)));
@@ -77,10 +107,12 @@ struct JobInfo {
   int32_t job, slot;
   int32_t na, nb, out;
   int32_t W1, W2, n1, n2;
-  int32_t o, e;
+  int64_t o, e;          // gap costs scaled by n1 n2
   int32_t err, abort, packed;
+  int32_t wide;           // 1: DP values in 64 bits
   int32_t nstrips, nchunks;
-  int32_t final_score, nops;
+  int64_t final_score;
+  int32_t nops;
   int32_t nd_u, nd_c;  // digits of U and of the counts in the MFMA tile products
   long long prof_off, up_off;
 };
@@ -106,29 +138,28 @@ __device__ inline bool wait_link(const EngineArgs& a, JobInfo& J, const int32_t*
 // 64 DP steps of one strip.  MASK: some cells of the chunk lie outside
 // 1 <= j <= W2 and must leave H/X/Y untouched.  score(k, j) gives s(i, j) of
 // this lane's row at step k.
-template <bool MASK, typename Score>
-__device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, int32_t o, int32_t e,
-                                         Score&& score, int32_t& H, int32_t& X, int32_t& Y,
-                                         int32_t& Hprev, int32_t bhv, int32_t bxv, int32_t& oh,
-                                         int32_t& ox, uint32_t (&tw)[16]) {
+template <bool MASK, typename T, typename Score>
+__device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, T o, T e, Score&& score, T& H,
+                                         T& X, T& Y, T& Hprev, T bhv, T bxv, T& oh, T& ox,
+                                         uint32_t (&tw)[16]) {
   uint32_t word = 0;
 #pragma unroll
   for (int k = 0; k < 64; ++k) {
     const int j = t0 + k - lane + 1;
-    const int32_t Hup = shr1(bhv, H);
-    const int32_t Xup = shr1(bxv, X);
+    const T Hup = shr1(bhv, H);
+    const T Xup = shr1(bxv, X);
     bhv = shl1(bhv, bhv);
     bxv = shl1(bxv, bxv);
-    const int32_t Hdiag = Hprev;
+    const T Hdiag = Hprev;
     Hprev = Hup;
-    const int32_t sc = score(k, j);
-    const int32_t M = Hdiag + sc;
-    const int32_t xo = Hup - o, xe = Xup - e;
-    const int32_t Xn = max(xo, xe);
-    const int32_t yo = H - o, ye = Y - e;
-    const int32_t Yn = max(yo, ye);
-    const int32_t t2 = max(Xn, Yn);
-    const int32_t Hn = max(M, t2);
+    const T sc = (T)score(k, j);
+    const T M = Hdiag + sc;
+    const T xo = Hup - o, xe = Xup - e;
+    const T Xn = max(xo, xe);
+    const T yo = H - o, ye = Y - e;
+    const T Yn = max(yo, ye);
+    const T t2 = max(Xn, Yn);
+    const T Hn = max(M, t2);
     const uint32_t hc = (M >= t2) ? 0u : ((Xn >= Yn) ? 1u : 2u);
     // 0 extend only, 1 both, 2 open only (stored as sign + 1)
     const uint32_t xc = (uint32_t)(sign3(xo - xe) + 1);
@@ -193,13 +224,13 @@ struct RingScore {
 
 // One strip of the DP (run by one wave).  Returns false if the job aborted.
 // PACK: U fits in 16 bits, so column scores use packed dot products.
-template <int A, bool PACK>
+template <int A, bool PACK, typename T>
 __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                          int32_t* prog, uint32_t* tbw, int32_t* links, const int32_t* Ssh,
                          const uint16_t* P1, const uint16_t* P2) {
   constexpr int CW = ColWords<A>::value;
   const int W1 = J.W1, W2 = J.W2, nchunks = J.nchunks, nstrips = J.nstrips;
-  const int32_t o = J.o, e = J.e;
+  const T o = (T)J.o, e = (T)J.e;
   const int i = 64 * s + lane + 1;
   const int ie = min(i, W1);
   int32_t U[PACK ? 1 : A];
@@ -229,20 +260,23 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
       for (int b = 0; b < A; ++b) U[b] = Uf[b];
     }
   }
-  int32_t H = -(o + (ie - 1) * e);
-  int32_t X = kNeg32, Y = kNeg32;
-  int32_t Hprev = (s == 0) ? 0 : -(o + (64 * s - 1) * e);
+  T H = -(o + (T)(ie - 1) * e);
+  T X = DpNeg<T>::value, Y = DpNeg<T>::value;
+  T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
   uint32_t* tbs = tbw + (int64_t)s * nchunks * 16 * 64;
-  const int stride = a.link_stride;
-  const int32_t* inH = links + (int64_t)(s - 1) * 2 * stride;
-  const int32_t* inX = inH + stride;
-  int32_t* outH = links + (int64_t)s * 2 * stride;
-  int32_t* outX = outH + stride;
+  // boundary rows: H and X of each strip's last row, link_stride 32-bit
+  // words per row (half as many 64-bit values)
+  const int stride = a.link_stride / (int)(sizeof(T) / 4);
+  T* lk = reinterpret_cast<T*>(links);
+  const T* inH = lk + (int64_t)(s - 1) * 2 * stride;
+  const T* inX = inH + stride;
+  T* outH = lk + (int64_t)s * 2 * stride;
+  T* outX = outH + stride;
   // the next chunk's P2 columns and boundary row are loaded during the current
   // chunk (the boundary only if its producer is already far enough)
   constexpr int NW = (A + 1) / 2;
   uint32_t pcol[NW];
-  int32_t pbh = 0, pbx = kNeg32;
+  T pbh = 0, pbx = DpNeg<T>::value;
   bool have_link = (s == 0);
   auto prefetch = [&](int c, bool block) -> bool {
     const int jn = 64 * c + 1 + lane;
@@ -252,8 +286,8 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
       for (int m = 0; m < NW; ++m) pcol[m] = src[m];
     }
     if (s == 0) {
-      pbh = jn <= W2 ? -(o + (jn - 1) * e) : 0;
-      pbx = kNeg32;
+      pbh = jn <= W2 ? -(o + (T)(jn - 1) * e) : (T)0;
+      pbx = DpNeg<T>::value;
       have_link = true;
       return true;
     }
@@ -283,7 +317,7 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
         pbx = load_wg(inX + jn);
       }
     }
-    const int32_t bh = pbh, bx = pbx;
+    const T bh = pbh, bx = pbx;
     if (jn <= W2) {
       uint32_t* dst = ring + ((jn - 1) & (kColRing - 1)) * CW;
 #pragma unroll
@@ -293,7 +327,7 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
     }
     __threadfence_block();
     if (c + 1 < nchunks) prefetch(c + 1, false);
-    int32_t oh = 0, ox = 0;
+    T oh = 0, ox = 0;
     const bool mask = (c == 0) || (t0 + 64 > W2);
     const RingScore<A, PACK> score{ring, Up, U};
     uint32_t tw[16];
@@ -434,14 +468,14 @@ __device__ inline void tile_scores(const long (&ua)[3][2][Tile<A>::KS],
 
 // One strip with MFMA tile scores (run by one wave).  Returns false if the
 // job aborted.
-template <int A>
+template <int A, typename T>
 __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                               int32_t* prog, uint32_t* tbw, int32_t* links, const int32_t* S32,
                               const uint16_t* P1, const uint16_t* P2) {
   constexpr int KS = Tile<A>::KS;
   const int W1 = J.W1, W2 = J.W2, nchunks = J.nchunks, nstrips = J.nstrips;
   const int nd_u = J.nd_u, nd_c = J.nd_c;
-  const int32_t o = J.o, e = J.e;
+  const T o = (T)J.o, e = (T)J.e;
   const int i = 64 * s + lane + 1;
   const int ie = min(i, W1);
   // A operands: U rows 64 s + 32 rb + (lane & 31), K entries 16 ks + 8 h + 0..7,
@@ -487,24 +521,27 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
       }
     }
   }
-  int32_t H = -(o + (ie - 1) * e);
-  int32_t X = kNeg32, Y = kNeg32;
-  int32_t Hprev = (s == 0) ? 0 : -(o + (64 * s - 1) * e);
+  T H = -(o + (T)(ie - 1) * e);
+  T X = DpNeg<T>::value, Y = DpNeg<T>::value;
+  T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
   uint32_t* tbs = tbw + (int64_t)s * nchunks * 16 * 64;
-  const int stride = a.link_stride;
-  const int32_t* inH = links + (int64_t)(s - 1) * 2 * stride;
-  const int32_t* inX = inH + stride;
-  int32_t* outH = links + (int64_t)s * 2 * stride;
-  int32_t* outX = outH + stride;
+  // boundary rows: H and X of each strip's last row, link_stride 32-bit
+  // words per row (half as many 64-bit values)
+  const int stride = a.link_stride / (int)(sizeof(T) / 4);
+  T* lk = reinterpret_cast<T*>(links);
+  const T* inH = lk + (int64_t)(s - 1) * 2 * stride;
+  const T* inX = inH + stride;
+  T* outH = lk + (int64_t)s * 2 * stride;
+  T* outX = outH + stride;
   const int ntiles = (W2 + 63) >> 6;
   uint32_t bw[2][KS][4];
-  int32_t pbh = 0, pbx = kNeg32;
+  T pbh = 0, pbx = DpNeg<T>::value;
   bool have_link = (s == 0);
   auto link_fetch = [&](int c, bool block) -> bool {
     const int jn = 64 * c + 1 + lane;
     if (s == 0) {
-      pbh = jn <= W2 ? -(o + (jn - 1) * e) : 0;
-      pbx = kNeg32;
+      pbh = jn <= W2 ? -(o + (T)(jn - 1) * e) : (T)0;
+      pbx = DpNeg<T>::value;
       have_link = true;
       return true;
     }
@@ -535,14 +572,14 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
         pbx = load_wg(inX + jn);
       }
     }
-    const int32_t bh = pbh, bx = pbx;
+    const T bh = pbh, bx = pbx;
     if (c < ntiles) tile_scores<A>(ua, bw, nd_u, nd_c, ring, c, lane);
     int32_t scv[64];
 #pragma unroll
     for (int k = 0; k < 64; ++k) scv[k] = (int32_t)ring[lane * kScPitch + (t0 & 127) + k];
     if (c + 1 < ntiles) tile_load_counts<A>(bw, P2, W2, c + 1, lane);
     if (c + 1 < nchunks) link_fetch(c + 1, false);
-    int32_t oh = 0, ox = 0;
+    T oh = 0, ox = 0;
     const bool mask = (c == 0) || (t0 + 64 > W2);
     auto score = [&](int k, int) -> int32_t { return scv[k]; };
     uint32_t tw[16];
@@ -870,7 +907,16 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         J.n2 = n2;
         const int64_t G = (int64_t)n1 * n2;
         const int64_t unit = max((int64_t)max(a.smax, a.go), (int64_t)1);
-        const int64_t bound = (int64_t)(W1 + W2 + 2) * G * unit;
+        // static bound of every DP value; 32-bit DP below 2^29, 64-bit DP up
+        // to kBound64 (beyond it the merge is rejected, as by the oracle)
+        const bool over64 =
+            (double)(W1 + W2 + 2) * (double)G * (double)unit >= (double)kBound64;
+        const int64_t bound = over64 ? kBound64 : (int64_t)(W1 + W2 + 2) * G * unit;
+        const int wide = bound >= (1ll << 29) ? 1 : 0;
+        // column scores are int32 (|s| <= n1 n2 max|S|); the tile products need
+        // |U| <= n1 max|S| within three signed base-256 digits
+        const bool score_over = (double)G * (double)max(a.smax, 1) >= 2147483647.0 ||
+                                (int64_t)n1 * a.smax > 8355711;
         const int nstrips = (W1 + 63) >> 6;
         const int nchunks = (W2 + 63 + 63) >> 6;
         J.nstrips = nstrips;
@@ -881,13 +927,13 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         if (W1 > kMaxWidth || W2 > kMaxWidth) {
           err = 1;
           raise_error(a.st, SAD_E_CAPACITY, cap, W_ENGINE_WIDTH);
-        } else if (bound >= (1ll << 29)) {
+        } else if (over64 || score_over) {
           err = 1;
           raise_error(a.st, SAD_E_OVERFLOW, bound, W_ENGINE_BOUND);
         } else if (tb_need > a.tb_words_per_wg) {
           err = 1;
           raise_error(a.st, SAD_E_CAPACITY, tb_need, W_ENGINE_TB);
-        } else if (nstrips > a.link_rows + 1 || W2 + 1 > a.link_stride) {
+        } else if (nstrips > a.link_rows + 1 || (W2 + 1) * (wide ? 2 : 1) > a.link_stride) {
           err = 1;
           raise_error(a.st, SAD_E_CAPACITY, (int64_t)max(W1, W2), W_ENGINE_LINK);
         } else if (n1 + n2 > 65535) {
@@ -910,8 +956,9 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         J.up_off = up_off;
         J.err = err;
         J.abort = 0;
-        J.o = (int32_t)(G * a.go);
-        J.e = (int32_t)(G * a.ge);
+        J.o = G * a.go;
+        J.e = G * a.ge;
+        J.wide = wide;
         J.packed = ((int64_t)n1 * a.smax <= 32767 && n2 <= 32767) ? 1 : 0;
         // signed base-256 digits of U (|U| <= n1 smax), base-128 digits of counts
         const int64_t umax = (int64_t)n1 * a.smax;
@@ -937,14 +984,27 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       __syncthreads();
       if (W1 > 0 && W2 > 0) {
         if constexpr (MFMA) {
+          if (J.wide) {
+            for (int s = wave; s < J.nstrips; s += kWaves)
+              if (!dp_strip_mfma<A, int64_t>(a, J, s, lane, myring, prog, tbw, links, S32, P1, P2))
+                break;
+          } else {
+            for (int s = wave; s < J.nstrips; s += kWaves)
+              if (!dp_strip_mfma<A, int32_t>(a, J, s, lane, myring, prog, tbw, links, S32, P1, P2))
+                break;
+          }
+        } else if (J.wide) {
           for (int s = wave; s < J.nstrips; s += kWaves)
-            if (!dp_strip_mfma<A>(a, J, s, lane, myring, prog, tbw, links, S32, P1, P2)) break;
+            if (!dp_strip<A, false, int64_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2))
+              break;
         } else if (J.packed) {
           for (int s = wave; s < J.nstrips; s += kWaves)
-            if (!dp_strip<A, true>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2)) break;
+            if (!dp_strip<A, true, int32_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2))
+              break;
         } else {
           for (int s = wave; s < J.nstrips; s += kWaves)
-            if (!dp_strip<A, false>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2)) break;
+            if (!dp_strip<A, false, int32_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2))
+              break;
         }
       }
       __builtin_amdgcn_s_waitcnt(0);  // tie bytes stored before the barrier
@@ -972,10 +1032,10 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       if (oo >= 0)
         for (int q = tid; q < nops; q += kThreads) a.ops_out[oo + q] = ops[base + q];
       if (tid == 0) {
-        int32_t score = J.final_score;
+        int64_t score = J.final_score;
         if (W1 == 0 || W2 == 0) {
           const int w = W1 + W2;
-          score = w == 0 ? 0 : -(J.o + (w - 1) * J.e);
+          score = w == 0 ? 0 : -(J.o + (int64_t)(w - 1) * J.e);
         }
         a.node_W[out] = nops;
         a.node_n[out] = J.n1 + J.n2;

@@ -113,6 +113,24 @@ def test_gap_models(hip):
 
 
 @pytest.mark.parametrize("mode", [1, 0])
+@pytest.mark.parametrize("alphabet", [20, 4])
+def test_wide_dp(hip, mode, alphabet):
+    """Merges whose static bound (W1 + W2 + 2) n1 n2 max(|S|, go) reaches 2^29
+    run the 64-bit DP; a large gap-open cost gets there with small inputs."""
+    B, pipeline = hip
+    _say(f"case wide dp mode={mode} A={alphabet}")
+    k = 3 if alphabet == 20 else 6
+    S = protein_matrix() if alphabet == 20 else dna_matrix()
+    s = generate(2027 + alphabet, 80, alphabet, 2, {"kind": "uniform_int", "lo": 90, "hi": 130},
+                 0.1, 0.02, k)
+    go, ge = 3000, 1
+    top = 40 * 40 * 2 * 130 * go
+    assert top >= 1 << 29
+    got, ref = run_both(B, pipeline, s, k, 1, S, go, ge, mode)
+    compare(got, ref, f"wide A={alphabet} mode {mode}")
+
+
+@pytest.mark.parametrize("mode", [1, 0])
 def test_prot2000_full(hip, mode):
     # mode 1: one persistent launch over all trees, MFMA tile scores;
     # mode 0: one launch per tree level, VALU column scores
