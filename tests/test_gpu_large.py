@@ -39,7 +39,7 @@ def check_rows(offsets, ids, colmap, width):
     assert used.all()
 
 
-@pytest.mark.parametrize("name,nbuckets", [("prot20k", 3)])
+@pytest.mark.parametrize("name,nbuckets", [("prot20k", 3), ("dna50k", 2), ("prot200k", 2)])
 def test_large_sampled(hip, name, nbuckets):
     B, pipeline = hip
     _say(f"case {name}")
