@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -294,7 +295,7 @@ struct TreeSet {
 struct EngineBuffers {
   int32_t *node_W, *node_n, *node_parent;
   int64_t *node_prof, *node_up;
-  int32_t *job_a, *job_b, *job_out, *job_next, *job_pending;
+  int32_t *job_a, *job_b, *job_out, *job_next, *job_pending, *job_link;
   int64_t *job_score, *job_cells, *job_ops_off;
   int32_t *queue, *queue_flag, *qctl;
   unsigned long long* tops;
@@ -332,6 +333,7 @@ static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, in
   cv.add(e.job_b, nslots);
   cv.add(e.job_out, nslots);
   cv.add(e.job_next, nslots);
+  cv.add(e.job_link, nslots);
   cv.add(e.job_pending, nslots);
   cv.add(e.job_score, nslots);
   cv.add(e.job_cells, nslots);
@@ -365,6 +367,7 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
   a.job_b = e.job_b;
   a.job_out = e.job_out;
   a.job_next = e.job_next;
+  a.job_link = e.job_link;
   a.job_pending = e.job_pending;
   a.job_score = e.job_score;
   a.job_cells = e.job_cells;
@@ -476,6 +479,17 @@ struct TreeOutputs {
   bool keep_engine;   // leave engine buffers for the caller to read nodes
 };
 
+// Guide trees built inside the engine launch (instead of merges given up
+// front): k-mer similarity matrices per group and where the merges go.
+struct FusedTrees {
+  uint32_t* const* F;            // carved with the caller's buffers (base carver)
+  int64_t* const* d_fm_off;
+  int32_t* d_merges;
+  // fills the similarity matrices after each carve (a regrown workspace
+  // loses earlier contents)
+  std::function<int32_t()> prepare;
+};
+
 // Tree levels for level-by-level launches: a job's level is one more than its
 // children's (leaf-leaf merges are level 0).  Writes the jobs grouped by
 // level into the queue (all flags set) and the level offsets to lvl_off.
@@ -570,7 +584,8 @@ static int32_t plan_priority(const TreeSet& ts, const int32_t* d_merges, const E
 
 static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
                          const sad_params* prm, int A, Carver& base_cv, EngineBuffers& e,
-                         const TreeOutputs& out, hipStream_t stream) {
+                         const TreeOutputs& out, hipStream_t stream,
+                         const FusedTrees* fused = nullptr) {
   const int N = ts.nleaves;
   int njobs = 0;
   for (int g = 0; g < ts.ngroups; ++g)
@@ -585,6 +600,10 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     if (r) return r;
     r = reset_status(c, stream);
     if (r) return r;
+    if (fused) {
+      r = fused->prepare();
+      if (r) return r;
+    }
     launch_fill_i32(e.node_parent, -1, 2 * (int64_t)std::max(N, 1), stream);
     launch_fill_i32(e.job_next, -1, std::max(N, 1), stream);
     launch_fill_i32(e.job_a, -1, std::max(N, 1), stream);
@@ -595,19 +614,31 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                                                 (unsigned long long)ts.total_len, e.qctl);
     launch_make_leaves(ts.d_codes, ts.d_offsets, ts.d_ids, N, A, 0, e.node_W, e.node_n,
                        e.node_prof, e.node_up, e.node_parent, e.prof_pool, ts.total_len, stream);
-    launch_make_jobs(d_merges, ts.d_group_off, ts.ngroups, N, N, e.node_parent, e.job_a, e.job_b,
-                     e.job_out, e.job_next, e.job_pending, e.queue, e.queue_flag, e.qctl + 1,
-                     stream);
+    launch_fill_i32(e.job_link, 0, std::max(N, 1), stream);
+    if (!fused)
+      launch_make_jobs(d_merges, ts.d_group_off, ts.ngroups, N, N, e.node_parent, e.job_a,
+                       e.job_b, e.job_out, e.job_next, e.job_pending, e.job_link, e.queue,
+                       e.queue_flag, e.qctl + 1, stream);
     EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                                nullptr, c->st);
+    if (fused) {
+      a.up_F = *fused->F;
+      a.up_fm_off = *fused->d_fm_off;
+      a.up_group_off = ts.d_group_off;
+      a.up_ngroups = ts.ngroups;
+      a.up_N = N;
+      a.up_merges = fused->d_merges;
+      a.up_next = e.qctl + 2;
+    }
     r = attach_phases(c, a, std::max(N, 1), stream);
     if (r) return r;
     // plain mode: one launch per tree level (jobs of a level are independent)
     std::vector<int32_t> lvl_off;
     if (prm->mode == SAD_PLAIN && njobs > 0) {
+      if (fused) return fail(SAD_E_INVAL, "level-by-level launches need the merges up front");
       r = plan_levels(c, ts, d_merges, e, njobs, &lvl_off, stream);
       if (r) return r;
-    } else if (njobs > 0) {
+    } else if (njobs > 0 && !fused) {
       r = plan_priority(ts, d_merges, e, stream);
       if (r) return r;
     }
@@ -785,29 +816,28 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   int32_t* nu;
   int64_t* d_fm_off;
   uint64_t* Sw;
+  // batched mode with small enough buckets: the guide trees are built inside
+  // the engine launch, which starts aligning each merge as soon as it is known
+  const bool fuse = prm->mode == SAD_BATCHED_MFMA && max_n <= engine_fused_max_group();
   Carver cv;
   cv.add(entries, (size_t)std::max<int64_t>(seqs->total_len, 1));
   cv.add(nu, std::max(n, 1));
   cv.add(d_fm_off, std::max(p, 1));
   cv.add(F, (size_t)std::max<int64_t>(fm_total, 1));
-  cv.add(Sw, (size_t)std::max<int64_t>(fm_total, 1));
-  r = cv.carve(c);
-  if (r) return r;
-  r = h2d(fm_off, d_fm_off, stream);
-  if (r) return r;
-  r = reset_status(c, stream);
-  if (r) return r;
-  launch_fill_i32(out->d_merge_list, -1, 2 * (int64_t)n, stream);
-  launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_score), 0, 2 * (int64_t)n, stream);
-  launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_cells), 0, 2 * (int64_t)n, stream);
-  launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st, stream);
-  KmerLists kl{entries, seqs->d_offsets, nu, seqs->d_offsets};
-  launch_fmatrix_groups(kl, d_bucket_off, d_members, p, n, d_fm_off, k, kspace, F, stream);
-  launch_upgma(F, d_fm_off, d_bucket_off, p, max_n, Sw, out->d_merge_list, d_bucket_off, c->st,
-               stream);
-  r = finish(c, stream);
-  if (r) return r;
-
+  if (!fuse) cv.add(Sw, (size_t)std::max<int64_t>(fm_total, 1));
+  // k-mer lists and per-bucket similarity matrices into the carved buffers
+  auto prepare = [&]() -> int32_t {
+    int32_t q = h2d(fm_off, d_fm_off, stream);
+    if (q) return q;
+    launch_fill_i32(out->d_merge_list, -1, 2 * (int64_t)n, stream);
+    launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_score), 0, 2 * (int64_t)n, stream);
+    launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_cells), 0, 2 * (int64_t)n, stream);
+    launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st,
+                      stream);
+    KmerLists kl{entries, seqs->d_offsets, nu, seqs->d_offsets};
+    launch_fmatrix_groups(kl, d_bucket_off, d_members, p, n, d_fm_off, k, kspace, F, stream);
+    return SAD_OK;
+  };
   TreeSet ts;
   ts.ngroups = p;
   ts.nleaves = n;
@@ -822,6 +852,22 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   EngineBuffers e{};
   TreeOutputs to{out->d_colmap, out->d_width, out->d_merge_score, out->d_merge_cells,
                  out->d_cells, false};
+  if (fuse) {
+    // the similarity matrices stay alive under the engine's workspace, which
+    // is carved after them on every attempt
+    const FusedTrees fz{&F, &d_fm_off, out->d_merge_list, prepare};
+    return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz);
+  }
+  r = cv.carve(c);
+  if (r) return r;
+  r = reset_status(c, stream);
+  if (r) return r;
+  r = prepare();
+  if (r) return r;
+  launch_upgma(F, d_fm_off, d_bucket_off, p, max_n, Sw, out->d_merge_list, d_bucket_off, c->st,
+               stream);
+  r = finish(c, stream);
+  if (r) return r;
   // the engine's workspace follows the k-mer/UPGMA buffers (merge lists are
   // in the caller's array, so those buffers are no longer needed)
   Carver base;
@@ -1130,6 +1176,7 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   launch_onehot_seq(ga_stage, ga_len_d, std::max(GL, 1), A, e.prof_pool + Wtot * A, stream);
   launch_fill_i32(e.node_parent, -1, 2 * q + 1, stream);
   launch_fill_i32(e.queue_flag, 0, q, stream);
+  launch_fill_i32(e.job_link, 0, q, stream);
   init_refine_ctl_kernel<<<1, 1, 0, stream>>>(e.tops, (unsigned long long)prof_fixed,
                                               (unsigned long long)(Wtot + GL), e.qctl);
   launch_refine_nodes(q, d_wo, d_width_u, d_rows_u, Wtot * A, Wtot, ga_len_d, A, 0, e.node_W,

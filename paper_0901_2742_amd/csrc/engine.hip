@@ -29,6 +29,7 @@
 #include <cstdlib>
 
 #include "sad_internal.h"
+#include "upgma_core.h"
 
 namespace sad {
 
@@ -844,6 +845,89 @@ __device__ void merge(const uint8_t* ops, int base, int nops, const uint16_t* P1
   }
 }
 
+// ---------------------------------------------------------------- job hand-off
+// Appends ready job j to the queue (one thread).
+__device__ inline void push_job(const EngineArgs& a, int j) {
+  __threadfence();
+  const int pos = atomicAdd(a.queue_tail, 1);
+  __hip_atomic_store(&a.queue[pos], j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();
+  __hip_atomic_store(&a.queue_flag[pos], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A finished job releases its share of its parent's count if the parent
+// already exists; otherwise the parent's creation does it (one thread).
+__device__ inline void job_finished(const EngineArgs& a, int job) {
+  const int old = atomicCAS(&a.job_link[job], 0, 1);
+  if (old != 2) return;
+  __threadfence();
+  const int nx = __hip_atomic_load(&a.job_next[job], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (atomicSub(&a.job_pending[nx], 1) == 1) push_job(a, nx);
+}
+
+// Creates the job of merge `step` of group g (cluster ids ia < ib, leaves
+// below n) as soon as UPGMA decides it (one thread).  Its count starts at one
+// per internal child plus one for the creation itself.
+__device__ inline void create_job(const EngineArgs& a, int g0, int n, int step, int ia, int ib) {
+  const int N = a.up_N;
+  const int s = g0 + step;
+  const int na = ia < n ? g0 + ia : N + g0 + (ia - n);
+  const int nb = ib < n ? g0 + ib : N + g0 + (ib - n);
+  a.job_a[s] = na;
+  a.job_b[s] = nb;
+  a.job_out[s] = N + s;
+  a.node_parent[na] = N + s;
+  a.node_parent[nb] = N + s;
+  __hip_atomic_store(&a.job_pending[s], 1 + (ia >= n) + (ib >= n), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();
+  const int kids[2] = {ia, ib};
+  for (int q = 0; q < 2; ++q) {
+    if (kids[q] < n) continue;
+    const int c = g0 + (kids[q] - n);
+    __hip_atomic_store(&a.job_next[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    if (atomicCAS(&a.job_link[c], 0, 2) == 1) atomicSub(&a.job_pending[s], 1);
+  }
+  if (atomicSub(&a.job_pending[s], 1) == 1) push_job(a, s);
+}
+
+// Largest group whose guide tree is built inside the engine: the triangle of
+// 64-bit pair sums must fit in the score ring's LDS and the five cluster
+// arrays in the traceback staging block.
+constexpr int kFusedMaxN = 182;
+
+// UPGMA of group g by the whole workgroup, pair sums in LDS (ring), cluster
+// arrays in tbst.
+__device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t* tbst, Cand* red,
+                           int32_t* nrec) {
+  const int g0 = a.up_group_off[g], n = a.up_group_off[g + 1] - g0;
+  if (n <= 1) return;
+  const int tid = threadIdx.x;
+  uint64_t* tri = reinterpret_cast<uint64_t*>(ring);
+  int32_t* id = reinterpret_cast<int32_t*>(tbst);
+  int32_t* sz = id + n;
+  int32_t* active = id + 2 * n;
+  int32_t* best = id + 3 * n;
+  int32_t* rec = id + 4 * n;
+  for (int x = tid; x < n; x += kThreads) {
+    id[x] = x;
+    sz[x] = 1;
+    active[x] = 1;
+  }
+  const uint32_t* Fg = a.up_F + a.up_fm_off[g];
+  for (int64_t q = tid; q < (int64_t)n * n; q += kThreads) {
+    const int x = (int)(q / n), y = (int)(q % n);
+    if (x < y) tri[x * n - x * (x + 1) / 2 + y - x - 1] = Fg[q];
+  }
+  __threadfence_block();
+  __syncthreads();
+  const TriS S{tri, n};
+  upgma_group(S, n, id, sz, active, best, rec, nrec, red, a.up_merges + 2 * (int64_t)g0, g, a.st,
+              [&](int step, int ia, int ib) { create_job(a, g0, n, step, ia, ib); });
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- kernel
 template <int A, bool MFMA>
 __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
@@ -868,6 +952,25 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   uint32_t* myring = ring + wave * kRingWords;
   __syncthreads();
 
+  if constexpr (MFMA) {
+    static_assert(kUpgmaThreads == kThreads, "tree phase uses the engine's workgroup shape");
+    static_assert(5 * kFusedMaxN <= kStageT4 * 64, "cluster arrays fit the staging block");
+    static_assert((int64_t)kFusedMaxN * (kFusedMaxN - 1) / 2 * 8 <=
+                      (int64_t)kWaves * kRingWords * 4, "pair sums fit the score ring");
+    // guide trees first; their merges become jobs for the other workgroups
+    __shared__ Cand ured[2 * kUpgmaWaves];
+    __shared__ int32_t unrec, ugrp;
+    if (a.up_ngroups > 0) {
+      for (;;) {
+        if (tid == 0) ugrp = atomicAdd(a.up_next, 1);
+        __syncthreads();
+        const int g = ugrp;
+        __syncthreads();
+        if (g >= a.up_ngroups) break;
+        fused_tree(a, g, ring, tbst, ured, &unrec);
+      }
+    }
+  }
   uint64_t tk0 = 0, tk1 = 0, tk2 = 0, tk3 = 0, tk35 = 0;  // phase timestamps (thread 0)
   for (;;) {
     // ---- fetch a ready job (thread 0) and describe it to the workgroup
@@ -1084,22 +1187,12 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         r[7] = (long long)tk35;
       }
     }
-    if (tid == 0 && !a.no_push) {
-      const int nx = a.job_next[job];
-      if (nx >= 0) {
-        const int prev = atomicSub(&a.job_pending[nx], 1);
-        if (prev == 1) {
-          __threadfence();
-          const int pos = atomicAdd(a.queue_tail, 1);
-          __hip_atomic_store(&a.queue[pos], nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __threadfence();
-          __hip_atomic_store(&a.queue_flag[pos], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-    }
+    if (tid == 0 && !a.no_push) job_finished(a, job);
     __syncthreads();
   }
 }
+
+int engine_fused_max_group() { return kFusedMaxN; }
 
 int engine_workgroups() {
   int per_cu = kEngineWGPerCU;

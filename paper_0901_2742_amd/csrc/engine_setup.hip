@@ -67,8 +67,8 @@ __global__ void make_jobs_kernel(const int32_t* __restrict__ merges,
                                  const int32_t* __restrict__ group_off, int ngroups, int nslots,
                                  int32_t internal_base, int32_t* node_parent, int32_t* job_a,
                                  int32_t* job_b, int32_t* job_out, int32_t* job_next,
-                                 int32_t* job_pending, int32_t* queue, int32_t* queue_flag,
-                                 int32_t* queue_tail) {
+                                 int32_t* job_pending, int32_t* job_link, int32_t* queue,
+                                 int32_t* queue_flag, int32_t* queue_tail) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nslots) return;
   int lo = 0, hi = ngroups;
@@ -92,12 +92,15 @@ __global__ void make_jobs_kernel(const int32_t* __restrict__ merges,
   node_parent[a] = internal_base + s;
   node_parent[b] = internal_base + s;
   int pending = 0;
+  // parents exist before any job runs: every child's hand-off word says so
   if (la >= ng) {
     job_next[g0 + (la - ng)] = s;
+    job_link[g0 + (la - ng)] = 2;
     ++pending;
   }
   if (lb >= ng) {
     job_next[g0 + (lb - ng)] = s;
+    job_link[g0 + (lb - ng)] = 2;
     ++pending;
   }
   job_pending[s] = pending;
@@ -110,12 +113,13 @@ __global__ void make_jobs_kernel(const int32_t* __restrict__ merges,
 
 void launch_make_jobs(const int32_t* merges, const int32_t* group_off, int ngroups, int nslots,
                       int32_t internal_base, int32_t* node_parent, int32_t* job_a, int32_t* job_b,
-                      int32_t* job_out, int32_t* job_next, int32_t* job_pending, int32_t* queue,
-                      int32_t* queue_flag, int32_t* queue_tail, hipStream_t stream) {
+                      int32_t* job_out, int32_t* job_next, int32_t* job_pending, int32_t* job_link,
+                      int32_t* queue, int32_t* queue_flag, int32_t* queue_tail,
+                      hipStream_t stream) {
   if (nslots <= 0) return;
   make_jobs_kernel<<<(nslots + 255) / 256, 256, 0, stream>>>(
       merges, group_off, ngroups, nslots, internal_base, node_parent, job_a, job_b, job_out,
-      job_next, job_pending, queue, queue_flag, queue_tail);
+      job_next, job_pending, job_link, queue, queue_flag, queue_tail);
 }
 
 // Column of every residue in its tree's root: leaf node of member position r

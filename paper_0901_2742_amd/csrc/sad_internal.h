@@ -150,6 +150,20 @@ struct EngineArgs {
   long long* job_rec;  // optional: per job slot W1, W2, ops and five phase timestamps (8 words)
   int32_t nrec;        // job slots in job_rec
   int32_t no_push;     // 1: finished jobs do not queue their parents (level-by-level launches)
+  // Per job slot: hand-off word between a finished job and its parent's
+  // creation (0 neither yet, 1 the job finished first, 2 the parent exists):
+  // whichever comes second releases the job's share of the parent's count.
+  int32_t* job_link;
+  // Fused guide trees (up_ngroups > 0): workgroups first build the UPGMA
+  // trees of groups claimed from *up_next, creating each merge's job as soon
+  // as it is decided; leaves are nodes group_off[g] + x, internal nodes
+  // up_N + slot.
+  const uint32_t* up_F;
+  const int64_t* up_fm_off;
+  const int32_t* up_group_off;
+  int32_t up_ngroups, up_N;
+  int32_t* up_merges;
+  int32_t* up_next;
   DevStatus* st;
 };
 void launch_engine(const EngineArgs& a, int nwg, hipStream_t stream);
@@ -163,10 +177,12 @@ void launch_make_leaves(const uint8_t* codes, const int64_t* offsets, const int3
                         int64_t* node_prof, int64_t* node_up, int32_t* node_parent,
                         uint16_t* prof_pool, int64_t total_len, hipStream_t stream);
 // Jobs from UPGMA merge lists (one group per bucket, slots = member positions).
+int engine_fused_max_group();  // largest group the engine builds its guide tree for
 void launch_make_jobs(const int32_t* merges, const int32_t* group_off, int ngroups, int nslots,
                       int32_t internal_base, int32_t* node_parent, int32_t* job_a, int32_t* job_b,
-                      int32_t* job_out, int32_t* job_next, int32_t* job_pending, int32_t* queue,
-                      int32_t* queue_flag, int32_t* queue_tail, hipStream_t stream);
+                      int32_t* job_out, int32_t* job_next, int32_t* job_pending, int32_t* job_link,
+                      int32_t* queue, int32_t* queue_flag, int32_t* queue_tail,
+                      hipStream_t stream);
 void launch_colmap(const int64_t* offsets, const int32_t* ids, int nleaves,
                    const int32_t* node_parent, const int64_t* node_up, const int32_t* up_pool,
                    int32_t* colmap, DevStatus* st, hipStream_t stream);
