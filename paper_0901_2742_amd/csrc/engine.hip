@@ -686,13 +686,82 @@ __device__ inline void ops_store(uint8_t* ops, int cap, int lane, int32_t acc, i
   if (lane >= 64 - pend) ops[cap - 1 - (k - 64 + lane)] = (uint8_t)state_op(acc);
 }
 
-// Writes the op string to ops[cap - n .. cap); returns n.  Whole wave.
-__device__ __forceinline__ int traceback(const uint32_t* tbw, uint32_t* tbst, uint8_t* ops, int W1,
-                                         int W2, int nchunks, int lane) {
+// Tie words of the strip the walk is on, from 16 x 64-word blocks staged in
+// LDS on demand.
+struct StageSource {
+  const uint32_t* tbw;
+  uint32_t* tbst;
   Stage st;
-  st.s = -1;
-  st.t4a = 0;
-  const int stride_s = nchunks * 16 * 64, T4 = nchunks * 16;
+  int stride_s, T4;
+  __device__ void cover(int lane, int s, int t4lo, int t4hi) {
+    stage_cover(tbw, tbst, st, stride_s, T4, lane, s, t4lo, t4hi);
+  }
+  __device__ uint32_t word(int, int t4, int lc) const { return tbst[(t4 - st.t4a) * 64 + lc]; }
+  __device__ void finish() {}
+};
+
+// Whole strips in LDS, copied by a helper wave (strip_loader) while the walk
+// proceeds: strip s goes to buffer s & 1.  The walk waits for ready[b] == s
+// and, leaving a strip, sets consumed[b] to it so the buffer can be refilled.
+struct StripSource {
+  const uint32_t* buf;
+  int words;  // per strip
+  int32_t* ready;
+  int32_t* consumed;
+  int32_t* fin;
+  int64_t wait_ticks;
+  int cur;
+  __device__ void cover(int, int s, int, int) {
+    if (s == cur) return;
+    if (cur >= 0)
+      __hip_atomic_store(&consumed[cur & 1], cur, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    cur = s;
+    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(&ready[s & 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != s) {
+      __builtin_amdgcn_s_sleep(1);
+      // the loader always makes progress; the limit only guards a broken wait
+      if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > wait_ticks) break;
+    }
+  }
+  __device__ uint32_t word(int s, int t4, int lc) const {
+    return buf[(s & 1) * words + t4 * 64 + lc];
+  }
+  __device__ void finish() {
+    __hip_atomic_store(fin, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+// Helper wave of StripSource: copies strips sL, sL - 1, ... (each nchunks x
+// 4 KB, contiguous) into the two LDS buffers with direct-to-LDS loads.
+__device__ void strip_loader(const uint32_t* tbw, uint32_t* buf, int words, int sL,
+                             int32_t* ready, int32_t* consumed, int32_t* fin, int64_t wait_ticks,
+                             int lane) {
+  for (int s = sL; s >= 0; --s) {
+    const int b = s & 1;
+    if (s <= sL - 2) {
+      const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+      while (__hip_atomic_load(&consumed[b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) !=
+             s + 2) {
+        if (__hip_atomic_load(fin, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
+        __builtin_amdgcn_s_sleep(1);
+        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > wait_ticks) return;
+      }
+    } else if (__hip_atomic_load(fin, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+      return;
+    }
+    const uint32_t* src = tbw + (int64_t)s * words + lane * 4;
+    uint32_t* dst = buf + b * words;
+    for (int q = 0; q < words; q += 256)
+      __builtin_amdgcn_global_load_lds(src + q, (__attribute__((address_space(3))) void*)(dst + q),
+                                       16, 0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_store(&ready[b], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// Writes the op string to ops[cap - n .. cap); returns n.  Whole wave.
+template <typename Src>
+__device__ __forceinline__ int traceback(Src& src, uint8_t* ops, int W1, int W2, int lane) {
   const int cap = W1 + W2;
   int32_t acc = 0;
   int k = 0, kst = 0;
@@ -706,12 +775,12 @@ __device__ __forceinline__ int traceback(const uint32_t* tbw, uint32_t* tbst, ui
     const int ilow = max(lo, i - 7);
     const int t_hi = j - 1 + l;
     const int t_lo = max(0, j - 8) + ((ilow - 1) & 63);
-    stage_cover(tbw, tbst, st, stride_s, T4, lane, s, t_lo >> 2, t_hi >> 2);
+    src.cover(lane, s, t_lo >> 2, t_hi >> 2);
     const int ci = i - qi, cj = j - qj;
     uint32_t byte = 0;
     if (ci >= lo && cj >= 1) {
       const int lc = (ci - 1) & 63, t = cj - 1 + lc;
-      const uint32_t word = tbst[((t >> 2) - st.t4a) * 64 + lc];
+      const uint32_t word = src.word(s, t >> 2, lc);
       byte = (word >> (8 * (t & 3))) & 0xffu;
     }
     const int32_t v = (int32_t)next_table(byte);
@@ -733,6 +802,7 @@ __device__ __forceinline__ int traceback(const uint32_t* tbw, uint32_t* tbst, ui
     i -= idx >> 3;
     j -= idx & 7;
   }
+  src.finish();
   for (; i > 0; --i) {
     if (k - kst == 64) {
       ops_store(ops, cap, lane, acc, k, kst);
@@ -940,6 +1010,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   __shared__ int32_t Ssh[A * A];
   __shared__ int32_t prog[kMaxStrips];
   __shared__ int32_t gcnt[2 * kMaxWidth / 64];
+  __shared__ int32_t tbctl[5];  // strip staging: ready[2], consumed[2], fin
   __shared__ JobInfo J;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int q = tid; q < A * A; q += kThreads) Ssh[q] = a.S[q];
@@ -1084,6 +1155,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
 
     if (!J.err) {
       for (int L = tid; L < kMaxStrips; L += kThreads) prog[L] = 0;
+      if (tid < 5) tbctl[tid] = tid < 4 ? -1 : 0;
       __syncthreads();
       if (W1 > 0 && W2 > 0) {
         if constexpr (MFMA) {
@@ -1120,8 +1192,23 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
     }
     if (tid == 0) tk2 = __builtin_amdgcn_s_memrealtime();
     if (!J.err) {
-      if (wave == 0) {
-        const int n = traceback(tbw, tbst, ops, W1, W2, J.nchunks, lane);
+      const int nchunks = J.nchunks;
+      const int sw = nchunks * 16 * 64;  // tie words per strip
+      bool strips_in_lds = false;
+      if constexpr (MFMA) strips_in_lds = 2 * sw <= kWaves * kRingWords;
+      if (strips_in_lds) {
+        // wave 1 streams whole strips into the (idle) score ring
+        if (wave == 0) {
+          StripSource src{ring, sw, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks, -1};
+          const int n = traceback(src, ops, W1, W2, lane);
+          if (lane == 0) J.nops = n;
+        } else if (wave == 1) {
+          strip_loader(tbw, ring, sw, (W1 - 1) >> 6, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks,
+                       lane);
+        }
+      } else if (wave == 0) {
+        StageSource src{tbw, tbst, Stage{-1, 0}, sw, nchunks * 16};
+        const int n = traceback(src, ops, W1, W2, lane);
         if (lane == 0) J.nops = n;
       }
       __syncthreads();
