@@ -164,11 +164,29 @@ int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off, const int3
                    int32_t ga_cap, int32_t* ga_len, sad_msa* global_out, int32_t* n_steps,
                    hipStream_t stream);
 
-/* Kernel timing for measurement tools.  While enabled, every launch of the
+/* Autotuner for sad_align_buckets (batching of the bucket merges, Section
+ * 2.3.3 step 11).  Runs the call on the given buckets under each candidate
+ * schedule, twice each, timing the second run with HIP events on `stream`:
+ * batched mode: persistent grid of 1, 3/4 or 1/2 workgroup per CU, guide trees
+ * built inside the engine launch or by a separate kernel; plain mode: 1, 2 or
+ * 3 workgroups per CU for the per-level launches.  The fastest is kept in a
+ * process-wide cache keyed by (alphabet, n, p, mode, largest bucket, total
+ * length) and used by later sad_align_buckets calls with that key; results
+ * never depend on the schedule.  `out` receives the last run's (identical)
+ * results.  *grid_out = chosen workgroup count (0 = default), *fuse_out = 1
+ * trees in the launch, 0 separate (either may be NULL). */
+int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off, const int32_t* d_members,
+                 const sad_params* prm, sad_msa* out, int32_t* grid_out, int32_t* fuse_out,
+                 hipStream_t stream);
+
+/* Kernel timing for measurement tools.  on & 1: every launch of the
  * alignment engine kernel (the DP + traceback + merge kernel that dominates
- * stages 3 and 4) is bracketed by HIP events on the call's stream; the
- * accumulated time and launch count are read (and optionally reset) with
- * sad_profile_read.  Disabled by default; enabling adds no device work. */
+ * stages 3 and 4) is bracketed by HIP events on the call's stream (a replayed
+ * launch too: the engine is a graph of its own); the accumulated time and
+ * launch count are read (and optionally reset) with sad_profile_read.  on & 2: per-job phase
+ * ticks and per-job records as well (sad_profile_phases, sad_profile_jobs;
+ * this turns the graph replay of sad_align_buckets off).  Disabled by
+ * default. */
 int32_t sad_profile_enable(int32_t on);
 int32_t sad_profile_read(double* engine_ms, int64_t* engine_launches, int32_t reset);
 /* Per-job phase times of the alignment engine while profiling is enabled,
@@ -183,6 +201,16 @@ int32_t sad_profile_phases(double* ms_out, int64_t* jobs, int32_t reset);
  * to it).  Copies min(cap, n) records to host memory `out` (may be NULL);
  * *njobs = n. */
 int32_t sad_profile_jobs(int64_t* out, int64_t cap, int64_t* njobs);
+
+/* Graphs: in batched mode with the guide trees built inside the engine
+ * launch, sad_align_buckets records its device work (k-mer lists, similarity
+ * matrices, engine set-up, the persistent launch, result kernels) into a
+ * hipGraph after a successful eager call and replays it on later calls whose
+ * baked-in arguments (buffers, sizes, parameters, stream) are unchanged;
+ * SAD_GRAPHS=0 in the environment disables this. */
+
+/* Graph captures and replays of sad_align_buckets since the last reset. */
+int32_t sad_profile_graphs(int64_t* captured, int64_t* replayed, int32_t reset);
 
 /* Message for the calling thread's last non-OK status (static storage). */
 const char* sad_last_error(void);

@@ -26,8 +26,8 @@ SAD_PLAIN = 0
 SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
-EXPORTS = ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine",
-           "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs",
+EXPORTS = ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine", "sad_tune",
+           "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs", "sad_profile_graphs",
            "sad_last_error",
            "sad_release",
            "sad_version")
@@ -84,6 +84,10 @@ def lib():
         L.sad_profile_phases.restype = I32
         L.sad_profile_jobs.argtypes = [P, ctypes.c_int64, P]
         L.sad_profile_jobs.restype = I32
+        L.sad_tune.argtypes = [P, P, P, P, P, P, P, P]
+        L.sad_tune.restype = I32
+        L.sad_profile_graphs.argtypes = [P, P, I32]
+        L.sad_profile_graphs.restype = I32
         L.sad_last_error.restype = ctypes.c_char_p
         L.sad_version.restype = ctypes.c_char_p
         L.sad_release.restype = None
@@ -147,13 +151,18 @@ class Params:
                          self.gap_extend, self.mode)
 
 
-def sad_kmer_rank(seqs: DeviceSeqs, prm: Params):
+def sad_kmer_rank(seqs: DeviceSeqs, prm: Params, out: dict | None = None):
     """Stage 1: globalised k-mer rank.  Returns (key[n] uint64 as int64 tensor,
-    sample_ids int32 tensor)."""
+    sample_ids int32 tensor).  `out` (a dict, filled on first use) keeps the
+    output buffers across calls."""
     dev = seqs.codes.device
-    key = torch.empty(max(seqs.n, 1), dtype=torch.int64, device=dev)
     cap = max(prm.s_max, prm.p) + prm.p
-    sid = torch.empty(cap, dtype=torch.int32, device=dev)
+    if out is None:
+        out = {}
+    if "key" not in out:
+        out["key"] = torch.empty(max(seqs.n, 1), dtype=torch.int64, device=dev)
+        out["sid"] = torch.empty(cap, dtype=torch.int32, device=dev)
+    key, sid = out["key"], out["sid"]
     ns = ctypes.c_int32(0)
     s, p = seqs.c_struct(), prm.c_struct()
     code = lib().sad_kmer_rank(ctypes.byref(s), ctypes.byref(p), _ptr(key), _ptr(sid), cap,
@@ -162,25 +171,28 @@ def sad_kmer_rank(seqs: DeviceSeqs, prm: Params):
     return key[:seqs.n], sid[:ns.value]
 
 
-def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params):
-    """Stage 2: pivots and buckets.  Returns a dict of device tensors."""
+def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params, bufs: dict | None = None):
+    """Stage 2: pivots and buckets.  Returns a dict of device tensors; `bufs`
+    (a dict, filled on first use) keeps the buffers across calls."""
     dev = key.device
     n, p = seqs.n, prm.p
-    out = dict(pivot_key=torch.empty(max(p - 1, 1), dtype=torch.int64, device=dev),
-               pivot_id=torch.empty(max(p - 1, 1), dtype=torch.int32, device=dev),
-               bucket=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
-               bucket_off=torch.empty(p + 1, dtype=torch.int32, device=dev),
-               members=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
+    if bufs is None:
+        bufs = {}
+    if "bucket_off" not in bufs:
+        bufs.update(pivot_key=torch.empty(max(p - 1, 1), dtype=torch.int64, device=dev),
+                    pivot_id=torch.empty(max(p - 1, 1), dtype=torch.int32, device=dev),
+                    bucket=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                    bucket_off=torch.empty(p + 1, dtype=torch.int32, device=dev),
+                    members=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
     s, pp = seqs.c_struct(), prm.c_struct()
     code = lib().sad_partition(ctypes.byref(s), _ptr(key), ctypes.byref(pp),
-                               _ptr(out["pivot_key"]), _ptr(out["pivot_id"]), _ptr(out["bucket"]),
-                               _ptr(out["bucket_off"]), _ptr(out["members"]), _stream())
+                               _ptr(bufs["pivot_key"]), _ptr(bufs["pivot_id"]),
+                               _ptr(bufs["bucket"]), _ptr(bufs["bucket_off"]),
+                               _ptr(bufs["members"]), _stream())
     _check(code, "sad_partition")
-    out["pivot_key"] = out["pivot_key"][:p - 1]
-    out["pivot_id"] = out["pivot_id"][:p - 1]
-    out["bucket"] = out["bucket"][:n]
-    out["members"] = out["members"][:n]
-    return out
+    return dict(pivot_key=bufs["pivot_key"][:p - 1], pivot_id=bufs["pivot_id"][:p - 1],
+                bucket=bufs["bucket"][:n], bucket_off=bufs["bucket_off"],
+                members=bufs["members"][:n])
 
 
 def _msa_tensors(n_res: int, n_width: int, n_steps: int, dev):
@@ -236,8 +248,9 @@ def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor
     return out
 
 
-def sad_profile_enable(on: bool) -> None:
-    lib().sad_profile_enable(1 if on else 0)
+def sad_profile_enable(on: bool, phases: bool = False) -> None:
+    """Engine kernel timing; with phases=True also per-job phase records."""
+    lib().sad_profile_enable((1 if on else 0) | (2 if on and phases else 0))
 
 
 def sad_profile_read(reset: bool = False):
@@ -256,6 +269,28 @@ def sad_profile_phases(reset: bool = False):
     lib().sad_profile_phases(out, ctypes.byref(n), 1 if reset else 0)
     return dict(wait=out[0], dp=out[1], traceback=out[2], merge=out[3], publish=out[4],
                 jobs=n.value)
+
+
+def sad_tune(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, prm: Params,
+             out: dict | None = None):
+    """Autotunes the schedule of sad_align_buckets for these buckets (cached for
+    later calls with the same workload shape).  Returns (grid, fuse)."""
+    dev = seqs.codes.device
+    if out is None:
+        out = _msa_tensors(seqs.total_len, prm.p, seqs.n, dev)
+    s, pp, m = seqs.c_struct(), prm.c_struct(), _msa_struct(out)
+    g, f = ctypes.c_int32(0), ctypes.c_int32(0)
+    code = lib().sad_tune(ctypes.byref(s), _ptr(bucket_off), _ptr(members), ctypes.byref(pp),
+                          ctypes.byref(m), ctypes.byref(g), ctypes.byref(f), _stream())
+    _check(code, "sad_tune")
+    return g.value, f.value
+
+
+def sad_profile_graphs(reset: bool = False):
+    """(captures, replays) of the bucket-alignment graph since the last reset."""
+    c, r = ctypes.c_int64(0), ctypes.c_int64(0)
+    lib().sad_profile_graphs(ctypes.byref(c), ctypes.byref(r), 1 if reset else 0)
+    return c.value, r.value
 
 
 def sad_profile_jobs():

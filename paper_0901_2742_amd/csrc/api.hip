@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
+#include <map>
 #include <functional>
 #include <cstdio>
 #include <cstring>
@@ -28,6 +30,12 @@ struct DeviceCtx {
   unsigned long long* phase = nullptr;  // engine phase ticks (profiling)
   long long* jobrec = nullptr;          // per-job records (profiling)
   int64_t jobrec_cap = 0;
+  // captured launch sequence of the batched bucket alignment, replayed while
+  // every baked-in argument is unchanged
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};  // set-up, engine, results
+  std::vector<unsigned char> gkey;
+  std::vector<unsigned char> last_key;  // of the previous eager call
 };
 
 static std::mutex g_mu;
@@ -35,7 +43,9 @@ static std::vector<DeviceCtx> g_ctx;
 static thread_local std::string g_err;
 
 // engine-kernel timing (sad_profile_enable / sad_profile_read)
-static bool g_prof_on = false;
+static bool g_prof_on = false;   // engine kernel timing (HIP events)
+static bool g_phase_on = false;  // per-phase ticks and per-job records
+static int64_t g_graph_captured = 0, g_graph_replayed = 0;
 static double g_prof_ms = 0.0;
 static int64_t g_prof_launches = 0;
 static unsigned long long g_phase[6] = {0, 0, 0, 0, 0, 0};
@@ -174,7 +184,8 @@ static const char* where_name(int32_t w) {
 }
 
 static int32_t reset_status(DeviceCtx* c, hipStream_t s) {
-  HIPCHK(hipMemsetAsync(c->st, 0, sizeof(DevStatus), s));
+  static_assert(sizeof(DevStatus) % 4 == 0, "status is whole words");
+  launch_fill_i32(reinterpret_cast<int32_t*>(c->st), 0, sizeof(DevStatus) / 4, s);
   return SAD_OK;
 }
 
@@ -316,8 +327,8 @@ static int64_t tb_words_for(int wcap) {
 }
 
 static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, int njobs,
-                        int64_t prof_cap, int64_t up_cap, int wcap) {
-  e.nwg = std::max(1, std::min(njobs, engine_workgroups()));
+                        int64_t prof_cap, int64_t up_cap, int wcap, int grid = 0) {
+  e.nwg = std::max(1, std::min(njobs, grid > 0 ? grid : engine_workgroups()));
   e.prof_cap = prof_cap;
   e.up_cap = up_cap;
   e.tb_words = tb_words_for(wcap);
@@ -410,7 +421,7 @@ static int32_t attach_phases(DeviceCtx* c, EngineArgs& a, int nslots, hipStream_
   a.phase_acc = nullptr;
   a.job_rec = nullptr;
   a.nrec = 0;
-  if (!g_prof_on) return SAD_OK;
+  if (!g_phase_on) return SAD_OK;
   if (!c->phase) HIPCHK(hipMalloc(&c->phase, 8 * sizeof(unsigned long long)));
   HIPCHK(hipMemsetAsync(c->phase, 0, 8 * sizeof(unsigned long long), s));
   a.phase_acc = c->phase;
@@ -485,10 +496,63 @@ struct FusedTrees {
   uint32_t* const* F;            // carved with the caller's buffers (base carver)
   int64_t* const* d_fm_off;
   int32_t* d_merges;
-  // fills the similarity matrices after each carve (a regrown workspace
-  // loses earlier contents)
-  std::function<int32_t()> prepare;
+  // after each carve (a regrown workspace loses earlier contents): host
+  // upload of the matrix offsets, then the kernels that fill the matrices
+  std::function<int32_t()> upload;
+  std::function<void(hipStream_t)> kernels;
 };
+
+static bool graphs_enabled() {
+  const char* v = getenv("SAD_GRAPHS");
+  return !(v && v[0] == '0');
+}
+
+static void drop_graph(DeviceCtx* c) {
+  for (hipGraphExec_t& x : c->gexec) {
+    if (x) (void)hipGraphExecDestroy(x);
+    x = nullptr;
+  }
+  c->gkey.clear();
+}
+
+// Records the three parts of `enqueue(part, stream)` (kernel launches only:
+// set-up, the engine launch, result kernels) on the context's capture stream
+// as three graphs kept under `key` (the engine's own graph so that the
+// timing events can bracket it on the caller's stream).  Any failure leaves
+// the eager path in charge.
+template <class F>
+static void capture_graph(DeviceCtx* c, const std::vector<unsigned char>& key, F&& enqueue) {
+  drop_graph(c);
+  if (!c->cap_stream &&
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->cap_stream = nullptr;
+    (void)hipGetLastError();
+    return;
+  }
+  hipGraphExec_t ex[3] = {nullptr, nullptr, nullptr};
+  bool ok = true;
+  for (int part = 0; part < 3 && ok; ++part) {
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      ok = false;
+      break;
+    }
+    enqueue(part, c->cap_stream);
+    ok = hipStreamEndCapture(c->cap_stream, &g) == hipSuccess && g;
+    if (ok) ok = hipGraphInstantiate(&ex[part], g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+  }
+  (void)hipGetLastError();
+  if (!ok) {
+    for (hipGraphExec_t x : ex)
+      if (x) (void)hipGraphExecDestroy(x);
+    return;
+  }
+  for (int q = 0; q < 3; ++q) c->gexec[q] = ex[q];
+  c->gkey = key;
+  std::lock_guard<std::mutex> lk(g_mu);
+  ++g_graph_captured;
+}
 
 // Tree levels for level-by-level launches: a job's level is one more than its
 // children's (leaf-leaf merges are level 0).  Writes the jobs grouped by
@@ -585,7 +649,7 @@ static int32_t plan_priority(const TreeSet& ts, const int32_t* d_merges, const E
 static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
                          const sad_params* prm, int A, Carver& base_cv, EngineBuffers& e,
                          const TreeOutputs& out, hipStream_t stream,
-                         const FusedTrees* fused = nullptr) {
+                         const FusedTrees* fused = nullptr, int grid = 0) {
   const int N = ts.nleaves;
   int njobs = 0;
   for (int g = 0; g < ts.ngroups; ++g)
@@ -595,26 +659,84 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
   int64_t up_cap = ts.total_len * 6 + 4096;
   for (int attempt = 0; attempt < 8; ++attempt) {
     Carver cv = base_cv;
-    plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, prof_cap, up_cap, wcap);
+    plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, prof_cap, up_cap, wcap, grid);
     int32_t r = cv.carve(c);
     if (r) return r;
-    r = reset_status(c, stream);
-    if (r) return r;
     if (fused) {
-      r = fused->prepare();
+      r = fused->upload();
       if (r) return r;
     }
-    launch_fill_i32(e.node_parent, -1, 2 * (int64_t)std::max(N, 1), stream);
-    launch_fill_i32(e.job_next, -1, std::max(N, 1), stream);
-    launch_fill_i32(e.job_a, -1, std::max(N, 1), stream);
-    launch_fill_i32(e.queue_flag, 0, std::max(njobs, 1), stream);
-    launch_fill_i32(reinterpret_cast<int32_t*>(e.job_ops_off), -1, 2 * (int64_t)std::max(N, 1),
-                    stream);
-    init_engine_ctl_kernel<<<1, 1, 0, stream>>>(e.tops, (unsigned long long)ts.total_len * A,
-                                                (unsigned long long)ts.total_len, e.qctl);
-    launch_make_leaves(ts.d_codes, ts.d_offsets, ts.d_ids, N, A, 0, e.node_W, e.node_n,
-                       e.node_prof, e.node_up, e.node_parent, e.prof_pool, ts.total_len, stream);
-    launch_fill_i32(e.job_link, 0, std::max(N, 1), stream);
+    // device work before the engine (everything here is capturable)
+    auto setup = [&](hipStream_t st) {
+      reset_status(c, st);
+      if (fused) fused->kernels(st);
+      launch_fill_i32(e.node_parent, -1, 2 * (int64_t)std::max(N, 1), st);
+      launch_fill_i32(e.job_next, -1, std::max(N, 1), st);
+      launch_fill_i32(e.job_a, -1, std::max(N, 1), st);
+      launch_fill_i32(e.queue_flag, 0, std::max(njobs, 1), st);
+      launch_fill_i32(reinterpret_cast<int32_t*>(e.job_ops_off), -1,
+                      2 * (int64_t)std::max(N, 1), st);
+      init_engine_ctl_kernel<<<1, 1, 0, st>>>(e.tops, (unsigned long long)ts.total_len * A,
+                                              (unsigned long long)ts.total_len, e.qctl);
+      launch_make_leaves(ts.d_codes, ts.d_offsets, ts.d_ids, N, A, 0, e.node_W, e.node_n,
+                         e.node_prof, e.node_up, e.node_parent, e.prof_pool, ts.total_len, st);
+      launch_fill_i32(e.job_link, 0, std::max(N, 1), st);
+    };
+    auto results = [&](hipStream_t st) {
+      if (out.d_colmap)
+        launch_colmap(ts.d_offsets, ts.d_ids, N, e.node_parent, e.node_up, e.up_pool,
+                      out.d_colmap, c->st, st);
+      if (out.d_width) launch_widths(ts.d_group_off, ts.ngroups, N, e.node_W, out.d_width, st);
+      if (out.d_cells_total)
+        launch_fill_i32(reinterpret_cast<int32_t*>(out.d_cells_total), 0, 2, st);
+      if (out.d_score)
+        launch_job_results(e.job_a, e.job_score, e.job_cells, N, out.d_score, out.d_cells,
+                           out.d_cells_total, st);
+    };
+    // the batched launch with its guide trees built inside has no host step
+    // between setup and results: it is captured once into a hipGraph and
+    // replayed while its arguments (all baked into the graph) are unchanged
+    const bool graphable = fused && !g_phase_on && njobs > 0 && graphs_enabled();
+    std::vector<unsigned char> gkey;
+    if (graphable) {
+      EngineArgs ka = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend,
+                                  prm->mode, nullptr, c->st);
+      const uintptr_t extra[] = {(uintptr_t)ts.d_codes, (uintptr_t)ts.d_offsets,
+                                 (uintptr_t)ts.d_ids, (uintptr_t)ts.d_group_off,
+                                 (uintptr_t)*fused->F, (uintptr_t)*fused->d_fm_off,
+                                 (uintptr_t)fused->d_merges, (uintptr_t)out.d_colmap,
+                                 (uintptr_t)out.d_width, (uintptr_t)out.d_score,
+                                 (uintptr_t)out.d_cells, (uintptr_t)out.d_cells_total,
+                                 (uintptr_t)e.prof_pool, (uintptr_t)c->st,
+                                 (uintptr_t)N, (uintptr_t)ts.ngroups, (uintptr_t)ts.total_len,
+                                 (uintptr_t)A, (uintptr_t)e.nwg, (uintptr_t)stream};
+      gkey.resize(sizeof(ka) + sizeof(extra));
+      std::memcpy(gkey.data(), &ka, sizeof(ka));
+      std::memcpy(gkey.data() + sizeof(ka), extra, sizeof(extra));
+      if (c->gexec[0] && c->gkey == gkey) {
+        // the engine's graph is bracketed by the timing events on the stream
+        HIPCHK(hipGraphLaunch(c->gexec[0], stream));
+        EngineTimer timer(stream);
+        HIPCHK(hipGraphLaunch(c->gexec[1], stream));
+        timer.stop();
+        HIPCHK(hipGraphLaunch(c->gexec[2], stream));
+        {
+          std::lock_guard<std::mutex> lk(g_mu);
+          ++g_graph_replayed;
+        }
+        DevStatus d{};
+        r = read_status(c, stream, &d);
+        if (r) return r;
+        if (d.code == 0) {
+          timer.collect();
+          return SAD_OK;
+        }
+        // a replay that reports an error is redone eagerly (which also
+        // handles capacity retries)
+        drop_graph(c);
+      }
+    }
+    setup(stream);
     if (!fused)
       launch_make_jobs(d_merges, ts.d_group_off, ts.ngroups, N, N, e.node_parent, e.job_a,
                        e.job_b, e.job_out, e.job_next, e.job_pending, e.job_link, e.queue,
@@ -676,21 +798,55 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
       continue;
     }
     if (d.code) return status_to_code(d);
-    // results
     r = reset_status(c, stream);
     if (r) return r;
-    if (out.d_colmap)
-      launch_colmap(ts.d_offsets, ts.d_ids, N, e.node_parent, e.node_up, e.up_pool, out.d_colmap,
-                    c->st, stream);
-    if (out.d_width) launch_widths(ts.d_group_off, ts.ngroups, N, e.node_W, out.d_width, stream);
-    if (out.d_cells_total)
-      launch_fill_i32(reinterpret_cast<int32_t*>(out.d_cells_total), 0, 2, stream);
-    if (out.d_score)
-      launch_job_results(e.job_a, e.job_score, e.job_cells, N, out.d_score, out.d_cells,
-                         out.d_cells_total, stream);
-    return finish(c, stream);
+    results(stream);
+    r = finish(c, stream);
+    if (r || !graphable) return r;
+    // capture only when the same arguments come twice in a row
+    if (c->last_key != gkey) {
+      c->last_key = gkey;
+      return SAD_OK;
+    }
+    capture_graph(c, gkey, [&](int part, hipStream_t st) {
+      if (part == 0) setup(st);
+      if (part == 1) launch_engine(a, e.nwg, st);
+      if (part == 2) results(st);
+    });
+    return SAD_OK;
   }
   return fail(SAD_E_CAPACITY, "alignment engine workspace did not converge");
+}
+
+// ---------------------------------------------------------------- autotune
+// Schedule of the bucket alignment: persistent grid size (0 = one workgroup
+// per CU times the default occupancy) and whether the guide trees are built
+// inside the engine launch (-1 = default rule).  The results do not depend
+// on it.  sad_tune measures the candidates on the caller's data and caches
+// the fastest per workload shape; sad_align_buckets looks the shape up.
+struct Schedule {
+  int grid = 0;
+  int fuse = -1;
+};
+
+struct TuneKey {
+  int A, n, p, mode, max_n;
+  int64_t total_len;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(A, n, p, mode, max_n, total_len) <
+           std::tie(o.A, o.n, o.p, o.mode, o.max_n, o.total_len);
+  }
+};
+
+static std::mutex g_tune_mu;
+static std::map<TuneKey, Schedule> g_tune;
+static thread_local const Schedule* g_forced = nullptr;  // set while sad_tune measures
+
+static Schedule schedule_for(const TuneKey& k) {
+  if (g_forced) return *g_forced;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(k);
+  return it == g_tune.end() ? Schedule{} : it->second;
 }
 
 }  // namespace sad
@@ -818,7 +974,9 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   uint64_t* Sw;
   // batched mode with small enough buckets: the guide trees are built inside
   // the engine launch, which starts aligning each merge as soon as it is known
-  const bool fuse = prm->mode == SAD_BATCHED_MFMA && max_n <= engine_fused_max_group();
+  const Schedule sched = schedule_for(TuneKey{A, n, p, (int)prm->mode, max_n, seqs->total_len});
+  const bool fuse = prm->mode == SAD_BATCHED_MFMA && max_n <= engine_fused_max_group() &&
+                    sched.fuse != 0;
   Carver cv;
   cv.add(entries, (size_t)std::max<int64_t>(seqs->total_len, 1));
   cv.add(nu, std::max(n, 1));
@@ -826,17 +984,14 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   cv.add(F, (size_t)std::max<int64_t>(fm_total, 1));
   if (!fuse) cv.add(Sw, (size_t)std::max<int64_t>(fm_total, 1));
   // k-mer lists and per-bucket similarity matrices into the carved buffers
-  auto prepare = [&]() -> int32_t {
-    int32_t q = h2d(fm_off, d_fm_off, stream);
-    if (q) return q;
-    launch_fill_i32(out->d_merge_list, -1, 2 * (int64_t)n, stream);
-    launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_score), 0, 2 * (int64_t)n, stream);
-    launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_cells), 0, 2 * (int64_t)n, stream);
-    launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st,
-                      stream);
+  auto upload = [&]() -> int32_t { return h2d(fm_off, d_fm_off, stream); };
+  auto kernels = [&](hipStream_t st) {
+    launch_fill_i32(out->d_merge_list, -1, 2 * (int64_t)n, st);
+    launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_score), 0, 2 * (int64_t)n, st);
+    launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_cells), 0, 2 * (int64_t)n, st);
+    launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st, st);
     KmerLists kl{entries, seqs->d_offsets, nu, seqs->d_offsets};
-    launch_fmatrix_groups(kl, d_bucket_off, d_members, p, n, d_fm_off, k, kspace, F, stream);
-    return SAD_OK;
+    launch_fmatrix_groups(kl, d_bucket_off, d_members, p, n, d_fm_off, k, kspace, F, st);
   };
   TreeSet ts;
   ts.ngroups = p;
@@ -855,15 +1010,16 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   if (fuse) {
     // the similarity matrices stay alive under the engine's workspace, which
     // is carved after them on every attempt
-    const FusedTrees fz{&F, &d_fm_off, out->d_merge_list, prepare};
-    return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz);
+    const FusedTrees fz{&F, &d_fm_off, out->d_merge_list, upload, kernels};
+    return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz, sched.grid);
   }
   r = cv.carve(c);
   if (r) return r;
   r = reset_status(c, stream);
   if (r) return r;
-  r = prepare();
+  r = upload();
   if (r) return r;
+  kernels(stream);
   launch_upgma(F, d_fm_off, d_bucket_off, p, max_n, Sw, out->d_merge_list, d_bucket_off, c->st,
                stream);
   r = finish(c, stream);
@@ -871,7 +1027,64 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   // the engine's workspace follows the k-mer/UPGMA buffers (merge lists are
   // in the caller's array, so those buffers are no longer needed)
   Carver base;
-  return run_trees(c, ts, out->d_merge_list, prm, A, base, e, to, stream);
+  return run_trees(c, ts, out->d_merge_list, prm, A, base, e, to, stream, nullptr, sched.grid);
+}
+
+extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                            const int32_t* d_members, const sad_params* prm, sad_msa* out,
+                            int32_t* grid_out, int32_t* fuse_out, hipStream_t stream) {
+  if (!prm || !out || !seqs) return fail(SAD_E_INVAL, "null argument");
+  if (!d_bucket_off) return fail(SAD_E_INVAL, "null device array");
+  DeviceCtx* c = nullptr;
+  int32_t r = get_ctx(&c);
+  if (r) return r;
+  std::vector<int32_t> off;
+  r = d2h(c, d_bucket_off, (size_t)prm->p + 1, off, stream);
+  if (r) return r;
+  int max_n = 0;
+  for (int b = 0; b < prm->p; ++b) max_n = std::max(max_n, off[b + 1] - off[b]);
+  const TuneKey key{seqs->alphabet, seqs->n, prm->p, (int)prm->mode, max_n, seqs->total_len};
+  const int cus = std::max(1, engine_workgroups());
+  std::vector<Schedule> cand;
+  if (prm->mode == SAD_BATCHED_MFMA) {
+    // one workgroup per CU fits (LDS); try smaller grids and both tree modes
+    for (int fuse : {1, 0})
+      for (int den : {4, 3, 2}) cand.push_back(Schedule{cus * den / 4, fuse});
+  } else {
+    for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, 0});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  Schedule best{};
+  float best_ms = 0.0f;
+  for (const Schedule& sc : cand) {
+    g_forced = &sc;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && r == SAD_OK; ++rep) {
+      HIPCHK(hipEventRecord(e0, stream));
+      r = sad_align_buckets(seqs, d_bucket_off, d_members, prm, out, stream);
+      HIPCHK(hipEventRecord(e1, stream));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));  // the second (warm) run counts
+    }
+    g_forced = nullptr;
+    if (r) break;
+    if (best_ms == 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = sc;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r) return r;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+  }
+  if (grid_out) *grid_out = best.grid;
+  if (fuse_out) *fuse_out = best.fuse;
+  return SAD_OK;
 }
 
 namespace sad {
@@ -1214,7 +1427,8 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
 
 extern "C" int32_t sad_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_mu);
-  g_prof_on = on != 0;
+  g_prof_on = (on & 1) != 0;
+  g_phase_on = (on & 2) != 0;
   return SAD_OK;
 }
 
@@ -1242,6 +1456,14 @@ extern "C" int32_t sad_profile_phases(double* ms_out, int64_t* jobs, int32_t res
   return SAD_OK;
 }
 
+extern "C" int32_t sad_profile_graphs(int64_t* captured, int64_t* replayed, int32_t reset) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (captured) *captured = g_graph_captured;
+  if (replayed) *replayed = g_graph_replayed;
+  if (reset) g_graph_captured = g_graph_replayed = 0;
+  return SAD_OK;
+}
+
 extern "C" int32_t sad_profile_jobs(int64_t* out, int64_t cap, int64_t* njobs) {
   std::lock_guard<std::mutex> lk(g_mu);
   const int64_t n = (int64_t)g_jobrec.size() / 8;
@@ -1265,6 +1487,9 @@ extern "C" void sad_release(void) {
     if (c.h_small) hipHostFree(c.h_small);
     if (c.phase) hipFree(c.phase);
     if (c.jobrec) hipFree(c.jobrec);
+    for (hipGraphExec_t x : c.gexec)
+      if (x) hipGraphExecDestroy(x);
+    if (c.cap_stream) hipStreamDestroy(c.cap_stream);
     c = DeviceCtx{};
   }
 }

@@ -12,12 +12,18 @@ def to_device(codes, offsets, alphabet: int) -> B.DeviceSeqs:
     return B.DeviceSeqs.from_numpy(codes, offsets, alphabet)
 
 
-def run_device(seqs: B.DeviceSeqs, prm: B.Params) -> dict:
-    """All four stages; results stay on the device."""
-    key, samples = B.sad_kmer_rank(seqs, prm)
-    part = B.sad_partition(seqs, key, prm)
-    al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm)
-    rf = B.sad_refine(seqs, part["bucket_off"], part["members"], al, prm)
+def run_device(seqs: B.DeviceSeqs, prm: B.Params, bufs: dict | None = None) -> dict:
+    """All four stages; results stay on the device.  `bufs` (a dict, filled on
+    first use) keeps every output buffer across calls, so repeated passes over
+    the same input reuse them (and the library can replay its captured launch)."""
+    if bufs is None:
+        bufs = {}
+    key, samples = B.sad_kmer_rank(seqs, prm, bufs.setdefault("rank", {}))
+    part = B.sad_partition(seqs, key, prm, bufs.setdefault("part", {}))
+    al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm, bufs.get("align"))
+    bufs["align"] = al
+    rf = B.sad_refine(seqs, part["bucket_off"], part["members"], al, prm, bufs.get("refine"))
+    bufs["refine"] = rf
     return dict(key=key, samples=samples, part=part, align=al, refine=rf)
 
 
