@@ -307,6 +307,8 @@ struct EngineBuffers {
   int32_t *node_W, *node_n, *node_parent;
   int64_t *node_prof, *node_up;
   int32_t *job_a, *job_b, *job_out, *job_next, *job_pending, *job_link;
+  int32_t *coop_next, *coop_strips, *coop_owner;
+  int64_t* coop_score;
   int64_t *job_score, *job_cells, *job_ops_off;
   int32_t *queue, *queue_flag, *qctl;
   unsigned long long* tops;
@@ -345,18 +347,56 @@ static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, in
   cv.add(e.job_out, nslots);
   cv.add(e.job_next, nslots);
   cv.add(e.job_link, nslots);
+  cv.add(e.coop_next, nslots);
+  cv.add(e.coop_strips, nslots);
+  cv.add(e.coop_owner, nslots);
+  cv.add(e.coop_score, nslots);
   cv.add(e.job_pending, nslots);
   cv.add(e.job_score, nslots);
   cv.add(e.job_cells, nslots);
   cv.add(e.job_ops_off, nslots);
-  cv.add(e.queue, std::max(njobs, 1));
-  cv.add(e.queue_flag, std::max(njobs, 1));
-  cv.add(e.qctl, 4);
+  // merges and the helper tickets of cooperative merges
+  cv.add(e.queue, (size_t)std::max(njobs, 1) * (1 + kMaxHelpers));
+  cv.add(e.queue_flag, (size_t)std::max(njobs, 1) * (1 + kMaxHelpers));
+  cv.add(e.qctl, 8);
   cv.add(e.tops, 2);
   cv.add(e.prof_pool, (size_t)prof_cap);
   cv.add(e.up_pool, (size_t)up_cap);
   cv.add(e.tb, (size_t)e.nwg * (size_t)e.tb_words);
   cv.add(e.bnd, (size_t)e.nwg * (size_t)e.link_words);
+}
+
+// Boundary rows of cooperative merges cross workgroups (and L2 slices), so
+// they live in uncached device memory: one area per owner workgroup, one
+// workgroup per CU.  Allocated once per device and kept until the process
+// ends (uncached memory that a kernel has read is never handed back).
+// SAD_COOP=0 turns cooperation off.
+static int32_t* coop_buffer(int32_t* wgs) {
+  static std::mutex mu;
+  static int32_t* buf[64] = {};
+  static int32_t cnt[64] = {};
+  *wgs = 0;
+  const char* v = getenv("SAD_COOP");
+  if (v && v[0] == '0') return nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!buf[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      return nullptr;
+    void* p = nullptr;
+    if (hipExtMallocWithFlags(&p, (size_t)cus * kCoopWordsPerWG * sizeof(int32_t),
+                              hipDeviceMallocUncached) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    buf[dev] = static_cast<int32_t*>(p);
+    cnt[dev] = cus;
+  }
+  *wgs = cnt[dev];
+  return buf[dev];
 }
 
 static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const int8_t* S, int go,
@@ -388,6 +428,19 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
   a.queue_flag = e.queue_flag;
   a.queue_head = e.qctl;
   a.queue_tail = e.qctl + 1;
+  a.queue_cap = std::max(njobs, 1) * (1 + kMaxHelpers);
+  a.jobs_done = e.qctl + 3;
+  a.finished = e.qctl + 4;
+  a.coop_next = e.coop_next;
+  a.coop_strips = e.coop_strips;
+  a.coop_owner = e.coop_owner;
+  a.coop_score = e.coop_score;
+  a.coop_words_per_wg = kCoopWordsPerWG;
+  a.coop_wgs = 0;
+  if (mode == SAD_BATCHED_MFMA) {
+    a.coop_buf = coop_buffer(&a.coop_wgs);
+    if (!a.coop_buf) a.coop_wgs = 0;
+  }
   a.tb = e.tb;
   a.tb_words_per_wg = e.tb_words;
   a.bnd = e.bnd;
@@ -471,10 +524,8 @@ __global__ void init_engine_ctl_kernel(unsigned long long* tops, unsigned long l
                                        unsigned long long up0, int32_t* qctl) {
   tops[0] = prof0;
   tops[1] = up0;
-  qctl[0] = 0;
-  qctl[1] = 0;
-  qctl[2] = 0;
-  qctl[3] = 0;
+  // queue head, tail, next guide tree, merges done, finished
+  for (int q = 0; q < 8; ++q) qctl[q] = 0;
 }
 
 // Progressive alignment of every group of leaves along its UPGMA tree.
@@ -673,7 +724,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
       launch_fill_i32(e.node_parent, -1, 2 * (int64_t)std::max(N, 1), st);
       launch_fill_i32(e.job_next, -1, std::max(N, 1), st);
       launch_fill_i32(e.job_a, -1, std::max(N, 1), st);
-      launch_fill_i32(e.queue_flag, 0, std::max(njobs, 1), st);
+      launch_fill_i32(e.queue_flag, 0, (int64_t)std::max(njobs, 1) * (1 + kMaxHelpers), st);
       launch_fill_i32(reinterpret_cast<int32_t*>(e.job_ops_off), -1,
                       2 * (int64_t)std::max(N, 1), st);
       init_engine_ctl_kernel<<<1, 1, 0, st>>>(e.tops, (unsigned long long)ts.total_len * A,
@@ -1133,8 +1184,8 @@ __global__ void init_refine_ctl_kernel(unsigned long long* tops, unsigned long l
                                        unsigned long long up0, int32_t* qctl) {
   tops[0] = prof0;
   tops[1] = up0;
-  qctl[0] = 0;
-  qctl[1] = 0;
+  // queue head, tail, merges done, finished
+  for (int q = 0; q < 8; ++q) qctl[q] = 0;
 }
 
 }  // namespace sad
@@ -1388,7 +1439,7 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                         hipMemcpyDeviceToDevice, stream));
   launch_onehot_seq(ga_stage, ga_len_d, std::max(GL, 1), A, e.prof_pool + Wtot * A, stream);
   launch_fill_i32(e.node_parent, -1, 2 * q + 1, stream);
-  launch_fill_i32(e.queue_flag, 0, q, stream);
+  launch_fill_i32(e.queue_flag, 0, (int64_t)q * (1 + kMaxHelpers), stream);
   launch_fill_i32(e.job_link, 0, q, stream);
   init_refine_ctl_kernel<<<1, 1, 0, stream>>>(e.tops, (unsigned long long)prof_fixed,
                                               (unsigned long long)(Wtot + GL), e.qctl);

@@ -115,6 +115,7 @@ struct JobInfo {
   int64_t final_score;
   int32_t nops;
   int32_t nd_u, nd_c;  // digits of U and of the counts in the MFMA tile products
+  int32_t coop, helper, owner;  // cooperative merge; this workgroup only helps; owner workgroup
   long long prof_off, up_off;
 };
 
@@ -135,6 +136,58 @@ __device__ inline bool wait_link(const EngineArgs& a, JobInfo& J, const int32_t*
   }
   return true;
 }
+
+// Progress of a strip boundary row: an LDS counter of this workgroup, or an
+// uncached word written by another workgroup (cooperative merges).
+__device__ inline int32_t link_progress(const int32_t* lds, const int32_t* coop) {
+  if (lds) return __hip_atomic_load(lds, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int32_t v = __hip_atomic_load(coop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  asm volatile("" ::: "memory");  // the row's loads come after the progress load
+  return v;
+}
+
+// Waits until the boundary row has `need` columns; false on abort or time-out.
+__device__ inline bool wait_progress(const EngineArgs& a, JobInfo& J, const int32_t* lds,
+                                     const int32_t* coop, int need) {
+  if (link_progress(lds, coop) >= need) return true;
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+  while (link_progress(lds, coop) < need) {
+    if (__hip_atomic_load(&J.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
+    __builtin_amdgcn_s_sleep(1);
+    if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
+      __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if ((threadIdx.x & 63) == 0) raise_error(a.st, SAD_E_DEVICE, need, W_ENGINE_WAIT);
+      return false;
+    }
+  }
+  return true;
+}
+
+// A value of a boundary row, written by this workgroup or (cooperative
+// merges) by another: an agent-scope load, which does not take a line that
+// this CU's vector L1 may hold from before.  (One load form for both keeps the
+// compiler's address-space inference intact.)
+template <typename T>
+__device__ inline T load_link(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Where a strip's boundary rows come from and go to: the row above (H and X
+// of the previous strip's last row) under its progress counter, this strip's
+// last row and the counter to publish (null when no strip follows), and
+// where H(W1, W2) goes if this strip holds row W1.
+template <typename T>
+struct StripLinks {
+  const T* inH;
+  const T* inX;
+  const int32_t* in_lds;
+  const int32_t* in_coop;
+  T* outH;
+  T* outX;
+  int32_t* out_lds;
+  int32_t* out_coop;
+  int64_t* score;
+};
 
 // 64 DP steps of one strip.  MASK: some cells of the chunk lie outside
 // 1 <= j <= W2 and must leave H/X/Y untouched.  score(k, j) gives s(i, j) of
@@ -471,7 +524,7 @@ __device__ inline void tile_scores(const long (&ua)[3][2][Tile<A>::KS],
 // job aborted.
 template <int A, typename T>
 __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
-                              int32_t* prog, uint32_t* tbw, int32_t* links, const int32_t* S32,
+                              uint32_t* tbw, const StripLinks<T>& L, const int32_t* S32,
                               const uint16_t* P1, const uint16_t* P2) {
   constexpr int KS = Tile<A>::KS;
   const int W1 = J.W1, W2 = J.W2, nchunks = J.nchunks, nstrips = J.nstrips;
@@ -526,14 +579,6 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
   T X = DpNeg<T>::value, Y = DpNeg<T>::value;
   T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
   uint32_t* tbs = tbw + (int64_t)s * nchunks * 16 * 64;
-  // boundary rows: H and X of each strip's last row, link_stride 32-bit
-  // words per row (half as many 64-bit values)
-  const int stride = a.link_stride / (int)(sizeof(T) / 4);
-  T* lk = reinterpret_cast<T*>(links);
-  const T* inH = lk + (int64_t)(s - 1) * 2 * stride;
-  const T* inX = inH + stride;
-  T* outH = lk + (int64_t)s * 2 * stride;
-  T* outX = outH + stride;
   const int ntiles = (W2 + 63) >> 6;
   uint32_t bw[2][KS][4];
   T pbh = 0, pbx = DpNeg<T>::value;
@@ -548,15 +593,14 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
     }
     const int need = min(W2, 64 * c + 64);
     if (block) {
-      if (!wait_link(a, J, prog, s - 1, need)) return false;
-    } else if (__hip_atomic_load(&prog[s - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <
-               need) {
+      if (!wait_progress(a, J, L.in_lds, L.in_coop, need)) return false;
+    } else if (link_progress(L.in_lds, L.in_coop) < need) {
       have_link = false;
       return true;
     }
     if (jn <= W2) {
-      pbh = load_wg(inH + jn);
-      pbx = load_wg(inX + jn);
+      pbh = load_link(L.inH + jn);
+      pbx = load_link(L.inX + jn);
     }
     have_link = true;
     return true;
@@ -567,10 +611,10 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
     const int t0 = 64 * c;
     const int jn = t0 + 1 + lane;
     if (!have_link) {
-      if (!wait_link(a, J, prog, s - 1, min(W2, t0 + 64))) return false;
+      if (!wait_progress(a, J, L.in_lds, L.in_coop, min(W2, t0 + 64))) return false;
       if (jn <= W2) {
-        pbh = load_wg(inH + jn);
-        pbx = load_wg(inX + jn);
+        pbh = load_link(L.inH + jn);
+        pbx = load_link(L.inX + jn);
       }
     }
     const T bh = pbh, bx = pbx;
@@ -588,23 +632,119 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
       dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
     else
       dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
-    if (s + 1 < nstrips) {
+    if (L.outH) {
       // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
       const int jo = t0 + lane - 62;
       if (jo >= 1 && jo <= W2) {
-        outH[jo] = oh;
-        outX[jo] = ox;
+        L.outH[jo] = oh;
+        L.outX[jo] = ox;
       }
       const int done = (c + 1 == nchunks) ? W2 : min(W2, t0 + 1);
-      __builtin_amdgcn_s_waitcnt(0);  // the link stores have reached L2
-      __hip_atomic_store(&prog[s], done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __builtin_amdgcn_s_waitcnt(0);  // the link stores are complete
+      if (L.out_lds) {
+        __hip_atomic_store(L.out_lds, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        asm volatile("" ::: "memory");
+        __hip_atomic_store(L.out_coop, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     // tie words after the release, so that the wait above covers only the
     // link stores (and this chunk's loads)
 #pragma unroll
     for (int q = 0; q < 16; ++q) tbs[(t0 / 4 + q) * 64 + lane] = tw[q];
   }
-  if (s == ((W1 - 1) >> 6) && lane == ((W1 - 1) & 63)) J.final_score = H;
+  if (s == ((W1 - 1) >> 6) && lane == ((W1 - 1) & 63)) *L.score = (int64_t)H;
+  return true;
+}
+
+// Boundary rows of strip s of the current merge.  Within a workgroup they are
+// rows of its own link buffer (indexed by strip) under LDS counters; between
+// groups of a cooperative merge (COOP), rows of the owner's uncached area.
+// Every field is chosen by a select and written once, so that the struct stays
+// in registers.
+template <typename T, bool COOP>
+__device__ inline StripLinks<T> strip_links(const EngineArgs& a, JobInfo& J, int s, int32_t* prog,
+                                            int32_t* links, int32_t* area) {
+  const int ns = J.nstrips;
+  const int stride = a.link_stride / (int)(sizeof(T) / 4);
+  T* lk = reinterpret_cast<T*>(links);
+  const bool has_in = s > 0, has_out = s + 1 < ns;
+  const bool in_c = COOP && has_in && s % kCoopGroupStrips == 0;
+  const bool out_c = COOP && has_out && s % kCoopGroupStrips == kCoopGroupStrips - 1;
+  // group boundary rows: row b sits below group b
+  const int bi = s / kCoopGroupStrips - 1, bo = s / kCoopGroupStrips;
+  int32_t* rin = COOP ? area + 64 + (int64_t)bi * 2 * kCoopRowWords : nullptr;
+  int32_t* rout = COOP ? area + 64 + (int64_t)bo * 2 * kCoopRowWords : nullptr;
+  T* lin = lk + (int64_t)(s - 1) * 2 * stride;
+  T* lout = lk + (int64_t)s * 2 * stride;
+  StripLinks<T> L;
+  L.inH = !has_in ? nullptr : (in_c ? reinterpret_cast<const T*>(rin) : lin);
+  L.inX = !has_in ? nullptr
+                  : (in_c ? reinterpret_cast<const T*>(rin + kCoopRowWords) : lin + stride);
+  L.in_lds = (has_in && !in_c) ? &prog[s - 1] : nullptr;
+  L.in_coop = in_c ? area + bi : nullptr;
+  L.outH = !has_out ? nullptr : (out_c ? reinterpret_cast<T*>(rout) : lout);
+  L.outX = !has_out ? nullptr
+                    : (out_c ? reinterpret_cast<T*>(rout + kCoopRowWords) : lout + stride);
+  L.out_lds = (has_out && !out_c) ? &prog[s] : nullptr;
+  L.out_coop = out_c ? area + bo : nullptr;
+  L.score = COOP ? &a.coop_score[J.job] : &J.final_score;
+  return L;
+}
+
+// The DP of a cooperative merge on this workgroup: groups of 4 strips are
+// claimed in increasing order from the merge's counter (the owner starts with
+// group 0), wave w runs strip 4 g + w of each claimed group g.  Wave 0 claims
+// the next group when it reaches it, so the groups of one workgroup overlap as
+// the strips of one merge do.  Every finished strip makes its tie bytes (and
+// H(W1, W2)) visible device-wide, then counts itself.
+template <int A, typename T>
+__device__ bool coop_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, uint32_t* myring,
+                        int32_t* prog, int32_t* links, const int32_t* S32, const uint16_t* P1,
+                        const uint16_t* P2, int32_t* glist, int32_t* gstate) {
+  const int ns = J.nstrips;
+  const int ngroups = (ns + kCoopGroupStrips - 1) / kCoopGroupStrips;
+  uint32_t* tbw = a.tb + (int64_t)J.owner * a.tb_words_per_wg;
+  int32_t* area = a.coop_buf + (int64_t)J.owner * a.coop_words_per_wg;
+  for (int k = 0;; ++k) {
+    if (wave == 0 && lane == 0 &&
+        k >= __hip_atomic_load(&gstate[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+      const int g = atomicAdd(&a.coop_next[J.job], 1);
+      if (g < ngroups) {
+        for (int q = 0; q < kCoopGroupStrips; ++q) prog[g * kCoopGroupStrips + q] = 0;
+        glist[k] = g;
+        __hip_atomic_store(&gstate[0], k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        __hip_atomic_store(&gstate[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+    int have = 0;
+    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+      have = __hip_atomic_load(&gstate[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (have > k) break;
+      if (__hip_atomic_load(&gstate[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+        have = __hip_atomic_load(&gstate[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        break;
+      }
+      if (__hip_atomic_load(&J.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
+      __builtin_amdgcn_s_sleep(1);
+      if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
+        __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return false;
+      }
+    }
+    if (have <= k) break;
+    const int g = glist[k];
+    const int s = g * kCoopGroupStrips + wave;
+    if (s < ns) {
+      const StripLinks<T> L = strip_links<T, true>(a, J, s, prog, links, area);
+      if (!dp_strip_mfma<A, T>(a, J, s, lane, myring, tbw, L, S32, P1, P2)) return false;
+      __builtin_amdgcn_s_waitcnt(0);
+      __threadfence();
+      if (lane == 0) atomicAdd(&a.coop_strips[J.job], 1);
+    }
+  }
   return true;
 }
 
@@ -920,6 +1060,10 @@ __device__ void merge(const uint8_t* ops, int base, int nops, const uint16_t* P1
 __device__ inline void push_job(const EngineArgs& a, int j) {
   __threadfence();
   const int pos = atomicAdd(a.queue_tail, 1);
+  if (pos >= a.queue_cap) {  // cannot happen: at most 1 + kMaxHelpers tickets per merge
+    raise_error(a.st, SAD_E_CAPACITY, pos, W_ENGINE);
+    return;
+  }
   __hip_atomic_store(&a.queue[pos], j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __threadfence();
   __hip_atomic_store(&a.queue_flag[pos], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1011,8 +1155,11 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   __shared__ int32_t prog[kMaxStrips];
   __shared__ int32_t gcnt[2 * kMaxWidth / 64];
   __shared__ int32_t tbctl[5];  // strip staging: ready[2], consumed[2], fin
+  __shared__ int32_t glist[kCoopMaxGroups];  // groups of a cooperative merge claimed here
+  __shared__ int32_t gstate[2];              // groups claimed, no group left
   __shared__ JobInfo J;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
   for (int q = tid; q < A * A; q += kThreads) Ssh[q] = a.S[q];
   if constexpr (MFMA) {
     // S with its columns zero-padded to 32 (the K extent of the tile products)
@@ -1050,11 +1197,21 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       const int slot = atomicAdd(a.queue_head, 1);
       J.slot = slot;
       J.job = -1;
-      if (slot < a.njobs) {
+      J.helper = 0;
+      // the batched kernel's queue also carries helper tickets, so its slots
+      // outnumber the merges: workgroups leave when every merge is done
+      const int bound = MFMA ? a.queue_cap : a.njobs;
+      if (slot < bound) {
         const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
         bool ok = true;
-        while (__hip_atomic_load(&a.queue_flag[slot], __ATOMIC_ACQUIRE,
+        // relaxed polls (an agent-scope acquire invalidates cache lines that
+        // the working workgroups use); the fence below orders the job's reads
+        while (__hip_atomic_load(&a.queue_flag[slot], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          if (MFMA && __hip_atomic_load(a.finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = false;
+            break;
+          }
           __builtin_amdgcn_s_sleep(8);
           if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
             raise_error(a.st, SAD_E_DEVICE, slot, W_ENGINE_WAIT);
@@ -1064,7 +1221,10 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         }
         if (ok) {
           __threadfence();
-          J.job = __hip_atomic_load(&a.queue[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int ticket =
+              __hip_atomic_load(&a.queue[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          J.job = ticket & (kHelperTicket - 1);
+          J.helper = (ticket & kHelperTicket) ? 1 : 0;
         }
       }
       const int job = J.job;
@@ -1098,7 +1258,9 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         const int64_t tb_need = (int64_t)nstrips * nchunks * 16 * 64;
         const int cap = W1 + W2;
         int err = 0;
-        if (W1 > kMaxWidth || W2 > kMaxWidth) {
+        if (J.helper) {
+          // a helper only runs strips; its owner checked the merge already
+        } else if (W1 > kMaxWidth || W2 > kMaxWidth) {
           err = 1;
           raise_error(a.st, SAD_E_CAPACITY, cap, W_ENGINE_WIDTH);
         } else if (over64 || score_over) {
@@ -1115,7 +1277,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
           raise_error(a.st, SAD_E_CAPACITY, n1 + n2, W_ENGINE);
         }
         long long prof_off = 0, up_off = 0;
-        if (!err) {
+        if (!err && !J.helper) {
           prof_off = (long long)atomicAdd(a.prof_top, (unsigned long long)cap * A);
           up_off = (long long)atomicAdd(a.up_top, (unsigned long long)cap);
           if (prof_off + (long long)cap * A > a.prof_cap) {
@@ -1139,6 +1301,36 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         J.nd_u = umax <= 127 ? 1 : (umax <= 32639 ? 2 : 3);
         J.nd_c = n2 <= 127 ? 1 : (n2 <= 16383 ? 2 : 3);
         J.final_score = 0;
+        J.coop = 0;
+        J.owner = (int)blockIdx.x;
+        if constexpr (MFMA) {
+          const int ngroups = (nstrips + kCoopGroupStrips - 1) / kCoopGroupStrips;
+          if (J.helper) {
+            J.coop = 1;
+            J.owner = __hip_atomic_load(&a.coop_owner[job], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) - 1;
+            gstate[0] = 0;
+            gstate[1] = 0;
+          } else if (!err && ngroups > 1 && (int)blockIdx.x < a.coop_wgs) {
+            // cooperative merge: reset its boundary-row progress, group and
+            // strip counters, then queue helper tickets (the owner runs
+            // group 0 and claims further groups like any helper)
+            J.coop = 1;
+            int32_t* area = a.coop_buf + (int64_t)blockIdx.x * a.coop_words_per_wg;
+            for (int b = 0; b + 1 < ngroups; ++b)
+              __hip_atomic_store(&area[b], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a.coop_next[job] = 1;
+            a.coop_strips[job] = 0;
+            a.coop_owner[job] = (int)blockIdx.x + 1;
+            glist[0] = 0;
+            gstate[0] = 1;
+            gstate[1] = 0;
+            __builtin_amdgcn_s_waitcnt(0);
+            __threadfence();
+            for (int h = 0; h < min(ngroups - 1, kMaxHelpers); ++h)
+              push_job(a, job | kHelperTicket);
+          }
+        }
       }
     }
     __syncthreads();
@@ -1159,14 +1351,25 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       __syncthreads();
       if (W1 > 0 && W2 > 0) {
         if constexpr (MFMA) {
-          if (J.wide) {
-            for (int s = wave; s < J.nstrips; s += kWaves)
-              if (!dp_strip_mfma<A, int64_t>(a, J, s, lane, myring, prog, tbw, links, S32, P1, P2))
-                break;
+          if (J.coop) {
+            if (J.wide)
+              coop_dp<A, int64_t>(a, J, wave, lane, myring, prog, links, S32, P1, P2, glist,
+                                  gstate);
+            else
+              coop_dp<A, int32_t>(a, J, wave, lane, myring, prog, links, S32, P1, P2, glist,
+                                  gstate);
+          } else if (J.wide) {
+            for (int s = wave; s < J.nstrips; s += kWaves) {
+              const StripLinks<int64_t> L =
+                  strip_links<int64_t, false>(a, J, s, prog, links, nullptr);
+              if (!dp_strip_mfma<A, int64_t>(a, J, s, lane, myring, tbw, L, S32, P1, P2)) break;
+            }
           } else {
-            for (int s = wave; s < J.nstrips; s += kWaves)
-              if (!dp_strip_mfma<A, int32_t>(a, J, s, lane, myring, prog, tbw, links, S32, P1, P2))
-                break;
+            for (int s = wave; s < J.nstrips; s += kWaves) {
+              const StripLinks<int32_t> L =
+                  strip_links<int32_t, false>(a, J, s, prog, links, nullptr);
+              if (!dp_strip_mfma<A, int32_t>(a, J, s, lane, myring, tbw, L, S32, P1, P2)) break;
+            }
           }
         } else if (J.wide) {
           for (int s = wave; s < J.nstrips; s += kWaves)
@@ -1190,91 +1393,118 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         __syncthreads();
       }
     }
-    if (tid == 0) tk2 = __builtin_amdgcn_s_memrealtime();
-    if (!J.err) {
-      const int nchunks = J.nchunks;
-      const int sw = nchunks * 16 * 64;  // tie words per strip
-      bool strips_in_lds = false;
-      if constexpr (MFMA) strips_in_lds = 2 * sw <= kWaves * kRingWords;
-      if (strips_in_lds) {
-        // wave 1 streams whole strips into the (idle) score ring
-        if (wave == 0) {
-          StripSource src{ring, sw, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks, -1};
+    // a helper's part ends with its strips; the rest is the owner's
+    if (!J.helper) {
+      if (J.coop && !J.err) {
+        // every strip of the merge done (some on other workgroups), their tie
+        // bytes and H(W1, W2) visible here
+        if (tid == 0) {
+          const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+          while (__hip_atomic_load(&a.coop_strips[job], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) < J.nstrips) {
+            __builtin_amdgcn_s_sleep(2);
+            if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
+              raise_error(a.st, SAD_E_DEVICE, job, W_ENGINE_WAIT);
+              J.err = 1;
+              break;
+            }
+          }
+          __threadfence();
+          J.final_score =
+              __hip_atomic_load(&a.coop_score[job], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+      }
+      if (tid == 0) tk2 = __builtin_amdgcn_s_memrealtime();
+      if (!J.err) {
+        const int nchunks = J.nchunks;
+        const int sw = nchunks * 16 * 64;  // tie words per strip
+        bool strips_in_lds = false;
+        if constexpr (MFMA) strips_in_lds = 2 * sw <= kWaves * kRingWords;
+        if (strips_in_lds) {
+          // wave 1 streams whole strips into the (idle) score ring
+          if (wave == 0) {
+            StripSource src{ring, sw, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks, -1};
+            const int n = traceback(src, ops, W1, W2, lane);
+            if (lane == 0) J.nops = n;
+          } else if (wave == 1) {
+            strip_loader(tbw, ring, sw, (W1 - 1) >> 6, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks,
+                         lane);
+          }
+        } else if (wave == 0) {
+          StageSource src{tbw, tbst, Stage{-1, 0}, sw, nchunks * 16};
           const int n = traceback(src, ops, W1, W2, lane);
           if (lane == 0) J.nops = n;
-        } else if (wave == 1) {
-          strip_loader(tbw, ring, sw, (W1 - 1) >> 6, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks,
-                       lane);
         }
-      } else if (wave == 0) {
-        StageSource src{tbw, tbst, Stage{-1, 0}, sw, nchunks * 16};
-        const int n = traceback(src, ops, W1, W2, lane);
-        if (lane == 0) J.nops = n;
+        __syncthreads();
+        if (tid == 0) tk3 = __builtin_amdgcn_s_memrealtime();
+        const int nops = J.nops;
+        const int base = W1 + W2 - nops;
+        // jobs that export their op string (refinement) leave the column maps
+        // alone: several of them share the same second node
+        merge<A>(ops, base, nops, P1, P2, a.prof_pool + J.prof_off, oo >= 0 ? nullptr : up1,
+                 oo >= 0 ? nullptr : up2, gcnt);
+        if (oo >= 0)
+          for (int q = tid; q < nops; q += kThreads) a.ops_out[oo + q] = ops[base + q];
+        if (tid == 0) {
+          int64_t score = J.final_score;
+          if (W1 == 0 || W2 == 0) {
+            const int w = W1 + W2;
+            score = w == 0 ? 0 : -(J.o + (int64_t)(w - 1) * J.e);
+          }
+          a.node_W[out] = nops;
+          a.node_n[out] = J.n1 + J.n2;
+          a.node_prof[out] = J.prof_off;
+          a.node_up[out] = J.up_off;
+          a.job_score[job] = score;
+          a.job_cells[job] = (int64_t)W1 * W2;
+        }
+      } else {
+        // keep the DAG consistent and every later access in bounds
+        if (oo < 0) {
+          for (int q = tid; q < W1; q += kThreads) up1[q] = 0;
+          for (int q = tid; q < W2; q += kThreads) up2[q] = 0;
+        }
+        if (tid == 0) {
+          a.node_W[out] = 0;
+          a.node_n[out] = J.n1 + J.n2;
+          a.node_prof[out] = 0;
+          a.node_up[out] = 0;
+          a.job_score[job] = 0;
+          a.job_cells[job] = (int64_t)W1 * W2;
+        }
       }
       __syncthreads();
-      if (tid == 0) tk3 = __builtin_amdgcn_s_memrealtime();
-      const int nops = J.nops;
-      const int base = W1 + W2 - nops;
-      // jobs that export their op string (refinement) leave the column maps
-      // alone: several of them share the same second node
-      merge<A>(ops, base, nops, P1, P2, a.prof_pool + J.prof_off, oo >= 0 ? nullptr : up1,
-               oo >= 0 ? nullptr : up2, gcnt);
-      if (oo >= 0)
-        for (int q = tid; q < nops; q += kThreads) a.ops_out[oo + q] = ops[base + q];
-      if (tid == 0) {
-        int64_t score = J.final_score;
-        if (W1 == 0 || W2 == 0) {
-          const int w = W1 + W2;
-          score = w == 0 ? 0 : -(J.o + (int64_t)(w - 1) * J.e);
+      if (tid == 0) tk35 = __builtin_amdgcn_s_memrealtime();
+      __threadfence();
+      __syncthreads();
+      if (tid == 0 && a.phase_acc) {
+        const uint64_t tk4 = __builtin_amdgcn_s_memrealtime();
+        if (tk3 < tk2) tk3 = tk2;
+        atomicAdd(&a.phase_acc[0], (unsigned long long)(tk1 - tk0));
+        atomicAdd(&a.phase_acc[1], (unsigned long long)(tk2 - tk1));
+        atomicAdd(&a.phase_acc[2], (unsigned long long)(tk3 - tk2));
+        atomicAdd(&a.phase_acc[3], (unsigned long long)(tk35 - tk3));
+        atomicAdd(&a.phase_acc[4], 1ull);
+        atomicAdd(&a.phase_acc[5], (unsigned long long)(tk4 - tk35));
+        if (a.job_rec && job < a.nrec) {
+          long long* r = a.job_rec + (int64_t)job * 8;
+          r[0] = W1;
+          r[1] = W2;
+          r[2] = J.err ? 0 : J.nops;
+          r[3] = (long long)tk0;
+          r[4] = (long long)tk1;
+          r[5] = (long long)tk2;
+          r[6] = (long long)tk3;
+          r[7] = (long long)tk35;
         }
-        a.node_W[out] = nops;
-        a.node_n[out] = J.n1 + J.n2;
-        a.node_prof[out] = J.prof_off;
-        a.node_up[out] = J.up_off;
-        a.job_score[job] = score;
-        a.job_cells[job] = (int64_t)W1 * W2;
       }
-    } else {
-      // keep the DAG consistent and every later access in bounds
-      if (oo < 0) {
-        for (int q = tid; q < W1; q += kThreads) up1[q] = 0;
-        for (int q = tid; q < W2; q += kThreads) up2[q] = 0;
+      if (tid == 0 && !a.no_push) job_finished(a, job);
+      if constexpr (MFMA) {
+        if (tid == 0 && atomicAdd(a.jobs_done, 1) == a.njobs - 1)
+          __hip_atomic_store(a.finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (tid == 0) {
-        a.node_W[out] = 0;
-        a.node_n[out] = J.n1 + J.n2;
-        a.node_prof[out] = 0;
-        a.node_up[out] = 0;
-        a.job_score[job] = 0;
-        a.job_cells[job] = (int64_t)W1 * W2;
-      }
-    }
-    __syncthreads();
-    if (tid == 0) tk35 = __builtin_amdgcn_s_memrealtime();
-    __threadfence();
-    __syncthreads();
-    if (tid == 0 && a.phase_acc) {
-      const uint64_t tk4 = __builtin_amdgcn_s_memrealtime();
-      if (tk3 < tk2) tk3 = tk2;
-      atomicAdd(&a.phase_acc[0], (unsigned long long)(tk1 - tk0));
-      atomicAdd(&a.phase_acc[1], (unsigned long long)(tk2 - tk1));
-      atomicAdd(&a.phase_acc[2], (unsigned long long)(tk3 - tk2));
-      atomicAdd(&a.phase_acc[3], (unsigned long long)(tk35 - tk3));
-      atomicAdd(&a.phase_acc[4], 1ull);
-      atomicAdd(&a.phase_acc[5], (unsigned long long)(tk4 - tk35));
-      if (a.job_rec && job < a.nrec) {
-        long long* r = a.job_rec + (int64_t)job * 8;
-        r[0] = W1;
-        r[1] = W2;
-        r[2] = J.err ? 0 : J.nops;
-        r[3] = (long long)tk0;
-        r[4] = (long long)tk1;
-        r[5] = (long long)tk2;
-        r[6] = (long long)tk3;
-        r[7] = (long long)tk35;
-      }
-    }
-    if (tid == 0 && !a.no_push) job_finished(a, job);
+    }  // owner
     __syncthreads();
   }
 }
