@@ -307,7 +307,7 @@ struct EngineBuffers {
   int32_t *node_W, *node_n, *node_parent;
   int64_t *node_prof, *node_up;
   int32_t *job_a, *job_b, *job_out, *job_next, *job_pending, *job_link;
-  int32_t *coop_next, *coop_strips, *coop_owner;
+  int32_t *coop_next, *coop_strips, *coop_owner, *coop_tag;
   int64_t* coop_score;
   int64_t *job_score, *job_cells, *job_ops_off;
   int32_t *queue, *queue_flag, *qctl;
@@ -350,6 +350,7 @@ static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, in
   cv.add(e.coop_next, nslots);
   cv.add(e.coop_strips, nslots);
   cv.add(e.coop_owner, nslots);
+  cv.add(e.coop_tag, nslots);
   cv.add(e.coop_score, nslots);
   cv.add(e.job_pending, nslots);
   cv.add(e.job_score, nslots);
@@ -368,9 +369,10 @@ static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, in
 
 // Boundary rows of cooperative merges cross workgroups (and L2 slices), so
 // they live in uncached device memory: one area per owner workgroup, one
-// workgroup per CU.  Allocated once per device and kept until the process
-// ends (uncached memory that a kernel has read is never handed back).
-// SAD_COOP=0 turns cooperation off.
+// workgroup per CU.  Allocated once per device, zeroed (no word carries a tag
+// before the first merge), and kept until the process ends (uncached memory
+// that a kernel has read is never handed back).  SAD_COOP=0 turns
+// cooperation off.
 static int32_t* coop_buffer(int32_t* wgs) {
   static std::mutex mu;
   static int32_t* buf[64] = {};
@@ -387,15 +389,56 @@ static int32_t* coop_buffer(int32_t* wgs) {
         cus <= 0)
       return nullptr;
     void* p = nullptr;
-    if (hipExtMallocWithFlags(&p, (size_t)cus * kCoopWordsPerWG * sizeof(int32_t),
-                              hipDeviceMallocUncached) != hipSuccess) {
+    const size_t bytes = (size_t)cus * kCoopWordsPerWG * sizeof(int32_t);
+    if (hipExtMallocWithFlags(&p, bytes, hipDeviceMallocUncached) != hipSuccess) {
       (void)hipGetLastError();
       return nullptr;
+    }
+    if (hipMemset(p, 0, bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;  // left allocated: never handed back, never used
     }
     buf[dev] = static_cast<int32_t*>(p);
     cnt[dev] = cus;
   }
   *wgs = cnt[dev];
+  return buf[dev];
+}
+
+// Boundary rows of the batched engine's 32-bit strips inside a workgroup:
+// tagged words, so the memory must hold nothing else and start at zero.  One
+// area per workgroup, allocated for the largest grid seen (at least one
+// workgroup per CU), zeroed, and kept for the process; a larger grid replaces
+// it after the device has finished with the old one.
+static int32_t* tag_rows(int nwg) {
+  static std::mutex mu;
+  static int32_t* buf[64] = {};
+  static int cap[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cap[dev] < nwg) {
+    const int want = std::max(nwg, engine_workgroups());
+    if (buf[dev]) {
+      if (hipDeviceSynchronize() != hipSuccess) return nullptr;
+      (void)hipFree(buf[dev]);
+      buf[dev] = nullptr;
+      cap[dev] = 0;
+    }
+    void* p = nullptr;
+    const size_t bytes = (size_t)want * kTagRowWordsPerWG * sizeof(int32_t);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    if (hipMemset(p, 0, bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(p);
+      return nullptr;
+    }
+    buf[dev] = static_cast<int32_t*>(p);
+    cap[dev] = want;
+  }
   return buf[dev];
 }
 
@@ -434,12 +477,15 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
   a.coop_next = e.coop_next;
   a.coop_strips = e.coop_strips;
   a.coop_owner = e.coop_owner;
+  a.coop_tag = e.coop_tag;
   a.coop_score = e.coop_score;
   a.coop_words_per_wg = kCoopWordsPerWG;
   a.coop_wgs = 0;
   if (mode == SAD_BATCHED_MFMA) {
     a.coop_buf = coop_buffer(&a.coop_wgs);
     if (!a.coop_buf) a.coop_wgs = 0;
+    a.trow = tag_rows(e.nwg);  // null: the launch is refused
+    a.trow_words_per_wg = kTagRowWordsPerWG;
   }
   a.tb = e.tb;
   a.tb_words_per_wg = e.tb_words;
@@ -794,6 +840,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                        e.queue_flag, e.qctl + 1, stream);
     EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                                nullptr, c->st);
+    if (prm->mode == SAD_BATCHED_MFMA && !a.trow) return SAD_E_DEVICE;
     if (fused) {
       a.up_F = *fused->F;
       a.up_fm_off = *fused->d_fm_off;
@@ -1449,6 +1496,7 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                      e.job_ops_off, e.queue, e.queue_flag, e.qctl + 1, e.node_parent, stream);
   EngineArgs a = engine_args(e, q, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
                              rf_ops, c->st);
+  if (prm->mode == SAD_BATCHED_MFMA && !a.trow) return SAD_E_DEVICE;
   r = attach_phases(c, a, q, stream);
   if (r) return r;
   EngineTimer timer(stream);

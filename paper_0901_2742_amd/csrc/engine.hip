@@ -116,6 +116,8 @@ struct JobInfo {
   int32_t nops;
   int32_t nd_u, nd_c;  // digits of U and of the counts in the MFMA tile products
   int32_t coop, helper, owner;  // cooperative merge; this workgroup only helps; owner workgroup
+  uint32_t tag;                 // tag of the merge's group boundary rows
+  uint32_t ltag;                // first of 16 tags of this workgroup's own rows
   long long prof_off, up_off;
 };
 
@@ -137,21 +139,17 @@ __device__ inline bool wait_link(const EngineArgs& a, JobInfo& J, const int32_t*
   return true;
 }
 
-// Progress of a strip boundary row: an LDS counter of this workgroup, or an
-// uncached word written by another workgroup (cooperative merges).
-__device__ inline int32_t link_progress(const int32_t* lds, const int32_t* coop) {
-  if (lds) return __hip_atomic_load(lds, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-  const int32_t v = __hip_atomic_load(coop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  asm volatile("" ::: "memory");  // the row's loads come after the progress load
-  return v;
+// Progress of a strip boundary row of this workgroup (an LDS counter).
+__device__ inline int32_t link_progress(const int32_t* lds) {
+  return __hip_atomic_load(lds, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Waits until the boundary row has `need` columns; false on abort or time-out.
 __device__ inline bool wait_progress(const EngineArgs& a, JobInfo& J, const int32_t* lds,
-                                     const int32_t* coop, int need) {
-  if (link_progress(lds, coop) >= need) return true;
+                                     int need) {
+  if (link_progress(lds) >= need) return true;
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
-  while (link_progress(lds, coop) < need) {
+  while (link_progress(lds) < need) {
     if (__hip_atomic_load(&J.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
     __builtin_amdgcn_s_sleep(1);
     if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
@@ -172,33 +170,53 @@ __device__ inline T load_link(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Where a strip's boundary rows come from and go to: the row above (H and X
-// of the previous strip's last row) under its progress counter, this strip's
-// last row and the counter to publish (null when no strip follows), and
-// where H(W1, W2) goes if this strip holds row W1.
+// Where a strip's boundary rows come from and go to (64-bit DP): the row
+// above (H and X of the previous strip's last row) under its progress
+// counter, this strip's last row and the counter to publish (null when no
+// strip follows), and where H(W1, W2) goes if this strip holds row W1.
 template <typename T>
 struct StripLinks {
   const T* inH;
   const T* inX;
   const int32_t* in_lds;
-  const int32_t* in_coop;
   T* outH;
   T* outX;
   int32_t* out_lds;
-  int32_t* out_coop;
   int64_t* score;
 };
 
-// 64 DP steps of one strip.  MASK: some cells of the chunk lie outside
-// 1 <= j <= W2 and must leave H/X/Y untouched.  score(k, j) gives s(i, j) of
-// this lane's row at step k.
-template <bool MASK, typename T, typename Score>
-__device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, T o, T e, Score&& score, T& H,
-                                         T& X, T& Y, T& Hprev, T bhv, T bxv, T& oh, T& ox,
+// Boundary rows of a 32-bit strip are tagged instead: each column is a 64-bit
+// word, value in the low half and a tag in the high half, written once per tag
+// with no fence; the reader loads a column until its tag matches.  The rows
+// live in memory that holds nothing but such words (zeroed once, tags never
+// reused), so a stale word never carries the tag a reader waits for.
+struct TagLinks {
+  const uint64_t* inH;  // row above (null for strip 0)
+  const uint64_t* inX;
+  uint64_t* outH;       // this strip's last row (null for the last strip)
+  uint64_t* outX;
+  uint32_t in_tag, out_tag;
+  int64_t* score;       // H(W1, W2) goes here if this strip holds row W1
+};
+
+__device__ inline uint64_t tag_word(int32_t v, uint32_t tag) {
+  return (uint64_t)(uint32_t)v | ((uint64_t)tag << 32);
+}
+__device__ inline uint32_t tag_of(uint64_t w) { return (uint32_t)(w >> 32); }
+
+// DP steps K0..K1-1 (K0 a multiple of 4) of the 64 steps of one chunk of a
+// strip.  MASK: some cells of the chunk lie outside 1 <= j <= W2 and must
+// leave H/X/Y untouched.  score(k, j) gives s(i, j) of this lane's row at step
+// k.  bhv/bxv hold the row above the strip (lane 0 the column of the current
+// step) and shift one lane per step; oh/ox collect the strip's last row.
+template <bool MASK, int K0, int K1, typename T, typename Score>
+__device__ __forceinline__ void dp_steps(int t0, int lane, int W2, T o, T e, Score&& score, T& H,
+                                         T& X, T& Y, T& Hprev, T& bhv, T& bxv, T& oh, T& ox,
                                          uint32_t (&tw)[16]) {
+  static_assert(K0 % 4 == 0 && K1 % 4 == 0, "tie words hold 4 steps");
   uint32_t word = 0;
 #pragma unroll
-  for (int k = 0; k < 64; ++k) {
+  for (int k = K0; k < K1; ++k) {
     const int j = t0 + k - lane + 1;
     const T Hup = shr1(bhv, H);
     const T Xup = shr1(bxv, X);
@@ -232,6 +250,14 @@ __device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, T o, T e, Sco
     oh = shl1(H, oh);
     ox = shl1(X, ox);
   }
+}
+
+// All 64 DP steps of one chunk of a strip.
+template <bool MASK, typename T, typename Score>
+__device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, T o, T e, Score&& score, T& H,
+                                         T& X, T& Y, T& Hprev, T bhv, T bxv, T& oh, T& ox,
+                                         uint32_t (&tw)[16]) {
+  dp_steps<MASK, 0, 64>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
 }
 
 // Column score from a P2 column staged in the wave's LDS ring: packed 16-bit
@@ -520,8 +546,55 @@ __device__ inline void tile_scores(const long (&ua)[3][2][Tile<A>::KS],
     }
 }
 
-// One strip with MFMA tile scores (run by one wave).  Returns false if the
-// job aborted.
+// A operands of the tile products of strip s: U rows 64 s + 32 rb + (lane & 31),
+// K entries 16 ks + 8 h + 0..7, as signed base-256 digits.
+template <int A>
+__device__ inline void tile_rows(long (&ua)[3][2][Tile<A>::KS], const uint16_t* P1,
+                                 const int32_t* S32, int W1, int s, int lane) {
+  constexpr int KS = Tile<A>::KS;
+  const int m = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+    const int row = 64 * s + 32 * rb + m;
+    const bool ok = row < W1;
+    const uint16_t* crow = P1 + (int64_t)(ok ? row : 0) * A;
+    int32_t u[KS][8];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) u[ks][q] = 0;
+#pragma unroll 1
+    for (int q = 0; q < A; ++q) {
+      const int32_t cq = ok ? (int32_t)crow[q] : 0;
+      const int32_t* Sq = S32 + q * 32 + 8 * h;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int x = 0; x < 8; ++x) u[ks][x] += cq * Sq[16 * ks + x];
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      int32_t d0[8], d1[8], d2[8];
+#pragma unroll
+      for (int x = 0; x < 8; ++x) {
+        const int32_t v = u[ks][x];
+        const int32_t a0 = (int32_t)((uint32_t)v << 24) >> 24;
+        const int32_t v1 = (v - a0) >> 8;
+        const int32_t a1 = (int32_t)((uint32_t)v1 << 24) >> 24;
+        d0[x] = a0;
+        d1[x] = a1;
+        d2[x] = (v1 - a1) >> 8;
+      }
+      ua[0][rb][ks] = pack_bytes8(d0);
+      ua[1][rb][ks] = pack_bytes8(d1);
+      ua[2][rb][ks] = pack_bytes8(d2);
+    }
+  }
+}
+
+// One strip of a 64-bit DP with MFMA tile scores (run by one wave), boundary
+// rows a chunk at a time under LDS counters.  Returns false if the job
+// aborted.
 template <int A, typename T>
 __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                               uint32_t* tbw, const StripLinks<T>& L, const int32_t* S32,
@@ -532,49 +605,8 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
   const T o = (T)J.o, e = (T)J.e;
   const int i = 64 * s + lane + 1;
   const int ie = min(i, W1);
-  // A operands: U rows 64 s + 32 rb + (lane & 31), K entries 16 ks + 8 h + 0..7,
-  // as signed base-256 digits
   long ua[3][2][KS];
-  {
-    const int m = lane & 31, h = lane >> 5;
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      const int row = 64 * s + 32 * rb + m;
-      const bool ok = row < W1;
-      const uint16_t* crow = P1 + (int64_t)(ok ? row : 0) * A;
-      int32_t u[KS][8];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) u[ks][q] = 0;
-#pragma unroll 1
-      for (int q = 0; q < A; ++q) {
-        const int32_t cq = ok ? (int32_t)crow[q] : 0;
-        const int32_t* Sq = S32 + q * 32 + 8 * h;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-          for (int x = 0; x < 8; ++x) u[ks][x] += cq * Sq[16 * ks + x];
-      }
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        int32_t d0[8], d1[8], d2[8];
-#pragma unroll
-        for (int x = 0; x < 8; ++x) {
-          const int32_t v = u[ks][x];
-          const int32_t a0 = (int32_t)((uint32_t)v << 24) >> 24;
-          const int32_t v1 = (v - a0) >> 8;
-          const int32_t a1 = (int32_t)((uint32_t)v1 << 24) >> 24;
-          d0[x] = a0;
-          d1[x] = a1;
-          d2[x] = (v1 - a1) >> 8;
-        }
-        ua[0][rb][ks] = pack_bytes8(d0);
-        ua[1][rb][ks] = pack_bytes8(d1);
-        ua[2][rb][ks] = pack_bytes8(d2);
-      }
-    }
-  }
+  tile_rows<A>(ua, P1, S32, W1, s, lane);
   T H = -(o + (T)(ie - 1) * e);
   T X = DpNeg<T>::value, Y = DpNeg<T>::value;
   T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
@@ -593,8 +625,8 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
     }
     const int need = min(W2, 64 * c + 64);
     if (block) {
-      if (!wait_progress(a, J, L.in_lds, L.in_coop, need)) return false;
-    } else if (link_progress(L.in_lds, L.in_coop) < need) {
+      if (!wait_progress(a, J, L.in_lds, need)) return false;
+    } else if (link_progress(L.in_lds) < need) {
       have_link = false;
       return true;
     }
@@ -610,13 +642,7 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
   for (int c = 0; c < nchunks; ++c) {
     const int t0 = 64 * c;
     const int jn = t0 + 1 + lane;
-    if (!have_link) {
-      if (!wait_progress(a, J, L.in_lds, L.in_coop, min(W2, t0 + 64))) return false;
-      if (jn <= W2) {
-        pbh = load_link(L.inH + jn);
-        pbx = load_link(L.inX + jn);
-      }
-    }
+    if (!have_link && !link_fetch(c, true)) return false;
     const T bh = pbh, bx = pbx;
     if (c < ntiles) tile_scores<A>(ua, bw, nd_u, nd_c, ring, c, lane);
     int32_t scv[64];
@@ -632,21 +658,16 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
       dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
     else
       dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+    // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
+    const int jo = t0 + lane - 62;
     if (L.outH) {
-      // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
-      const int jo = t0 + lane - 62;
       if (jo >= 1 && jo <= W2) {
         L.outH[jo] = oh;
         L.outX[jo] = ox;
       }
       const int done = (c + 1 == nchunks) ? W2 : min(W2, t0 + 1);
       __builtin_amdgcn_s_waitcnt(0);  // the link stores are complete
-      if (L.out_lds) {
-        __hip_atomic_store(L.out_lds, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      } else {
-        asm volatile("" ::: "memory");
-        __hip_atomic_store(L.out_coop, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      __hip_atomic_store(L.out_lds, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     // tie words after the release, so that the wait above covers only the
     // link stores (and this chunk's loads)
@@ -657,92 +678,211 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
   return true;
 }
 
-// Boundary rows of strip s of the current merge.  Within a workgroup they are
-// rows of its own link buffer (indexed by strip) under LDS counters; between
-// groups of a cooperative merge (COOP), rows of the owner's uncached area.
-// Every field is chosen by a select and written once, so that the struct stays
-// in registers.
-template <typename T, bool COOP>
+// Boundary rows of strip s of the current merge (64-bit DP): rows of the
+// workgroup's link buffer (indexed by strip) under LDS counters.  Every field
+// is chosen by a select and written once, so that the struct stays in
+// registers.
+template <typename T>
 __device__ inline StripLinks<T> strip_links(const EngineArgs& a, JobInfo& J, int s, int32_t* prog,
-                                            int32_t* links, int32_t* area) {
+                                            int32_t* links) {
   const int ns = J.nstrips;
   const int stride = a.link_stride / (int)(sizeof(T) / 4);
   T* lk = reinterpret_cast<T*>(links);
   const bool has_in = s > 0, has_out = s + 1 < ns;
-  const bool in_c = COOP && has_in && s % kCoopGroupStrips == 0;
-  const bool out_c = COOP && has_out && s % kCoopGroupStrips == kCoopGroupStrips - 1;
-  // group boundary rows: row b sits below group b
-  const int bi = s / kCoopGroupStrips - 1, bo = s / kCoopGroupStrips;
-  int32_t* rin = COOP ? area + 64 + (int64_t)bi * 2 * kCoopRowWords : nullptr;
-  int32_t* rout = COOP ? area + 64 + (int64_t)bo * 2 * kCoopRowWords : nullptr;
   T* lin = lk + (int64_t)(s - 1) * 2 * stride;
   T* lout = lk + (int64_t)s * 2 * stride;
   StripLinks<T> L;
-  L.inH = !has_in ? nullptr : (in_c ? reinterpret_cast<const T*>(rin) : lin);
-  L.inX = !has_in ? nullptr
-                  : (in_c ? reinterpret_cast<const T*>(rin + kCoopRowWords) : lin + stride);
-  L.in_lds = (has_in && !in_c) ? &prog[s - 1] : nullptr;
-  L.in_coop = in_c ? area + bi : nullptr;
-  L.outH = !has_out ? nullptr : (out_c ? reinterpret_cast<T*>(rout) : lout);
-  L.outX = !has_out ? nullptr
-                    : (out_c ? reinterpret_cast<T*>(rout + kCoopRowWords) : lout + stride);
-  L.out_lds = (has_out && !out_c) ? &prog[s] : nullptr;
-  L.out_coop = out_c ? area + bo : nullptr;
-  L.score = COOP ? &a.coop_score[J.job] : &J.final_score;
+  L.inH = has_in ? lin : nullptr;
+  L.inX = has_in ? lin + stride : nullptr;
+  L.in_lds = has_in ? &prog[s - 1] : nullptr;
+  L.outH = has_out ? lout : nullptr;
+  L.outX = has_out ? lout + stride : nullptr;
+  L.out_lds = has_out ? &prog[s] : nullptr;
+  L.score = &J.final_score;
   return L;
 }
 
-// The DP of a cooperative merge on this workgroup: groups of 4 strips are
-// claimed in increasing order from the merge's counter (the owner starts with
-// group 0), wave w runs strip 4 g + w of each claimed group g.  Wave 0 claims
-// the next group when it reaches it, so the groups of one workgroup overlap as
-// the strips of one merge do.  Every finished strip makes its tie bytes (and
-// H(W1, W2)) visible device-wide, then counts itself.
-template <int A, typename T>
-__device__ bool coop_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, uint32_t* myring,
-                        int32_t* prog, int32_t* links, const int32_t* S32, const uint16_t* P1,
-                        const uint16_t* P2, int32_t* glist, int32_t* gstate) {
+// One strip of a 32-bit DP with MFMA tile scores and tagged boundary rows
+// (run by one wave).  The row above is read a chunk ahead; a chunk whose
+// columns do not all carry the tag yet is read again until they do.  The
+// strip's last row is written at the end of each chunk with no fence, so the
+// wave never waits for its own stores.  False when the job aborted.
+template <int A>
+__device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
+                                uint32_t* tbw, const TagLinks& L, const int32_t* S32,
+                                const uint16_t* P1, const uint16_t* P2) {
+  using T = int32_t;
+  constexpr int KS = Tile<A>::KS;
+  const int W1 = J.W1, W2 = J.W2, nchunks = J.nchunks;
+  const int nd_u = J.nd_u, nd_c = J.nd_c;
+  const T o = (T)J.o, e = (T)J.e;
+  const int i = 64 * s + lane + 1;
+  const int ie = min(i, W1);
+  long ua[3][2][KS];
+  tile_rows<A>(ua, P1, S32, W1, s, lane);
+  T H = -(o + (T)(ie - 1) * e);
+  T X = DpNeg<T>::value, Y = DpNeg<T>::value;
+  T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
+  uint32_t* tbs = tbw + (int64_t)s * nchunks * 16 * 64;
+  const int ntiles = (W2 + 63) >> 6;
+  uint32_t bw[2][KS][4];
+  // above-row words of the next chunk, loaded one chunk ahead
+  uint64_t nh = 0, nx = 0;
+  auto fetch = [&](int c) {
+    const int jn = 64 * c + 1 + lane;
+    if (jn <= W2) {
+      nh = load_link(L.inH + jn);
+      nx = load_link(L.inX + jn);
+    }
+  };
+  if (L.inH) fetch(0);
+  tile_load_counts<A>(bw, P2, W2, 0, lane);
+  for (int c = 0; c < nchunks; ++c) {
+    const int t0 = 64 * c;
+    const int jn = t0 + 1 + lane;
+    T bh, bx;
+    if (!L.inH) {
+      bh = jn <= W2 ? -(o + (T)(jn - 1) * e) : (T)0;
+      bx = DpNeg<T>::value;
+    } else {
+      const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+      while (!__all(jn > W2 || (tag_of(nh) == L.in_tag && tag_of(nx) == L.in_tag))) {
+        if (__hip_atomic_load(&J.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+          return false;
+        __builtin_amdgcn_s_sleep(1);
+        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
+          __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (lane == 0) raise_error(a.st, SAD_E_DEVICE, jn, W_ENGINE_WAIT);
+          return false;
+        }
+        fetch(c);
+      }
+      bh = (T)(int32_t)(uint32_t)nh;
+      bx = (T)(int32_t)(uint32_t)nx;
+    }
+    if (c < ntiles) tile_scores<A>(ua, bw, nd_u, nd_c, ring, c, lane);
+    int32_t scv[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) scv[k] = (int32_t)ring[lane * kScPitch + (t0 & 127) + k];
+    if (c + 1 < ntiles) tile_load_counts<A>(bw, P2, W2, c + 1, lane);
+    if (L.inH && c + 1 < nchunks) fetch(c + 1);
+    T oh = 0, ox = 0;
+    const bool mask = (c == 0) || (t0 + 64 > W2);
+    auto score = [&](int k, int) -> int32_t { return scv[k]; };
+    uint32_t tw[16];
+    if (mask)
+      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+    else
+      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+    if (L.outH) {
+      // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
+      const int jo = t0 + lane - 62;
+      if (jo >= 1 && jo <= W2) {
+        __hip_atomic_store(L.outH + jo, tag_word(oh, L.out_tag), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(L.outX + jo, tag_word(ox, L.out_tag), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tbs[(t0 / 4 + q) * 64 + lane] = tw[q];
+  }
+  if (s == ((W1 - 1) >> 6) && lane == ((W1 - 1) & 63)) *L.score = (int64_t)H;
+  return true;
+}
+
+// Rows of a 32-bit strip s in the k-th group this workgroup runs.  Rows inside
+// a group are the workgroup's own (row s mod 4, tag ltag + k).  Rows between
+// groups: in a cooperative merge the owner's uncached area (row of the group
+// boundary, the merge's tag); otherwise the workgroup's row 3 (tag ltag + the
+// group of the writing strip).
+__device__ inline TagLinks tag_links(const EngineArgs& a, JobInfo& J, int s, int k) {
+  const int ns = J.nstrips;
+  constexpr int64_t R2 = 2 * (int64_t)kCoopRowLen;  // an H row and an X row
+  uint64_t* lrows =
+      reinterpret_cast<uint64_t*>(a.trow + (int64_t)blockIdx.x * a.trow_words_per_wg +
+                                  kCoopHeadWords);
+  uint64_t* crows =
+      reinterpret_cast<uint64_t*>(a.coop_buf + (int64_t)J.owner * a.coop_words_per_wg +
+                                  kCoopHeadWords);
+  const bool has_in = s > 0, has_out = s + 1 < ns;
+  const bool grp_in = s % kCoopGroupStrips == 0;
+  const bool grp_out = s % kCoopGroupStrips == kCoopGroupStrips - 1;
+  const int g = s / kCoopGroupStrips;
+  uint64_t* rin = grp_in ? (J.coop ? crows + (int64_t)(g - 1) * R2 : lrows + 3 * R2)
+                         : lrows + (int64_t)((s - 1) % kCoopGroupStrips) * R2;
+  uint64_t* rout = grp_out ? (J.coop ? crows + (int64_t)g * R2 : lrows + 3 * R2)
+                           : lrows + (int64_t)(s % kCoopGroupStrips) * R2;
+  TagLinks L;
+  L.inH = has_in ? rin : nullptr;
+  L.inX = has_in ? rin + kCoopRowLen : nullptr;
+  L.outH = has_out ? rout : nullptr;
+  L.outX = has_out ? rout + kCoopRowLen : nullptr;
+  L.in_tag = grp_in ? (J.coop ? J.tag : J.ltag + (uint32_t)(k - 1)) : J.ltag + (uint32_t)k;
+  L.out_tag = (grp_out && J.coop) ? J.tag : J.ltag + (uint32_t)k;
+  L.score = J.coop ? &a.coop_score[J.job] : &J.final_score;
+  return L;
+}
+
+// The 32-bit DP of a merge on this workgroup.  The strips form groups of 4;
+// wave w runs strip 4 g + w of each group g the workgroup takes.  Alone, the
+// workgroup takes every group in order.  In a cooperative merge the groups
+// are claimed in increasing order from the merge's counter (the owner starts
+// with group 0); wave 0 claims the next group when it reaches it, so the
+// groups of one workgroup overlap as the strips of one merge do, and every
+// finished strip makes its tie bytes (and H(W1, W2)) visible device-wide,
+// then counts itself.
+template <int A>
+__device__ bool tagged_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, uint32_t* myring,
+                          const int32_t* S32, const uint16_t* P1, const uint16_t* P2,
+                          int32_t* glist, int32_t* gstate) {
   const int ns = J.nstrips;
   const int ngroups = (ns + kCoopGroupStrips - 1) / kCoopGroupStrips;
   uint32_t* tbw = a.tb + (int64_t)J.owner * a.tb_words_per_wg;
-  int32_t* area = a.coop_buf + (int64_t)J.owner * a.coop_words_per_wg;
   for (int k = 0;; ++k) {
-    if (wave == 0 && lane == 0 &&
-        k >= __hip_atomic_load(&gstate[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-      const int g = atomicAdd(&a.coop_next[J.job], 1);
-      if (g < ngroups) {
-        for (int q = 0; q < kCoopGroupStrips; ++q) prog[g * kCoopGroupStrips + q] = 0;
-        glist[k] = g;
-        __hip_atomic_store(&gstate[0], k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      } else {
-        __hip_atomic_store(&gstate[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    int g = k;
+    if (J.coop) {
+      if (wave == 0 && lane == 0 &&
+          k >= __hip_atomic_load(&gstate[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+        const int c = atomicAdd(&a.coop_next[J.job], 1);
+        if (c < ngroups) {
+          glist[k] = c;
+          __hip_atomic_store(&gstate[0], k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+          __hip_atomic_store(&gstate[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
       }
-    }
-    int have = 0;
-    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
-    for (;;) {
-      have = __hip_atomic_load(&gstate[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (have > k) break;
-      if (__hip_atomic_load(&gstate[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+      int have = 0;
+      const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+      for (;;) {
         have = __hip_atomic_load(&gstate[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        break;
+        if (have > k) break;
+        if (__hip_atomic_load(&gstate[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+          have = __hip_atomic_load(&gstate[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          break;
+        }
+        if (__hip_atomic_load(&J.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+          return false;
+        __builtin_amdgcn_s_sleep(1);
+        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
+          __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          return false;
+        }
       }
-      if (__hip_atomic_load(&J.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
-      __builtin_amdgcn_s_sleep(1);
-      if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
-        __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        return false;
-      }
+      if (have <= k) break;
+      g = glist[k];
+    } else if (g >= ngroups) {
+      break;
     }
-    if (have <= k) break;
-    const int g = glist[k];
     const int s = g * kCoopGroupStrips + wave;
     if (s < ns) {
-      const StripLinks<T> L = strip_links<T, true>(a, J, s, prog, links, area);
-      if (!dp_strip_mfma<A, T>(a, J, s, lane, myring, tbw, L, S32, P1, P2)) return false;
-      __builtin_amdgcn_s_waitcnt(0);
-      __threadfence();
-      if (lane == 0) atomicAdd(&a.coop_strips[J.job], 1);
+      const TagLinks L = tag_links(a, J, s, k);
+      if (!dp_strip_tagged<A>(a, J, s, lane, myring, tbw, L, S32, P1, P2)) return false;
+      if (J.coop) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __threadfence();
+        if (lane == 0) atomicAdd(&a.coop_strips[J.job], 1);
+      }
     }
   }
   return true;
@@ -1303,22 +1443,45 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         J.final_score = 0;
         J.coop = 0;
         J.owner = (int)blockIdx.x;
+        J.tag = 0;
+        J.ltag = 0;
         if constexpr (MFMA) {
+          if (!err && !wide) {
+            // 16 fresh tags for this workgroup's own rows (only its thread 0
+            // touches its counter)
+            int32_t* head = a.trow + (int64_t)blockIdx.x * a.trow_words_per_wg;
+            J.ltag = (uint32_t)head[0] + 1u;
+            head[0] = (int32_t)(J.ltag + 15u);
+          }
           const int ngroups = (nstrips + kCoopGroupStrips - 1) / kCoopGroupStrips;
+          // workgroups waiting for a ticket that no merge has filled yet
+          const int idle = __hip_atomic_load(a.queue_head, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) -
+                           __hip_atomic_load(a.queue_tail, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
           if (J.helper) {
             J.coop = 1;
             J.owner = __hip_atomic_load(&a.coop_owner[job], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT) - 1;
+            J.tag = (uint32_t)__hip_atomic_load(&a.coop_tag[job], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
             gstate[0] = 0;
             gstate[1] = 0;
-          } else if (!err && ngroups > 1 && (int)blockIdx.x < a.coop_wgs) {
-            // cooperative merge: reset its boundary-row progress, group and
-            // strip counters, then queue helper tickets (the owner runs
-            // group 0 and claims further groups like any helper)
+          } else if (!err && !wide && ngroups > 1 && idle > 0 &&
+                     (int)blockIdx.x < a.coop_wgs) {
+            // cooperative merge while workgroups wait idle: a fresh tag for
+            // its boundary rows, its group and strip counters, then helper
+            // tickets (the owner runs group 0 and claims further groups like
+            // any helper)
             J.coop = 1;
             int32_t* area = a.coop_buf + (int64_t)blockIdx.x * a.coop_words_per_wg;
-            for (int b = 0; b + 1 < ngroups; ++b)
-              __hip_atomic_store(&area[b], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // only this workgroup's thread 0 touches its counter: no RMW
+            // atomic on uncached memory needed
+            J.tag = (uint32_t)__hip_atomic_load(&area[0], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            __hip_atomic_store(&area[0], (int32_t)J.tag, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            a.coop_tag[job] = (int32_t)J.tag;
             a.coop_next[job] = 1;
             a.coop_strips[job] = 0;
             a.coop_owner[job] = (int)blockIdx.x + 1;
@@ -1327,8 +1490,8 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
             gstate[1] = 0;
             __builtin_amdgcn_s_waitcnt(0);
             __threadfence();
-            for (int h = 0; h < min(ngroups - 1, kMaxHelpers); ++h)
-              push_job(a, job | kHelperTicket);
+            const int nh = min(min(ngroups - 1, kMaxHelpers), idle);
+            for (int h = 0; h < nh; ++h) push_job(a, job | kHelperTicket);
           }
         }
       }
@@ -1351,25 +1514,14 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
       __syncthreads();
       if (W1 > 0 && W2 > 0) {
         if constexpr (MFMA) {
-          if (J.coop) {
-            if (J.wide)
-              coop_dp<A, int64_t>(a, J, wave, lane, myring, prog, links, S32, P1, P2, glist,
-                                  gstate);
-            else
-              coop_dp<A, int32_t>(a, J, wave, lane, myring, prog, links, S32, P1, P2, glist,
-                                  gstate);
-          } else if (J.wide) {
+          if (J.wide) {
             for (int s = wave; s < J.nstrips; s += kWaves) {
-              const StripLinks<int64_t> L =
-                  strip_links<int64_t, false>(a, J, s, prog, links, nullptr);
+              const StripLinks<int64_t> L = strip_links<int64_t>(a, J, s, prog, links);
               if (!dp_strip_mfma<A, int64_t>(a, J, s, lane, myring, tbw, L, S32, P1, P2)) break;
             }
           } else {
-            for (int s = wave; s < J.nstrips; s += kWaves) {
-              const StripLinks<int32_t> L =
-                  strip_links<int32_t, false>(a, J, s, prog, links, nullptr);
-              if (!dp_strip_mfma<A, int32_t>(a, J, s, lane, myring, tbw, L, S32, P1, P2)) break;
-            }
+            // alone or cooperative (the tagged rows hold 32-bit values)
+            tagged_dp<A>(a, J, wave, lane, myring, S32, P1, P2, glist, gstate);
           }
         } else if (J.wide) {
           for (int s = wave; s < J.nstrips; s += kWaves)

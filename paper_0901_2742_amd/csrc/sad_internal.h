@@ -16,13 +16,18 @@ namespace sad {
 constexpr int kMaxLen = 8192;        // longest accepted sequence
 constexpr int kMaxWidth = 4096;      // widest profile a DP accepts
 // cooperative merges: strips per group, helper tickets per merge, and the
-// layout of a workgroup's boundary-row area (progress words, then per group
-// boundary an H row and an X row of kMaxWidth + 1 values of up to 64 bits)
+// layout of a workgroup's boundary-row area (a head of 32-bit words, word 0
+// the workgroup's tag counter, then per group boundary an H row and an X row
+// of kMaxWidth + 1 tagged 64-bit words)
 constexpr int kCoopGroupStrips = 4;
 constexpr int kMaxHelpers = 3;
 constexpr int kCoopMaxGroups = kMaxWidth / 64 / kCoopGroupStrips;
-constexpr int kCoopRowWords = 2 * (kMaxWidth + 1);
-constexpr int64_t kCoopWordsPerWG = 64 + (int64_t)(kCoopMaxGroups - 1) * 2 * kCoopRowWords;
+constexpr int kCoopHeadWords = 64;
+constexpr int kCoopRowLen = kMaxWidth + 1;
+constexpr int64_t kCoopWordsPerWG =
+    kCoopHeadWords + (int64_t)(kCoopMaxGroups - 1) * 2 * kCoopRowLen * 2;
+// a workgroup's own tagged rows: the same head, then 4 H/X row pairs
+constexpr int64_t kTagRowWordsPerWG = kCoopHeadWords + (int64_t)4 * 2 * kCoopRowLen * 2;
 constexpr int32_t kHelperTicket = 1 << 30;
 constexpr int kMaxAlpha = 20;
 constexpr int kMaxGroup = 8000;      // largest bucket (UPGMA keeps 5 ints per member in LDS)
@@ -173,22 +178,29 @@ struct EngineArgs {
   int32_t up_ngroups, up_N;
   int32_t* up_merges;
   int32_t* up_next;
-  // Cooperative merges (batched kernel): a merge of more than 4 strips is cut
-  // into groups of 4 consecutive strips; its owner and helper workgroups
-  // (queued as tickets job | kHelperTicket) claim the groups in order.
-  // Boundary rows between groups pass through coop_buf (uncached memory, one
-  // area per owner workgroup: progress words, then H and X rows per group
-  // boundary), the owner's tie-byte scratch receives every strip.
+  // Cooperative merges (batched kernel, 32-bit DP): a merge of more than 4
+  // strips is cut into groups of 4 consecutive strips; its owner and helper
+  // workgroups (queued as tickets job | kHelperTicket while workgroups wait
+  // idle) claim the groups in order.  Boundary rows between groups pass
+  // through coop_buf (uncached memory, one area per owner workgroup: a tag
+  // counter, then tagged H and X rows per group boundary), the owner's
+  // tie-byte scratch receives every strip.
   int32_t queue_cap;        // tickets the queue holds
   int32_t* jobs_done;       // merges finished; the last one sets *finished
   int32_t* finished;
   int32_t* coop_next;       // per job slot: next group to claim
   int32_t* coop_strips;     // per job slot: strips finished
   int32_t* coop_owner;      // per job slot: owner workgroup + 1
+  int32_t* coop_tag;        // per job slot: tag of its group boundary rows
   int64_t* coop_score;      // per job slot: H(W1, W2)
   int32_t* coop_buf;
   int64_t coop_words_per_wg;
   int32_t coop_wgs;         // owner workgroups coop_buf has room for (0: no cooperation)
+  // Boundary rows of the 32-bit strips inside a workgroup (batched kernel):
+  // per workgroup a tag counter, then 4 tagged H/X row pairs (zeroed once,
+  // kept for the process)
+  int32_t* trow;
+  int64_t trow_words_per_wg;
   DevStatus* st;
 };
 void launch_engine(const EngineArgs& a, int nwg, hipStream_t stream);
