@@ -1253,11 +1253,11 @@ constexpr int kFusedMaxN = 182;
 
 // UPGMA of group g by the whole workgroup, pair sums in LDS (ring), cluster
 // arrays in tbst.
-__device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t* tbst, Cand* red,
-                           int32_t* nrec) {
+__device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t* tbst,
+                           int32_t* mlist, int32_t* mcount) {
   const int g0 = a.up_group_off[g], n = a.up_group_off[g + 1] - g0;
   if (n <= 1) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   uint64_t* tri = reinterpret_cast<uint64_t*>(ring);
   int32_t* id = reinterpret_cast<int32_t*>(tbst);
   int32_t* sz = id + n;
@@ -1274,11 +1274,47 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
     const int x = (int)(q / n), y = (int)(q % n);
     if (x < y) tri[x * n - x * (x + 1) / 2 + y - x - 1] = Fg[q];
   }
+  if (tid == 0) *mcount = 0;
   __threadfence_block();
   __syncthreads();
+  // (groups here are below kUpgmaW64MaxN: 64-bit cross products are exact)
   const TriS S{tri, n};
-  upgma_group(S, n, id, sz, active, best, rec, nrec, red, a.up_merges + 2 * (int64_t)g0, g, a.st,
-              [&](int step, int ia, int ib) { create_job(a, g0, n, step, ia, ib); });
+  upgma_init_best<true>(S, n, id, sz, active, best);
+  __syncthreads();
+  if (wave == 0) {
+    // the merge steps; each decided merge is listed for wave 1
+    const bool ok = upgma_steps<true>(
+        S, n, id, sz, active, best, rec, a.up_merges + 2 * (int64_t)g0, g, a.st,
+        [&](int step, int ia, int ib) {
+          mlist[2 * step] = ia;
+          mlist[2 * step + 1] = ib;
+          __hip_atomic_store(mcount, step + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        });
+    if (!ok && lane == 0)
+      __hip_atomic_store(mcount, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else if (wave == 1) {
+    // jobs for the listed merges, up to 64 at a time (one lane each), so that
+    // their fences and atomics are paid once per batch
+    int k0 = 0;
+    uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+    while (k0 < n - 1) {
+      const int avail = __hip_atomic_load(mcount, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (avail < 0) break;
+      if (avail == k0) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
+          if (lane == 0) raise_error(a.st, SAD_E_DEVICE, g, W_ENGINE_WAIT);
+          break;
+        }
+        continue;
+      }
+      const int kb = min(avail, k0 + 64);
+      const int k = k0 + lane;
+      if (k < kb) create_job(a, g0, n, k, mlist[2 * k], mlist[2 * k + 1]);
+      k0 = kb;
+      t_start = __builtin_amdgcn_s_memrealtime();
+    }
+  }
   __syncthreads();
 }
 
@@ -1290,7 +1326,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t ring[kWaves * kRingWords];
   __shared__ int32_t S32[MFMA ? A * 32 : 1];
   __shared__ uint32_t tbst[kStageT4 * 64];
-  __shared__ uint8_t ops[2 * kMaxWidth];
+  __shared__ __attribute__((aligned(16))) uint8_t ops[2 * kMaxWidth];
   __shared__ int32_t Ssh[A * A];
   __shared__ int32_t prog[kMaxStrips];
   __shared__ int32_t gcnt[2 * kMaxWidth / 64];
@@ -1316,8 +1352,8 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
     static_assert((int64_t)kFusedMaxN * (kFusedMaxN - 1) / 2 * 8 <=
                       (int64_t)kWaves * kRingWords * 4, "pair sums fit the score ring");
     // guide trees first; their merges become jobs for the other workgroups
-    __shared__ Cand ured[2 * kUpgmaWaves];
-    __shared__ int32_t unrec, ugrp;
+    static_assert(2 * (kFusedMaxN - 1) * 4 <= 2 * kMaxWidth, "merge list fits the ops buffer");
+    __shared__ int32_t umcount, ugrp;
     if (a.up_ngroups > 0) {
       for (;;) {
         if (tid == 0) ugrp = atomicAdd(a.up_next, 1);
@@ -1325,7 +1361,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         const int g = ugrp;
         __syncthreads();
         if (g >= a.up_ngroups) break;
-        fused_tree(a, g, ring, tbst, ured, &unrec);
+        fused_tree(a, g, ring, tbst, reinterpret_cast<int32_t*>(ops), &umcount);
       }
     }
   }

@@ -6,20 +6,28 @@
 
 namespace sad {
 
+// The whole workgroup loads the sums and finds every cluster's best partner;
+// wave 0 then runs the merge steps.
+template <bool W64, typename St>
+__device__ inline void upgma_run(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
+                                 int32_t* best, int32_t* rec, int32_t* mo, int g, DevStatus* st) {
+  upgma_init_best<W64>(S, n, id, sz, active, best);
+  __syncthreads();
+  if ((threadIdx.x >> 6) == 0)
+    upgma_steps<W64>(S, n, id, sz, active, best, rec, mo, g, st, [](int, int, int) {});
+}
+
 __global__ __launch_bounds__(kUpgmaThreads) void upgma_kernel(
     const uint32_t* __restrict__ F, const int64_t* __restrict__ fm_off,
     const int32_t* __restrict__ group_off, uint64_t* __restrict__ Sw,
     int32_t* __restrict__ merges_out, const int32_t* __restrict__ merge_base, int lds_n,
     DevStatus* st) {
   extern __shared__ __attribute__((aligned(16))) uint64_t shq[];
-  __shared__ Cand red[2 * kUpgmaWaves];
-  __shared__ int32_t nrec;
   const int g = blockIdx.x;
   const int n = group_off[g + 1] - group_off[g];
   if (n <= 1) return;
   const bool in_lds = n <= lds_n;
   // LDS: [triangle of lds_n (lds_n - 1) / 2 u64][5 lds_n-or-n i32]
-  const int64_t tri_words = in_lds ? (int64_t)n * (n - 1) / 2 : 0;
   int32_t* sh = reinterpret_cast<int32_t*>(shq + (in_lds ? (int64_t)lds_n * (lds_n - 1) / 2 : 0));
   int32_t* id = sh;
   int32_t* sz = sh + n;
@@ -34,22 +42,28 @@ __global__ __launch_bounds__(kUpgmaThreads) void upgma_kernel(
     sz[a] = 1;
     active[a] = 1;
   }
+  const bool w64 = n <= kUpgmaW64MaxN;
   if (in_lds) {
     const TriS S{shq, n};
     for (int64_t q = tid; q < (int64_t)n * n; q += kUpgmaThreads) {
       const int a = (int)(q / n), b = (int)(q % n);
       if (a < b) shq[a * n - a * (a + 1) / 2 + b - a - 1] = Fg[q];
     }
-    (void)tri_words;
     __threadfence_block();
     __syncthreads();
-    upgma_group(S, n, id, sz, active, best, rec, &nrec, red, mo, g, st, [](int, int, int) {});
+    if (w64)
+      upgma_run<true>(S, n, id, sz, active, best, rec, mo, g, st);
+    else
+      upgma_run<false>(S, n, id, sz, active, best, rec, mo, g, st);
   } else {
     const FullS S{Sw + fm_off[g], n};
     for (int64_t q = tid; q < (int64_t)n * n; q += kUpgmaThreads) S.t[q] = Fg[q];
     __threadfence_block();
     __syncthreads();
-    upgma_group(S, n, id, sz, active, best, rec, &nrec, red, mo, g, st, [](int, int, int) {});
+    if (w64)
+      upgma_run<true>(S, n, id, sz, active, best, rec, mo, g, st);
+    else
+      upgma_run<false>(S, n, id, sz, active, best, rec, mo, g, st);
   }
 }
 

@@ -2,13 +2,19 @@
 // engine's fused tree phase (device code only).
 //
 // Each step merges the active pair with the largest average similarity
-// S_AB / (|A| |B|), compared exactly by 128-bit cross products; ties go to
-// the smallest (min id, max id).  The union keeps the slot of its first member
+// S_AB / (|A| |B|), compared exactly by cross products; ties go to the
+// smallest (min id, max id).  The union keeps the slot of its first member
 // and S(A u B, C) = S(A, C) + S(B, C).  Every active cluster keeps its best
 // partner under that same order, so the global choice is a reduction over
 // clusters; after a merge only clusters whose best partner was one of the two
-// merged ones are rescanned (one wave each), the others compare their best
-// with the union.
+// merged ones are rescanned, the others compare their best with the union.
+//
+// The steps run on one wave: a step is a few wave-wide reductions (DPP within
+// rows, two swizzles across them) with no workgroup barrier.  While a group
+// has at most kUpgmaW64MaxN members the cross products fit 64 bits: a pair
+// sum is at most |A| |B| 2^31 with |A| |B| <= n^2 / 4, so s1 p2 < 2^64 when
+// n^4 / 16 * 2^31 < 2^64, i.e. n < 608.  Larger groups compare 128-bit
+// products.
 #pragma once
 #include "sad_internal.h"
 
@@ -19,52 +25,103 @@ constexpr int kUpgmaWaves = kUpgmaThreads / 64;
 // largest group whose upper triangle of 64-bit sums fits in LDS next to the
 // per-cluster arrays
 constexpr int kUpgmaLdsN = 190;
+constexpr int kUpgmaW64MaxN = 600;
 
-struct Cand {
-  uint64_t s;     // summed similarity
-  uint64_t prod;  // |A| |B|
-  uint64_t key;   // (min id << 32) | max id; all ones = no candidate
-  int32_t a, b;   // slots
+// A candidate pair: summed similarity, |A| |B|, the pair of ids packed as
+// (min << 16) | max (ids < 2 kMaxGroup < 2^16; all ones = no candidate) and
+// the pair of slots packed as a | b << 16.
+struct WCand {
+  uint64_t s;
+  uint64_t p;
+  uint32_t key;
+  uint32_t ab;
 };
 
-// 128-bit compare of s1 * p2 against s2 * p1
+__device__ inline uint32_t pair_key16(int ia, int ib) {
+  return ((uint32_t)min(ia, ib) << 16) | (uint32_t)max(ia, ib);
+}
+
+// sign of s1 p2 - s2 p1
+template <bool W64>
 __device__ inline int cmp_avg(uint64_t s1, uint64_t p1, uint64_t s2, uint64_t p2) {
-  const uint64_t lo1 = s1 * p2, hi1 = __umul64hi(s1, p2);
-  const uint64_t lo2 = s2 * p1, hi2 = __umul64hi(s2, p1);
-  if (hi1 != hi2) return hi1 > hi2 ? 1 : -1;
-  if (lo1 != lo2) return lo1 > lo2 ? 1 : -1;
-  return 0;
-}
-
-__device__ inline bool better(uint64_t s1, uint64_t p1, uint64_t k1, uint64_t s2, uint64_t p2,
-                              uint64_t k2) {
-  if (k1 == ~0ull) return false;
-  if (k2 == ~0ull) return true;
-  const int c = cmp_avg(s1, p1, s2, p2);
-  if (c != 0) return c > 0;
-  return k1 < k2;
-}
-
-__device__ inline uint64_t pair_key(int ia, int ib) {
-  const uint32_t lo = (uint32_t)min(ia, ib), hi = (uint32_t)max(ia, ib);
-  return ((uint64_t)lo << 32) | hi;
-}
-
-__device__ inline void cand_take_if_better(Cand& c, const Cand& o) {
-  if (better(o.s, o.prod, o.key, c.s, c.prod, c.key)) c = o;
-}
-
-// wave-wide best candidate (every lane ends with it)
-__device__ inline Cand wave_best(Cand c) {
-  for (int o = 32; o > 0; o >>= 1) {
-    Cand x;
-    x.s = __shfl_xor(c.s, o, 64);
-    x.prod = __shfl_xor(c.prod, o, 64);
-    x.key = __shfl_xor(c.key, o, 64);
-    x.a = __shfl_xor(c.a, o, 64);
-    x.b = __shfl_xor(c.b, o, 64);
-    cand_take_if_better(c, x);
+  if constexpr (W64) {
+    const uint64_t l = s1 * p2, r = s2 * p1;
+    return l > r ? 1 : (l < r ? -1 : 0);
+  } else {
+    const uint64_t lo1 = s1 * p2, hi1 = __umul64hi(s1, p2);
+    const uint64_t lo2 = s2 * p1, hi2 = __umul64hi(s2, p1);
+    if (hi1 != hi2) return hi1 > hi2 ? 1 : -1;
+    if (lo1 != lo2) return lo1 > lo2 ? 1 : -1;
+    return 0;
   }
+}
+
+// x comes before y in the merge order
+template <bool W64>
+__device__ inline bool wc_better(const WCand& x, const WCand& y) {
+  if (x.key == ~0u) return false;
+  if (y.key == ~0u) return true;
+  const int c = cmp_avg<W64>(x.s, x.p, y.s, y.p);
+  if (c != 0) return c > 0;
+  return x.key < y.key;
+}
+
+__device__ inline WCand wc_none() {
+  WCand c;
+  c.s = 0;
+  c.p = 1;
+  c.key = ~0u;
+  c.ab = 0;
+  return c;
+}
+
+template <int CTRL>
+__device__ inline uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ inline uint64_t dpp64(uint64_t v) {
+  return (uint64_t)dpp32<CTRL>((uint32_t)v) | ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32);
+}
+template <int CTRL>
+__device__ inline WCand wc_dpp(const WCand& c) {
+  WCand x;
+  x.s = dpp64<CTRL>(c.s);
+  x.p = dpp64<CTRL>(c.p);
+  x.key = dpp32<CTRL>(c.key);
+  x.ab = dpp32<CTRL>(c.ab);
+  return x;
+}
+__device__ inline WCand wc_xor(const WCand& c, int m) {
+  WCand x;
+  x.s = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)c.s, m, 64) |
+        ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(c.s >> 32), m, 64) << 32);
+  x.p = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)c.p, m, 64) |
+        ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(c.p >> 32), m, 64) << 32);
+  x.key = (uint32_t)__shfl_xor((int)c.key, m, 64);
+  x.ab = (uint32_t)__shfl_xor((int)c.ab, m, 64);
+  return x;
+}
+
+// The first candidate of the wave in the merge order, in every lane (all 64
+// lanes active).  Pairings: lanes ^1 and ^2 within a quad, the mirrored quad
+// of each half row, the mirrored half of each row, then rows ^16 and ^32;
+// after each stage every lane of the group holds the group's first.
+template <bool W64>
+__device__ inline WCand wave_first(WCand c) {
+  WCand x;
+  x = wc_dpp<0xB1>(c);  // quad_perm [1, 0, 3, 2]
+  if (wc_better<W64>(x, c)) c = x;
+  x = wc_dpp<0x4E>(c);  // quad_perm [2, 3, 0, 1]
+  if (wc_better<W64>(x, c)) c = x;
+  x = wc_dpp<0x141>(c);  // row_half_mirror
+  if (wc_better<W64>(x, c)) c = x;
+  x = wc_dpp<0x140>(c);  // row_mirror
+  if (wc_better<W64>(x, c)) c = x;
+  x = wc_xor(c, 16);
+  if (wc_better<W64>(x, c)) c = x;
+  x = wc_xor(c, 32);
+  if (wc_better<W64>(x, c)) c = x;
   return c;
 }
 
@@ -93,117 +150,126 @@ struct FullS {
   }
 };
 
-// best partner of slot r among active slots (whole wave; result in every lane)
-template <typename St>
+// Makes one lane's earlier LDS / global writes visible to the wave's later
+// reads (and keeps the compiler from moving accesses across).
+__device__ inline void wave_sync() {
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Best partner of slot r among the active slots (whole wave; -1 if none).
+template <bool W64, typename St>
 __device__ inline int wave_best_partner(const St& S, int n, int r, const int32_t* id,
                                         const int32_t* sz, const int32_t* active) {
   const int lane = threadIdx.x & 63;
-  Cand c;
-  c.s = 0;
-  c.prod = 1;
-  c.key = ~0ull;
-  c.a = r;
-  c.b = -1;
+  WCand c = wc_none();
   const uint64_t sr = (uint64_t)sz[r];
   const int ir = id[r];
   for (int b = lane; b < n; b += 64) {
     if (b == r || !active[b]) continue;
-    Cand x;
+    WCand x;
     x.s = S.get(r, b);
-    x.prod = sr * (uint64_t)sz[b];
-    x.key = pair_key(ir, id[b]);
-    x.a = r;
-    x.b = b;
-    cand_take_if_better(c, x);
+    x.p = sr * (uint64_t)sz[b];
+    x.key = pair_key16(ir, id[b]);
+    x.ab = (uint32_t)b;
+    if (wc_better<W64>(x, c)) c = x;
   }
-  return wave_best(c).b;
+  c = wave_first<W64>(c);
+  return c.key == ~0u ? -1 : (int)c.ab;
 }
 
-template <typename St, typename OnMerge>
-__device__ void upgma_group(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
-                            int32_t* best, int32_t* rec, int32_t* nrec, Cand* red, int32_t* mo,
-                            int g, DevStatus* st, OnMerge&& on_merge) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+// Best partners of every slot (the whole workgroup, kUpgmaWaves waves).
+template <bool W64, typename St>
+__device__ inline void upgma_init_best(const St& S, int n, const int32_t* id, const int32_t* sz,
+                                       const int32_t* active, int32_t* best) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int r = wave; r < n; r += kUpgmaWaves) {
-    const int b = wave_best_partner(S, n, r, id, sz, active);
+    const int b = wave_best_partner<W64>(S, n, r, id, sz, active);
     if (lane == 0) best[r] = b;
   }
-  __syncthreads();
+}
+
+// The n - 1 merge steps, run by one wave after upgma_init_best.  mo receives
+// the merges (min id, max id); on_merge(step, min id, max id) is called by
+// lane 0 as soon as a merge is decided.  rec: scratch of n slots.  Returns
+// false (after raising an error) if a step finds no pair.
+template <bool W64, typename St, typename OnMerge>
+__device__ bool upgma_steps(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
+                            int32_t* best, int32_t* rec, int32_t* mo, int g, DevStatus* st,
+                            OnMerge&& on_merge) {
+  const int lane = threadIdx.x & 63;
   for (int step = 0; step < n - 1; ++step) {
-    // the best pair is the best of the clusters' best pairs
-    Cand c;
-    c.key = ~0ull;
-    c.s = 0;
-    c.prod = 1;
-    c.a = c.b = -1;
-    for (int a = tid; a < n; a += kUpgmaThreads) {
-      const int b = best[a];
-      if (!active[a] || b < 0) continue;
-      Cand x;
-      x.s = S.get(a, b);
-      x.prod = (uint64_t)sz[a] * (uint64_t)sz[b];
-      x.key = pair_key(id[a], id[b]);
-      x.a = min(a, b);
-      x.b = max(a, b);
-      cand_take_if_better(c, x);
+    // the best pair is the first of the clusters' best pairs
+    WCand c = wc_none();
+    for (int r = lane; r < n; r += 64) {
+      const int b = best[r];
+      if (!active[r] || b < 0) continue;
+      WCand x;
+      x.s = S.get(r, b);
+      x.p = (uint64_t)sz[r] * (uint64_t)sz[b];
+      x.key = pair_key16(id[r], id[b]);
+      x.ab = (uint32_t)min(r, b) | ((uint32_t)max(r, b) << 16);
+      if (wc_better<W64>(x, c)) c = x;
     }
-    c = wave_best(c);
-    if (lane == 0) red[(step & 1) * kUpgmaWaves + wave] = c;
-    __syncthreads();
-    // (red alternates halves between steps, so no barrier is needed before
-    // the next step's writes)
-    Cand w = red[(step & 1) * kUpgmaWaves];
-#pragma unroll
-    for (int q = 1; q < kUpgmaWaves; ++q) cand_take_if_better(w, red[(step & 1) * kUpgmaWaves + q]);
-    const int ba = w.a, bb = w.b;
-    if (ba < 0) {
-      if (tid == 0) raise_error(st, SAD_E_INVAL, g, W_UPGMA);
-      return;
+    c = wave_first<W64>(c);
+    if (c.key == ~0u) {
+      if (lane == 0) raise_error(st, SAD_E_INVAL, g, W_UPGMA);
+      return false;
     }
-    if (tid == 0) {
+    const int ba = (int)(c.ab & 0xffffu), bb = (int)(c.ab >> 16);
+    if (lane == 0) {
       const int ia = id[ba], ib = id[bb];
       mo[2 * step] = min(ia, ib);
       mo[2 * step + 1] = max(ia, ib);
       on_merge(step, min(ia, ib), max(ia, ib));
     }
     // S(new, c) = S(a, c) + S(b, c) for the remaining active clusters
-    for (int q = tid; q < n; q += kUpgmaThreads) {
+    for (int q = lane; q < n; q += 64) {
       if (!active[q] || q == ba || q == bb) continue;
       S.set(ba, q, S.get(ba, q) + S.get(bb, q));
     }
-    __threadfence_block();
-    __syncthreads();
-    if (tid == 0) {
+    wave_sync();
+    if (lane == 0) {
       sz[ba] += sz[bb];
       id[ba] = n + step;
       active[bb] = 0;
-      *nrec = 0;
     }
-    __syncthreads();
+    wave_sync();
     if (step == n - 2) break;
-    // best partners: rescan clusters that pointed at a merged cluster,
-    // otherwise compare with the union
-    for (int q = tid; q < n; q += kUpgmaThreads) {
-      if (!active[q]) continue;
-      const int b = best[q];
-      if (q == ba || b == ba || b == bb) {
-        rec[atomicAdd(nrec, 1)] = q;
-      } else {
-        const uint64_t sb = S.get(q, b), pb = (uint64_t)sz[q] * (uint64_t)sz[b];
-        const uint64_t sn = S.get(q, ba), pn = (uint64_t)sz[q] * (uint64_t)sz[ba];
-        if (better(sn, pn, pair_key(id[q], id[ba]), sb, pb, pair_key(id[q], id[b]))) best[q] = ba;
+    // best partners: clusters that pointed at a merged cluster are listed
+    // for a rescan, the others compare their best with the union
+    int nrec = 0;
+    for (int q0 = 0; q0 < n; q0 += 64) {
+      const int q = q0 + lane;
+      bool again = false;
+      if (q < n && active[q]) {
+        const int b = best[q];
+        if (q == ba || b == ba || b == bb) {
+          again = true;
+        } else {
+          WCand cur, uni;
+          cur.s = S.get(q, b);
+          cur.p = (uint64_t)sz[q] * (uint64_t)sz[b];
+          cur.key = pair_key16(id[q], id[b]);
+          uni.s = S.get(q, ba);
+          uni.p = (uint64_t)sz[q] * (uint64_t)sz[ba];
+          uni.key = pair_key16(id[q], id[ba]);
+          if (wc_better<W64>(uni, cur)) best[q] = ba;
+        }
       }
+      const uint64_t m = __ballot(again);
+      if (again) rec[nrec + (int)__popcll(m & ((1ull << lane) - 1ull))] = q;
+      nrec += (int)__popcll(m);
     }
-    __syncthreads();
-    const int nr = *nrec;
-    for (int q = wave; q < nr; q += kUpgmaWaves) {
-      const int r = rec[q];
-      const int b = wave_best_partner(S, n, r, id, sz, active);
+    wave_sync();
+    for (int t = 0; t < nrec; ++t) {
+      const int r = rec[t];
+      const int b = wave_best_partner<W64>(S, n, r, id, sz, active);
       if (lane == 0) best[r] = b;
     }
-    __syncthreads();
+    wave_sync();
   }
+  return true;
 }
-
 
 }  // namespace sad
