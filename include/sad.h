@@ -196,7 +196,9 @@ int32_t sad_profile_read(double* engine_ms, int64_t* engine_launches, int32_t re
 int32_t sad_profile_phases(double* ms_out, int64_t* jobs, int32_t reset);
 /* Per-job records of the most recent engine launch made while profiling was
  * enabled: 8 int64 per job slot (slots without a job are all zero), {W1, W2, ops, fetch, start, DP end,
- * traceback end, merge end}, times in nanoseconds from the launch's first job
+ * traceback end, merge end}; the first word also carries, in bit 32, whether the
+ * merge ran cooperatively and, in bits 40..47, how many strip groups its owner
+ * ran itself.  Times in nanoseconds from the launch's first job
  * fetch (fetch = the workgroup asked the queue; start = the job was handed
  * to it).  Copies min(cap, n) records to host memory `out` (may be NULL);
  * *njobs = n. */

@@ -161,10 +161,10 @@ __device__ inline bool wait_progress(const EngineArgs& a, JobInfo& J, const int3
   return true;
 }
 
-// A value of a boundary row, written by this workgroup or (cooperative
-// merges) by another: an agent-scope load, which does not take a line that
-// this CU's vector L1 may hold from before.  (One load form for both keeps the
-// compiler's address-space inference intact.)
+// A word of a boundary row, written by another wave of this workgroup or (in
+// a cooperative merge) by another workgroup: agent-scope atomic stores and
+// loads, which go past the CU's vector L1 (so a polling loop never sees a
+// stale line) and are never merged or hoisted by the compiler.
 template <typename T>
 __device__ inline T load_link(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -191,8 +191,9 @@ struct StripLinks {
 // live in memory that holds nothing but such words (zeroed once, tags never
 // reused), so a stale word never carries the tag a reader waits for.
 struct TagLinks {
-  const uint64_t* inH;  // row above (null for strip 0)
-  const uint64_t* inX;
+  const uint64_t* inH;  // row above (strip 0: a row of this workgroup, read
+  const uint64_t* inX;  // but unused)
+  bool has_in;          // the strip has a row above
   uint64_t* outH;       // this strip's last row (null for the last strip)
   uint64_t* outX;
   uint32_t in_tag, out_tag;
@@ -703,17 +704,23 @@ __device__ inline StripLinks<T> strip_links(const EngineArgs& a, JobInfo& J, int
 }
 
 // One strip of a 32-bit DP with MFMA tile scores and tagged boundary rows
-// (run by one wave).  The row above is read a chunk ahead; a chunk whose
-// columns do not all carry the tag yet is read again until they do.  The
-// strip's last row is written at the end of each chunk with no fence, so the
-// wave never waits for its own stores.  False when the job aborted.
+// (run by one wave), in chunks of 32 steps: a chunk needs 32 columns of the row
+// above, so the next strip trails this one by 63 + 32 steps rather than
+// 63 + 64.  The 64 x 64 score tile of columns 64 m + 1 .. 64 m + 64 is made at
+// the start of chunk 2 m; chunks 2 m and 2 m + 1 read only tiles m - 1 and m,
+// and tile m + 1 overwrites their ring slots only at chunk 2 m + 2.  The row
+// above is read a chunk ahead, and again until every column carries the tag;
+// the strip's last row is written at the end of each chunk with no fence, so
+// the wave never waits for its own stores.  False when the job aborted.
 template <int A>
 __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                                 uint32_t* tbw, const TagLinks& L, const int32_t* S32,
                                 const uint16_t* P1, const uint16_t* P2) {
   using T = int32_t;
   constexpr int KS = Tile<A>::KS;
-  const int W1 = J.W1, W2 = J.W2, nchunks = J.nchunks;
+  constexpr int CW = 32;  // steps (columns of the row above) per chunk
+  const int W1 = J.W1, W2 = J.W2;
+  const int nch = (W2 + 63 + CW - 1) / CW;  // chunks of CW steps
   const int nd_u = J.nd_u, nd_c = J.nd_c;
   const T o = (T)J.o, e = (T)J.e;
   const int i = 64 * s + lane + 1;
@@ -723,30 +730,37 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
   T H = -(o + (T)(ie - 1) * e);
   T X = DpNeg<T>::value, Y = DpNeg<T>::value;
   T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
-  uint32_t* tbs = tbw + (int64_t)s * nchunks * 16 * 64;
+  // tie words: the strip's block of J.nchunks x 16 x 64 words, word (t / 4, lane)
+  uint32_t* tbs = tbw + (int64_t)s * J.nchunks * 16 * 64;
   const int ntiles = (W2 + 63) >> 6;
   uint32_t bw[2][KS][4];
-  // above-row words of the next chunk, loaded one chunk ahead
+  // above-row words of the next chunk (lanes 0..CW-1), loaded one chunk ahead
+  // (strip 0's row above is the DP's boundary row, selected at the check: no
+  // path writes these registers other than by the loads)
+  // The loads are unconditional (no branch in the middle of a chunk): every
+  // lane reads a column of the row, clamped to 1..W2 (strip 0 reads a row of
+  // this workgroup and ignores it).
+  const bool has_in = L.has_in;
   uint64_t nh = 0, nx = 0;
   auto fetch = [&](int c) {
-    const int jn = 64 * c + 1 + lane;
-    if (jn <= W2) {
-      nh = load_link(L.inH + jn);
-      nx = load_link(L.inX + jn);
-    }
+    const int jn = min(max(CW * min(c, nch - 1) + 1 + lane, 1), W2);
+    nh = load_link(L.inH + jn);
+    nx = load_link(L.inX + jn);
   };
-  if (L.inH) fetch(0);
-  tile_load_counts<A>(bw, P2, W2, 0, lane);
-  for (int c = 0; c < nchunks; ++c) {
-    const int t0 = 64 * c;
-    const int jn = t0 + 1 + lane;
-    T bh, bx;
-    if (!L.inH) {
-      bh = jn <= W2 ? -(o + (T)(jn - 1) * e) : (T)0;
-      bx = DpNeg<T>::value;
-    } else {
+  // Loads and stores share one in-order counter, so waiting for a load also
+  // waits for every store issued before it.  The row above of chunk c + 1 is
+  // therefore read before chunk c's stores and checked right after them, in
+  // the same iteration (the loop is rotated: the check of chunk c + 1 ends
+  // iteration c), so that the wait covers that read and the count loads
+  // before it but leaves the stores in flight; the poll only runs when a tag
+  // is missing.
+  T bh = 0, bx = 0;
+  auto check = [&](int c) -> bool {
+    const int jn = CW * c + 1 + lane;
+    const bool need = has_in && lane < CW && jn <= W2;
+    if (!__all(!need || (tag_of(nh) == L.in_tag && tag_of(nx) == L.in_tag))) {
       const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
-      while (!__all(jn > W2 || (tag_of(nh) == L.in_tag && tag_of(nx) == L.in_tag))) {
+      do {
         if (__hip_atomic_load(&J.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
           return false;
         __builtin_amdgcn_s_sleep(1);
@@ -756,28 +770,48 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
           return false;
         }
         fetch(c);
-      }
-      bh = (T)(int32_t)(uint32_t)nh;
-      bx = (T)(int32_t)(uint32_t)nx;
+      } while (!__all(!need || (tag_of(nh) == L.in_tag && tag_of(nx) == L.in_tag)));
     }
-    if (c < ntiles) tile_scores<A>(ua, bw, nd_u, nd_c, ring, c, lane);
-    int32_t scv[64];
+    bh = has_in ? (T)(int32_t)(uint32_t)nh : (jn <= W2 ? -(o + (T)(jn - 1) * e) : (T)0);
+    bx = has_in ? (T)(int32_t)(uint32_t)nx : DpNeg<T>::value;
+    return true;
+  };
+  tile_load_counts<A>(bw, P2, W2, 0, lane);
+  fetch(0);
+  if (!check(0)) return false;
+  for (int c = 0; c < nch; ++c) {
+    const int t0 = CW * c;
+    const int m = c >> 1;
+    if ((c & 1) == 0 && m < ntiles) {
+      tile_scores<A>(ua, bw, nd_u, nd_c, ring, m, lane);
+      if (m + 1 < ntiles) tile_load_counts<A>(bw, P2, W2, m + 1, lane);
+    }
+    int32_t scv[CW];
 #pragma unroll
-    for (int k = 0; k < 64; ++k) scv[k] = (int32_t)ring[lane * kScPitch + (t0 & 127) + k];
-    if (c + 1 < ntiles) tile_load_counts<A>(bw, P2, W2, c + 1, lane);
-    if (L.inH && c + 1 < nchunks) fetch(c + 1);
+    for (int k = 0; k < CW; ++k) scv[k] = (int32_t)ring[lane * kScPitch + (t0 & 127) + k];
     T oh = 0, ox = 0;
-    const bool mask = (c == 0) || (t0 + 64 > W2);
+    T bhv = bh, bxv = bx;
+    const bool mask = (t0 < 63) || (t0 + CW > W2);
     auto score = [&](int k, int) -> int32_t { return scv[k]; };
     uint32_t tw[16];
-    if (mask)
-      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
-    else
-      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+    // the next chunk's row above is read half-way through this one: early
+    // enough to arrive by the check, late enough that a strip trailing its
+    // producer as closely as it can still finds it written
+    constexpr int KF = CW / 2;
+    if (mask) {
+      dp_steps<true, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+      fetch(c + 1);
+      dp_steps<true, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+    } else {
+      dp_steps<false, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+      fetch(c + 1);
+      dp_steps<false, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+    }
     if (L.outH) {
-      // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
-      const int jo = t0 + lane - 62;
-      if (jo >= 1 && jo <= W2) {
+      // lanes 64 - CW .. 63 hold the last row's values of steps t0 .. t0 + CW - 1,
+      // i.e. columns t0 + lane - (64 - CW) - 62
+      const int jo = t0 + lane - (64 - CW) - 62;
+      if (lane >= 64 - CW && jo >= 1 && jo <= W2) {
         __hip_atomic_store(L.outH + jo, tag_word(oh, L.out_tag), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(L.outX + jo, tag_word(ox, L.out_tag), __ATOMIC_RELAXED,
@@ -785,7 +819,8 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
       }
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) tbs[(t0 / 4 + q) * 64 + lane] = tw[q];
+    for (int q = 0; q < CW / 4; ++q) tbs[(t0 / 4 + q) * 64 + lane] = tw[q];
+    if (c + 1 < nch && !check(c + 1)) return false;
   }
   if (s == ((W1 - 1) >> 6) && lane == ((W1 - 1) & 63)) *L.score = (int64_t)H;
   return true;
@@ -814,8 +849,9 @@ __device__ inline TagLinks tag_links(const EngineArgs& a, JobInfo& J, int s, int
   uint64_t* rout = grp_out ? (J.coop ? crows + (int64_t)g * R2 : lrows + 3 * R2)
                            : lrows + (int64_t)(s % kCoopGroupStrips) * R2;
   TagLinks L;
-  L.inH = has_in ? rin : nullptr;
-  L.inX = has_in ? rin + kCoopRowLen : nullptr;
+  L.has_in = has_in;
+  L.inH = has_in ? rin : lrows;
+  L.inX = has_in ? rin + kCoopRowLen : lrows + kCoopRowLen;
   L.outH = has_out ? rout : nullptr;
   L.outX = has_out ? rout + kCoopRowLen : nullptr;
   L.in_tag = grp_in ? (J.coop ? J.tag : J.ltag + (uint32_t)(k - 1)) : J.ltag + (uint32_t)k;
@@ -1677,7 +1713,9 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         atomicAdd(&a.phase_acc[5], (unsigned long long)(tk4 - tk35));
         if (a.job_rec && job < a.nrec) {
           long long* r = a.job_rec + (int64_t)job * 8;
-          r[0] = W1;
+          // W1; cooperative flag; groups the owner ran itself (LDS claim count)
+          r[0] = (long long)W1 | ((long long)J.coop << 32) |
+                 ((long long)(J.coop ? gstate[0] : 0) << 40);
           r[1] = W2;
           r[2] = J.err ? 0 : J.nops;
           r[3] = (long long)tk0;
