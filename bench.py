@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--workload", default="prot2000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--sweep-p", default="", metavar="P1,P2,...",
+                    help="instead of the benchmark line, one line per bucket count p: step time "
+                         "and alignment quality (Q) of the pipeline on the workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a buffer of this many MiB once (a kernel "
                          "of known traffic for scaling hardware byte counters)")
@@ -120,6 +123,32 @@ def main():
     s = make_inputs(args.workload)
     seqs = pipeline.to_device(s.codes, s.offsets, s.alphabet)
     S = w.subst()
+    cls, ncls = s.homology_classes()
+    d_cls = torch.tensor(cls, device="cuda")
+
+    def quality(colmap):
+        a, t = B.sad_quality(torch.tensor(colmap, dtype=torch.int32, device="cuda"), d_cls, ncls)
+        return {"Q": round(a / t, 5) if t else None, "aligned_pairs": a, "true_pairs": t}
+
+    if args.sweep_p:
+        # bucket-count sweep: time and quality of the pipeline at each p
+        # (the default schedule at every p: the sweep is over p, not schedules)
+        for p in [int(x) for x in args.sweep_p.split(",") if x]:
+            print(f"sweep: p = {p}", file=sys.stderr, flush=True)
+            prm_s = B.Params(w.kmer_k, p, S, w.gap_open, w.gap_extend, w.s_max,
+                             B.SAD_BATCHED_MFMA)
+            res_s, ms_s, eng_s, nl = timed_steps(pipeline.run_device, seqs, prm_s, args.steps,
+                                                 args.warmup, B, torch)
+            h = pipeline.to_host(res_s, s.n, p, seqs.total_len)
+            cl = h["align"]["cells"] + h["refine"]["cells"]
+            sizes = np.diff(h["part"]["bucket_off"])
+            line = {"sweep": "buckets", "workload": w.name, "p": p, "ms_per_step": round(ms_s, 3),
+                    "value": round(cl / (ms_s / 1e3) / 1e9, 3), "unit": "GCUPS",
+                    "dp_cells_per_step": cl, "largest_bucket": int(sizes.max()),
+                    "engine_ms_per_step": round(eng_s / args.steps, 3),
+                    "quality": quality(h["refine"]["colmap"])}
+            print(json.dumps(line), flush=True)
+        return
     prm = B.Params(w.kmer_k, w.p, S, w.gap_open, w.gap_extend, w.s_max, B.SAD_BATCHED_MFMA)
     # autotune the bucket alignment's schedule on this workload (cached for
     # the process), then time the pipeline with it
@@ -140,6 +169,7 @@ def main():
         del src, dst
     cells = host["align"]["cells"] + host["refine"]["cells"]
     gcups = cells / (ms / 1e3) / 1e9
+    qual = quality(host["refine"]["colmap"])
     seq_s = s.n / (ms / 1e3)
     # engine kernel: algorithmic int32 ops over its measured launch time
     eng_ops = cells * args.steps * OPS_PER_CELL
@@ -155,6 +185,7 @@ def main():
                    "parallelism": "single GPU"},
         "seq_per_s": round(seq_s, 2),
         "dp_cells_per_step": cells,
+        "quality": qual,
         "mode": "batched",
         "schedule": {"engine_workgroups": tuned[0], "trees_in_launch": bool(tuned[1]),
                      "graph_captures": graphs[0], "graph_replays": graphs[1]},

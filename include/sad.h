@@ -189,6 +189,20 @@ int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off, const int32_
  * default. */
 int32_t sad_profile_enable(int32_t on);
 int32_t sad_profile_read(double* engine_ms, int64_t* engine_launches, int32_t reset);
+/* Alignment quality against a known homology (Section 4, the Q measure: the
+ * correctly aligned residue pairs over the residue pairs of the reference).
+ * The reference is given as homology classes: residues r and r' form a
+ * reference pair iff d_class[r] == d_class[r'] (a class holds at most one
+ * residue of each sequence, so the two lie in different sequences); the pair
+ * is aligned iff d_colmap[r] == d_colmap[r'] (e.g. the glued column map of
+ * sad_refine).  Inputs (device): d_colmap[total], d_class[total] with classes
+ * 0..nclass-1.  Outputs (host): *aligned_pairs, *true_pairs; Q = aligned /
+ * true.  SAD_E_INVAL for a class id out of range (checked on the device),
+ * total outside 0..2^31-1 or nclass < 1.  Device workspace: the library's. */
+int32_t sad_quality(const int32_t* d_colmap, const int32_t* d_class, int64_t total,
+                    int32_t nclass, uint64_t* aligned_pairs, uint64_t* true_pairs,
+                    hipStream_t stream);
+
 /* Per-job phase times of the alignment engine while profiling is enabled,
  * summed over jobs (milliseconds): ms_out[0] waiting for a ready job,
  * [1] DP, [2] traceback, [3] merge, [4] publication (device-scope fence and

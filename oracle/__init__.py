@@ -15,6 +15,8 @@ Parity status per step (what pins it, in ``tests/test_oracle_*.py``):
                                 numpy column scores, score recomputation
   progressive / refine / glue   replay invariants (degapped rows, restriction,
                                 no all-gap columns, recomputed merge scores)
+  quality counts (Q)            brute-force enumeration of residue pairs,
+                                perfect and shifted alignments
 The whole pipeline has no printed example in the paper: end to end it is pinned
 only through those invariants.
 """
@@ -272,3 +274,21 @@ def run_pipeline(codes, offsets, A: int, k: int, p: int, S, go: int, ge: int,
     rf = refine(codes, offsets, A, part["bucket_off"], part["members"], al["colmap"],
                 al["width"], k, S, go, ge)
     return dict(key=key, samples=samples, part=part, align=al, refine=rf)
+
+
+def quality_counts(colmap, cls):
+    """Q measure of Section 4 against homology classes: (aligned pairs, true
+    pairs).  A true pair is two residues of one class; it is aligned when the
+    alignment puts both in one column.  Counted per class and per (class,
+    column) group: a group of m residues holds m (m - 1) / 2 pairs."""
+    colmap = np.asarray(colmap, dtype=np.int64)
+    cls = np.asarray(cls, dtype=np.int64)
+    if colmap.shape != cls.shape:
+        raise ValueError("colmap and classes differ in length")
+    if colmap.size == 0:
+        return 0, 0
+    _, m = np.unique(cls, return_counts=True)
+    true_pairs = int((m * (m - 1) // 2).sum())
+    _, g = np.unique(np.stack([cls, colmap], axis=1), axis=0, return_counts=True)
+    aligned = int((g * (g - 1) // 2).sum())
+    return aligned, true_pairs

@@ -27,6 +27,7 @@ SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
 EXPORTS = ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine", "sad_tune",
+           "sad_quality",
            "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs", "sad_profile_graphs",
            "sad_last_error",
            "sad_release",
@@ -88,6 +89,8 @@ def lib():
         L.sad_tune.restype = I32
         L.sad_profile_graphs.argtypes = [P, P, I32]
         L.sad_profile_graphs.restype = I32
+        L.sad_quality.argtypes = [P, P, ctypes.c_int64, I32, P, P, P]
+        L.sad_quality.restype = I32
         L.sad_last_error.restype = ctypes.c_char_p
         L.sad_version.restype = ctypes.c_char_p
         L.sad_release.restype = None
@@ -291,6 +294,23 @@ def sad_profile_graphs(reset: bool = False):
     c, r = ctypes.c_int64(0), ctypes.c_int64(0)
     lib().sad_profile_graphs(ctypes.byref(c), ctypes.byref(r), 1 if reset else 0)
     return c.value, r.value
+
+
+def sad_quality(colmap, cls, nclass: int):
+    """Alignment quality against homology classes (include/sad.h): returns
+    (aligned_pairs, true_pairs) for device int32 tensors colmap and cls of one
+    length; Q = aligned / true."""
+    total = int(colmap.numel())
+    if int(cls.numel()) != total:
+        raise ValueError("colmap and class ids differ in length")
+    if colmap.dtype != torch.int32 or cls.dtype != torch.int32:
+        raise ValueError("colmap and class ids must be int32")
+    a, t = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    code = lib().sad_quality(_ptr(colmap.contiguous()) if total else None,
+                             _ptr(cls.contiguous()) if total else None, total, int(nclass),
+                             ctypes.byref(a), ctypes.byref(t), _stream())
+    _check(code, "sad_quality")
+    return a.value, t.value
 
 
 def sad_profile_jobs():

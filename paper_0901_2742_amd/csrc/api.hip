@@ -7,6 +7,7 @@
 #include <tuple>
 #include <map>
 #include <functional>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -45,6 +46,16 @@ static thread_local std::string g_err;
 // engine-kernel timing (sad_profile_enable / sad_profile_read)
 static bool g_prof_on = false;   // engine kernel timing (HIP events)
 static bool g_phase_on = false;  // per-phase ticks and per-job records
+
+// SAD_LOG=1: one line on stderr per alignment-engine launch (status, expired
+// waits, workspace sizes)
+static bool log_enabled() {
+  static const bool on = [] {
+    const char* v = getenv("SAD_LOG");
+    return v && atoi(v) > 0;
+  }();
+  return on;
+}
 static int64_t g_graph_captured = 0, g_graph_replayed = 0;
 static double g_prof_ms = 0.0;
 static int64_t g_prof_launches = 0;
@@ -179,6 +190,7 @@ static const char* where_name(int32_t w) {
     case W_ENGINE_WAIT: return "alignment engine (queue wait limit)";
     case W_REFINE: return "refine";
     case W_ENGINE_LINK: return "alignment engine (strip boundary scratch)";
+    case W_QUALITY: return "quality (class id out of range)";
     default: return "device";
   }
 }
@@ -321,7 +333,8 @@ struct EngineBuffers {
   int nwg;
 };
 
-// Engine scratch sized for profiles up to wcap columns.
+// Engine scratch sized for profiles up to wcap columns; wide_links: strip
+// boundary rows hold 64-bit values (some merge may need the 64-bit DP).
 static int64_t tb_words_for(int wcap) {
   int64_t strips = (wcap + 63) / 64;
   int64_t chunks = (wcap + 63 + 63) / 64;
@@ -329,13 +342,14 @@ static int64_t tb_words_for(int wcap) {
 }
 
 static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, int njobs,
-                        int64_t prof_cap, int64_t up_cap, int wcap, int grid = 0) {
+                        int64_t prof_cap, int64_t up_cap, int wcap, bool wide_links,
+                        int grid = 0) {
   e.nwg = std::max(1, std::min(njobs, grid > 0 ? grid : engine_workgroups()));
   e.prof_cap = prof_cap;
   e.up_cap = up_cap;
   e.tb_words = tb_words_for(wcap);
   e.link_rows = std::max(1, (wcap + 63) / 64 - 1);
-  e.link_stride = wcap + 1;
+  e.link_stride = (wcap + 1) * (wide_links ? 2 : 1);
   e.link_words = (int64_t)e.link_rows * 2 * e.link_stride;
   cv.add(e.node_W, nnodes);
   cv.add(e.node_n, nnodes);
@@ -474,6 +488,7 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
   a.queue_cap = std::max(njobs, 1) * (1 + kMaxHelpers);
   a.jobs_done = e.qctl + 3;
   a.finished = e.qctl + 4;
+  a.wait_sites = e.qctl + 5;
   a.coop_next = e.coop_next;
   a.coop_strips = e.coop_strips;
   a.coop_owner = e.coop_owner;
@@ -752,11 +767,22 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
   for (int g = 0; g < ts.ngroups; ++g)
     njobs += std::max(0, ts.h_group_off[g + 1] - ts.h_group_off[g] - 1);
   int wcap = std::min(kMaxWidth, std::max(2 * ts.max_len + 64, 128));
+  int max_group = 0;
+  for (int g = 0; g < ts.ngroups; ++g)
+    max_group = std::max(max_group, ts.h_group_off[g + 1] - ts.h_group_off[g]);
+  int smax = 0;
+  for (int q = 0; q < A * A; ++q) smax = std::max(smax, std::abs((int)prm->subst[q]));
+  const double unit = (double)std::max(std::max(smax, (int)prm->gap_open), 1);
   int64_t prof_cap = (int64_t)A * (ts.total_len * 6 + 4096);
   int64_t up_cap = ts.total_len * 6 + 4096;
   for (int attempt = 0; attempt < 8; ++attempt) {
     Carver cv = base_cv;
-    plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, prof_cap, up_cap, wcap, grid);
+    // a merge takes the 64-bit DP when (W1 + W2 + 2) n1 n2 max(smax, go)
+    // reaches 2^29 (n1 + n2 at most the largest group)
+    const double g2 = std::floor(max_group / 2.0) * std::ceil(max_group / 2.0);
+    const bool wide_links = (2.0 * wcap + 2.0) * g2 * unit >= (double)(1 << 29);
+    plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, prof_cap, up_cap, wcap,
+                wide_links, grid);
     int32_t r = cv.carve(c);
     if (r) return r;
     if (fused) {
@@ -881,6 +907,16 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     DevStatus d{};
     r = read_status(c, stream, &d);
     if (r) return r;
+    if (log_enabled()) {
+      int32_t sites = 0;
+      HIPCHK(hipMemcpy(&sites, a.wait_sites, sizeof(sites), hipMemcpyDeviceToHost));
+      const int64_t detail = ((int64_t)d.detail_hi << 32) | (uint32_t)d.detail_lo;
+      fprintf(stderr,
+              "[sad] engine attempt %d: %d merges, status %d (%s, detail %lld), expired wait "
+              "sites 0x%x, width cap %d, pools %lld/%lld\n",
+              attempt, njobs, d.code, d.code ? where_name(d.where) : "ok", (long long)detail,
+              sites, wcap, (long long)prof_cap, (long long)up_cap);
+    }
     if (njobs > 0) timer.collect();
     r = collect_phases(c, a, stream);
     if (r) return r;
@@ -1477,7 +1513,7 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   const int64_t up_cap = Wtot + GL + ops_tot + 1;
   EngineBuffers e{};
   Carver cv;
-  plan_engine(cv, e, 2 * q + 1, q, q, prof_cap, up_cap, rwcap);
+  plan_engine(cv, e, 2 * q + 1, q, q, prof_cap, up_cap, rwcap, true);
   r = cv.carve(c);
   if (r) return r;
   r = reset_status(c, stream);
@@ -1594,3 +1630,37 @@ extern "C" void sad_release(void) {
 }
 
 extern "C" const char* sad_version(void) { return "sad-gfx950 0.1"; }
+
+extern "C" int32_t sad_quality(const int32_t* d_colmap, const int32_t* d_class, int64_t total,
+                               int32_t nclass, uint64_t* aligned_pairs, uint64_t* true_pairs,
+                               hipStream_t stream) {
+  using namespace sad;
+  if (!aligned_pairs || !true_pairs) return fail(SAD_E_INVAL, "null output");
+  if (total < 0 || total > INT32_MAX || nclass < 1 || nclass > INT32_MAX - 1)
+    return fail(SAD_E_INVAL, "total or class count out of range");
+  if (total > 0 && (!d_colmap || !d_class)) return fail(SAD_E_INVAL, "null input");
+  DeviceCtx* c = nullptr;
+  int32_t r = get_ctx(&c);
+  if (r) return r;
+  int32_t *cnt = nullptr, *off = nullptr, *cursor = nullptr, *cols = nullptr;
+  unsigned long long* sums = nullptr;
+  Carver cv;
+  cv.add(cnt, (size_t)nclass);
+  cv.add(off, (size_t)nclass + 1);
+  cv.add(cursor, (size_t)nclass);
+  cv.add(cols, (size_t)std::max<int64_t>(total, 1));
+  cv.add(sums, 2);
+  r = cv.carve(c);
+  if (r) return r;
+  r = reset_status(c, stream);
+  if (r) return r;
+  launch_quality(d_colmap, d_class, total, nclass, cnt, off, cursor, cols, sums, c->st, stream);
+  r = finish(c, stream);
+  if (r) return r;
+  unsigned long long h[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  *aligned_pairs = h[0];
+  *true_pairs = h[1];
+  return SAD_OK;
+}

@@ -121,6 +121,18 @@ struct JobInfo {
   long long prof_off, up_off;
 };
 
+// Bounded waits of the engine, by site: a wait that runs out of time sets the
+// site's bit in *wait_sites (kept even when an earlier error holds the status)
+// and raises SAD_E_DEVICE with the site in the detail's high word.
+enum WaitSite : int {
+  WS_QUEUE = 0, WS_LINK = 1, WS_PROGRESS = 2, WS_ROW = 3, WS_GROUP = 4, WS_COOP = 5,
+  WS_STRIP = 6, WS_LOADER = 7, WS_TREE = 8,
+};
+__device__ inline void wait_expired(DevStatus* st, int32_t* sites, int site, int64_t detail) {
+  if (sites) atomicOr(sites, 1 << site);
+  raise_error(st, SAD_E_DEVICE, ((int64_t)site << 32) | (uint32_t)detail, W_ENGINE_WAIT);
+}
+
 // Waits until link L has `need` columns; false on abort or time-out.
 __device__ inline bool wait_link(const EngineArgs& a, JobInfo& J, const int32_t* prog, int L,
                                  int need) {
@@ -132,7 +144,7 @@ __device__ inline bool wait_link(const EngineArgs& a, JobInfo& J, const int32_t*
     __builtin_amdgcn_s_sleep(1);
     if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
       __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if ((threadIdx.x & 63) == 0) raise_error(a.st, SAD_E_DEVICE, L, W_ENGINE_WAIT);
+      if ((threadIdx.x & 63) == 0) wait_expired(a.st, a.wait_sites, WS_LINK, L);
       return false;
     }
   }
@@ -154,7 +166,7 @@ __device__ inline bool wait_progress(const EngineArgs& a, JobInfo& J, const int3
     __builtin_amdgcn_s_sleep(1);
     if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
       __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if ((threadIdx.x & 63) == 0) raise_error(a.st, SAD_E_DEVICE, need, W_ENGINE_WAIT);
+      if ((threadIdx.x & 63) == 0) wait_expired(a.st, a.wait_sites, WS_PROGRESS, need);
       return false;
     }
   }
@@ -766,7 +778,7 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
         __builtin_amdgcn_s_sleep(1);
         if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
           __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          if (lane == 0) raise_error(a.st, SAD_E_DEVICE, jn, W_ENGINE_WAIT);
+          if (lane == 0) wait_expired(a.st, a.wait_sites, WS_ROW, jn);
           return false;
         }
         fetch(c);
@@ -902,6 +914,7 @@ __device__ bool tagged_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, u
         __builtin_amdgcn_s_sleep(1);
         if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
           __hip_atomic_store(&J.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (lane == 0) wait_expired(a.st, a.wait_sites, WS_GROUP, k);
           return false;
         }
       }
@@ -1027,6 +1040,8 @@ struct StripSource {
   int32_t* fin;
   int64_t wait_ticks;
   int cur;
+  DevStatus* st;
+  int32_t* wsites;
   __device__ void cover(int, int s, int, int) {
     if (s == cur) return;
     if (cur >= 0)
@@ -1036,7 +1051,10 @@ struct StripSource {
     while (__hip_atomic_load(&ready[s & 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != s) {
       __builtin_amdgcn_s_sleep(1);
       // the loader always makes progress; the limit only guards a broken wait
-      if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > wait_ticks) break;
+      if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > wait_ticks) {
+        if ((threadIdx.x & 63) == 0) wait_expired(st, wsites, WS_STRIP, s);
+        break;
+      }
     }
   }
   __device__ uint32_t word(int s, int t4, int lc) const {
@@ -1051,7 +1069,7 @@ struct StripSource {
 // 4 KB, contiguous) into the two LDS buffers with direct-to-LDS loads.
 __device__ void strip_loader(const uint32_t* tbw, uint32_t* buf, int words, int sL,
                              int32_t* ready, int32_t* consumed, int32_t* fin, int64_t wait_ticks,
-                             int lane) {
+                             DevStatus* st, int32_t* wsites, int lane) {
   for (int s = sL; s >= 0; --s) {
     const int b = s & 1;
     if (s <= sL - 2) {
@@ -1060,7 +1078,10 @@ __device__ void strip_loader(const uint32_t* tbw, uint32_t* buf, int words, int 
              s + 2) {
         if (__hip_atomic_load(fin, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
         __builtin_amdgcn_s_sleep(1);
-        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > wait_ticks) return;
+        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > wait_ticks) {
+          if (lane == 0) wait_expired(st, wsites, WS_LOADER, s);
+          return;
+        }
       }
     } else if (__hip_atomic_load(fin, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) {
       return;
@@ -1339,7 +1360,7 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
       if (avail == k0) {
         __builtin_amdgcn_s_sleep(1);
         if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
-          if (lane == 0) raise_error(a.st, SAD_E_DEVICE, g, W_ENGINE_WAIT);
+          if (lane == 0) wait_expired(a.st, a.wait_sites, WS_TREE, g);
           break;
         }
         continue;
@@ -1426,7 +1447,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
           }
           __builtin_amdgcn_s_sleep(8);
           if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
-            raise_error(a.st, SAD_E_DEVICE, slot, W_ENGINE_WAIT);
+            wait_expired(a.st, a.wait_sites, WS_QUEUE, slot);
             ok = false;
             break;
           }
@@ -1539,7 +1560,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
                                                 __HIP_MEMORY_SCOPE_AGENT);
             gstate[0] = 0;
             gstate[1] = 0;
-          } else if (!err && !wide && ngroups > 1 && idle > 0 &&
+          } else if (!err && !wide && W1 > 0 && W2 > 0 && ngroups > 1 && idle > 0 &&
                      (int)blockIdx.x < a.coop_wgs) {
             // cooperative merge while workgroups wait idle: a fresh tag for
             // its boundary rows, its group and strip counters, then helper
@@ -1628,7 +1649,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
                                    __HIP_MEMORY_SCOPE_AGENT) < J.nstrips) {
             __builtin_amdgcn_s_sleep(2);
             if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t_start) > a.wait_ticks) {
-              raise_error(a.st, SAD_E_DEVICE, job, W_ENGINE_WAIT);
+              wait_expired(a.st, a.wait_sites, WS_COOP, job);
               J.err = 1;
               break;
             }
@@ -1648,12 +1669,13 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
         if (strips_in_lds) {
           // wave 1 streams whole strips into the (idle) score ring
           if (wave == 0) {
-            StripSource src{ring, sw, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks, -1};
+            StripSource src{ring, sw, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks, -1, a.st,
+                            a.wait_sites};
             const int n = traceback(src, ops, W1, W2, lane);
             if (lane == 0) J.nops = n;
           } else if (wave == 1) {
             strip_loader(tbw, ring, sw, (W1 - 1) >> 6, tbctl, tbctl + 2, tbctl + 4, a.wait_ticks,
-                         lane);
+                         a.st, a.wait_sites, lane);
           }
         } else if (wave == 0) {
           StageSource src{tbw, tbst, Stage{-1, 0}, sw, nchunks * 16};

@@ -55,7 +55,7 @@ __device__ inline void raise_error(DevStatus* st, int32_t code, int64_t detail, 
 enum Where : int32_t {
   W_VALIDATE = 1, W_KMER = 2, W_RANK = 3, W_PART = 4, W_UPGMA = 5, W_ENGINE = 6,
   W_ENGINE_POOL = 7, W_ENGINE_TB = 8, W_ENGINE_WIDTH = 9, W_ENGINE_BOUND = 10,
-  W_ENGINE_WAIT = 11, W_REFINE = 12, W_ENGINE_LINK = 13,
+  W_ENGINE_WAIT = 11, W_REFINE = 12, W_ENGINE_LINK = 13, W_QUALITY = 14,
 };
 
 // ------------------------------------------------------------------ arena
@@ -112,6 +112,11 @@ void launch_partition(const uint64_t* key, int n, int p, const int32_t* sorted,
                       hipStream_t stream);
 
 // upgma.hip: one workgroup per group; F given per group at fm_off (n_g x n_g).
+// alignment quality against homology classes (quality.hip): sums[0] aligned
+// pairs, sums[1] true pairs; cnt/cursor nclass, off nclass + 1, cols total
+void launch_quality(const int32_t* colmap, const int32_t* cls, int64_t total, int32_t nclass,
+                    int32_t* cnt, int32_t* off, int32_t* cursor, int32_t* cols,
+                    unsigned long long* sums, DevStatus* st, hipStream_t stream);
 void launch_upgma(const uint32_t* F, const int64_t* fm_off, const int32_t* group_off,
                   int ngroups, int max_n, uint64_t* Swork, int32_t* merges_out,
                   const int32_t* merge_base, DevStatus* st, hipStream_t stream);
@@ -188,6 +193,7 @@ struct EngineArgs {
   int32_t queue_cap;        // tickets the queue holds
   int32_t* jobs_done;       // merges finished; the last one sets *finished
   int32_t* finished;
+  int32_t* wait_sites;      // bit w set when a wait of site w ran out of time
   int32_t* coop_next;       // per job slot: next group to claim
   int32_t* coop_strips;     // per job slot: strips finished
   int32_t* coop_owner;      // per job slot: owner workgroup + 1

@@ -131,6 +131,19 @@ def test_wide_dp(hip, mode, alphabet):
 
 
 @pytest.mark.parametrize("mode", [1, 0])
+def test_large_bucket(hip, mode):
+    """One bucket of 700 members: guide tree beyond the 64-bit cross-product
+    range (128-bit comparisons), built outside the engine launch, and merges
+    near the root whose bound (W1 + W2 + 2) n1 n2 go passes 2^29 (64-bit DP,
+    64-bit strip boundary rows) from the first engine attempt."""
+    B, pipeline = hip
+    _say(f"case large bucket mode={mode}")
+    s = generate(6007, 700, 20, 2, {"kind": "uniform_int", "lo": 24, "hi": 40}, 0.1, 0.02, 3)
+    got, ref = run_both(B, pipeline, s, 3, 1, protein_matrix(), 40, 2, mode)
+    compare(got, ref, f"large bucket mode {mode}")
+
+
+@pytest.mark.parametrize("mode", [1, 0])
 def test_prot2000_full(hip, mode):
     # mode 1: one persistent launch over all trees, MFMA tile scores;
     # mode 0: one launch per tree level, VALU column scores

@@ -49,6 +49,12 @@ class SeqSet:
     def seq(self, i: int) -> np.ndarray:
         return self.codes[self.offsets[i]:self.offsets[i + 1]]
 
+    def homology_classes(self):
+        """The homology ids renumbered 0..nclass-1 (int32), and nclass."""
+        _, inv = np.unique(self.homology, return_inverse=True)
+        inv = inv.astype(np.int32).reshape(-1)
+        return inv, int(inv.max()) + 1 if inv.size else 1
+
     def sha256(self) -> str:
         h = hashlib.sha256()
         h.update(np.int64(self.alphabet).tobytes())
