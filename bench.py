@@ -42,6 +42,12 @@ def parse():
     ap.add_argument("--sweep-p", default="", metavar="P1,P2,...",
                     help="instead of the benchmark line, one line per bucket count p: step time "
                          "and alignment quality (Q) of the pipeline on the workload")
+    ap.add_argument("--rank-study", default="", metavar="N1,N2,...",
+                    help="instead of the benchmark line, one line per set size N: the "
+                         "centralised rank (all N as the sample) against the globalised rank "
+                         "(p (p - 1) samples at most), their statistics and histograms")
+    ap.add_argument("--rank-p", type=int, default=16,
+                    help="bucket count p of the globalised rank in --rank-study")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a buffer of this many MiB once (a kernel "
                          "of known traffic for scaling hardware byte counters)")
@@ -103,6 +109,49 @@ def timed_steps(run, seqs, prm, steps, warmup, B, torch):
     return res, t0.elapsed_time(t1) / steps, eng_ms, launches
 
 
+def rank_study(args, B, pipeline, torch):
+    """Centralised vs globalised k-mer rank on synthetic proteins: families of
+    250 around roots of normal length (mean 316, sd 60, within 100..600), 10%
+    substitutions and 2% indels per leaf, k = 3; the centralised rank is timed
+    on the GPU (HIP events over 3 calls after one warm-up)."""
+    import numpy as np
+
+    from paper_0901_2742_amd.rankstats import rank_stats
+    from workloads import generate
+
+    p = args.rank_p
+    for n in [int(x) for x in args.rank_study.split(",") if x]:
+        print(f"rank study: N = {n}", file=sys.stderr, flush=True)
+        s = generate(5000 + n, n, 20, max(1, n // 250),
+                     {"kind": "normal", "mean": 316, "sd": 60, "lo": 100, "hi": 600},
+                     0.10, 0.02, 3)
+        seqs = pipeline.to_device(s.codes, s.offsets, s.alphabet)
+        prm = B.Params(3, p, np.zeros((20, 20), np.int8), 10, 1, 1024, B.SAD_BATCHED_MFMA)
+        key, sid = B.sad_kmer_rank(seqs, prm)
+        central = B.sad_rank_against(seqs, 3)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(3):
+            central = B.sad_rank_against(seqs, 3)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / 3
+        g = key.cpu().numpy().view(np.uint64)
+        c = central.cpu().numpy().view(np.uint64)
+        st = rank_stats(c, g, n, int(sid.numel()))
+        line = {"study": "rank", "n": n, "p": p, "global_samples": int(sid.numel()),
+                "central_ms": round(ms, 3), "central_pairs": n * n}
+        def sig(v):
+            return float(f"{v:.6g}")
+
+        line.update({k: (sig(v) if isinstance(v, float) else v) for k, v in st.items()
+                     if k not in ("central", "global", "hist_edges")})
+        line["central"] = {k: sig(v) for k, v in st["central"].items()}
+        line["global"] = {k: sig(v) for k, v in st["global"].items()}
+        print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -119,6 +168,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.rank_study:
+        rank_study(args, B, pipeline, torch)
+        return
     w = workload(args.workload)
     s = make_inputs(args.workload)
     seqs = pipeline.to_device(s.codes, s.offsets, s.alphabet)

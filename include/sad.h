@@ -104,6 +104,21 @@ int32_t sad_kmer_rank(const sad_seqs* seqs, const sad_params* prm, uint64_t* d_k
                       hipStream_t stream);
 
 /*
+ * Rank against a given sample (Section 2.3.1, Table 1): d_key[i] = sum over
+ * the n_samples ids s in d_sample_ids of F(i, s) for every sequence i (self
+ * included when i is listed), the globalised rank's formula with the sample
+ * chosen by the caller.  d_sample_ids == NULL takes all n sequences: the
+ * centralised rank, each sequence against the whole set, which the sampled
+ * (globalised) rank of sad_kmer_rank approximates.  Inputs: seqs as for
+ * sad_kmer_rank, kmer_k >= 1, d_sample_ids[n_samples] (device, ids in [0, n))
+ * or NULL.  Output: d_key[n] (device uint64, caller-owned).  SAD_E_INVAL for
+ * a bad sequence set, k, count or id (ids are checked on the device; an id
+ * out of range is never dereferenced).
+ */
+int32_t sad_rank_against(const sad_seqs* seqs, int32_t kmer_k, const int32_t* d_sample_ids,
+                         int32_t n_samples, uint64_t* d_key, hipStream_t stream);
+
+/*
  * Stage 2 -- regular-sampling partition (Section 2.3.2, steps 7-10).  Each chunk
  * is sorted by the composite key (key_i, i); p-1 keys are taken at positions
  * floor(t w / p), t = 1..p-1; the p(p-1) gathered keys Y are sorted and the

@@ -76,6 +76,7 @@ def _declare(L):
     L.sadref_fhat.argtypes = [P, I64, P, I64, ctypes.c_int, ctypes.c_int]
     L.sadref_fhat.restype = ctypes.c_uint32
     L.sadref_kmer_rank.argtypes = [I32, I32, P, P, I32, I32, I32, P, P, I32, P]
+    L.sadref_rank_against.argtypes = [I32, I32, P, P, I32, P, I32, P, I32, P]
     L.sadref_partition.argtypes = [I32, P, I32, P, P, P, P, P]
     L.sadref_upgma.argtypes = [I32, P, P]
     L.sadref_profile_align.argtypes = [P, I32, I32, P, I32, I32, I32, P, I32, I32, P, P, P]
@@ -84,7 +85,8 @@ def _declare(L):
     L.sadref_consensus.argtypes = [P, I32, I32, I32, P, P]
     L.sadref_refine.argtypes = [I32, I32, P, P, I32, P, P, P, P, I32, P, I32, I32,
                                 P, I32, P, P, P, P, P, P, P, P]
-    for f in ("sadref_kmer_list", "sadref_kmer_rank", "sadref_partition", "sadref_upgma",
+    for f in ("sadref_kmer_list", "sadref_kmer_rank", "sadref_rank_against", "sadref_partition",
+              "sadref_upgma",
               "sadref_profile_align", "sadref_align_buckets", "sadref_consensus",
               "sadref_refine"):
         getattr(L, f).restype = ctypes.c_int
@@ -143,6 +145,23 @@ def kmer_rank(codes, offsets, A: int, k: int, p: int, s_max: int = 1024):
                                 cap, _p(ns))
     _check(st, "kmer_rank")
     return key[:n].copy(), sid[:int(ns[0])].copy()
+
+
+def rank_against(codes, offsets, A: int, k: int, samples=None, rows=None):
+    """K_i = sum over the samples s of F(i, s) for the listed rows (Section
+    2.3.1).  samples=None: all N sequences, i.e. the centralised rank that the
+    globalised rank (against the k p samples) approximates; rows=None: all."""
+    codes, offsets = _c(codes, np.uint8), _c(offsets, np.int64)
+    n = len(offsets) - 1
+    sp = None if samples is None else _c(samples, np.int32)
+    rp = None if rows is None else _c(rows, np.int32)
+    nr = n if rp is None else len(rp)
+    key = np.zeros(max(nr, 1), np.uint64)
+    st = lib().sadref_rank_against(n, A, _p(codes), _p(offsets), k,
+                                   None if sp is None else _p(sp), 0 if sp is None else len(sp),
+                                   None if rp is None else _p(rp), nr, _p(key))
+    _check(st, "rank_against")
+    return key[:nr].copy()
 
 
 def partition(key, p: int):

@@ -242,6 +242,38 @@ int sadref_kmer_rank(int32_t n, int32_t A, const uint8_t* codes, const int64_t* 
 /* Regular sampling, pivots and buckets (Section 2.3.2)                 */
 /* ------------------------------------------------------------------ */
 
+/* Rank of listed rows against a listed sample (Section 2.3.1): for each row i
+ * in rows[0..nrows), key[t] = sum over the samples s of F(i, s), self
+ * included when i is itself a sample.  samples == NULL takes all n sequences
+ * (the centralised rank, every sequence against all N); rows == NULL takes
+ * rows 0..n-1.  Sample and row ids outside [0, n) are rejected. */
+int sadref_rank_against(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                        int32_t kmer_k, const int32_t* samples, int32_t n_samples,
+                        const int32_t* rows, int32_t nrows, uint64_t* key) {
+  int st = validate_seqs(n, A, codes, offsets, kmer_k);
+  if (st) return st;
+  if (samples == NULL) n_samples = n;
+  if (rows == NULL) nrows = n;
+  if (n_samples < 0 || nrows < 0) return SADREF_E_INVAL;
+  for (int32_t t = 0; samples && t < n_samples; ++t)
+    if (samples[t] < 0 || samples[t] >= n) return SADREF_E_INVAL;
+  for (int32_t t = 0; rows && t < nrows; ++t)
+    if (rows[t] < 0 || rows[t] >= n) return SADREF_E_INVAL;
+  kmer_list_t* kl = (kmer_list_t*)malloc(sizeof(kmer_list_t) * (size_t)(n > 0 ? n : 1));
+  for (int32_t i = 0; i < n; ++i)
+    build_list(&kl[i], codes + offsets[i], offsets[i + 1] - offsets[i], A, kmer_k);
+  for (int32_t t = 0; t < nrows; ++t) {
+    const int32_t i = rows ? rows[t] : t;
+    uint64_t sum = 0;
+    for (int32_t u = 0; u < n_samples; ++u)
+      sum += fhat_lists(&kl[i], &kl[samples ? samples[u] : u], kmer_k);
+    key[t] = sum;
+  }
+  for (int32_t i = 0; i < n; ++i) free_list(&kl[i]);
+  free(kl);
+  return SADREF_OK;
+}
+
 int sadref_partition(int32_t n, const uint64_t* key, int32_t p,
                      uint64_t* pivot_key, int32_t* pivot_id,
                      int32_t* bucket, int32_t* bucket_off, int32_t* members) {

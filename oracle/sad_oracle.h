@@ -48,6 +48,12 @@ uint32_t sadref_fhat(const uint8_t* xi, int64_t Li, const uint8_t* xj, int64_t L
 /* Step 1 of the algorithm (local rank, samples, globalised rank; Sections 2
  * and 2.3.1).  key[i] = sum over samples s of F(i,s).  sample_ids receives the
  * p * k_s sample ids (chunk-major). */
+/* Rank of rows against a sample list (all n when samples is NULL: the
+ * centralised rank); rows NULL: all rows. */
+int sadref_rank_against(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                        int32_t kmer_k, const int32_t* samples, int32_t n_samples,
+                        const int32_t* rows, int32_t nrows, uint64_t* key);
+
 int sadref_kmer_rank(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
                      int32_t kmer_k, int32_t p, int32_t s_max,
                      uint64_t* key, int32_t* sample_ids, int32_t sample_cap,

@@ -26,7 +26,7 @@ SAD_PLAIN = 0
 SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
-EXPORTS = ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine", "sad_tune",
+EXPORTS = ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets", "sad_refine", "sad_tune",
            "sad_quality",
            "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs", "sad_profile_graphs",
            "sad_last_error",
@@ -72,10 +72,12 @@ def lib():
         P = ctypes.c_void_p
         I32 = ctypes.c_int32
         L.sad_kmer_rank.argtypes = [P, P, P, P, I32, P, P]
+        L.sad_rank_against.argtypes = [P, I32, P, I32, P, P]
         L.sad_partition.argtypes = [P, P, P, P, P, P, P, P, P]
         L.sad_align_buckets.argtypes = [P, P, P, P, P, P]
         L.sad_refine.argtypes = [P, P, P, P, P, P, I32, P, P, P, P]
-        for f in ("sad_kmer_rank", "sad_partition", "sad_align_buckets", "sad_refine"):
+        for f in ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets",
+                  "sad_refine"):
             getattr(L, f).restype = I32
         L.sad_profile_enable.argtypes = [I32]
         L.sad_profile_enable.restype = I32
@@ -172,6 +174,26 @@ def sad_kmer_rank(seqs: DeviceSeqs, prm: Params, out: dict | None = None):
                                ctypes.byref(ns), _stream())
     _check(code, "sad_kmer_rank")
     return key[:seqs.n], sid[:ns.value]
+
+
+def sad_rank_against(seqs: DeviceSeqs, kmer_k: int, samples: torch.Tensor | None = None):
+    """K_i against the listed samples (int32 device tensor of ids) or, with
+    samples=None, against all n sequences (the centralised rank).  Returns
+    key[n] (uint64 as an int64 tensor)."""
+    dev = seqs.codes.device
+    key = torch.empty(max(seqs.n, 1), dtype=torch.int64, device=dev)
+    s = seqs.c_struct()
+    ns = 0
+    if samples is not None:
+        ns = samples.numel()
+        # an empty list still needs a non-null pointer (null means all n)
+        samples = samples.to(device=dev, dtype=torch.int32).contiguous() if ns else \
+            torch.zeros(1, dtype=torch.int32, device=dev)
+    code = lib().sad_rank_against(ctypes.byref(s), int(kmer_k),
+                                  None if samples is None else _ptr(samples), ns, _ptr(key),
+                                  _stream())
+    _check(code, "sad_rank_against")
+    return key[:seqs.n]
 
 
 def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params, bufs: dict | None = None):

@@ -1030,7 +1030,38 @@ extern "C" int32_t sad_kmer_rank(const sad_seqs* seqs, const sad_params* prm, ui
   launch_rowsum_chunk(kl, n, p, k, kspace, kloc, stream);
   launch_chunk_sort(kloc, n, p, sorted, stream);
   launch_pick_samples(sorted, n, p, ks, d_sample_ids, stream);
-  launch_rowsum_list(kl, n, d_sample_ids, S, k, kspace, d_key, stream);
+  launch_rowsum_list(kl, n, d_sample_ids, S, k, kspace, d_key, c->st, stream);
+  return finish(c, stream);
+}
+
+extern "C" int32_t sad_rank_against(const sad_seqs* seqs, int32_t kmer_k,
+                                    const int32_t* d_sample_ids, int32_t n_samples,
+                                    uint64_t* d_key, hipStream_t stream) {
+  int32_t r = check_seqs(seqs, kmer_k);
+  if (r) return r;
+  const int n = seqs->n, A = seqs->alphabet, k = kmer_k;
+  if (!d_sample_ids) n_samples = n;
+  if (n_samples < 0) return fail(SAD_E_INVAL, "negative sample count");
+  if (n > 0 && !d_key) return fail(SAD_E_INVAL, "null output");
+  if (n == 0) return SAD_OK;
+  DeviceCtx* c = nullptr;
+  r = get_ctx(&c);
+  if (r) return r;
+  r = validate_on_device(c, seqs, k, stream);
+  if (r) return r;
+  const int kspace = (int)kmer_space(A, k);
+  uint32_t* entries;
+  int32_t* nu;
+  Carver cv;
+  cv.add(entries, (size_t)std::max<int64_t>(seqs->total_len, 1));
+  cv.add(nu, std::max(n, 1));
+  r = cv.carve(c);
+  if (r) return r;
+  r = reset_status(c, stream);
+  if (r) return r;
+  launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st, stream);
+  KmerLists kl{entries, seqs->d_offsets, nu, seqs->d_offsets};
+  launch_rowsum_list(kl, n, d_sample_ids, n_samples, k, kspace, d_key, c->st, stream);
   return finish(c, stream);
 }
 

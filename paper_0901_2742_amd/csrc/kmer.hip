@@ -211,11 +211,13 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_chunk_kernel(KmerLists kl
   if (threadIdx.x == 0) out[r] = s;
 }
 
-// out(r) = sum over the listed columns of F(r, col)
-__global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl,
+// out(r) = sum over the listed columns of F(r, col); cols == nullptr lists
+// all n sequences.  A listed id outside [0, n) is reported and skipped.
+__global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl, int n,
                                                                     const int32_t* __restrict__ cols,
                                                                     int ncols, int k, int kspace,
-                                                                    uint64_t* __restrict__ out) {
+                                                                    uint64_t* __restrict__ out,
+                                                                    DevStatus* st) {
   extern __shared__ uint16_t hist[];
   __shared__ uint64_t red[kPairThreads / 64];
   const int r = blockIdx.x;
@@ -227,7 +229,11 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl,
   const int64_t Lr = seq_len(kl, r);
   uint64_t part = 0;
   for (int q = wave; q < ncols; q += nw) {
-    int j = cols[q];
+    const int j = cols ? cols[q] : q;
+    if (j < 0 || j >= n) {
+      if (r == 0 && (threadIdx.x & 63) == 0) raise_error(st, SAD_E_INVAL, q, W_RANK);
+      continue;
+    }
     int64_t cc = wave_common(hist, kl, j);
     part += fhat_of(cc, Lr, seq_len(kl, j), k);
   }
@@ -287,11 +293,11 @@ void launch_rowsum_chunk(const KmerLists& kl, int n, int p, int k, int kspace, u
 }
 
 void launch_rowsum_list(const KmerLists& kl, int n, const int32_t* cols, int ncols, int k,
-                        int kspace, uint64_t* out, hipStream_t stream) {
+                        int kspace, uint64_t* out, DevStatus* st, hipStream_t stream) {
   if (n <= 0) return;
   allow_lds((const void*)rowsum_list_kernel, hist_bytes(kspace));
-  rowsum_list_kernel<<<n, kPairThreads, hist_bytes(kspace), stream>>>(kl, cols, ncols, k, kspace,
-                                                                      out);
+  rowsum_list_kernel<<<n, kPairThreads, hist_bytes(kspace), stream>>>(kl, n, cols, ncols, k,
+                                                                      kspace, out, st);
 }
 
 void launch_fmatrix_groups(const KmerLists& kl, const int32_t* group_off, const int32_t* ids,

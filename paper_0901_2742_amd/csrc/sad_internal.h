@@ -96,7 +96,7 @@ void launch_kmer_lists(const uint8_t* codes, const int64_t* offsets, int n, int 
 void launch_rowsum_chunk(const KmerLists& kl, int n, int p, int k, int kspace,
                          uint64_t* out, hipStream_t stream);
 void launch_rowsum_list(const KmerLists& kl, int n, const int32_t* cols, int ncols, int k,
-                        int kspace, uint64_t* out, hipStream_t stream);
+                        int kspace, uint64_t* out, DevStatus* st, hipStream_t stream);
 void launch_fmatrix_groups(const KmerLists& kl, const int32_t* group_off, const int32_t* ids,
                            int ngroups, int64_t total_rows, const int64_t* fm_off, int k,
                            int kspace, uint32_t* F, hipStream_t stream);
