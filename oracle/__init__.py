@@ -85,10 +85,12 @@ def _declare(L):
     L.sadref_consensus.argtypes = [P, I32, I32, I32, P, P]
     L.sadref_refine.argtypes = [I32, I32, P, P, I32, P, P, P, P, I32, P, I32, I32,
                                 P, I32, P, P, P, P, P, P, P, P]
+    L.sadref_refine_template.argtypes = [I32, I32, P, P, I32, P, P, P, P, I32, P, I32, I32, I32,
+                                         P, I32, P, P, P, P, P, P, P, P]
     for f in ("sadref_kmer_list", "sadref_kmer_rank", "sadref_rank_against", "sadref_partition",
               "sadref_upgma",
               "sadref_profile_align", "sadref_align_buckets", "sadref_consensus",
-              "sadref_refine"):
+              "sadref_refine", "sadref_refine_template"):
         getattr(L, f).restype = ctypes.c_int
 
 
@@ -255,8 +257,14 @@ def align_buckets(codes, offsets, A: int, bucket_off, members, k: int, S, go: in
     return out
 
 
+TEMPLATES = {"ga": 0, "ga_msa": 1}
+
+
 def refine(codes, offsets, A: int, bucket_off, members, colmap_b, width_b, k: int, S,
-           go: int, ge: int):
+           go: int, ge: int, template: str = "ga"):
+    """Steps 12-15: ancestors, GA, each bucket against the template, glue.
+    template "ga": GA as a one-row profile; "ga_msa": the ancestors' alignment
+    as a profile of q rows (the paper's future-work template)."""
     codes, offsets = _c(codes, np.uint8), _c(offsets, np.int64)
     boff, mem, S = _c(bucket_off, np.int32), _c(members, np.int32), _c(S, np.int8)
     cb, wb = _c(colmap_b, np.int32), _c(width_b, np.int32)
@@ -273,9 +281,10 @@ def refine(codes, offsets, A: int, bucket_off, members, colmap_b, width_b, k: in
     mc = np.zeros(2 * p, np.int64)
     nm = np.zeros(1, np.int32)
     cells = np.zeros(1, np.int64)
-    st = lib().sadref_refine(n, A, _p(codes), _p(offsets), p, _p(boff), _p(mem), _p(cb), _p(wb),
-                             k, _p(S), go, ge, _p(ga), ga_cap, _p(ga_len), _p(cg), _p(wg),
-                             _p(ms), _p(ml), _p(mc), _p(nm), _p(cells))
+    st = lib().sadref_refine_template(n, A, _p(codes), _p(offsets), p, _p(boff), _p(mem), _p(cb),
+                                      _p(wb), k, _p(S), go, ge, TEMPLATES[template], _p(ga),
+                                      ga_cap, _p(ga_len), _p(cg), _p(wg), _p(ms), _p(ml), _p(mc),
+                                      _p(nm), _p(cells))
     _check(st, "refine")
     m = int(nm[0])
     return dict(ga=ga[:int(ga_len[0])].copy(), colmap=cg[:len(codes)].copy(), width=int(wg[0]),
@@ -284,14 +293,14 @@ def refine(codes, offsets, A: int, bucket_off, members, colmap_b, width_b, k: in
 
 
 def run_pipeline(codes, offsets, A: int, k: int, p: int, S, go: int, ge: int,
-                 s_max: int = 1024, want_ops: bool = False):
+                 s_max: int = 1024, want_ops: bool = False, template: str = "ga"):
     """All four steps in order, as the HIP library's calls chain them."""
     key, samples = kmer_rank(codes, offsets, A, k, p, s_max)
     part = partition(key, p)
     al = align_buckets(codes, offsets, A, part["bucket_off"], part["members"], k, S, go, ge,
                        want_ops=want_ops)
     rf = refine(codes, offsets, A, part["bucket_off"], part["members"], al["colmap"],
-                al["width"], k, S, go, ge)
+                al["width"], k, S, go, ge, template=template)
     return dict(key=key, samples=samples, part=part, align=al, refine=rf)
 
 

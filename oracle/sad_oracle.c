@@ -762,17 +762,23 @@ int sadref_consensus(const uint16_t* counts, int32_t W, int32_t n, int32_t A,
   return SADREF_OK;
 }
 
-int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
-                  int32_t p, const int32_t* bucket_off, const int32_t* members,
-                  const int32_t* colmap_b, const int32_t* width_b,
-                  int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge,
-                  uint8_t* ga, int32_t ga_cap, int32_t* ga_len,
-                  int32_t* colmap_g, int32_t* width_g,
-                  int64_t* merge_score_g, int32_t* merge_list_g, int64_t* merge_cells_g,
-                  int32_t* n_merges_g, int64_t* cells) {
+/* Refinement with a choice of template (Section 2.3.3, steps 12-15):
+ * tmpl 0 aligns every bucket with GA as a one-row profile (the consensus of
+ * the ancestors' alignment); tmpl 1 aligns every bucket with the ancestors'
+ * alignment itself, a profile of q rows (the richer template the paper leaves
+ * to future work).  With one non-empty bucket both are the bucket's own
+ * ancestor as one row. */
+int sadref_refine_template(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                           int32_t p, const int32_t* bucket_off, const int32_t* members,
+                           const int32_t* colmap_b, const int32_t* width_b,
+                           int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge, int32_t tmpl,
+                           uint8_t* ga, int32_t ga_cap, int32_t* ga_len,
+                           int32_t* colmap_g, int32_t* width_g,
+                           int64_t* merge_score_g, int32_t* merge_list_g, int64_t* merge_cells_g,
+                           int32_t* n_merges_g, int64_t* cells) {
   int st = validate_seqs(n, A, codes, offsets, kmer_k);
   if (st) return st;
-  if (p < 1 || go < ge || ge < 0) return SADREF_E_INVAL;
+  if (p < 1 || go < ge || ge < 0 || tmpl < 0 || tmpl > 1) return SADREF_E_INVAL;
   if (bucket_off[0] != 0 || bucket_off[p] != n) return SADREF_E_INVAL;
 
   /* bucket alignments as column-count profiles */
@@ -815,6 +821,9 @@ int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* off
   *cells = 0;
   uint8_t* GA = NULL;
   int32_t GL = 0;
+  /* the template profile: TW columns of counts over tn rows */
+  uint16_t* tprof = NULL;
+  int32_t TW = 0, tn = 1;
   if (st == SADREF_OK) {
     if (q == 1) {
       GL = (int32_t)anc_len[0];
@@ -828,6 +837,12 @@ int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* off
         node_t* root = &nodes[2 * q - 2];
         GA = (uint8_t*)malloc((size_t)(root->W > 0 ? root->W : 1));
         sadref_consensus(root->cnt, root->W, root->n, A, GA, &GL);
+        if (tmpl == 1) {
+          TW = root->W;
+          tn = root->n;
+          tprof = (uint16_t*)malloc(sizeof(uint16_t) * (size_t)(TW > 0 ? TW : 1) * (size_t)A);
+          memcpy(tprof, root->cnt, sizeof(uint16_t) * (size_t)TW * (size_t)A);
+        }
         nm = q - 1;
         for (int32_t t = 0; t < nm; ++t) *cells += merge_cells_g[t];
       }
@@ -845,32 +860,37 @@ int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* off
    * bucket's own columns stay together (only all-gap columns are inserted) */
   uint8_t** bops = (uint8_t**)calloc((size_t)(q > 0 ? q : 1), sizeof(uint8_t*));
   int32_t* bnops = (int32_t*)calloc((size_t)(q > 0 ? q : 1), sizeof(int32_t));
-  uint16_t* gap_prof = NULL;
+  if (st == SADREF_OK && tprof == NULL) {
+    /* GA as a one-row profile */
+    TW = GL;
+    tn = 1;
+    tprof = (uint16_t*)calloc((size_t)(GL > 0 ? GL : 1) * (size_t)A, sizeof(uint16_t));
+    for (int32_t c = 0; c < GL; ++c) tprof[(size_t)c * A + GA[c]] = 1;
+  }
   if (st == SADREF_OK) {
-    gap_prof = (uint16_t*)calloc((size_t)(GL > 0 ? GL : 1) * (size_t)A, sizeof(uint16_t));
-    for (int32_t c = 0; c < GL; ++c) gap_prof[(size_t)c * A + GA[c]] = 1;
     for (int32_t u = 0; u < q && st == SADREF_OK; ++u) {
       int32_t b = nonempty[u];
       int32_t W = width_b[b], nb = bucket_off[b + 1] - bucket_off[b];
-      bops[u] = (uint8_t*)malloc((size_t)(W + GL > 0 ? W + GL : 1));
+      bops[u] = (uint8_t*)malloc((size_t)(W + TW > 0 ? W + TW : 1));
       int64_t sc = 0;
-      st = sadref_profile_align(prof[b], W, nb, gap_prof, GL, 1, A, S, go, ge, bops[u],
+      st = sadref_profile_align(prof[b], W, nb, tprof, TW, tn, A, S, go, ge, bops[u],
                                 &bnops[u], &sc);
       merge_score_g[nm + u] = sc;
-      merge_cells_g[nm + u] = (int64_t)W * GL;
+      merge_cells_g[nm + u] = (int64_t)W * TW;
       merge_list_g[2 * (nm + u)] = b;
       merge_list_g[2 * (nm + u) + 1] = -1;
-      *cells += (int64_t)W * GL;
+      *cells += (int64_t)W * TW;
     }
   }
 
-  /* glue: before GA position j (and after the last one) an insert slot holds
-   * the bucket columns aligned to gaps there -- bucket by bucket, each in its
-   * own order -- then comes the shared column j; all-gap columns are dropped */
+  /* glue: before template column j (and after the last one) an insert slot
+   * holds the bucket columns aligned to gaps there -- bucket by bucket, each in
+   * its own order -- then comes the shared column j; all-gap columns are
+   * dropped */
   if (st == SADREF_OK) {
-    int64_t slots = (int64_t)GL + 1;
+    int64_t slots = (int64_t)TW + 1;
     int64_t* ins = (int64_t*)calloc((size_t)(q * slots > 0 ? q * slots : 1), sizeof(int64_t));
-    char* shared_used = (char*)calloc((size_t)(GL > 0 ? GL : 1), 1);
+    char* shared_used = (char*)calloc((size_t)(TW > 0 ? TW : 1), 1);
     for (int32_t u = 0; u < q; ++u) {
       int32_t j = 0;
       for (int32_t t = 0; t < bnops[u]; ++t) {
@@ -883,14 +903,14 @@ int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* off
     }
     /* start index of each (slot, bucket) block and each kept shared column */
     int64_t* blk = (int64_t*)malloc(sizeof(int64_t) * (size_t)(q * slots > 0 ? q * slots : 1));
-    int64_t* shared_at = (int64_t*)malloc(sizeof(int64_t) * (size_t)(GL > 0 ? GL : 1));
+    int64_t* shared_at = (int64_t*)malloc(sizeof(int64_t) * (size_t)(TW > 0 ? TW : 1));
     int64_t pos = 0;
     for (int64_t j = 0; j < slots; ++j) {
       for (int32_t u = 0; u < q; ++u) {
         blk[(int64_t)u * slots + j] = pos;
         pos += ins[(int64_t)u * slots + j];
       }
-      if (j < GL) {
+      if (j < TW) {
         shared_at[j] = shared_used[j] ? pos : -1;
         if (shared_used[j]) ++pos;
       }
@@ -937,8 +957,21 @@ int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* off
   free(anc_len);
   free(bops);
   free(bnops);
-  free(gap_prof);
+  free(tprof);
   free(GA);
   free(nonempty);
   return st;
+}
+
+int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                  int32_t p, const int32_t* bucket_off, const int32_t* members,
+                  const int32_t* colmap_b, const int32_t* width_b,
+                  int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge,
+                  uint8_t* ga, int32_t ga_cap, int32_t* ga_len,
+                  int32_t* colmap_g, int32_t* width_g,
+                  int64_t* merge_score_g, int32_t* merge_list_g, int64_t* merge_cells_g,
+                  int32_t* n_merges_g, int64_t* cells) {
+  return sadref_refine_template(n, A, codes, offsets, p, bucket_off, members, colmap_b, width_b,
+                                kmer_k, S, go, ge, 0, ga, ga_cap, ga_len, colmap_g, width_g,
+                                merge_score_g, merge_list_g, merge_cells_g, n_merges_g, cells);
 }

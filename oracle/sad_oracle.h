@@ -103,6 +103,16 @@ int sadref_consensus(const uint16_t* counts, int32_t W, int32_t n, int32_t A,
  * residue in the glued alignment, *width_g its width.  merge_score_g and
  * merge_cells_g (capacity 2p): the ancestor alignment's q-1 merges followed by
  * the q refinement alignments (q = non-empty buckets); merge_list_g[2p]. */
+/* Refinement against a chosen template: tmpl 0 = GA as one row (what
+ * sadref_refine does), 1 = the ancestors' alignment as a profile of q rows. */
+int sadref_refine_template(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                           int32_t p, const int32_t* bucket_off, const int32_t* members,
+                           const int32_t* colmap_b, const int32_t* width_b,
+                           int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge, int32_t tmpl,
+                           uint8_t* ga, int32_t ga_cap, int32_t* ga_len,
+                           int32_t* colmap_g, int32_t* width_g,
+                           int64_t* merge_score_g, int32_t* merge_list_g, int64_t* merge_cells_g,
+                           int32_t* n_merges_g, int64_t* cells);
 int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
                   int32_t p, const int32_t* bucket_off, const int32_t* members,
                   const int32_t* colmap_b, const int32_t* width_b,
