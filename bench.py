@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--sweep-p", default="", metavar="P1,P2,...",
                     help="instead of the benchmark line, one line per bucket count p: step time "
                          "and alignment quality (Q) of the pipeline on the workload")
+    ap.add_argument("--template", default="ga", choices=("ga", "ga_msa"),
+                    help="refinement template of --sweep-p runs (the benchmark line times "
+                         "\"ga\" and reports \"ga_msa\" beside it)")
     ap.add_argument("--rank-study", default="", metavar="N1,N2,...",
                     help="instead of the benchmark line, one line per set size N: the "
                          "centralised rank (all N as the sample) against the globalised rank "
@@ -88,10 +91,10 @@ def measured_traffic(workload: str):
         return None
 
 
-def timed_steps(run, seqs, prm, steps, warmup, B, torch):
+def timed_steps(run, seqs, prm, steps, warmup, B, torch, template="ga"):
     bufs = {}  # output buffers kept across passes, as a serving loop would
     for _ in range(warmup):
-        run(seqs, prm, bufs)
+        run(seqs, prm, bufs, template=template)
     torch.cuda.synchronize()
     B.sad_profile_read(reset=True)
     B.sad_profile_enable(True)
@@ -101,7 +104,7 @@ def timed_steps(run, seqs, prm, steps, warmup, B, torch):
     t0.record(stream)
     res = None
     for _ in range(steps):
-        res = run(seqs, prm, bufs)
+        res = run(seqs, prm, bufs, template=template)
     t1.record(stream)
     torch.cuda.synchronize()
     B.sad_profile_enable(False)
@@ -190,11 +193,12 @@ def main():
             prm_s = B.Params(w.kmer_k, p, S, w.gap_open, w.gap_extend, w.s_max,
                              B.SAD_BATCHED_MFMA)
             res_s, ms_s, eng_s, nl = timed_steps(pipeline.run_device, seqs, prm_s, args.steps,
-                                                 args.warmup, B, torch)
+                                                 args.warmup, B, torch, args.template)
             h = pipeline.to_host(res_s, s.n, p, seqs.total_len)
             cl = h["align"]["cells"] + h["refine"]["cells"]
             sizes = np.diff(h["part"]["bucket_off"])
-            line = {"sweep": "buckets", "workload": w.name, "p": p, "ms_per_step": round(ms_s, 3),
+            line = {"sweep": "buckets", "workload": w.name, "p": p, "template": args.template,
+                    "ms_per_step": round(ms_s, 3),
                     "value": round(cl / (ms_s / 1e3) / 1e9, 3), "unit": "GCUPS",
                     "dp_cells_per_step": cl, "largest_bucket": int(sizes.max()),
                     "engine_ms_per_step": round(eng_s / args.steps, 3),
@@ -250,6 +254,15 @@ def main():
                      "traffic": measured_traffic(w.name),
                      "ops_per_cell": OPS_PER_CELL},
     }
+    # the same pipeline with the ancestors' alignment as the refinement template
+    res_m, ms_m, _, _ = timed_steps(pipeline.run_device, seqs, prm, args.steps, args.warmup, B,
+                                    torch, "ga_msa")
+    host_m = pipeline.to_host(res_m, s.n, w.p, seqs.total_len)
+    cells_m = host_m["align"]["cells"] + host_m["refine"]["cells"]
+    out["template_ga_msa"] = {"ms_per_step": round(ms_m, 3),
+                              "value": round(cells_m / (ms_m / 1e3) / 1e9, 3), "unit": "GCUPS",
+                              "dp_cells_per_step": cells_m,
+                              "quality": quality(host_m["refine"]["colmap"])}
     if not args.no_plain:
         prm_p = B.Params(w.kmer_k, w.p, S, w.gap_open, w.gap_extend, w.s_max, B.SAD_PLAIN)
         tuned_p = B.sad_tune(seqs, part0["bucket_off"], part0["members"], prm_p)

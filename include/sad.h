@@ -52,6 +52,10 @@ extern "C" {
 #define SAD_PLAIN 0u            /* column scores on the vector ALUs */
 #define SAD_BATCHED_MFMA 1u     /* column scores on int8 matrix cores (same results) */
 
+/* refinement templates (sad_refine_template) */
+#define SAD_TEMPLATE_GA 0       /* GA, the consensus of the ancestors' alignment, as one row */
+#define SAD_TEMPLATE_GA_MSA 1   /* the ancestors' alignment itself, q rows */
+
 /* N sequences: residue codes of sequence i are d_codes[d_offsets[i] ..
  * d_offsets[i+1]).  total_len must equal d_offsets[n]; max_len must be >= every
  * length (both are checked on the device). */
@@ -178,6 +182,24 @@ int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off, const int3
                    const sad_msa* buckets, const sad_params* prm, uint8_t* d_ga,
                    int32_t ga_cap, int32_t* ga_len, sad_msa* global_out, int32_t* n_steps,
                    hipStream_t stream);
+
+/*
+ * Stage 4 with a choice of template.  SAD_TEMPLATE_GA is sad_refine.
+ * SAD_TEMPLATE_GA_MSA aligns each bucket alignment against the ancestors'
+ * alignment as a profile of q rows (the richer template that the paper's
+ * future-work section asks for; Section 2.3.3 speaks of the global ancestor
+ * "profile"): column scores sum over its q rows and gap costs scale with
+ * G = n_b q; the glue runs over its columns instead of GA's.  GA (the
+ * consensus) is still returned in d_ga.  With q = 1 both templates are the
+ * bucket's own ancestor as one row.  Merge cells of the refinement steps are
+ * W_b times the template's width.  SAD_E_INVAL for an unknown template; the
+ * value bound of sad_align_buckets applies to every refinement alignment.
+ */
+int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                            const int32_t* d_members, const sad_msa* buckets,
+                            const sad_params* prm, int32_t tmpl, uint8_t* d_ga, int32_t ga_cap,
+                            int32_t* ga_len, sad_msa* global_out, int32_t* n_steps,
+                            hipStream_t stream);
 
 /* Autotuner for sad_align_buckets (batching of the bucket merges, Section
  * 2.3.3 step 11).  Runs the call on the given buckets under each candidate

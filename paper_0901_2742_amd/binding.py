@@ -26,7 +26,7 @@ SAD_PLAIN = 0
 SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
-EXPORTS = ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets", "sad_refine", "sad_tune",
+EXPORTS = ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets", "sad_refine", "sad_refine_template", "sad_tune",
            "sad_quality",
            "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs", "sad_profile_graphs",
            "sad_last_error",
@@ -76,8 +76,9 @@ def lib():
         L.sad_partition.argtypes = [P, P, P, P, P, P, P, P, P]
         L.sad_align_buckets.argtypes = [P, P, P, P, P, P]
         L.sad_refine.argtypes = [P, P, P, P, P, P, I32, P, P, P, P]
+        L.sad_refine_template.argtypes = [P, P, P, P, P, I32, P, I32, P, P, P, P]
         for f in ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets",
-                  "sad_refine"):
+                  "sad_refine", "sad_refine_template"):
             getattr(L, f).restype = I32
         L.sad_profile_enable.argtypes = [I32]
         L.sad_profile_enable.restype = I32
@@ -247,10 +248,17 @@ def sad_align_buckets(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch
     return out
 
 
+SAD_TEMPLATE_GA = 0
+SAD_TEMPLATE_GA_MSA = 1
+TEMPLATES = {"ga": SAD_TEMPLATE_GA, "ga_msa": SAD_TEMPLATE_GA_MSA}
+
+
 def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, buckets: dict,
-               prm: Params, out: dict | None = None, ga_cap: int | None = None):
+               prm: Params, out: dict | None = None, ga_cap: int | None = None,
+               template: str = "ga"):
     """Stage 4: global ancestor, refinement and glue.  Returns a dict of device
-    tensors plus ``ga_len`` and ``n_steps``."""
+    tensors plus ``ga_len`` and ``n_steps``.  template "ga" (sad_refine: GA as
+    one row) or "ga_msa" (sad_refine_template: the ancestors' alignment)."""
     dev = seqs.codes.device
     if out is None:
         out = _msa_tensors(seqs.total_len, 1, 2 * prm.p, dev)
@@ -264,10 +272,17 @@ def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor
     nst = ctypes.c_int32(0)
     s, pp = seqs.c_struct(), prm.c_struct()
     mb, mg = _msa_struct(buckets), _msa_struct(out)
-    code = lib().sad_refine(ctypes.byref(s), _ptr(bucket_off), _ptr(members), ctypes.byref(mb),
-                            ctypes.byref(pp), _ptr(ga), ga_cap, ctypes.byref(gl), ctypes.byref(mg),
-                            ctypes.byref(nst), _stream())
-    _check(code, "sad_refine")
+    if template == "ga":
+        code = lib().sad_refine(ctypes.byref(s), _ptr(bucket_off), _ptr(members),
+                                ctypes.byref(mb), ctypes.byref(pp), _ptr(ga), ga_cap,
+                                ctypes.byref(gl), ctypes.byref(mg), ctypes.byref(nst), _stream())
+        _check(code, "sad_refine")
+    else:
+        code = lib().sad_refine_template(ctypes.byref(s), _ptr(bucket_off), _ptr(members),
+                                         ctypes.byref(mb), ctypes.byref(pp), TEMPLATES[template],
+                                         _ptr(ga), ga_cap, ctypes.byref(gl), ctypes.byref(mg),
+                                         ctypes.byref(nst), _stream())
+        _check(code, "sad_refine_template")
     out["ga_len"] = gl.value
     out["n_steps"] = nst.value
     return out

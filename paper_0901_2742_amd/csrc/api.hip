@@ -1304,12 +1304,14 @@ __global__ void init_refine_ctl_kernel(unsigned long long* tops, unsigned long l
 
 }  // namespace sad
 
-extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
-                              const int32_t* d_members, const sad_msa* buckets,
-                              const sad_params* prm, uint8_t* d_ga, int32_t ga_cap,
-                              int32_t* ga_len, sad_msa* gout, int32_t* n_steps,
-                              hipStream_t stream) {
+extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                                       const int32_t* d_members, const sad_msa* buckets,
+                                       const sad_params* prm, int32_t tmpl, uint8_t* d_ga,
+                                       int32_t ga_cap, int32_t* ga_len, sad_msa* gout,
+                                       int32_t* n_steps, hipStream_t stream) {
   if (!prm || !buckets || !gout || !ga_len || !n_steps) return fail(SAD_E_INVAL, "null argument");
+  if (tmpl != SAD_TEMPLATE_GA && tmpl != SAD_TEMPLATE_GA_MSA)
+    return fail(SAD_E_INVAL, "unknown refinement template");
   int32_t r = check_seqs(seqs, prm->kmer_k);
   if (r) return r;
   r = check_params(prm, seqs->alphabet, true);
@@ -1359,7 +1361,8 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
       *ga_merges, *ga_list, *ga_len_d, *ins, *used, *slot_total, *slot_start, *shared_at, *to_g;
   int64_t *d_wo, *anc_off, *stage_off, *ga_score, *ga_cells, *ga_cells_tot, *rf_ops_off, *ga_off0;
   uint32_t* cnt32;
-  uint16_t* prof16;
+  uint16_t *prof16, *tmpl16;
+  int32_t* tl_d;
   uint8_t *anc_stage, *anc_codes, *ga_stage, *rf_ops;
   int32_t* cnode_W;
   int32_t* cnode_n;
@@ -1392,6 +1395,10 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   kv.add(ga_len_d, 1);
   kv.add(ga_off0, 2);
   kv.add(to_g, (size_t)Wt1);
+  // the ancestors' alignment as a template (at most as wide as all ancestors)
+  const bool msa_tmpl = tmpl == SAD_TEMPLATE_GA_MSA && q > 1;
+  kv.add(tmpl16, msa_tmpl ? (size_t)Wt1 * A : 1);
+  kv.add(tl_d, 1);
   r = kv.carve_keep(c);
   if (r) return r;
   r = h2d(uidx, d_uidx, stream);
@@ -1479,6 +1486,9 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
     if (r) return r;
     r = reset_status(c, stream);
     if (r) return r;
+    if (msa_tmpl)
+      launch_copy_node_profile(e.node_W, e.node_prof, e.prof_pool, 2 * q - 2, A, tmpl16,
+                               Wt1 * A, tl_d, c->st, stream);
     launch_consensus(ga_list, 1, e.node_W, e.node_n, e.node_prof, e.prof_pool, A, ga_stage,
                      ga_off0, ga_len_d, stream);
     r = finish(c, stream);
@@ -1492,29 +1502,40 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   if (GL > ga_cap) return fail(SAD_E_CAPACITY, "GA capacity too small");
   if (GL > kMaxWidth) return fail(SAD_E_CAPACITY, "global ancestor wider than the library limit");
   if (GL > 0) HIPCHK(hipMemcpyAsync(d_ga, ga_stage, (size_t)GL, hipMemcpyDeviceToDevice, stream));
+  // the template: GA as one row, or the ancestors' alignment (TL columns, q rows)
+  int TL = GL, tn = 1;
+  if (msa_tmpl) {
+    std::vector<int32_t> tl;
+    r = d2h(c, tl_d, 1, tl, stream);
+    if (r) return r;
+    TL = tl[0];
+    tn = q;
+    if (TL > kMaxWidth) return fail(SAD_E_CAPACITY, "template wider than the library limit");
+  }
   {
-    std::vector<int32_t> gl{GL};
+    std::vector<int32_t> gl{GL}, tl{TL};
     r = h2d(gl, ga_len_d, stream);
+    if (!r) r = h2d(tl, tl_d, stream);
     if (r) return r;
   }
 
-  // ---- refinement: every bucket alignment against GA (one-row profile)
+  // ---- refinement: every bucket alignment against the template
   std::vector<int64_t> ops_off(q + 1);
   int64_t ops_tot = 0;
   for (int u = 0; u < q; ++u) {
     ops_off[u] = ops_tot;
-    ops_tot += width_u[u] + GL;
+    ops_tot += width_u[u] + TL;
   }
   ops_off[q] = ops_tot;
   {
     Carver kv2 = kv;
     kv2.add(rf_ops, (size_t)std::max<int64_t>(ops_tot, 1));
     kv2.add(rf_ops_off, q + 1);
-    kv2.add(ins, (size_t)q * (GL + 1));
-    kv2.add(used, std::max(GL, 1));
-    kv2.add(slot_total, GL + 1);
-    kv2.add(slot_start, GL + 1);
-    kv2.add(shared_at, std::max(GL, 1));
+    kv2.add(ins, (size_t)q * (TL + 1));
+    kv2.add(used, std::max(TL, 1));
+    kv2.add(slot_total, TL + 1);
+    kv2.add(slot_start, TL + 1);
+    kv2.add(shared_at, std::max(TL, 1));
     // same prefix as kv: earlier buffers keep their addresses and contents
     if (kv2.total() > c->keep_cap) {
       // grow while preserving: copy the prefix out through the work arena
@@ -1538,10 +1559,10 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   }
   r = h2d(ops_off, rf_ops_off, stream);
   if (r) return r;
-  const int rwcap = std::max(64, std::max(maxW, GL));
-  const int64_t prof_fixed = (Wtot + GL) * A;
+  const int rwcap = std::max(64, std::max(maxW, TL));
+  const int64_t prof_fixed = (Wtot + TL) * A;
   const int64_t prof_cap = prof_fixed + (ops_tot + 1) * A;
-  const int64_t up_cap = Wtot + GL + ops_tot + 1;
+  const int64_t up_cap = Wtot + TL + ops_tot + 1;
   EngineBuffers e{};
   Carver cv;
   plan_engine(cv, e, 2 * q + 1, q, q, prof_cap, up_cap, rwcap, true);
@@ -1551,13 +1572,19 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   if (r) return r;
   HIPCHK(hipMemcpyAsync(e.prof_pool, prof16, (size_t)Wtot * A * sizeof(uint16_t),
                         hipMemcpyDeviceToDevice, stream));
-  launch_onehot_seq(ga_stage, ga_len_d, std::max(GL, 1), A, e.prof_pool + Wtot * A, stream);
+  if (msa_tmpl) {
+    if (TL > 0)
+      HIPCHK(hipMemcpyAsync(e.prof_pool + Wtot * A, tmpl16, (size_t)TL * A * sizeof(uint16_t),
+                            hipMemcpyDeviceToDevice, stream));
+  } else {
+    launch_onehot_seq(ga_stage, ga_len_d, std::max(GL, 1), A, e.prof_pool + Wtot * A, stream);
+  }
   launch_fill_i32(e.node_parent, -1, 2 * q + 1, stream);
   launch_fill_i32(e.queue_flag, 0, (int64_t)q * (1 + kMaxHelpers), stream);
   launch_fill_i32(e.job_link, 0, q, stream);
   init_refine_ctl_kernel<<<1, 1, 0, stream>>>(e.tops, (unsigned long long)prof_fixed,
-                                              (unsigned long long)(Wtot + GL), e.qctl);
-  launch_refine_nodes(q, d_wo, d_width_u, d_rows_u, Wtot * A, Wtot, ga_len_d, A, 0, e.node_W,
+                                              (unsigned long long)(Wtot + TL), e.qctl);
+  launch_refine_nodes(q, d_wo, d_width_u, d_rows_u, Wtot * A, Wtot, tl_d, tn, A, 0, e.node_W,
                       e.node_n, e.node_prof, e.node_up, stream);
   launch_refine_jobs(q, rf_ops_off, e.job_a, e.job_b, e.job_out, e.job_next, e.job_pending,
                      e.job_ops_off, e.queue, e.queue_flag, e.qctl + 1, e.node_parent, stream);
@@ -1578,9 +1605,9 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
   // ---- glue
   r = reset_status(c, stream);
   if (r) return r;
-  launch_fill_i32(ins, 0, (int64_t)q * (GL + 1), stream);
-  launch_fill_i32(used, 0, std::max(GL, 1), stream);
-  launch_glue(rf_ops, rf_ops_off, e.node_W + q + 1, q, GL, ins, used, slot_total, slot_start,
+  launch_fill_i32(ins, 0, (int64_t)q * (TL + 1), stream);
+  launch_fill_i32(used, 0, std::max(TL, 1), stream);
+  launch_glue(rf_ops, rf_ops_off, e.node_W + q + 1, q, TL, ins, used, slot_total, slot_start,
               shared_at, gout->d_width, d_wo, to_g, seqs->d_offsets, d_members, d_bucket_off, p, n,
               d_uidx, buckets->d_colmap, gout->d_colmap, stream);
   refine_results_kernel<<<1, 1, 0, stream>>>(q, ga_score, ga_cells, ga_merges, e.job_score,
@@ -1589,6 +1616,15 @@ extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                                              gout->d_cells);
   *n_steps = 2 * q - 1;
   return finish(c, stream);
+}
+
+extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                              const int32_t* d_members, const sad_msa* buckets,
+                              const sad_params* prm, uint8_t* d_ga, int32_t ga_cap,
+                              int32_t* ga_len, sad_msa* gout, int32_t* n_steps,
+                              hipStream_t stream) {
+  return sad_refine_template(seqs, d_bucket_off, d_members, buckets, prm, SAD_TEMPLATE_GA, d_ga,
+                             ga_cap, ga_len, gout, n_steps, stream);
 }
 
 extern "C" int32_t sad_profile_enable(int32_t on) {

@@ -295,8 +295,8 @@ void launch_refine_jobs(int q, const int64_t* ops_off, int32_t* job_a, int32_t* 
 __global__ void refine_nodes_kernel(int q, const int64_t* __restrict__ wo,
                                     const int32_t* __restrict__ width_u,
                                     const int32_t* __restrict__ rows_u, int64_t ga_prof,
-                                    int64_t ga_up, const int32_t* __restrict__ ga_len, int A,
-                                    int64_t up_base, int32_t* node_W, int32_t* node_n,
+                                    int64_t ga_up, const int32_t* __restrict__ ga_len, int ga_n,
+                                    int A, int64_t up_base, int32_t* node_W, int32_t* node_n,
                                     int64_t* node_prof, int64_t* node_up) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u > q) return;
@@ -307,19 +307,46 @@ __global__ void refine_nodes_kernel(int q, const int64_t* __restrict__ wo,
     node_up[u] = up_base + wo[u];
   } else {
     node_W[u] = *ga_len;
-    node_n[u] = 1;
+    node_n[u] = ga_n;
     node_prof[u] = ga_prof;
     node_up[u] = ga_up;
   }
 }
 
 void launch_refine_nodes(int q, const int64_t* wo, const int32_t* width_u, const int32_t* rows_u,
-                         int64_t ga_prof, int64_t ga_up, const int32_t* ga_len, int A,
+                         int64_t ga_prof, int64_t ga_up, const int32_t* ga_len, int ga_n, int A,
                          int64_t up_base, int32_t* node_W, int32_t* node_n, int64_t* node_prof,
                          int64_t* node_up, hipStream_t stream) {
   refine_nodes_kernel<<<(q + 1 + 63) / 64, 64, 0, stream>>>(q, wo, width_u, rows_u, ga_prof, ga_up,
-                                                            ga_len, A, up_base, node_W, node_n,
-                                                            node_prof, node_up);
+                                                            ga_len, ga_n, A, up_base, node_W,
+                                                            node_n, node_prof, node_up);
+}
+
+// The profile of node `root` (W x A counts) copied out of an engine's pool;
+// *w_out = W.  A profile wider than the destination is reported.
+__global__ void copy_node_profile_kernel(const int32_t* __restrict__ node_W,
+                                         const int64_t* __restrict__ node_prof,
+                                         const uint16_t* __restrict__ pool, int root, int A,
+                                         uint16_t* __restrict__ dst, int64_t cap,
+                                         int32_t* __restrict__ w_out, DevStatus* st) {
+  const int W = node_W[root];
+  const int64_t n = (int64_t)W * A;
+  if (n > cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) raise_error(st, SAD_E_CAPACITY, n, W_REFINE);
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *w_out = W;
+  const uint16_t* src = pool + node_prof[root];
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+void launch_copy_node_profile(const int32_t* node_W, const int64_t* node_prof,
+                              const uint16_t* pool, int root, int A, uint16_t* dst, int64_t cap,
+                              int32_t* w_out, DevStatus* st, hipStream_t stream) {
+  copy_node_profile_kernel<<<64, 256, 0, stream>>>(node_W, node_prof, pool, root, A, dst, cap,
+                                                   w_out, st);
 }
 
 __global__ void onehot_seq_kernel(const uint8_t* __restrict__ codes, const int32_t* __restrict__ len,

@@ -257,9 +257,12 @@ void launch_refine_jobs(int q, const int64_t* ops_off, int32_t* job_a, int32_t* 
                         int64_t* job_ops_off, int32_t* queue, int32_t* queue_flag,
                         int32_t* queue_tail, int32_t* node_parent, hipStream_t stream);
 void launch_refine_nodes(int q, const int64_t* wo, const int32_t* width_u, const int32_t* rows_u,
-                         int64_t ga_prof, int64_t ga_up, const int32_t* ga_len, int A,
+                         int64_t ga_prof, int64_t ga_up, const int32_t* ga_len, int ga_n, int A,
                          int64_t up_base, int32_t* node_W, int32_t* node_n, int64_t* node_prof,
                          int64_t* node_up, hipStream_t stream);
+void launch_copy_node_profile(const int32_t* node_W, const int64_t* node_prof,
+                              const uint16_t* pool, int root, int A, uint16_t* dst, int64_t cap,
+                              int32_t* w_out, DevStatus* st, hipStream_t stream);
 void launch_onehot_seq(const uint8_t* codes, const int32_t* len, int maxlen, int A,
                        uint16_t* prof, hipStream_t stream);
 

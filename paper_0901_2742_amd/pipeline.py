@@ -12,17 +12,20 @@ def to_device(codes, offsets, alphabet: int) -> B.DeviceSeqs:
     return B.DeviceSeqs.from_numpy(codes, offsets, alphabet)
 
 
-def run_device(seqs: B.DeviceSeqs, prm: B.Params, bufs: dict | None = None) -> dict:
+def run_device(seqs: B.DeviceSeqs, prm: B.Params, bufs: dict | None = None,
+               template: str = "ga") -> dict:
     """All four stages; results stay on the device.  `bufs` (a dict, filled on
     first use) keeps every output buffer across calls, so repeated passes over
-    the same input reuse them (and the library can replay its captured launch)."""
+    the same input reuse them (and the library can replay its captured launch).
+    template: the refinement template ("ga" or "ga_msa")."""
     if bufs is None:
         bufs = {}
     key, samples = B.sad_kmer_rank(seqs, prm, bufs.setdefault("rank", {}))
     part = B.sad_partition(seqs, key, prm, bufs.setdefault("part", {}))
     al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm, bufs.get("align"))
     bufs["align"] = al
-    rf = B.sad_refine(seqs, part["bucket_off"], part["members"], al, prm, bufs.get("refine"))
+    rf = B.sad_refine(seqs, part["bucket_off"], part["members"], al, prm, bufs.get("refine"),
+                      template=template)
     bufs["refine"] = rf
     return dict(key=key, samples=samples, part=part, align=al, refine=rf)
 
@@ -52,8 +55,8 @@ def to_host(res: dict, n: int, p: int, total_len: int) -> dict:
     )
 
 
-def run(codes, offsets, alphabet: int, prm: B.Params) -> dict:
+def run(codes, offsets, alphabet: int, prm: B.Params, template: str = "ga") -> dict:
     seqs = to_device(codes, offsets, alphabet)
-    res = run_device(seqs, prm)
+    res = run_device(seqs, prm, template=template)
     torch.cuda.synchronize()
     return to_host(res, seqs.n, prm.p, seqs.total_len)
