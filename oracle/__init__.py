@@ -17,6 +17,13 @@ Parity status per step (what pins it, in ``tests/test_oracle_*.py``):
                                 no all-gap columns, recomputed merge scores)
   quality counts (Q)            brute-force enumeration of residue pairs,
                                 perfect and shifted alignments
+  rank against a sample         Counter-built F summed by rows, identical
+                                sequences, the globalised rank recomputed
+  q-row refinement template     one bucket, identical ancestors (scores x q),
+                                enumeration against the rebuilt template
+  tree-dependent refinement     an independent Python re-run of every step
+                                with exhaustive enumeration on tiny inputs;
+                                converged and optimal inputs unchanged
 The whole pipeline has no printed example in the paper: end to end it is pinned
 only through those invariants.
 """
@@ -87,7 +94,9 @@ def _declare(L):
                                 P, I32, P, P, P, P, P, P, P, P]
     L.sadref_refine_template.argtypes = [I32, I32, P, P, I32, P, P, P, P, I32, P, I32, I32, I32,
                                          P, I32, P, P, P, P, P, P, P, P]
-    for f in ("sadref_kmer_list", "sadref_kmer_rank", "sadref_rank_against", "sadref_partition",
+    L.sadref_refine_tree.argtypes = [I32, I32, P, P, I32, P, P, P, I32, P, I32, P, I32, I32, I32,
+                                     P, P, P, P, P, P, I32, P]
+    for f in ("sadref_refine_tree", "sadref_kmer_list", "sadref_kmer_rank", "sadref_rank_against", "sadref_partition",
               "sadref_upgma",
               "sadref_profile_align", "sadref_align_buckets", "sadref_consensus",
               "sadref_refine", "sadref_refine_template"):
@@ -290,6 +299,38 @@ def refine(codes, offsets, A: int, bucket_off, members, colmap_b, width_b, k: in
     return dict(ga=ga[:int(ga_len[0])].copy(), colmap=cg[:len(codes)].copy(), width=int(wg[0]),
                 merge_score=ms[:m].copy(), merge_list=ml[:2 * m].reshape(-1, 2).copy(),
                 merge_cells=mc[:m].copy(), cells=int(cells[0]))
+
+
+def refine_tree(codes, offsets, A: int, bucket_off, members, colmap, width: int, tree, k: int,
+                S, go: int, ge: int, passes: int = 1):
+    """Tree-dependent refinement of a glued alignment: for every edge of the
+    ancestors' guide tree (``tree``: its q - 1 merges as (a, b) pairs over
+    leaves 0..q-1 = the non-empty buckets in bucket order), deepest first, the
+    two sides' parts are re-aligned as profiles and kept iff the profile score
+    rises; up to ``passes`` passes, stopping after one that changes nothing."""
+    codes, offsets = _c(codes, np.uint8), _c(offsets, np.int64)
+    boff, mem, S = _c(bucket_off, np.int32), _c(members, np.int32), _c(S, np.int8)
+    cm = _c(colmap, np.int32)
+    tr = _c(np.asarray(tree).reshape(-1), np.int32)
+    n = len(offsets) - 1
+    p = len(boff) - 1
+    out = np.zeros(max(len(codes), 1), np.int32)
+    wout = np.zeros(1, np.int32)
+    nst = np.zeros(1, np.int32)
+    nacc = np.zeros(1, np.int32)
+    cap = max(1, passes * max(1, 2 * p))
+    rn = np.zeros(cap, np.int32)
+    ro = np.zeros(cap, np.int64)
+    rw = np.zeros(cap, np.int64)
+    st = lib().sadref_refine_tree(n, A, _p(codes), _p(offsets), p, _p(boff), _p(mem), _p(cm),
+                                  int(width), _p(tr) if len(tr) else None, k, _p(S), go, ge,
+                                  passes, _p(out), _p(wout), _p(nst), _p(rn), _p(ro), _p(rw), cap,
+                                  _p(nacc))
+    _check(st, "refine_tree")
+    m = min(int(nst[0]), cap)
+    return dict(colmap=out[:len(codes)].copy(), width=int(wout[0]), steps=int(nst[0]),
+                accepted=int(nacc[0]), rec_node=rn[:m].copy(), rec_old=ro[:m].copy(),
+                rec_new=rw[:m].copy())
 
 
 def run_pipeline(codes, offsets, A: int, k: int, p: int, S, go: int, ge: int,

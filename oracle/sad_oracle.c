@@ -975,3 +975,205 @@ int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* off
                                 kmer_k, S, go, ge, 0, ga, ga_cap, ga_len, colmap_g, width_g,
                                 merge_score_g, merge_list_g, merge_cells_g, n_merges_g, cells);
 }
+
+/* ------------------------------------------------------------------------
+ * Tree-dependent refinement of the glued alignment (the refinement of the
+ * global alignment that the paper's closing section asks for, in the manner
+ * of MUSCLE's tree-dependent stage): every edge of the ancestors' guide tree
+ * splits the buckets into two groups; the two groups' parts of the current
+ * alignment (all-gap columns dropped) are re-aligned as two profiles, and the
+ * result replaces the alignment iff its profile score beats the score of the
+ * alignment the two parts already have.  Edges are visited deepest first
+ * (ties by node id); the root's second child is skipped (same split as its
+ * first); passes repeat until one accepts nothing or `passes` are done. */
+
+/* score of aligning the two column profiles by the op string `ops`: column
+ * scores of M ops minus (go + (l - 1) ge) n1 n2 per maximal X run and per
+ * maximal Y run (terminal runs included) */
+static int64_t ops_score(const uint16_t* C1, int32_t n1, const uint16_t* C2, int32_t n2,
+                         int32_t A, const int8_t* S, int32_t go, int32_t ge, const uint8_t* ops,
+                         int32_t nops) {
+  const int64_t G = (int64_t)n1 * n2;
+  int64_t total = 0;
+  int32_t i = 0, j = 0, prev = -1;
+  for (int32_t t = 0; t < nops; ++t) {
+    const int op = ops[t];
+    if (op == SADREF_OP_M) {
+      int64_t sc = 0;
+      for (int32_t a = 0; a < A; ++a)
+        for (int32_t b = 0; b < A; ++b)
+          sc += (int64_t)C1[(size_t)i * A + a] * S[a * A + b] * (int64_t)C2[(size_t)j * A + b];
+      total += sc;
+      ++i;
+      ++j;
+    } else if (op == SADREF_OP_X) {
+      total -= (prev == SADREF_OP_X ? (int64_t)ge : (int64_t)go) * G;
+      ++i;
+    } else {
+      total -= (prev == SADREF_OP_Y ? (int64_t)ge : (int64_t)go) * G;
+      ++j;
+    }
+    prev = op;
+  }
+  return total;
+}
+
+int sadref_refine_tree(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                       int32_t p, const int32_t* bucket_off, const int32_t* members,
+                       const int32_t* colmap_in, int32_t width_in, const int32_t* tree,
+                       int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge, int32_t passes,
+                       int32_t* colmap_out, int32_t* width_out, int32_t* n_steps,
+                       int32_t* rec_node, int64_t* rec_old, int64_t* rec_new, int32_t rec_cap,
+                       int32_t* n_accepted) {
+  int st = validate_seqs(n, A, codes, offsets, kmer_k);
+  if (st) return st;
+  if (p < 1 || go < ge || ge < 0 || passes < 0 || width_in < 0) return SADREF_E_INVAL;
+  if (bucket_off[0] != 0 || bucket_off[p] != n) return SADREF_E_INVAL;
+  if (n > 65535) return SADREF_E_CAPACITY; /* column counts are 16-bit */
+  const int64_t total = offsets[n];
+  /* leaf u of the ancestor tree = the u-th non-empty bucket */
+  int32_t q = 0;
+  int32_t* seq_u = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  for (int32_t b = 0; b < p; ++b) {
+    if (bucket_off[b + 1] - bucket_off[b] <= 0) continue;
+    for (int32_t t = bucket_off[b]; t < bucket_off[b + 1]; ++t) seq_u[members[t]] = q;
+    ++q;
+  }
+  for (int64_t r = 0; r < total; ++r) {
+    if (colmap_in[r] < 0 || colmap_in[r] >= width_in) st = SADREF_E_INVAL;
+    colmap_out[r] = colmap_in[r];
+  }
+  int32_t W = width_in;
+  *n_steps = 0;
+  *n_accepted = 0;
+  const int32_t nn = q >= 2 ? 2 * q - 1 : 1;
+  int32_t* parent = (int32_t*)malloc(sizeof(int32_t) * (size_t)nn);
+  int32_t* depth = (int32_t*)malloc(sizeof(int32_t) * (size_t)nn);
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)nn);
+  char* in1 = (char*)malloc((size_t)(q > 0 ? q : 1));
+  int32_t nsplit = 0;
+  if (st == SADREF_OK && q >= 2) {
+    for (int32_t v = 0; v < nn; ++v) parent[v] = -1;
+    for (int32_t t = 0; t < q - 1; ++t) {
+      const int32_t a = tree[2 * t], b = tree[2 * t + 1];
+      if (a < 0 || b < 0 || a >= q + t || b >= q + t || parent[a] >= 0 || parent[b] >= 0 ||
+          a == b) {
+        st = SADREF_E_INVAL;
+        break;
+      }
+      parent[a] = q + t;
+      parent[b] = q + t;
+    }
+    if (st == SADREF_OK) {
+      /* depths from the root (node 2q - 2, the last merge), then the visiting
+       * order: deeper first, smaller id first among equals */
+      for (int32_t v = nn - 1; v >= 0; --v) depth[v] = parent[v] < 0 ? 0 : depth[parent[v]] + 1;
+      const int32_t skip = tree[2 * (q - 2) + 1];
+      for (int32_t v = 0; v < nn - 1; ++v)
+        if (v != skip) order[nsplit++] = v;
+      for (int32_t x = 1; x < nsplit; ++x) {  /* insertion sort by (-depth, id) */
+        const int32_t v = order[x];
+        int32_t y = x - 1;
+        while (y >= 0 && (depth[order[y]] < depth[v] ||
+                          (depth[order[y]] == depth[v] && order[y] > v))) {
+          order[y + 1] = order[y];
+          --y;
+        }
+        order[y + 1] = v;
+      }
+    }
+  }
+  for (int32_t pass = 0; pass < passes && st == SADREF_OK && q >= 2; ++pass) {
+    int32_t accepted = 0;
+    for (int32_t x = 0; x < nsplit && st == SADREF_OK; ++x) {
+      const int32_t v = order[x];
+      /* group 1: the sequences of the buckets (leaves) under v */
+      for (int32_t u = 0; u < q; ++u) {
+        int32_t w = u;
+        while (w >= 0 && w != v) w = parent[w];
+        in1[u] = w == v;
+      }
+      /* per column: counts of each group */
+      uint16_t* cnt = (uint16_t*)calloc((size_t)2 * (size_t)(W > 0 ? W : 1) * (size_t)A,
+                                        sizeof(uint16_t));
+      int32_t n1 = 0, n2 = 0;
+      for (int32_t i = 0; i < n; ++i) {
+        const int g = in1[seq_u[i]] ? 0 : 1;
+        if (g == 0) ++n1;
+        else ++n2;
+        for (int64_t r = offsets[i]; r < offsets[i + 1]; ++r)
+          cnt[((size_t)g * W + colmap_out[r]) * A + codes[r]] += 1;
+      }
+      /* the two parts as profiles (columns with a residue of the group) and
+       * the op string of their present alignment */
+      int32_t* idx1 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(W > 0 ? W : 1));
+      int32_t* idx2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(W > 0 ? W : 1));
+      uint16_t* C1 = (uint16_t*)calloc((size_t)(W > 0 ? W : 1) * A, sizeof(uint16_t));
+      uint16_t* C2 = (uint16_t*)calloc((size_t)(W > 0 ? W : 1) * A, sizeof(uint16_t));
+      uint8_t* old_ops = (uint8_t*)malloc((size_t)(W > 0 ? W : 1));
+      int32_t W1 = 0, W2 = 0;
+      for (int32_t c = 0; c < W; ++c) {
+        int h1 = 0, h2 = 0;
+        for (int32_t a = 0; a < A; ++a) {
+          h1 |= cnt[((size_t)0 * W + c) * A + a] > 0;
+          h2 |= cnt[((size_t)1 * W + c) * A + a] > 0;
+        }
+        idx1[c] = h1 ? W1 : -1;
+        idx2[c] = h2 ? W2 : -1;
+        if (h1) memcpy(C1 + (size_t)W1++ * A, cnt + ((size_t)0 * W + c) * A, sizeof(uint16_t) * A);
+        if (h2) memcpy(C2 + (size_t)W2++ * A, cnt + ((size_t)1 * W + c) * A, sizeof(uint16_t) * A);
+        old_ops[c] = h1 && h2 ? SADREF_OP_M : (h1 ? SADREF_OP_X : SADREF_OP_Y);
+        if (!h1 && !h2) st = SADREF_E_INVAL; /* an all-gap column */
+      }
+      const int64_t s_old = ops_score(C1, n1, C2, n2, A, S, go, ge, old_ops, W);
+      uint8_t* ops = (uint8_t*)malloc((size_t)(W1 + W2 > 0 ? W1 + W2 : 1));
+      int32_t nops = 0;
+      int64_t s_new = 0;
+      if (st == SADREF_OK)
+        st = sadref_profile_align(C1, W1, n1, C2, W2, n2, A, S, go, ge, ops, &nops, &s_new);
+      if (st == SADREF_OK) {
+        if (*n_steps < rec_cap) {
+          rec_node[*n_steps] = v;
+          rec_old[*n_steps] = s_old;
+          rec_new[*n_steps] = s_new;
+        }
+        ++*n_steps;
+        if (s_new > s_old) {
+          /* lay the residues out by the new op string */
+          int32_t* map1 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(W1 > 0 ? W1 : 1));
+          int32_t* map2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(W2 > 0 ? W2 : 1));
+          int32_t i = 0, j = 0;
+          for (int32_t t = 0; t < nops; ++t) {
+            if (ops[t] != SADREF_OP_Y) map1[i++] = t;
+            if (ops[t] != SADREF_OP_X) map2[j++] = t;
+          }
+          for (int32_t s = 0; s < n; ++s) {
+            const int g1 = in1[seq_u[s]];
+            for (int64_t r = offsets[s]; r < offsets[s + 1]; ++r)
+              colmap_out[r] = g1 ? map1[idx1[colmap_out[r]]] : map2[idx2[colmap_out[r]]];
+          }
+          W = nops;
+          ++accepted;
+          ++*n_accepted;
+          free(map1);
+          free(map2);
+        }
+      }
+      free(cnt);
+      free(idx1);
+      free(idx2);
+      free(C1);
+      free(C2);
+      free(old_ops);
+      free(ops);
+    }
+    if (accepted == 0) break;
+  }
+  *width_out = W;
+  free(seq_u);
+  free(parent);
+  free(depth);
+  free(order);
+  free(in1);
+  return st;
+}

@@ -125,4 +125,17 @@ int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* off
 #ifdef __cplusplus
 }
 #endif
+/* Tree-dependent refinement of the glued alignment: every edge of the
+ * ancestors' guide tree (tree: the q - 1 merges, leaves = non-empty buckets
+ * in bucket order) splits the sequences in two; the two parts are re-aligned
+ * as profiles and the result kept iff its profile score is higher.  Per step
+ * (node, old score, new score) is recorded while rec_cap allows. */
+int sadref_refine_tree(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                       int32_t p, const int32_t* bucket_off, const int32_t* members,
+                       const int32_t* colmap_in, int32_t width_in, const int32_t* tree,
+                       int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge, int32_t passes,
+                       int32_t* colmap_out, int32_t* width_out, int32_t* n_steps,
+                       int32_t* rec_node, int64_t* rec_old, int64_t* rec_new, int32_t rec_cap,
+                       int32_t* n_accepted);
+
 #endif
