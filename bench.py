@@ -263,6 +263,26 @@ def main():
                               "value": round(cells_m / (ms_m / 1e3) / 1e9, 3), "unit": "GCUPS",
                               "dp_cells_per_step": cells_m,
                               "quality": quality(host_m["refine"]["colmap"])}
+    # tree-dependent refinement of the glued alignment: one pass over the
+    # ancestor tree's edges, and passes until nothing changes (at most 8)
+    tr = {}
+    for passes in (1, 8):
+        B.sad_refine_tree(seqs, res["part"]["bucket_off"], res["part"]["members"],
+                          res["refine"], prm, passes)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 3
+        for _ in range(reps):
+            cm_t, w_t, st_t, acc_t, _ = B.sad_refine_tree(seqs, res["part"]["bucket_off"],
+                                                          res["part"]["members"], res["refine"],
+                                                          prm, passes)
+        e1.record()
+        torch.cuda.synchronize()
+        tr[f"passes_{passes}"] = {"ms": round(e0.elapsed_time(e1) / reps, 3), "steps": st_t,
+                                  "accepted": acc_t, "width": w_t,
+                                  "quality": quality(cm_t.cpu().numpy())}
+    out["tree_refine"] = tr
     if not args.no_plain:
         prm_p = B.Params(w.kmer_k, w.p, S, w.gap_open, w.gap_extend, w.s_max, B.SAD_PLAIN)
         tuned_p = B.sad_tune(seqs, part0["bucket_off"], part0["members"], prm_p)

@@ -201,6 +201,36 @@ int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bucket_off,
                             int32_t* ga_len, sad_msa* global_out, int32_t* n_steps,
                             hipStream_t stream);
 
+/*
+ * Tree-dependent refinement of the glued alignment (the refinement of the
+ * global alignment for divergent families that the paper's closing section
+ * asks for, in the manner of MUSCLE's tree-dependent stage).  Every edge of
+ * the ancestors' guide tree splits the sequences into the buckets below it
+ * and the rest; edges are visited deeper first (smaller node id first among
+ * equals; the root's second child is skipped, it splits like the first).  At
+ * each edge the two groups' parts of the current alignment (all-gap columns
+ * dropped) become two profiles; their present alignment is scored with the
+ * profile objective of sad_align_buckets (column scores C1 S C2^T, affine gap
+ * runs scaled by n1 n2, terminal gaps charged), the profiles are re-aligned
+ * optimally, and the new layout replaces the alignment iff its score is
+ * higher.  Passes over all edges repeat until one changes nothing or
+ * `passes` have run.  Each group's own rows keep their alignment.
+ * Inputs: seqs, d_bucket_off/d_members as for sad_refine; `glued` = the
+ * output of sad_refine / sad_refine_template: d_colmap[total_len], d_width[1]
+ * and d_merge_list, whose first q - 1 pairs are the ancestors' merges (leaves
+ * 0..q-1 = non-empty buckets in bucket order, merge t makes node q + t).
+ * Outputs: out->d_colmap[total_len], out->d_width[1] (device, may not alias
+ * glued's); *n_steps and *n_accepted (host); rec (host, rec_cap x 3 int64,
+ * may be NULL when rec_cap = 0): per step (tree node, present score, new
+ * score).  SAD_E_INVAL for a malformed tree or an alignment with an all-gap
+ * column; SAD_E_CAPACITY beyond 65535 sequences or a width above 4096; the
+ * value bound of sad_align_buckets applies to every re-alignment.
+ */
+int32_t sad_refine_tree(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                        const int32_t* d_members, const sad_msa* glued, const sad_params* prm,
+                        int32_t passes, sad_msa* out, int32_t* n_steps, int32_t* n_accepted,
+                        int64_t* rec, int32_t rec_cap, hipStream_t stream);
+
 /* Autotuner for sad_align_buckets (batching of the bucket merges, Section
  * 2.3.3 step 11).  Runs the call on the given buckets under each candidate
  * schedule, twice each, timing the second run with HIP events on `stream`:

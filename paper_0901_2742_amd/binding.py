@@ -26,7 +26,7 @@ SAD_PLAIN = 0
 SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
-EXPORTS = ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets", "sad_refine", "sad_refine_template", "sad_tune",
+EXPORTS = ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets", "sad_refine", "sad_refine_template", "sad_refine_tree", "sad_tune",
            "sad_quality",
            "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs", "sad_profile_graphs",
            "sad_last_error",
@@ -77,8 +77,9 @@ def lib():
         L.sad_align_buckets.argtypes = [P, P, P, P, P, P]
         L.sad_refine.argtypes = [P, P, P, P, P, P, I32, P, P, P, P]
         L.sad_refine_template.argtypes = [P, P, P, P, P, I32, P, I32, P, P, P, P]
+        L.sad_refine_tree.argtypes = [P, P, P, P, P, I32, P, P, P, P, I32, P]
         for f in ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets",
-                  "sad_refine", "sad_refine_template"):
+                  "sad_refine", "sad_refine_template", "sad_refine_tree"):
             getattr(L, f).restype = I32
         L.sad_profile_enable.argtypes = [I32]
         L.sad_profile_enable.restype = I32
@@ -231,8 +232,12 @@ def _msa_tensors(n_res: int, n_width: int, n_steps: int, dev):
 
 
 def _msa_struct(m: dict) -> SadMsa:
-    return SadMsa(m["colmap"].data_ptr(), m["width"].data_ptr(), m["merge_score"].data_ptr(),
-                  m["merge_list"].data_ptr(), m["merge_cells"].data_ptr(), m["cells"].data_ptr())
+    def ptr(key):
+        t = m.get(key)
+        return t.data_ptr() if t is not None else None
+
+    return SadMsa(ptr("colmap"), ptr("width"), ptr("merge_score"), ptr("merge_list"),
+                  ptr("merge_cells"), ptr("cells"))
 
 
 def sad_align_buckets(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor,
@@ -286,6 +291,28 @@ def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor
     out["ga_len"] = gl.value
     out["n_steps"] = nst.value
     return out
+
+
+def sad_refine_tree(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor,
+                    glued: dict, prm: Params, passes: int = 1, rec_cap: int = 0):
+    """Tree-dependent refinement of a glued alignment (the dict sad_refine
+    returns).  Returns (colmap tensor, width, steps, accepted, records) with
+    records an int64 array of (tree node, present score, new score) rows."""
+    dev = seqs.codes.device
+    colmap = torch.empty(max(seqs.total_len, 1), dtype=torch.int32, device=dev)
+    width = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {"colmap": colmap, "width": width}
+    mg, mo = _msa_struct(glued), _msa_struct(out)
+    rec = np.zeros((max(rec_cap, 1), 3), np.int64)
+    nst, nacc = ctypes.c_int32(0), ctypes.c_int32(0)
+    s, pp = seqs.c_struct(), prm.c_struct()
+    code = lib().sad_refine_tree(ctypes.byref(s), _ptr(bucket_off), _ptr(members),
+                                 ctypes.byref(mg), ctypes.byref(pp), int(passes), ctypes.byref(mo),
+                                 ctypes.byref(nst), ctypes.byref(nacc),
+                                 rec.ctypes.data_as(ctypes.c_void_p), int(rec_cap), _stream())
+    _check(code, "sad_refine_tree")
+    return (colmap[:seqs.total_len], int(width.item()), nst.value, nacc.value,
+            rec[:min(nst.value, rec_cap)].copy())
 
 
 def sad_profile_enable(on: bool, phases: bool = False) -> None:

@@ -1618,6 +1618,204 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
   return finish(c, stream);
 }
 
+extern "C" int32_t sad_refine_tree(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                                   const int32_t* d_members, const sad_msa* glued,
+                                   const sad_params* prm, int32_t passes, sad_msa* out,
+                                   int32_t* n_steps, int32_t* n_accepted, int64_t* rec,
+                                   int32_t rec_cap, hipStream_t stream) {
+  if (!prm || !glued || !out || !n_steps || !n_accepted || passes < 0 || rec_cap < 0 ||
+      (!rec && rec_cap > 0))
+    return fail(SAD_E_INVAL, "null or negative argument");
+  int32_t r = check_seqs(seqs, prm->kmer_k);
+  if (r) return r;
+  r = check_params(prm, seqs->alphabet, true);
+  if (r) return r;
+  if (!d_bucket_off || !d_members || !glued->d_colmap || !glued->d_width ||
+      !glued->d_merge_list || !out->d_colmap || !out->d_width)
+    return fail(SAD_E_INVAL, "null device array");
+  const int n = seqs->n, p = prm->p, A = seqs->alphabet;
+  *n_steps = 0;
+  *n_accepted = 0;
+  if (n > 65535) return fail(SAD_E_CAPACITY, "tree refinement counts residues in 16 bits");
+  DeviceCtx* c = nullptr;
+  r = get_ctx(&c);
+  if (r) return r;
+  r = validate_on_device(c, seqs, prm->kmer_k, stream);
+  if (r) return r;
+  std::vector<int32_t> off, wv;
+  r = d2h(c, d_bucket_off, (size_t)p + 1, off, stream);
+  if (!r) r = d2h(c, glued->d_width, 1, wv, stream);
+  if (r) return r;
+  if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
+  std::vector<int32_t> uidx(p, -1), size_u;
+  for (int b = 0; b < p; ++b) {
+    if (off[b + 1] < off[b]) return fail(SAD_E_INVAL, "bucket offsets must be non-decreasing");
+    if (off[b + 1] == off[b]) continue;
+    uidx[b] = (int)size_u.size();
+    size_u.push_back(off[b + 1] - off[b]);
+  }
+  const int q = (int)size_u.size();
+  int W = wv[0];
+  if (W < 0 || W > kMaxWidth) return fail(SAD_E_CAPACITY, "glued width beyond the library limit");
+  const int64_t total = seqs->total_len;
+  // the ancestors' guide tree: merges (a, b) over leaves 0..q-1, node q + t
+  // made by merge t; its edges in the order deeper first, then smaller id
+  // (the root's second child splits like its first and is skipped)
+  std::vector<int32_t> order;
+  std::vector<int8_t> in1tab;
+  if (q >= 2) {
+    std::vector<int32_t> tree;
+    r = d2h(c, glued->d_merge_list, 2 * (size_t)(q - 1), tree, stream);
+    if (r) return r;
+    const int nn = 2 * q - 1;
+    std::vector<int32_t> parent(nn, -1), depth(nn, 0);
+    for (int t = 0; t < q - 1; ++t) {
+      const int a = tree[2 * t], b = tree[2 * t + 1];
+      if (a < 0 || b < 0 || a >= q + t || b >= q + t || a == b || parent[a] >= 0 ||
+          parent[b] >= 0)
+        return fail(SAD_E_INVAL, "ancestor merge list is not a tree over the non-empty buckets");
+      parent[a] = parent[b] = q + t;
+    }
+    for (int v = nn - 1; v >= 0; --v) depth[v] = parent[v] < 0 ? 0 : depth[parent[v]] + 1;
+    const int skip = tree[2 * (q - 2) + 1];
+    for (int v = 0; v < nn - 1; ++v)
+      if (v != skip) order.push_back(v);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return depth[x] != depth[y] ? depth[x] > depth[y] : x < y;
+    });
+    in1tab.assign(order.size() * (size_t)q, 0);
+    for (size_t x = 0; x < order.size(); ++x)
+      for (int u = 0; u < q; ++u) {
+        int w = u;
+        while (w >= 0 && w != order[x]) w = parent[w];
+        in1tab[x * q + u] = w == order[x] ? 1 : 0;
+      }
+  }
+  // buffers kept across the steps
+  int32_t *seq_u, *d_uidx, *colA, *colB, *S32;
+  int8_t* d_in1;
+  Carver kv;
+  kv.add(seq_u, std::max(n, 1));
+  kv.add(d_uidx, p);
+  kv.add(colA, (size_t)std::max<int64_t>(total, 1));
+  kv.add(colB, (size_t)std::max<int64_t>(total, 1));
+  kv.add(S32, A * A);
+  kv.add(d_in1, std::max<size_t>(in1tab.size(), 1));
+  r = kv.carve_keep(c);
+  if (r) return r;
+  std::vector<int32_t> S32h(A * A);
+  for (int t = 0; t < A * A; ++t) S32h[t] = prm->subst[t];
+  r = h2d(uidx, d_uidx, stream);
+  if (!r) r = h2d(S32h, S32, stream);
+  if (!r) r = h2d(in1tab, d_in1, stream);
+  if (r) return r;
+  r = reset_status(c, stream);
+  if (r) return r;
+  launch_seq_leaf(d_bucket_off, p, d_members, d_uidx, n, seq_u, stream);
+  if (total > 0)
+    HIPCHK(hipMemcpyAsync(colA, glued->d_colmap, (size_t)total * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, stream));
+  r = finish(c, stream);
+  if (r) return r;
+  int steps = 0, accepted = 0;
+  for (int pass = 0; pass < passes && q >= 2 && W > 0; ++pass) {
+    int acc_pass = 0;
+    for (size_t x = 0; x < order.size(); ++x) {
+      int n1 = 0;
+      for (int u = 0; u < q; ++u)
+        if (in1tab[x * q + u]) n1 += size_u[u];
+      const int n2 = n - n1;
+      const int8_t* in1 = d_in1 + x * q;
+      // one merge of the two parts: nodes 0 (group 1) and 1 (group 2) -> 2
+      EngineBuffers e{};
+      Carver cv;
+      const int64_t prof_cap = 2 * (int64_t)W * A + (2 * (int64_t)W + 1) * A;
+      const int64_t up_cap = 4 * (int64_t)W + 1;
+      plan_engine(cv, e, 3, 1, 1, prof_cap, up_cap, std::max(64, W), true, 1);
+      uint32_t* cnt;
+      int32_t *idx1, *idx2, *wid, *map1, *map2;
+      uint8_t *oldops, *ops;
+      unsigned long long* s_old;
+      int64_t *res, *zero64, *opsoff;
+      cv.add(cnt, 2 * (size_t)W * A);
+      cv.add(idx1, W);
+      cv.add(idx2, W);
+      cv.add(map1, W);
+      cv.add(map2, W);
+      cv.add(wid, 4);
+      cv.add(oldops, W);
+      cv.add(ops, 2 * (size_t)W + 1);
+      cv.add(s_old, 2);
+      cv.add(res, 4);
+      cv.add(zero64, 1);
+      cv.add(opsoff, 2);
+      r = cv.carve(c);
+      if (r) return r;
+      const std::vector<int64_t> oo{0, 2 * (int64_t)W + 1}, z{0};
+      const std::vector<int32_t> n1v{0, 0, n1, 0};
+      r = h2d(oo, opsoff, stream);
+      if (!r) r = h2d(z, zero64, stream);
+      if (!r) r = h2d(n1v, wid, stream);
+      if (!r) r = reset_status(c, stream);
+      if (r) return r;
+      const int64_t G = (int64_t)n1 * n2;
+      launch_split_step(seqs->d_codes, seqs->d_offsets, n, colA, seq_u, in1, W, A, cnt, idx1,
+                        idx2, oldops, wid, e.prof_pool, 0, (int64_t)W * A, S32,
+                        G * prm->gap_open, G * prm->gap_extend, s_old, c->st, stream);
+      launch_fill_i32(e.node_parent, -1, 3, stream);
+      launch_fill_i32(e.queue_flag, 0, 1 + kMaxHelpers, stream);
+      launch_fill_i32(e.job_link, 0, 1, stream);
+      init_refine_ctl_kernel<<<1, 1, 0, stream>>>(e.tops, 2ull * W * A, 2ull * W, e.qctl);
+      launch_refine_nodes(1, zero64, wid, wid + 2, (int64_t)W * A, W, wid + 1, n2, A, 0,
+                          e.node_W, e.node_n, e.node_prof, e.node_up, stream);
+      launch_refine_jobs(1, opsoff, e.job_a, e.job_b, e.job_out, e.job_next, e.job_pending,
+                         e.job_ops_off, e.queue, e.queue_flag, e.qctl + 1, e.node_parent, stream);
+      EngineArgs a = engine_args(e, 1, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
+                                 ops, c->st);
+      if (prm->mode == SAD_BATCHED_MFMA && !a.trow) return SAD_E_DEVICE;
+      EngineTimer timer(stream);
+      launch_engine(a, e.nwg, stream);
+      timer.stop();
+      launch_split_result(s_old, e.job_score, e.node_W, 2, res, stream);
+      r = finish(c, stream);
+      if (r) return r;
+      timer.collect();
+      std::vector<int64_t> rv;
+      r = d2h(c, res, 3, rv, stream);
+      if (r) return r;
+      if (steps < rec_cap) {
+        rec[3 * (int64_t)steps] = order[x];
+        rec[3 * (int64_t)steps + 1] = rv[0];
+        rec[3 * (int64_t)steps + 2] = rv[1];
+      }
+      ++steps;
+      if (rv[1] > rv[0]) {
+        launch_split_apply(ops, e.node_W + 2, map1, map2, seqs->d_offsets, n, seq_u, in1, idx1,
+                           idx2, colA, colB, stream);
+        r = finish(c, stream);
+        if (r) return r;
+        std::swap(colA, colB);
+        W = (int)rv[2];
+        ++acc_pass;
+        ++accepted;
+        if (W > kMaxWidth) return fail(SAD_E_CAPACITY, "refined width beyond the library limit");
+      }
+    }
+    if (acc_pass == 0) break;
+  }
+  if (total > 0)
+    HIPCHK(hipMemcpyAsync(out->d_colmap, colA, (size_t)total * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, stream));
+  {
+    const std::vector<int32_t> wout{W};
+    r = h2d(wout, out->d_width, stream);
+    if (r) return r;
+  }
+  *n_steps = steps;
+  *n_accepted = accepted;
+  return finish(c, stream);
+}
+
 extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                               const int32_t* d_members, const sad_msa* buckets,
                               const sad_params* prm, uint8_t* d_ga, int32_t ga_cap,

@@ -263,6 +263,19 @@ void launch_refine_nodes(int q, const int64_t* wo, const int32_t* width_u, const
 void launch_copy_node_profile(const int32_t* node_W, const int64_t* node_prof,
                               const uint16_t* pool, int root, int A, uint16_t* dst, int64_t cap,
                               int32_t* w_out, DevStatus* st, hipStream_t stream);
+void launch_seq_leaf(const int32_t* bucket_off, int p, const int32_t* members,
+                     const int32_t* uidx, int n, int32_t* seq_u, hipStream_t stream);
+void launch_split_step(const uint8_t* codes, const int64_t* offsets, int n, const int32_t* colmap,
+                       const int32_t* seq_u, const int8_t* in1, int W, int A, uint32_t* cnt,
+                       int32_t* idx1, int32_t* idx2, uint8_t* ops, int32_t* wid, uint16_t* prof,
+                       int64_t off1, int64_t off2, const int32_t* S, int64_t o, int64_t e,
+                       unsigned long long* s_old, DevStatus* st, hipStream_t stream);
+void launch_split_result(const unsigned long long* s_old, const int64_t* job_score,
+                         const int32_t* node_W, int out_node, int64_t* out, hipStream_t stream);
+void launch_split_apply(const uint8_t* ops, const int32_t* nops, int32_t* map1, int32_t* map2,
+                        const int64_t* offsets, int n, const int32_t* seq_u, const int8_t* in1,
+                        const int32_t* idx1, const int32_t* idx2, const int32_t* colmap_in,
+                        int32_t* colmap_out, hipStream_t stream);
 void launch_onehot_seq(const uint8_t* codes, const int32_t* len, int maxlen, int A,
                        uint16_t* prof, hipStream_t stream);
 
