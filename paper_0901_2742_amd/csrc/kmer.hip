@@ -128,16 +128,18 @@ void launch_kmer_lists(const uint8_t* codes, const int64_t* offsets, int n, int 
 
 constexpr int kPairThreads = 256;
 
+// F = floor(c 2^31 / d), d = min(Li, Lj) - k + 1.  The numerator is below
+// 2^44 (c <= d <= 8192), so the double quotient is within one of the floor
+// and one integer correction makes it exact.
 __device__ inline uint32_t fhat_of(int64_t c, int64_t Li, int64_t Lj, int k) {
   int64_t L = Li < Lj ? Li : Lj;
   if (L < k) return 0u;
-  uint64_t d = (uint64_t)(L - k + 1);
-  return (uint32_t)(((uint64_t)c << 31) / d);
-}
-
-__device__ inline int64_t wave_sum64(int64_t v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  const uint64_t d = (uint64_t)(L - k + 1);
+  const uint64_t num = (uint64_t)c << 31;
+  uint64_t qt = (uint64_t)((double)num / (double)d);
+  if (qt * d > num) --qt;
+  else if ((qt + 1) * d <= num) ++qt;
+  return (uint32_t)qt;
 }
 
 // Loads row r's list into the histogram (hist must be zero).
@@ -155,19 +157,42 @@ __device__ inline void hist_clear(uint16_t* hist, int kspace) {
   for (int t = threadIdx.x; t < (kspace + 1) / 2; t += blockDim.x) h32[t] = 0;
 }
 
-// c between the histogram's row and column sequence c (wave-wide)
-__device__ inline int64_t wave_common(const uint16_t* hist, const KmerLists& kl, int c) {
-  const uint32_t* e = kl.entries + kl.off[c];
-  const int nc = kl.nu[c];
+__device__ inline int32_t wave_sum32(int32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// c between the histogram's row and two column sequences c0 and c1 (wave-
+// wide; c1 < 0: none).  Four entries per lane and column are loaded before
+// any is used, so a pair of lists of up to 256 entries costs one round trip.
+// Lanes past a list's end read the entry 0 (count 0, adds nothing).
+__device__ inline void wave_common2(const uint16_t* hist, const KmerLists& kl, int c0, int c1,
+                                    int32_t& r0, int32_t& r1) {
+  const uint32_t* e0 = kl.entries + kl.off[c0];
+  const int n0 = kl.nu[c0];
+  const uint32_t* e1 = c1 >= 0 ? kl.entries + kl.off[c1] : e0;
+  const int n1 = c1 >= 0 ? kl.nu[c1] : 0;
   const int lane = threadIdx.x & 63;
-  int64_t acc = 0;
-  for (int t = lane; t < nc; t += 64) {
-    uint32_t v = e[t];
-    uint32_t h = hist[v >> 16];
-    uint32_t cnt = v & 0xffff;
-    acc += cnt < h ? cnt : h;
+  const int nmax = n0 > n1 ? n0 : n1;
+  int32_t a0 = 0, a1 = 0;
+  for (int t0 = 0; t0 < nmax; t0 += 256) {
+    uint32_t v0[4], v1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + 64 * u + lane;
+      v0[u] = t < n0 ? e0[t] : 0u;
+      v1[u] = t < n1 ? e1[t] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t h0 = hist[v0[u] >> 16], h1 = hist[v1[u] >> 16];
+      const uint32_t k0 = v0[u] & 0xffffu, k1 = v1[u] & 0xffffu;
+      a0 += (int32_t)(k0 < h0 ? k0 : h0);
+      a1 += (int32_t)(k1 < h1 ? k1 : h1);
+    }
   }
-  return wave_sum64(acc);
+  r0 = wave_sum32(a0);
+  r1 = wave_sum32(a1);
 }
 
 __device__ inline int64_t seq_len(const KmerLists& kl, int i) {
@@ -203,9 +228,12 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_chunk_kernel(KmerLists kl
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t Lr = seq_len(kl, r);
   uint64_t part = 0;
-  for (int j = lo + wave; j < hi; j += nw) {
-    int64_t cc = wave_common(hist, kl, j);
-    part += fhat_of(cc, Lr, seq_len(kl, j), k);
+  for (int j = lo + wave; j < hi; j += 2 * nw) {
+    const int j2 = j + nw < hi ? j + nw : -1;
+    int32_t c0, c1;
+    wave_common2(hist, kl, j, j2, c0, c1);
+    part += fhat_of(c0, Lr, seq_len(kl, j), k);
+    if (j2 >= 0) part += fhat_of(c1, Lr, seq_len(kl, j2), k);
   }
   uint64_t s = block_sum_waves(part, red);
   if (threadIdx.x == 0) out[r] = s;
@@ -228,14 +256,23 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl,
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t Lr = seq_len(kl, r);
   uint64_t part = 0;
-  for (int q = wave; q < ncols; q += nw) {
-    const int j = cols ? cols[q] : q;
-    if (j < 0 || j >= n) {
+  for (int q = wave; q < ncols; q += 2 * nw) {
+    int j = cols ? cols[q] : q;
+    int j2 = q + nw < ncols ? (cols ? cols[q + nw] : q + nw) : -1;
+    if (j < 0 || j >= n || j2 < -1 || j2 >= n) {
       if (r == 0 && (threadIdx.x & 63) == 0) raise_error(st, SAD_E_INVAL, q, W_RANK);
-      continue;
+      if (j < 0 || j >= n) j = -1;
+      if (j2 < -1 || j2 >= n) j2 = -1;
     }
-    int64_t cc = wave_common(hist, kl, j);
-    part += fhat_of(cc, Lr, seq_len(kl, j), k);
+    if (j < 0) {  // only the second column (if any) counts
+      j = j2;
+      j2 = -1;
+      if (j < 0) continue;
+    }
+    int32_t c0, c1;
+    wave_common2(hist, kl, j, j2, c0, c1);
+    part += fhat_of(c0, Lr, seq_len(kl, j), k);
+    if (j2 >= 0) part += fhat_of(c1, Lr, seq_len(kl, j2), k);
   }
   uint64_t s = block_sum_waves(part, red);
   if (threadIdx.x == 0) out[r] = s;
@@ -270,10 +307,15 @@ __global__ __launch_bounds__(kPairThreads) void fmatrix_kernel(KmerLists kl,
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t Lr = seq_len(kl, r);
   uint32_t* Frow = F + fm_off[g] + (int64_t)a * ng;
-  for (int b = wave; b < ng; b += nw) {
-    int j = ids[g0 + b];
-    int64_t cc = wave_common(hist, kl, j);
-    if ((threadIdx.x & 63) == 0) Frow[b] = fhat_of(cc, Lr, seq_len(kl, j), k);
+  for (int b = wave; b < ng; b += 2 * nw) {
+    const int j = ids[g0 + b];
+    const int j2 = b + nw < ng ? ids[g0 + b + nw] : -1;
+    int32_t c0, c1;
+    wave_common2(hist, kl, j, j2, c0, c1);
+    if ((threadIdx.x & 63) == 0) {
+      Frow[b] = fhat_of(c0, Lr, seq_len(kl, j), k);
+      if (j2 >= 0) Frow[b + nw] = fhat_of(c1, Lr, seq_len(kl, j2), k);
+    }
   }
 }
 

@@ -152,24 +152,82 @@ void launch_compact(const uint8_t* stage, const int64_t* st_off, const int32_t* 
 
 // ------------------------------------------------------------------ glue
 
-// bucket u's op string (vs GA of length GL): X columns counted per slot j;
-// matched GA positions flagged.
-__global__ void glue_count_kernel(const uint8_t* __restrict__ ops, const int64_t* __restrict__ ops_off,
-                                  const int32_t* __restrict__ nops, int q, int GL,
-                                  int32_t* __restrict__ ins, int32_t* __restrict__ used) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= q) return;
+// Block-wide scans of one value per thread (NT threads, Hillis-Steele in LDS):
+// the exclusive prefix sum (total in *total) and the exclusive prefix maximum
+// (identity `lo`).
+constexpr int kGlueThreads = 256;
+
+template <int NT>
+__device__ inline int block_excl_sum(int v, int* sh, int* total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int d = 1; d < NT; d <<= 1) {
+    const int x = tid >= d ? sh[tid - d] : 0;
+    __syncthreads();
+    sh[tid] += x;
+    __syncthreads();
+  }
+  const int incl = sh[tid];
+  *total = sh[NT - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+template <int NT>
+__device__ inline int block_excl_max(int v, int lo, int* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int d = 1; d < NT; d <<= 1) {
+    const int x = tid >= d ? sh[tid - d] : lo;
+    __syncthreads();
+    sh[tid] = max(sh[tid], x);
+    __syncthreads();
+  }
+  const int r = tid > 0 ? sh[tid - 1] : lo;
+  __syncthreads();
+  return r;
+}
+
+// Bucket u's op string against the template (TL columns): op t lies in slot
+// j(t) = the number of non-X ops before it; an X op is the kin(t)-th of the run
+// of X ops in its slot, kin(t) = t - 1 - (the last non-X op before t).  One
+// workgroup per bucket, the ops in chunks of kGlueThreads.  Count pass: the
+// last X op of each run stores the run length as the slot's insert count;
+// M ops flag their template column.
+__global__ __launch_bounds__(kGlueThreads) void glue_count_kernel(
+    const uint8_t* __restrict__ ops, const int64_t* __restrict__ ops_off,
+    const int32_t* __restrict__ nops, int q, int GL, int32_t* __restrict__ ins,
+    int32_t* __restrict__ used) {
+  __shared__ int sh[kGlueThreads];
+  const int u = blockIdx.x;
   const uint8_t* o = ops + ops_off[u];
   int32_t* row = ins + (int64_t)u * (GL + 1);
-  int j = 0;
-  for (int t = 0; t < nops[u]; ++t) {
-    const uint8_t op = o[t];
-    if (op == 1) {
-      row[j] += 1;
-    } else {
-      if (op == 0) used[j] = 1;
-      ++j;
+  const int m = nops[u];
+  int cj = 0, clast = -1;
+  for (int t0 = 0; t0 < m; t0 += kGlueThreads) {
+    const int t = t0 + (int)threadIdx.x;
+    const int op = t < m ? o[t] : 3;
+    const int nonx = (t < m && op != 1) ? 1 : 0;
+    int tot = 0;
+    const int j = cj + block_excl_sum<kGlueThreads>(nonx, sh, &tot);
+    const int lastc = block_excl_max<kGlueThreads>(nonx ? t : -1, -1, sh);
+    const int last = max(clast, lastc);
+    if (t < m) {
+      if (op == 1) {
+        const bool run_end = t + 1 == m || o[t + 1] != 1;
+        if (run_end) row[j] = t - last;
+      } else if (op == 0) {
+        used[j] = 1;
+      }
     }
+    cj += tot;
+    // the last non-X op of this chunk, for the next one
+    if ((int)threadIdx.x == kGlueThreads - 1) sh[0] = max(lastc, nonx ? t : -1);
+    __syncthreads();
+    clast = max(clast, sh[0]);
+    __syncthreads();
   }
 }
 
@@ -187,45 +245,64 @@ __global__ void glue_slot_kernel(int32_t* __restrict__ ins, int q, int GL,
   slot_total[j] = acc;
 }
 
-__global__ void glue_scan_kernel(const int32_t* __restrict__ slot_total,
-                                 const int32_t* __restrict__ used, int GL,
-                                 int32_t* __restrict__ slot_start, int32_t* __restrict__ shared_at,
-                                 int32_t* __restrict__ width) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int pos = 0;
-  for (int j = 0; j <= GL; ++j) {
-    slot_start[j] = pos;
-    pos += slot_total[j];
-    if (j < GL) {
-      shared_at[j] = used[j] ? pos : -1;
-      if (used[j]) ++pos;
+// Glued positions: slot j starts after every earlier slot and every earlier
+// kept template column; template column j follows its slot (one workgroup).
+__global__ __launch_bounds__(kGlueThreads) void glue_scan_kernel(
+    const int32_t* __restrict__ slot_total, const int32_t* __restrict__ used, int GL,
+    int32_t* __restrict__ slot_start, int32_t* __restrict__ shared_at,
+    int32_t* __restrict__ width) {
+  __shared__ int sh[kGlueThreads];
+  int base = 0;
+  for (int j0 = 0; j0 <= GL; j0 += kGlueThreads) {
+    const int j = j0 + (int)threadIdx.x;
+    const int st = j <= GL ? slot_total[j] : 0;
+    const int us = j < GL ? (used[j] ? 1 : 0) : 0;
+    int tot = 0;
+    const int pre = base + block_excl_sum<kGlueThreads>(st + us, sh, &tot);
+    if (j <= GL) {
+      slot_start[j] = pre;
+      if (j < GL) shared_at[j] = us ? pre + st : -1;
     }
+    base += tot;
   }
-  width[0] = pos;
+  if (threadIdx.x == 0) width[0] = base;
 }
 
-// bucket column -> glued column, for bucket u
-__global__ void glue_map_kernel(const uint8_t* __restrict__ ops, const int64_t* __restrict__ ops_off,
-                                const int32_t* __restrict__ nops, int q, int GL,
-                                const int32_t* __restrict__ ins, const int32_t* __restrict__ slot_start,
-                                const int32_t* __restrict__ shared_at, const int64_t* __restrict__ wo,
-                                int32_t* __restrict__ to_g) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= q) return;
+// Map pass: bucket column i(t) (the number of M and X ops before t) goes to
+// slot_start[j] + (earlier buckets' inserts in slot j) + kin(t) for an X op,
+// to the template column's glued position for an M op.
+__global__ __launch_bounds__(kGlueThreads) void glue_map_kernel(
+    const uint8_t* __restrict__ ops, const int64_t* __restrict__ ops_off,
+    const int32_t* __restrict__ nops, int q, int GL, const int32_t* __restrict__ ins,
+    const int32_t* __restrict__ slot_start, const int32_t* __restrict__ shared_at,
+    const int64_t* __restrict__ wo, int32_t* __restrict__ to_g) {
+  __shared__ int sh[kGlueThreads];
+  const int u = blockIdx.x;
   const uint8_t* o = ops + ops_off[u];
   const int32_t* row = ins + (int64_t)u * (GL + 1);
   int32_t* dst = to_g + wo[u];
-  int i = 0, j = 0, kin = 0;
-  for (int t = 0; t < nops[u]; ++t) {
-    const uint8_t op = o[t];
-    if (op == 1) {
-      dst[i++] = slot_start[j] + row[j] + kin;
-      ++kin;
-    } else {
-      if (op == 0) dst[i++] = shared_at[j];
-      ++j;
-      kin = 0;
+  const int m = nops[u];
+  int ci = 0, cj = 0, clast = -1;
+  for (int t0 = 0; t0 < m; t0 += kGlueThreads) {
+    const int t = t0 + (int)threadIdx.x;
+    const int op = t < m ? o[t] : 3;
+    const int nonx = (t < m && op != 1) ? 1 : 0;
+    const int cons = (t < m && op != 2) ? 1 : 0;
+    int tj = 0, ti = 0;
+    const int j = cj + block_excl_sum<kGlueThreads>(nonx, sh, &tj);
+    const int i = ci + block_excl_sum<kGlueThreads>(cons, sh, &ti);
+    const int lastc = block_excl_max<kGlueThreads>(nonx ? t : -1, -1, sh);
+    const int last = max(clast, lastc);
+    if (t < m) {
+      if (op == 1) dst[i] = slot_start[j] + row[j] + (t - last - 1);
+      else if (op == 0) dst[i] = shared_at[j];
     }
+    cj += tj;
+    ci += ti;
+    if ((int)threadIdx.x == kGlueThreads - 1) sh[0] = max(lastc, nonx ? t : -1);
+    __syncthreads();
+    clast = max(clast, sh[0]);
+    __syncthreads();
   }
 }
 
@@ -251,11 +328,12 @@ void launch_glue(const uint8_t* ops, const int64_t* ops_off, const int32_t* nops
                  int n, const int32_t* uidx, const int32_t* colmap_b, int32_t* colmap_g,
                  hipStream_t stream) {
   if (q <= 0) return;
-  glue_count_kernel<<<(q + 63) / 64, 64, 0, stream>>>(ops, ops_off, nops, q, GL, ins, used);
+  glue_count_kernel<<<q, kGlueThreads, 0, stream>>>(ops, ops_off, nops, q, GL, ins, used);
   glue_slot_kernel<<<(GL + 1 + 255) / 256, 256, 0, stream>>>(ins, q, GL, slot_total);
-  glue_scan_kernel<<<1, 1, 0, stream>>>(slot_total, used, GL, slot_start, shared_at, width);
-  glue_map_kernel<<<(q + 63) / 64, 64, 0, stream>>>(ops, ops_off, nops, q, GL, ins, slot_start,
-                                                     shared_at, wo, to_g);
+  glue_scan_kernel<<<1, kGlueThreads, 0, stream>>>(slot_total, used, GL, slot_start, shared_at,
+                                                   width);
+  glue_map_kernel<<<q, kGlueThreads, 0, stream>>>(ops, ops_off, nops, q, GL, ins, slot_start,
+                                                   shared_at, wo, to_g);
   if (n > 0)
     glue_colmap_kernel<<<n, 128, 0, stream>>>(offsets, members, bucket_off, p, uidx, wo, colmap_b,
                                               to_g, colmap_g);
