@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--workload", default="prot2000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the q-row template and tree-refinement figures (profiling runs)")
     ap.add_argument("--sweep-p", default="", metavar="P1,P2,...",
                     help="instead of the benchmark line, one line per bucket count p: step time "
                          "and alignment quality (Q) of the pipeline on the workload")
@@ -110,6 +112,41 @@ def timed_steps(run, seqs, prm, steps, warmup, B, torch, template="ga"):
     B.sad_profile_enable(False)
     eng_ms, launches = B.sad_profile_read(reset=True)
     return res, t0.elapsed_time(t1) / steps, eng_ms, launches
+
+
+def extras(out, args, B, pipeline, torch, seqs, prm, s, w, res, quality):
+    """The refinement variants beside the benchmark line: the same pipeline
+    with the ancestors' alignment as the template, and tree-dependent
+    refinement of the glued alignment (one pass; passes until nothing
+    changes, at most 8)."""
+    res_m, ms_m, _, _ = timed_steps(pipeline.run_device, seqs, prm, args.steps, args.warmup, B,
+                                    torch, "ga_msa")
+    host_m = pipeline.to_host(res_m, s.n, w.p, seqs.total_len)
+    cells_m = host_m["align"]["cells"] + host_m["refine"]["cells"]
+    out["template_ga_msa"] = {"ms_per_step": round(ms_m, 3),
+                              "value": round(cells_m / (ms_m / 1e3) / 1e9, 3), "unit": "GCUPS",
+                              "dp_cells_per_step": cells_m,
+                              "quality": quality(host_m["refine"]["colmap"])}
+    # tree-dependent refinement of the glued alignment: one pass over the
+    # ancestor tree's edges, and passes until nothing changes (at most 8)
+    tr = {}
+    for passes in (1, 8):
+        B.sad_refine_tree(seqs, res["part"]["bucket_off"], res["part"]["members"],
+                          res["refine"], prm, passes)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 3
+        for _ in range(reps):
+            cm_t, w_t, st_t, acc_t, _ = B.sad_refine_tree(seqs, res["part"]["bucket_off"],
+                                                          res["part"]["members"], res["refine"],
+                                                          prm, passes)
+        e1.record()
+        torch.cuda.synchronize()
+        tr[f"passes_{passes}"] = {"ms": round(e0.elapsed_time(e1) / reps, 3), "steps": st_t,
+                                  "accepted": acc_t, "width": w_t,
+                                  "quality": quality(cm_t.cpu().numpy())}
+    out["tree_refine"] = tr
 
 
 def rank_study(args, B, pipeline, torch):
@@ -254,35 +291,8 @@ def main():
                      "traffic": measured_traffic(w.name),
                      "ops_per_cell": OPS_PER_CELL},
     }
-    # the same pipeline with the ancestors' alignment as the refinement template
-    res_m, ms_m, _, _ = timed_steps(pipeline.run_device, seqs, prm, args.steps, args.warmup, B,
-                                    torch, "ga_msa")
-    host_m = pipeline.to_host(res_m, s.n, w.p, seqs.total_len)
-    cells_m = host_m["align"]["cells"] + host_m["refine"]["cells"]
-    out["template_ga_msa"] = {"ms_per_step": round(ms_m, 3),
-                              "value": round(cells_m / (ms_m / 1e3) / 1e9, 3), "unit": "GCUPS",
-                              "dp_cells_per_step": cells_m,
-                              "quality": quality(host_m["refine"]["colmap"])}
-    # tree-dependent refinement of the glued alignment: one pass over the
-    # ancestor tree's edges, and passes until nothing changes (at most 8)
-    tr = {}
-    for passes in (1, 8):
-        B.sad_refine_tree(seqs, res["part"]["bucket_off"], res["part"]["members"],
-                          res["refine"], prm, passes)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        reps = 3
-        for _ in range(reps):
-            cm_t, w_t, st_t, acc_t, _ = B.sad_refine_tree(seqs, res["part"]["bucket_off"],
-                                                          res["part"]["members"], res["refine"],
-                                                          prm, passes)
-        e1.record()
-        torch.cuda.synchronize()
-        tr[f"passes_{passes}"] = {"ms": round(e0.elapsed_time(e1) / reps, 3), "steps": st_t,
-                                  "accepted": acc_t, "width": w_t,
-                                  "quality": quality(cm_t.cpu().numpy())}
-    out["tree_refine"] = tr
+    if not args.no_extras:
+        extras(out, args, B, pipeline, torch, seqs, prm, s, w, res, quality)
     if not args.no_plain:
         prm_p = B.Params(w.kmer_k, w.p, S, w.gap_open, w.gap_extend, w.s_max, B.SAD_PLAIN)
         tuned_p = B.sad_tune(seqs, part0["bucket_off"], part0["members"], prm_p)
