@@ -1336,12 +1336,12 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
   __syncthreads();
   // (groups here are below kUpgmaW64MaxN: 64-bit cross products are exact)
   const TriS S{tri, n};
-  upgma_init_best<true>(S, n, id, sz, active, best);
+  upgma_init_best<true, 1>(S, n, id, sz, active, best);
   __syncthreads();
   if (wave == 0) {
     // the merge steps; each decided merge is listed for wave 1
-    const bool ok = upgma_steps<true>(
-        S, n, id, sz, active, best, rec, a.up_merges + 2 * (int64_t)g0, g, a.st,
+    const bool ok = upgma_steps<true, 1>(
+        S, n, id, sz, active, best, rec, g, a.st,
         [&](int step, int ia, int ib) {
           mlist[2 * step] = ia;
           mlist[2 * step + 1] = ib;
@@ -1367,7 +1367,13 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
       }
       const int kb = min(avail, k0 + 64);
       const int k = k0 + lane;
-      if (k < kb) create_job(a, g0, n, k, mlist[2 * k], mlist[2 * k + 1]);
+      if (k < kb) {
+        const int ia = mlist[2 * k], ib = mlist[2 * k + 1];
+        // the merge list output (kept off the tree wave's path)
+        a.up_merges[2 * ((int64_t)g0 + k)] = ia;
+        a.up_merges[2 * ((int64_t)g0 + k) + 1] = ib;
+        create_job(a, g0, n, k, ia, ib);
+      }
       k0 = kb;
       t_start = __builtin_amdgcn_s_memrealtime();
     }

@@ -7,14 +7,25 @@
 namespace sad {
 
 // The whole workgroup loads the sums and finds every cluster's best partner;
-// wave 0 then runs the merge steps.
+// wave 0 then runs the merge steps.  With the sums in LDS the merges are
+// listed in LDS (ml) and copied to mo at the end, so that a step makes no
+// global access; with global sums (ml == nullptr) they go to mo directly.
 template <bool W64, typename St>
 __device__ inline void upgma_run(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
-                                 int32_t* best, int32_t* rec, int32_t* mo, int g, DevStatus* st) {
-  upgma_init_best<W64>(S, n, id, sz, active, best);
+                                 int32_t* best, int32_t* rec, int32_t* ml, int32_t* mo, int g,
+                                 DevStatus* st) {
+  upgma_init_best<W64, 4>(S, n, id, sz, active, best);
   __syncthreads();
-  if ((threadIdx.x >> 6) == 0)
-    upgma_steps<W64>(S, n, id, sz, active, best, rec, mo, g, st, [](int, int, int) {});
+  if ((threadIdx.x >> 6) == 0) {
+    int32_t* dst = ml ? ml : mo;
+    upgma_steps<W64, 4>(S, n, id, sz, active, best, rec, g, st, [&](int step, int ia, int ib) {
+      dst[2 * step] = ia;
+      dst[2 * step + 1] = ib;
+    });
+  }
+  __syncthreads();
+  if (ml)
+    for (int q = threadIdx.x; q < 2 * (n - 1); q += kUpgmaThreads) mo[q] = ml[q];
 }
 
 __global__ __launch_bounds__(kUpgmaThreads) void upgma_kernel(
@@ -28,12 +39,14 @@ __global__ __launch_bounds__(kUpgmaThreads) void upgma_kernel(
   if (n <= 1) return;
   const bool in_lds = n <= lds_n;
   // LDS: [triangle of lds_n (lds_n - 1) / 2 u64][5 lds_n-or-n i32]
+  //      [merge list, 2 lds_n i32, when the sums are in LDS]
   int32_t* sh = reinterpret_cast<int32_t*>(shq + (in_lds ? (int64_t)lds_n * (lds_n - 1) / 2 : 0));
   int32_t* id = sh;
   int32_t* sz = sh + n;
   int32_t* active = sh + 2 * n;
   int32_t* best = sh + 3 * n;
   int32_t* rec = sh + 4 * n;
+  int32_t* ml = in_lds ? sh + 5 * lds_n : nullptr;
   const uint32_t* Fg = F + fm_off[g];
   int32_t* mo = merges_out + 2 * (int64_t)merge_base[g];
   const int tid = threadIdx.x;
@@ -52,18 +65,18 @@ __global__ __launch_bounds__(kUpgmaThreads) void upgma_kernel(
     __threadfence_block();
     __syncthreads();
     if (w64)
-      upgma_run<true>(S, n, id, sz, active, best, rec, mo, g, st);
+      upgma_run<true>(S, n, id, sz, active, best, rec, ml, mo, g, st);
     else
-      upgma_run<false>(S, n, id, sz, active, best, rec, mo, g, st);
+      upgma_run<false>(S, n, id, sz, active, best, rec, ml, mo, g, st);
   } else {
     const FullS S{Sw + fm_off[g], n};
     for (int64_t q = tid; q < (int64_t)n * n; q += kUpgmaThreads) S.t[q] = Fg[q];
     __threadfence_block();
     __syncthreads();
     if (w64)
-      upgma_run<true>(S, n, id, sz, active, best, rec, mo, g, st);
+      upgma_run<true>(S, n, id, sz, active, best, rec, nullptr, mo, g, st);
     else
-      upgma_run<false>(S, n, id, sz, active, best, rec, mo, g, st);
+      upgma_run<false>(S, n, id, sz, active, best, rec, nullptr, mo, g, st);
   }
 }
 
@@ -75,7 +88,8 @@ void launch_upgma(const uint32_t* F, const int64_t* fm_off, const int32_t* group
   // 5 max(n) words either way
   const int lds_n = std::min(max_n, kUpgmaLdsN);
   const size_t tri = (size_t)lds_n * (lds_n - 1) / 2 * sizeof(uint64_t);
-  size_t lds = tri + (size_t)5 * max_n * sizeof(int32_t);
+  // (the merge lists of groups kept in LDS follow their 5 lds_n words)
+  size_t lds = tri + (size_t)std::max(5 * max_n, 7 * lds_n) * sizeof(int32_t);
   int use_lds_n = lds_n;
   if (lds > 160 * 1024 - 1024) {
     // large groups present: all groups use the global sums

@@ -27,29 +27,30 @@ constexpr int kUpgmaWaves = kUpgmaThreads / 64;
 constexpr int kUpgmaLdsN = 190;
 constexpr int kUpgmaW64MaxN = 600;
 
-// A candidate pair: summed similarity, |A| |B|, the pair of ids packed as
-// (min << 16) | max (ids < 2 kMaxGroup < 2^16; all ones = no candidate) and
-// the pair of slots packed as a | b << 16.
+// A candidate pair: summed similarity, |A| |B| (at most (kMaxGroup / 2)^2 <
+// 2^32) and the pair of ids packed as (min << 16) | max (ids < 2 kMaxGroup <
+// 2^16; all ones = no candidate).  The key names the pair, so the slots of the
+// winner of a wave reduction are read from the lane whose own candidate has
+// the winning key (winner_lane) instead of travelling with it.
 struct WCand {
   uint64_t s;
-  uint64_t p;
+  uint32_t p;
   uint32_t key;
-  uint32_t ab;
 };
 
 __device__ inline uint32_t pair_key16(int ia, int ib) {
   return ((uint32_t)min(ia, ib) << 16) | (uint32_t)max(ia, ib);
 }
 
-// sign of s1 p2 - s2 p1
+// sign of s1 p2 - s2 p1 (64 x 32-bit products)
 template <bool W64>
-__device__ inline int cmp_avg(uint64_t s1, uint64_t p1, uint64_t s2, uint64_t p2) {
+__device__ inline int cmp_avg(uint64_t s1, uint32_t p1, uint64_t s2, uint32_t p2) {
   if constexpr (W64) {
-    const uint64_t l = s1 * p2, r = s2 * p1;
+    const uint64_t l = s1 * (uint64_t)p2, r = s2 * (uint64_t)p1;
     return l > r ? 1 : (l < r ? -1 : 0);
   } else {
-    const uint64_t lo1 = s1 * p2, hi1 = __umul64hi(s1, p2);
-    const uint64_t lo2 = s2 * p1, hi2 = __umul64hi(s2, p1);
+    const uint64_t lo1 = s1 * (uint64_t)p2, hi1 = __umul64hi(s1, (uint64_t)p2);
+    const uint64_t lo2 = s2 * (uint64_t)p1, hi2 = __umul64hi(s2, (uint64_t)p1);
     if (hi1 != hi2) return hi1 > hi2 ? 1 : -1;
     if (lo1 != lo2) return lo1 > lo2 ? 1 : -1;
     return 0;
@@ -71,8 +72,13 @@ __device__ inline WCand wc_none() {
   c.s = 0;
   c.p = 1;
   c.key = ~0u;
-  c.ab = 0;
   return c;
+}
+
+// First lane whose own candidate `mine` is the wave's winner `w` (-1 if none).
+__device__ inline int winner_lane(const WCand& mine, const WCand& w) {
+  const uint64_t m = __ballot(w.key != ~0u && mine.key == w.key);
+  return m ? __ffsll((unsigned long long)m) - 1 : -1;
 }
 
 template <int CTRL>
@@ -87,19 +93,16 @@ template <int CTRL>
 __device__ inline WCand wc_dpp(const WCand& c) {
   WCand x;
   x.s = dpp64<CTRL>(c.s);
-  x.p = dpp64<CTRL>(c.p);
+  x.p = dpp32<CTRL>(c.p);
   x.key = dpp32<CTRL>(c.key);
-  x.ab = dpp32<CTRL>(c.ab);
   return x;
 }
 __device__ inline WCand wc_xor(const WCand& c, int m) {
   WCand x;
   x.s = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)c.s, m, 64) |
         ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(c.s >> 32), m, 64) << 32);
-  x.p = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)c.p, m, 64) |
-        ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(c.p >> 32), m, 64) << 32);
+  x.p = (uint32_t)__shfl_xor((int)c.p, m, 64);
   x.key = (uint32_t)__shfl_xor((int)c.key, m, 64);
-  x.ab = (uint32_t)__shfl_xor((int)c.ab, m, 64);
   return x;
 }
 
@@ -157,76 +160,128 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// The step loops take UB slots per lane at a time and load all their pair
+// sums before using any (with the sums in global memory each load is a round
+// trip: the standalone kernel uses UB = 4; the engine's tree phase, sums in
+// LDS, uses 1).  A slot that is out of range or the row itself reads a valid
+// stand-in pair whose value is ignored.
+
+__device__ inline int other_slot(int r) { return r == 0 ? 1 : 0; }
+
 // Best partner of slot r among the active slots (whole wave; -1 if none).
-template <bool W64, typename St>
+template <bool W64, int UB, typename St>
 __device__ inline int wave_best_partner(const St& S, int n, int r, const int32_t* id,
                                         const int32_t* sz, const int32_t* active) {
   const int lane = threadIdx.x & 63;
   WCand c = wc_none();
-  const uint64_t sr = (uint64_t)sz[r];
+  int cb = -1;
+  const uint32_t sr = (uint32_t)sz[r];
   const int ir = id[r];
-  for (int b = lane; b < n; b += 64) {
-    if (b == r || !active[b]) continue;
-    WCand x;
-    x.s = S.get(r, b);
-    x.p = sr * (uint64_t)sz[b];
-    x.key = pair_key16(ir, id[b]);
-    x.ab = (uint32_t)b;
-    if (wc_better<W64>(x, c)) c = x;
+  for (int b0 = lane; b0 < n; b0 += 64 * UB) {
+    uint64_t sv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int b = b0 + 64 * u;
+      sv[u] = S.get(r, (b < n && b != r) ? b : other_slot(r));
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int b = b0 + 64 * u;
+      if (b >= n || b == r || !active[b]) continue;
+      WCand x;
+      x.s = sv[u];
+      x.p = sr * (uint32_t)sz[b];
+      x.key = pair_key16(ir, id[b]);
+      if (wc_better<W64>(x, c)) {
+        c = x;
+        cb = b;
+      }
+    }
   }
-  c = wave_first<W64>(c);
-  return c.key == ~0u ? -1 : (int)c.ab;
+  const WCand w = wave_first<W64>(c);
+  const int src = winner_lane(c, w);
+  return src < 0 ? -1 : __builtin_amdgcn_readlane(cb, src);
 }
 
 // Best partners of every slot (the whole workgroup, kUpgmaWaves waves).
-template <bool W64, typename St>
+template <bool W64, int UB, typename St>
 __device__ inline void upgma_init_best(const St& S, int n, const int32_t* id, const int32_t* sz,
                                        const int32_t* active, int32_t* best) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int r = wave; r < n; r += kUpgmaWaves) {
-    const int b = wave_best_partner<W64>(S, n, r, id, sz, active);
+    const int b = wave_best_partner<W64, UB>(S, n, r, id, sz, active);
     if (lane == 0) best[r] = b;
   }
 }
 
-// The n - 1 merge steps, run by one wave after upgma_init_best.  mo receives
-// the merges (min id, max id); on_merge(step, min id, max id) is called by
-// lane 0 as soon as a merge is decided.  rec: scratch of n slots.  Returns
-// false (after raising an error) if a step finds no pair.
-template <bool W64, typename St, typename OnMerge>
+// The n - 1 merge steps, run by one wave after upgma_init_best.
+// on_merge(step, min id, max id) is called by lane 0 as soon as a merge is
+// decided and records it (the caller keeps the merge list: with the sums in
+// LDS a step then touches no global memory, so its wave-local fences cost no
+// memory round trip).  rec: scratch of n slots.  Returns false (after raising
+// an error) if a step finds no pair.
+template <bool W64, int UB, typename St, typename OnMerge>
 __device__ bool upgma_steps(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
-                            int32_t* best, int32_t* rec, int32_t* mo, int g, DevStatus* st,
+                            int32_t* best, int32_t* rec, int g, DevStatus* st,
                             OnMerge&& on_merge) {
   const int lane = threadIdx.x & 63;
   for (int step = 0; step < n - 1; ++step) {
     // the best pair is the first of the clusters' best pairs
     WCand c = wc_none();
-    for (int r = lane; r < n; r += 64) {
-      const int b = best[r];
-      if (!active[r] || b < 0) continue;
-      WCand x;
-      x.s = S.get(r, b);
-      x.p = (uint64_t)sz[r] * (uint64_t)sz[b];
-      x.key = pair_key16(id[r], id[b]);
-      x.ab = (uint32_t)min(r, b) | ((uint32_t)max(r, b) << 16);
-      if (wc_better<W64>(x, c)) c = x;
+    uint32_t cab = 0;
+    for (int r0 = lane; r0 < n; r0 += 64 * UB) {
+      int bs[UB];
+      uint64_t sv[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int r = r0 + 64 * u;
+        bs[u] = r < n && active[r] ? best[r] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int r = r0 + 64 * u;
+        sv[u] = bs[u] >= 0 ? S.get(r, bs[u]) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int r = r0 + 64 * u, b = bs[u];
+        if (b < 0) continue;
+        WCand x;
+        x.s = sv[u];
+        x.p = (uint32_t)sz[r] * (uint32_t)sz[b];
+        x.key = pair_key16(id[r], id[b]);
+        if (wc_better<W64>(x, c)) {
+          c = x;
+          cab = (uint32_t)min(r, b) | ((uint32_t)max(r, b) << 16);
+        }
+      }
     }
-    c = wave_first<W64>(c);
-    if (c.key == ~0u) {
+    const WCand w = wave_first<W64>(c);
+    const int src = winner_lane(c, w);
+    if (src < 0) {
       if (lane == 0) raise_error(st, SAD_E_INVAL, g, W_UPGMA);
       return false;
     }
-    const int ba = (int)(c.ab & 0xffffu), bb = (int)(c.ab >> 16);
+    const uint32_t ab = (uint32_t)__builtin_amdgcn_readlane((int)cab, src);
+    const int ba = (int)(ab & 0xffffu), bb = (int)(ab >> 16);
     if (lane == 0) {
       const int ia = id[ba], ib = id[bb];
-      mo[2 * step] = min(ia, ib);
-      mo[2 * step + 1] = max(ia, ib);
       on_merge(step, min(ia, ib), max(ia, ib));
     }
     // S(new, c) = S(a, c) + S(b, c) for the remaining active clusters
-    for (int q = lane; q < n; q += 64) {
-      if (!active[q] || q == ba || q == bb) continue;
-      S.set(ba, q, S.get(ba, q) + S.get(bb, q));
+    for (int q0 = lane; q0 < n; q0 += 64 * UB) {
+      uint64_t va[UB], vb[UB];
+      bool on[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int q = q0 + 64 * u;
+        on[u] = q < n && active[q] && q != ba && q != bb;
+        va[u] = on[u] ? S.get(ba, q) : 0;
+        vb[u] = on[u] ? S.get(bb, q) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u)
+        if (on[u]) S.set(ba, q0 + 64 * u, va[u] + vb[u]);
     }
     wave_sync();
     if (lane == 0) {
@@ -239,32 +294,48 @@ __device__ bool upgma_steps(const St& S, int n, int32_t* id, int32_t* sz, int32_
     // best partners: clusters that pointed at a merged cluster are listed
     // for a rescan, the others compare their best with the union
     int nrec = 0;
-    for (int q0 = 0; q0 < n; q0 += 64) {
-      const int q = q0 + lane;
-      bool again = false;
-      if (q < n && active[q]) {
-        const int b = best[q];
-        if (q == ba || b == ba || b == bb) {
-          again = true;
-        } else {
+    for (int q0 = 0; q0 < n; q0 += 64 * UB) {
+      int bs[UB];
+      bool cmp[UB], again[UB];
+      uint64_t vc[UB], vu[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int q = q0 + 64 * u + lane;
+        const bool on = q < n && active[q];
+        bs[u] = on ? best[q] : -1;
+        again[u] = on && (q == ba || bs[u] == ba || bs[u] == bb);
+        cmp[u] = on && !again[u];
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int q = q0 + 64 * u + lane;
+        vc[u] = cmp[u] ? S.get(q, bs[u]) : 0;
+        vu[u] = cmp[u] ? S.get(q, ba) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int q = q0 + 64 * u + lane;
+        if (cmp[u]) {
+          const int b = bs[u];
           WCand cur, uni;
-          cur.s = S.get(q, b);
-          cur.p = (uint64_t)sz[q] * (uint64_t)sz[b];
+          cur.s = vc[u];
+          cur.p = (uint32_t)sz[q] * (uint32_t)sz[b];
           cur.key = pair_key16(id[q], id[b]);
-          uni.s = S.get(q, ba);
-          uni.p = (uint64_t)sz[q] * (uint64_t)sz[ba];
+          uni.s = vu[u];
+          uni.p = (uint32_t)sz[q] * (uint32_t)sz[ba];
           uni.key = pair_key16(id[q], id[ba]);
           if (wc_better<W64>(uni, cur)) best[q] = ba;
         }
+        // rescans listed in slot order
+        const uint64_t m = __ballot(again[u]);
+        if (again[u]) rec[nrec + (int)__popcll(m & ((1ull << lane) - 1ull))] = q;
+        nrec += (int)__popcll(m);
       }
-      const uint64_t m = __ballot(again);
-      if (again) rec[nrec + (int)__popcll(m & ((1ull << lane) - 1ull))] = q;
-      nrec += (int)__popcll(m);
     }
     wave_sync();
     for (int t = 0; t < nrec; ++t) {
       const int r = rec[t];
-      const int b = wave_best_partner<W64>(S, n, r, id, sz, active);
+      const int b = wave_best_partner<W64, UB>(S, n, r, id, sz, active);
       if (lane == 0) best[r] = b;
     }
     wave_sync();
