@@ -28,6 +28,11 @@ struct DeviceCtx {
   DevStatus* h_st = nullptr;  // pinned host copy
   int64_t* h_small = nullptr; // pinned host scratch for small readbacks
   size_t h_small_cap = 0;
+  // pinned staging of small uploads: copies are queued without a host wait
+  // and the area is reused only after its stream has been synchronised
+  char* up = nullptr;
+  size_t up_cap = 0, up_off = 0;
+  hipStream_t up_stream = nullptr;
   unsigned long long* phase = nullptr;  // engine phase ticks (profiling)
   long long* jobrec = nullptr;          // per-job records (profiling)
   int64_t jobrec_cap = 0;
@@ -110,6 +115,8 @@ static int32_t fail(int32_t code, const std::string& msg) {
       return fail(SAD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
   } while (0)
 
+constexpr size_t kUploadBytes = 1 << 20;
+
 static int32_t get_ctx(DeviceCtx** out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -120,8 +127,22 @@ static int32_t get_ctx(DeviceCtx** out) {
     HIPCHK(hipMalloc(&c.st, sizeof(DevStatus)));
     HIPCHK(hipHostMalloc(&c.h_st, sizeof(DevStatus), hipHostMallocDefault));
   }
+  if (!c.up) {
+    if (hipHostMalloc(&c.up, kUploadBytes, hipHostMallocDefault) == hipSuccess) {
+      c.up_cap = kUploadBytes;
+    } else {
+      c.up = nullptr;  // uploads then wait for their copy
+      c.up_cap = 0;
+    }
+  }
   *out = &c;
   return SAD_OK;
+}
+
+// Called right after stream s has been synchronised: uploads staged for it
+// have completed, so their area can be reused.
+static void uploads_done(DeviceCtx* c, hipStream_t s) {
+  if (c && s == c->up_stream) c->up_off = 0;
 }
 
 static int32_t ensure_host_small(DeviceCtx* c, size_t count) {
@@ -205,6 +226,7 @@ static int32_t reset_status(DeviceCtx* c, hipStream_t s) {
 static int32_t read_status(DeviceCtx* c, hipStream_t s, DevStatus* out) {
   HIPCHK(hipMemcpyAsync(c->h_st, c->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  uploads_done(c, s);
   HIPCHK(hipGetLastError());
   *out = *c->h_st;
   return SAD_OK;
@@ -231,16 +253,38 @@ static int32_t d2h(DeviceCtx* c, const T* dptr, size_t count, std::vector<T>& ou
   if (r) return r;
   HIPCHK(hipMemcpyAsync(c->h_small, dptr, count * sizeof(T), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  uploads_done(c, s);
   out.resize(count);
   std::memcpy(out.data(), c->h_small, count * sizeof(T));
   return SAD_OK;
 }
 
+// Host-to-device copy of a small host array.  Staged in the context's pinned
+// upload area and queued without waiting (the area is reused only after the
+// stream is next synchronised); without room, a plain copy that waits.
 template <class T>
 static int32_t h2d(const std::vector<T>& in, T* dptr, hipStream_t s) {
   if (in.empty()) return SAD_OK;
-  HIPCHK(hipMemcpyAsync(dptr, in.data(), in.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  const size_t bytes = in.size() * sizeof(T);
+  DeviceCtx* c = nullptr;
+  int32_t r = get_ctx(&c);
+  if (r) return r;
+  if (c->up && c->up_off > 0 && s != c->up_stream) {
+    // uploads pending on another stream: let them finish first
+    HIPCHK(hipStreamSynchronize(c->up_stream));
+    c->up_off = 0;
+  }
+  if (c->up && c->up_off + bytes <= c->up_cap) {
+    char* src = c->up + c->up_off;
+    std::memcpy(src, in.data(), bytes);
+    c->up_off += (bytes + 255) & ~size_t(255);
+    c->up_stream = s;
+    HIPCHK(hipMemcpyAsync(dptr, src, bytes, hipMemcpyHostToDevice, s));
+    return SAD_OK;
+  }
+  HIPCHK(hipMemcpyAsync(dptr, in.data(), bytes, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
+  uploads_done(c, s);
   return SAD_OK;
 }
 
@@ -1885,6 +1929,11 @@ extern "C" void sad_release(void) {
     if (c.st) hipFree(c.st);
     if (c.h_st) hipHostFree(c.h_st);
     if (c.h_small) hipHostFree(c.h_small);
+    if (c.up) {
+      // staged uploads may still be queued
+      if (c.up_off > 0) (void)hipStreamSynchronize(c.up_stream);
+      hipHostFree(c.up);
+    }
     if (c.phase) hipFree(c.phase);
     if (c.jobrec) hipFree(c.jobrec);
     for (hipGraphExec_t x : c.gexec)
