@@ -51,6 +51,7 @@ static thread_local std::string g_err;
 // engine-kernel timing (sad_profile_enable / sad_profile_read)
 static bool g_prof_on = false;   // engine kernel timing (HIP events)
 static bool g_phase_on = false;  // per-phase ticks and per-job records
+static bool g_tuning = false;    // sad_tune is timing candidates (no graph capture)
 
 // SAD_LOG=1: one line on stderr per alignment-engine launch (status, expired
 // waits, workspace sizes)
@@ -863,7 +864,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     // the batched launch with its guide trees built inside has no host step
     // between setup and results: it is captured once into a hipGraph and
     // replayed while its arguments (all baked into the graph) are unchanged
-    const bool graphable = fused && !g_phase_on && njobs > 0 && graphs_enabled();
+    const bool graphable = fused && !g_phase_on && !g_tuning && njobs > 0 && graphs_enabled();
     std::vector<unsigned char> gkey;
     if (graphable) {
       EngineArgs ka = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend,
@@ -1267,15 +1268,20 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
   HIPCHK(hipEventCreate(&e1));
   Schedule best{};
   float best_ms = 0.0f;
+  // every candidate runs eagerly (no graph capture while tuning): one warm-up
+  // run, then the fastest of three timed runs counts
+  g_tuning = true;
   for (const Schedule& sc : cand) {
     g_forced = &sc;
     float ms = 0.0f;
-    for (int rep = 0; rep < 2 && r == SAD_OK; ++rep) {
-      HIPCHK(hipEventRecord(e0, stream));
-      r = sad_align_buckets(seqs, d_bucket_off, d_members, prm, out, stream);
-      HIPCHK(hipEventRecord(e1, stream));
-      HIPCHK(hipEventSynchronize(e1));
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));  // the second (warm) run counts
+    for (int rep = 0; rep < 4 && r == SAD_OK; ++rep) {
+      float t = 0.0f;
+      if (hipEventRecord(e0, stream) != hipSuccess) r = fail(SAD_E_DEVICE, "event record");
+      if (!r) r = sad_align_buckets(seqs, d_bucket_off, d_members, prm, out, stream);
+      if (!r && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                 hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        r = fail(SAD_E_DEVICE, "event timing");
+      if (!r && rep > 0 && (rep == 1 || t < ms)) ms = t;
     }
     g_forced = nullptr;
     if (r) break;
@@ -1284,6 +1290,7 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
       best = sc;
     }
   }
+  g_tuning = false;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (r) return r;
