@@ -162,38 +162,49 @@ __device__ inline int32_t wave_sum32(int32_t v) {
   return v;
 }
 
-// c between the histogram's row and two column sequences c0 and c1 (wave-
-// wide; c1 < 0: none).  Four entries per lane and column are loaded before
-// any is used, so a pair of lists of up to 256 entries costs one round trip.
-// Lanes past a list's end read the entry 0 (count 0, adds nothing).
-__device__ inline void wave_common2(const uint16_t* hist, const KmerLists& kl, int c0, int c1,
-                                    int32_t& r0, int32_t& r1) {
-  const uint32_t* e0 = kl.entries + kl.off[c0];
-  const int n0 = kl.nu[c0];
-  const uint32_t* e1 = c1 >= 0 ? kl.entries + kl.off[c1] : e0;
-  const int n1 = c1 >= 0 ? kl.nu[c1] : 0;
-  const int lane = threadIdx.x & 63;
-  const int nmax = n0 > n1 ? n0 : n1;
-  int32_t a0 = 0, a1 = 0;
-  for (int t0 = 0; t0 < nmax; t0 += 256) {
-    uint32_t v0[4], v1[4];
+// c between the histogram's row and NC column sequences cs[0..NC) (wave-wide;
+// cs[q] < 0: none).  Four entries per lane and column are loaded before any
+// is used, so NC lists of up to 256 entries cost one round trip.  Lanes past
+// a list's end read the entry 0 (count 0, adds nothing).
+template <int NC>
+__device__ inline void wave_common_n(const uint16_t* hist, const KmerLists& kl, const int* cs,
+                                     int32_t* res) {
+  const uint32_t* e[NC];
+  int nl[NC];
+  int nmax = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = t0 + 64 * u + lane;
-      v0[u] = t < n0 ? e0[t] : 0u;
-      v1[u] = t < n1 ? e1[t] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t h0 = hist[v0[u] >> 16], h1 = hist[v1[u] >> 16];
-      const uint32_t k0 = v0[u] & 0xffffu, k1 = v1[u] & 0xffffu;
-      a0 += (int32_t)(k0 < h0 ? k0 : h0);
-      a1 += (int32_t)(k1 < h1 ? k1 : h1);
-    }
+  for (int q = 0; q < NC; ++q) {
+    e[q] = kl.entries + kl.off[cs[q] >= 0 ? cs[q] : cs[0]];
+    nl[q] = cs[q] >= 0 ? kl.nu[cs[q]] : 0;
+    nmax = nl[q] > nmax ? nl[q] : nmax;
   }
-  r0 = wave_sum32(a0);
-  r1 = wave_sum32(a1);
+  const int lane = threadIdx.x & 63;
+  int32_t acc[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) acc[q] = 0;
+  for (int t0 = 0; t0 < nmax; t0 += 256) {
+    uint32_t v[NC][4];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + 64 * u + lane;
+        v[q][u] = t < nl[q] ? e[q][t] : 0u;
+      }
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t h = hist[v[q][u] >> 16], k = v[q][u] & 0xffffu;
+        acc[q] += (int32_t)(k < h ? k : h);
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) res[q] = wave_sum32(acc[q]);
 }
+
+// columns per wave pass in the pair-sum kernels
+constexpr int kPairCols = 4;
 
 __device__ inline int64_t seq_len(const KmerLists& kl, int i) {
   return kl.seq_off[i + 1] - kl.seq_off[i];
@@ -228,12 +239,15 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_chunk_kernel(KmerLists kl
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t Lr = seq_len(kl, r);
   uint64_t part = 0;
-  for (int j = lo + wave; j < hi; j += 2 * nw) {
-    const int j2 = j + nw < hi ? j + nw : -1;
-    int32_t c0, c1;
-    wave_common2(hist, kl, j, j2, c0, c1);
-    part += fhat_of(c0, Lr, seq_len(kl, j), k);
-    if (j2 >= 0) part += fhat_of(c1, Lr, seq_len(kl, j2), k);
+  for (int j = lo + wave; j < hi; j += kPairCols * nw) {
+    int cs[kPairCols];
+    int32_t cc[kPairCols];
+#pragma unroll
+    for (int q = 0; q < kPairCols; ++q) cs[q] = j + q * nw < hi ? j + q * nw : -1;
+    wave_common_n<kPairCols>(hist, kl, cs, cc);
+#pragma unroll
+    for (int q = 0; q < kPairCols; ++q)
+      if (cs[q] >= 0) part += fhat_of(cc[q], Lr, seq_len(kl, cs[q]), k);
   }
   uint64_t s = block_sum_waves(part, red);
   if (threadIdx.x == 0) out[r] = s;
@@ -256,23 +270,34 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl,
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t Lr = seq_len(kl, r);
   uint64_t part = 0;
-  for (int q = wave; q < ncols; q += 2 * nw) {
-    int j = cols ? cols[q] : q;
-    int j2 = q + nw < ncols ? (cols ? cols[q + nw] : q + nw) : -1;
-    if (j < 0 || j >= n || j2 < -1 || j2 >= n) {
-      if (r == 0 && (threadIdx.x & 63) == 0) raise_error(st, SAD_E_INVAL, q, W_RANK);
-      if (j < 0 || j >= n) j = -1;
-      if (j2 < -1 || j2 >= n) j2 = -1;
+  for (int q0 = wave; q0 < ncols; q0 += kPairCols * nw) {
+    int cs[kPairCols];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < kPairCols; ++q) {
+      const int qq = q0 + q * nw;
+      int j = qq < ncols ? (cols ? cols[qq] : qq) : -1;
+      if (qq < ncols && (j < 0 || j >= n)) {
+        if (r == 0 && (threadIdx.x & 63) == 0) raise_error(st, SAD_E_INVAL, qq, W_RANK);
+        j = -1;
+      }
+      cs[q] = j;
+      any = any || j >= 0;
     }
-    if (j < 0) {  // only the second column (if any) counts
-      j = j2;
-      j2 = -1;
-      if (j < 0) continue;
-    }
-    int32_t c0, c1;
-    wave_common2(hist, kl, j, j2, c0, c1);
-    part += fhat_of(c0, Lr, seq_len(kl, j), k);
-    if (j2 >= 0) part += fhat_of(c1, Lr, seq_len(kl, j2), k);
+    if (!any) continue;
+    // the first listed column must be valid (it names the stand-in list)
+    if (cs[0] < 0)
+#pragma unroll
+      for (int q = 1; q < kPairCols; ++q)
+        if (cs[0] < 0 && cs[q] >= 0) {
+          cs[0] = cs[q];
+          cs[q] = -1;
+        }
+    int32_t cc[kPairCols];
+    wave_common_n<kPairCols>(hist, kl, cs, cc);
+#pragma unroll
+    for (int q = 0; q < kPairCols; ++q)
+      if (cs[q] >= 0) part += fhat_of(cc[q], Lr, seq_len(kl, cs[q]), k);
   }
   uint64_t s = block_sum_waves(part, red);
   if (threadIdx.x == 0) out[r] = s;
@@ -307,15 +332,16 @@ __global__ __launch_bounds__(kPairThreads) void fmatrix_kernel(KmerLists kl,
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t Lr = seq_len(kl, r);
   uint32_t* Frow = F + fm_off[g] + (int64_t)a * ng;
-  for (int b = wave; b < ng; b += 2 * nw) {
-    const int j = ids[g0 + b];
-    const int j2 = b + nw < ng ? ids[g0 + b + nw] : -1;
-    int32_t c0, c1;
-    wave_common2(hist, kl, j, j2, c0, c1);
-    if ((threadIdx.x & 63) == 0) {
-      Frow[b] = fhat_of(c0, Lr, seq_len(kl, j), k);
-      if (j2 >= 0) Frow[b + nw] = fhat_of(c1, Lr, seq_len(kl, j2), k);
-    }
+  for (int b = wave; b < ng; b += kPairCols * nw) {
+    int cs[kPairCols];
+    int32_t cc[kPairCols];
+#pragma unroll
+    for (int q = 0; q < kPairCols; ++q) cs[q] = b + q * nw < ng ? ids[g0 + b + q * nw] : -1;
+    wave_common_n<kPairCols>(hist, kl, cs, cc);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int q = 0; q < kPairCols; ++q)
+        if (cs[q] >= 0) Frow[b + q * nw] = fhat_of(cc[q], Lr, seq_len(kl, cs[q]), k);
   }
 }
 

@@ -70,6 +70,16 @@ def test_listed_sample_matches_kmer_rank(hip):
     assert np.array_equal(got, oracle.rank_against(d.codes, d.offsets, 4, 6, samples=smp))
 
 
+def test_central_rank_dna_k8(hip):
+    """k = 8 on DNA: a 4^8-entry (128 KB) histogram per row in LDS."""
+    B, pipeline, torch = hip
+    _say("case central rank DNA k=8")
+    d = generate(8080, 240, 4, 3, {"kind": "uniform_int", "lo": 300, "hi": 700}, 0.05, 0.01, 8)
+    seqs = pipeline.to_device(d.codes, d.offsets, d.alphabet)
+    got = B.sad_rank_against(seqs, 8).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, oracle.rank_against(d.codes, d.offsets, 4, 8))
+
+
 def test_rank_against_errors(hip):
     B, pipeline, torch = hip
     _say("case rank against errors")
