@@ -247,6 +247,34 @@ static int32_t finish(DeviceCtx* c, hipStream_t s) {
   return status_to_code(d);
 }
 
+// finish() and up to two small device-to-host reads in one synchronisation:
+// the reads are taken whatever the status, and returned only when it is OK.
+template <class T1, class T2 = int32_t>
+static int32_t finish_read(DeviceCtx* c, hipStream_t s, const T1* d1, size_t n1,
+                           std::vector<T1>& o1, const T2* d2 = nullptr, size_t n2 = 0,
+                           std::vector<T2>* o2 = nullptr) {
+  const size_t b1 = n1 * sizeof(T1), b2 = d2 ? n2 * sizeof(T2) : 0;
+  const size_t off2 = (b1 + 15) & ~size_t(15);
+  int32_t r = ensure_host_small(c, (off2 + b2) / 8 + 2);
+  if (r) return r;
+  char* h = reinterpret_cast<char*>(c->h_small);
+  HIPCHK(hipMemcpyAsync(c->h_st, c->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  if (b1) HIPCHK(hipMemcpyAsync(h, d1, b1, hipMemcpyDeviceToHost, s));
+  if (b2) HIPCHK(hipMemcpyAsync(h + off2, d2, b2, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  uploads_done(c, s);
+  HIPCHK(hipGetLastError());
+  const DevStatus d = *c->h_st;
+  if (d.code) return status_to_code(d);
+  o1.resize(n1);
+  if (b1) std::memcpy(o1.data(), h, b1);
+  if (o2) {
+    o2->resize(n2);
+    if (b2) std::memcpy(o2->data(), h + off2, b2);
+  }
+  return SAD_OK;
+}
+
 template <class T>
 static int32_t d2h(DeviceCtx* c, const T* dptr, size_t count, std::vector<T>& out, hipStream_t s) {
   size_t words = (count * sizeof(T) + 7) / 8;
@@ -333,6 +361,19 @@ static int32_t validate_on_device(DeviceCtx* c, const sad_seqs* s, int k, hipStr
   if (r) return r;
   launch_validate(*s, k, c->st, stream);
   return finish(c, stream);
+}
+
+// The same validation, with up to two small reads of caller arrays in the
+// same synchronisation (for calls whose next step is to read them).
+template <class T1, class T2 = int32_t>
+static int32_t validate_read(DeviceCtx* c, const sad_seqs* s, int k, hipStream_t stream,
+                             const T1* d1, size_t n1, std::vector<T1>& o1,
+                             const T2* d2 = nullptr, size_t n2 = 0,
+                             std::vector<T2>* o2 = nullptr) {
+  int32_t r = reset_status(c, stream);
+  if (r) return r;
+  launch_validate(*s, k, c->st, stream);
+  return finish_read(c, stream, d1, n1, o1, d2, n2, o2);
 }
 
 static void chunk_sizes(int n, int p, int* w_min) {
@@ -1160,10 +1201,8 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   DeviceCtx* c = nullptr;
   r = get_ctx(&c);
   if (r) return r;
-  r = validate_on_device(c, seqs, k, stream);
-  if (r) return r;
   std::vector<int32_t> off;
-  r = d2h(c, d_bucket_off, (size_t)p + 1, off, stream);
+  r = validate_read(c, seqs, k, stream, d_bucket_off, (size_t)p + 1, off);
   if (r) return r;
   if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
   int64_t fm_total = 0;
@@ -1375,12 +1414,9 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
   DeviceCtx* c = nullptr;
   r = get_ctx(&c);
   if (r) return r;
-  r = validate_on_device(c, seqs, k, stream);
-  if (r) return r;
   std::vector<int32_t> off, wid;
-  r = d2h(c, d_bucket_off, (size_t)p + 1, off, stream);
-  if (r) return r;
-  r = d2h(c, buckets->d_width, (size_t)p, wid, stream);
+  r = validate_read(c, seqs, k, stream, d_bucket_off, (size_t)p + 1, off,
+                    (const int32_t*)buckets->d_width, (size_t)p, &wid);
   if (r) return r;
   if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
 
@@ -1477,16 +1513,14 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
   launch_consensus(cons_list, q, cnode_W, cnode_n, cnode_prof, prof16, A, anc_stage, stage_off,
                    anc_len, stream);
   launch_compact(anc_stage, stage_off, anc_len, q, anc_off, anc_codes, stream);
-  r = finish(c, stream);
-  if (r) return r;
   std::vector<int64_t> h_anc_off;
-  r = d2h(c, anc_off, (size_t)q + 1, h_anc_off, stream);
+  r = finish_read(c, stream, anc_off, (size_t)q + 1, h_anc_off);
   if (r) return r;
   int max_anc = 0;
   for (int u = 0; u < q; ++u) max_anc = std::max<int>(max_anc, (int)(h_anc_off[u + 1] - h_anc_off[u]));
 
-  // ---- global ancestor
-  int GL = 0;
+  // ---- global ancestor (and the width of the ancestors' alignment)
+  int GL = 0, TLq = 0;
   if (q == 1) {
     GL = (int)h_anc_off[1];
     HIPCHK(hipMemcpyAsync(ga_stage, anc_codes, (size_t)std::max(GL, 0), hipMemcpyDeviceToDevice,
@@ -1542,12 +1576,12 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
                                Wt1 * A, tl_d, c->st, stream);
     launch_consensus(ga_list, 1, e.node_W, e.node_n, e.node_prof, e.prof_pool, A, ga_stage,
                      ga_off0, ga_len_d, stream);
-    r = finish(c, stream);
-    if (r) return r;
-    std::vector<int32_t> gl;
-    r = d2h(c, ga_len_d, 1, gl, stream);
+    std::vector<int32_t> gl, tl;
+    r = finish_read(c, stream, ga_len_d, 1, gl, (const int32_t*)tl_d, msa_tmpl ? 1 : 0,
+                    msa_tmpl ? &tl : nullptr);
     if (r) return r;
     GL = gl[0];
+    if (msa_tmpl) TLq = tl[0];
   }
   *ga_len = GL;
   if (GL > ga_cap) return fail(SAD_E_CAPACITY, "GA capacity too small");
@@ -1556,10 +1590,7 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
   // the template: GA as one row, or the ancestors' alignment (TL columns, q rows)
   int TL = GL, tn = 1;
   if (msa_tmpl) {
-    std::vector<int32_t> tl;
-    r = d2h(c, tl_d, 1, tl, stream);
-    if (r) return r;
-    TL = tl[0];
+    TL = TLq;
     tn = q;
     if (TL > kMaxWidth) return fail(SAD_E_CAPACITY, "template wider than the library limit");
   }
@@ -1691,11 +1722,9 @@ extern "C" int32_t sad_refine_tree(const sad_seqs* seqs, const int32_t* d_bucket
   DeviceCtx* c = nullptr;
   r = get_ctx(&c);
   if (r) return r;
-  r = validate_on_device(c, seqs, prm->kmer_k, stream);
-  if (r) return r;
   std::vector<int32_t> off, wv;
-  r = d2h(c, d_bucket_off, (size_t)p + 1, off, stream);
-  if (!r) r = d2h(c, glued->d_width, 1, wv, stream);
+  r = validate_read(c, seqs, prm->kmer_k, stream, d_bucket_off, (size_t)p + 1, off,
+                    (const int32_t*)glued->d_width, (size_t)1, &wv);
   if (r) return r;
   if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
   std::vector<int32_t> uidx(p, -1), size_u;
