@@ -837,11 +837,8 @@ static int32_t plan_priority(const TreeSet& ts, const int32_t* d_merges, const E
   }
   std::stable_sort(ready.begin(), ready.end(),
                    [&](int a, int b) { return path[a] > path[b]; });
-  if (!ready.empty())
-    HIPCHK(hipMemcpyAsync(e.queue, ready.data(), ready.size() * sizeof(int32_t),
-                          hipMemcpyHostToDevice, stream));
-  HIPCHK(hipStreamSynchronize(stream));
-  return SAD_OK;
+  // queued through the pinned upload area: no wait here
+  return h2d(ready, e.queue, stream);
 }
 
 static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
