@@ -1128,12 +1128,32 @@ __device__ __forceinline__ int traceback(Src& src, uint8_t* ops, int W1, int W2,
     // the window's cells outside the strip or left of column 1 are never
     // reached: at most l + 1 row steps and j column steps
     const int n = min(kWindowOps, min(l + 1, j));
+    // the window's states are collected in a scalar, 3 bits per op, and
+    // appended to acc once: its lanes move down by n and lanes 64 - n .. 63
+    // take the n new states (the newest in lane 63)
     int idx = 0;
-    for (int r = 0; r < n; ++r) {
+    uint32_t packed = 0;
+    auto walk = [&](int r) {
       const uint32_t tab = (uint32_t)__builtin_amdgcn_readlane(v, idx);
       sg = (int)((tab >> (4 * sg)) & 7u);
       idx += (int)((kWindowStep >> (4 * sg)) & 15u);
-      acc = __builtin_amdgcn_update_dpp(sg, acc, 0x130, 0xf, 0xf, false);
+      packed |= (uint32_t)sg << (3 * r);
+    };
+    if (n == kWindowOps) {
+      // a full window (the common case) needs no per-op count test
+#pragma unroll
+      for (int r = 0; r < kWindowOps; ++r) walk(r);
+    } else {
+#pragma unroll
+      for (int r = 0; r < kWindowOps; ++r) {
+        if (r >= n) break;
+        walk(r);
+      }
+    }
+    {
+      const int32_t moved = __builtin_amdgcn_ds_bpermute(min(lane + n, 63) << 2, acc);
+      const int rr = lane - (64 - n);
+      acc = rr >= 0 ? (int32_t)((packed >> (3 * rr)) & 7u) : moved;
     }
     k += n;
     i -= idx >> 3;
