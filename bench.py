@@ -195,8 +195,9 @@ def rank_study(args, B, pipeline, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU and this benchmark measures one GPU "
+              f"only (asked for --gpus {args.gpus}); sharding across GPUs is not implemented",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

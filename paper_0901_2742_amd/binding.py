@@ -268,7 +268,9 @@ def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor
     if out is None:
         out = _msa_tensors(seqs.total_len, 1, 2 * prm.p, dev)
     if ga_cap is None:
-        ga_cap = max(int(buckets["width"][:prm.p].sum().item()), 1)
+        # GA is no longer than the sum of the ancestors, each no longer than its
+        # bucket's width, which is at most the bucket's residue count
+        ga_cap = max(seqs.total_len, 1)
     ga = out.get("ga")
     if ga is None or ga.numel() < ga_cap:
         ga = torch.empty(max(ga_cap, 1), dtype=torch.uint8, device=dev)
