@@ -10,7 +10,7 @@
 // merged ones are rescanned, the others compare their best with the union.
 //
 // The steps run on one wave: a step is a few wave-wide reductions (DPP within
-// rows, two swizzles across them) with no workgroup barrier.  While a group
+// rows, row broadcasts across them) with no workgroup barrier.  While a group
 // has at most kUpgmaW64MaxN members the cross products fit 64 bits: a pair
 // sum is at most |A| |B| 2^31 with |A| |B| <= n^2 / 4, so s1 p2 < 2^64 when
 // n^4 / 16 * 2^31 < 2^64, i.e. n < 608.  Larger groups compare 128-bit
@@ -42,29 +42,23 @@ __device__ inline uint32_t pair_key16(int ia, int ib) {
   return ((uint32_t)min(ia, ib) << 16) | (uint32_t)max(ia, ib);
 }
 
-// sign of s1 p2 - s2 p1 (64 x 32-bit products)
-template <bool W64>
-__device__ inline int cmp_avg(uint64_t s1, uint32_t p1, uint64_t s2, uint32_t p2) {
-  if constexpr (W64) {
-    const uint64_t l = s1 * (uint64_t)p2, r = s2 * (uint64_t)p1;
-    return l > r ? 1 : (l < r ? -1 : 0);
-  } else {
-    const uint64_t lo1 = s1 * (uint64_t)p2, hi1 = __umul64hi(s1, (uint64_t)p2);
-    const uint64_t lo2 = s2 * (uint64_t)p1, hi2 = __umul64hi(s2, (uint64_t)p1);
-    if (hi1 != hi2) return hi1 > hi2 ? 1 : -1;
-    if (lo1 != lo2) return lo1 > lo2 ? 1 : -1;
-    return 0;
-  }
-}
-
-// x comes before y in the merge order
+// x comes before y in the merge order: the larger average s / p (compared by
+// the cross products x.s y.p and y.s x.p, 64 x 32 bits), then the smaller
+// key.  "No candidate" (s 0, p 1, key all ones) comes after every pair under
+// this same order (a pair's key is below all ones and its average is at least
+// 0), so it needs no test of its own.  Both comparisons are evaluated in every
+// lane and combined without branches.
 template <bool W64>
 __device__ inline bool wc_better(const WCand& x, const WCand& y) {
-  if (x.key == ~0u) return false;
-  if (y.key == ~0u) return true;
-  const int c = cmp_avg<W64>(x.s, x.p, y.s, y.p);
-  if (c != 0) return c > 0;
-  return x.key < y.key;
+  const bool key_first = x.key < y.key;
+  if constexpr (W64) {
+    const uint64_t l = x.s * (uint64_t)y.p, r = y.s * (uint64_t)x.p;
+    return (l > r) | ((l == r) & key_first);
+  } else {
+    const uint64_t lo1 = x.s * (uint64_t)y.p, hi1 = __umul64hi(x.s, (uint64_t)y.p);
+    const uint64_t lo2 = y.s * (uint64_t)x.p, hi2 = __umul64hi(y.s, (uint64_t)x.p);
+    return (hi1 > hi2) | ((hi1 == hi2) & ((lo1 > lo2) | ((lo1 == lo2) & key_first)));
+  }
 }
 
 __device__ inline WCand wc_none() {
@@ -75,43 +69,44 @@ __device__ inline WCand wc_none() {
   return c;
 }
 
-// First lane whose own candidate `mine` is the wave's winner `w` (-1 if none).
-__device__ inline int winner_lane(const WCand& mine, const WCand& w) {
-  const uint64_t m = __ballot(w.key != ~0u && mine.key == w.key);
+// First lane whose own candidate has the wave's winning key wk (-1 if none).
+__device__ inline int winner_lane(uint32_t mine_key, uint32_t wk) {
+  const uint64_t m = __ballot(wk != ~0u && mine_key == wk);
   return m ? __ffsll((unsigned long long)m) - 1 : -1;
 }
 
-template <int CTRL>
+// A lane's candidate moved by a DPP pattern; rows outside ROWS keep their own
+// (with every row written, no lane keeps its old value: a plain DPP move).
+template <int CTRL, int ROWS = 0xf>
 __device__ inline uint32_t dpp32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+  if constexpr (ROWS == 0xf)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, false);
+  else
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROWS, 0xf, false);
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xf>
 __device__ inline uint64_t dpp64(uint64_t v) {
-  return (uint64_t)dpp32<CTRL>((uint32_t)v) | ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32);
+  return (uint64_t)dpp32<CTRL, ROWS>((uint32_t)v) |
+         ((uint64_t)dpp32<CTRL, ROWS>((uint32_t)(v >> 32)) << 32);
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xf>
 __device__ inline WCand wc_dpp(const WCand& c) {
   WCand x;
-  x.s = dpp64<CTRL>(c.s);
-  x.p = dpp32<CTRL>(c.p);
-  x.key = dpp32<CTRL>(c.key);
-  return x;
-}
-__device__ inline WCand wc_xor(const WCand& c, int m) {
-  WCand x;
-  x.s = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)c.s, m, 64) |
-        ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(c.s >> 32), m, 64) << 32);
-  x.p = (uint32_t)__shfl_xor((int)c.p, m, 64);
-  x.key = (uint32_t)__shfl_xor((int)c.key, m, 64);
+  x.s = dpp64<CTRL, ROWS>(c.s);
+  x.p = dpp32<CTRL, ROWS>(c.p);
+  x.key = dpp32<CTRL, ROWS>(c.key);
   return x;
 }
 
-// The first candidate of the wave in the merge order, in every lane (all 64
-// lanes active).  Pairings: lanes ^1 and ^2 within a quad, the mirrored quad
-// of each half row, the mirrored half of each row, then rows ^16 and ^32;
-// after each stage every lane of the group holds the group's first.
+// The key of the wave's first candidate in the merge order (all ones if no
+// lane has one), wave-uniform; all 64 lanes active.  Within each row of 16
+// lanes: lanes ^1 and ^2 of a quad, the mirrored quad of each half row, the
+// mirrored half of the row (after each stage every lane of the group holds
+// the group's first).  Across rows, by row broadcasts: lane 15 of rows 0 and
+// 2 into rows 1 and 3, then lane 31 into rows 2 and 3, which leaves the
+// wave's first in lane 63.
 template <bool W64>
-__device__ inline WCand wave_first(WCand c) {
+__device__ inline uint32_t wave_first_key(WCand c) {
   WCand x;
   x = wc_dpp<0xB1>(c);  // quad_perm [1, 0, 3, 2]
   if (wc_better<W64>(x, c)) c = x;
@@ -121,11 +116,11 @@ __device__ inline WCand wave_first(WCand c) {
   if (wc_better<W64>(x, c)) c = x;
   x = wc_dpp<0x140>(c);  // row_mirror
   if (wc_better<W64>(x, c)) c = x;
-  x = wc_xor(c, 16);
+  x = wc_dpp<0x142, 0xa>(c);  // row_bcast:15 into rows 1 and 3
   if (wc_better<W64>(x, c)) c = x;
-  x = wc_xor(c, 32);
+  x = wc_dpp<0x143, 0xc>(c);  // row_bcast:31 into rows 2 and 3
   if (wc_better<W64>(x, c)) c = x;
-  return c;
+  return (uint32_t)__builtin_amdgcn_readlane((int)c.key, 63);
 }
 
 // Pair sums in LDS: upper triangle, a < b at a n - a (a + 1) / 2 + b - a - 1.
@@ -198,8 +193,7 @@ __device__ inline int wave_best_partner(const St& S, int n, int r, const int32_t
       }
     }
   }
-  const WCand w = wave_first<W64>(c);
-  const int src = winner_lane(c, w);
+  const int src = winner_lane(c.key, wave_first_key<W64>(c));
   return src < 0 ? -1 : __builtin_amdgcn_readlane(cb, src);
 }
 
@@ -256,8 +250,7 @@ __device__ bool upgma_steps(const St& S, int n, int32_t* id, int32_t* sz, int32_
         }
       }
     }
-    const WCand w = wave_first<W64>(c);
-    const int src = winner_lane(c, w);
+    const int src = winner_lane(c.key, wave_first_key<W64>(c));
     if (src < 0) {
       if (lane == 0) raise_error(st, SAD_E_INVAL, g, W_UPGMA);
       return false;
