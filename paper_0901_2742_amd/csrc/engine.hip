@@ -1356,7 +1356,7 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
   __syncthreads();
   // (groups here are below kUpgmaW64MaxN: 64-bit cross products are exact)
   const TriS S{tri, n};
-  upgma_init_best<true, 1>(S, n, id, sz, active, best);
+  upgma_init_best<true>(S, n, id, sz, active, best);
   __syncthreads();
   if (wave == 0) {
     // the merge steps; each decided merge is listed for wave 1

@@ -14,7 +14,7 @@ template <bool W64, typename St>
 __device__ inline void upgma_run(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
                                  int32_t* best, int32_t* rec, int32_t* ml, int32_t* mo, int g,
                                  DevStatus* st) {
-  upgma_init_best<W64, 4>(S, n, id, sz, active, best);
+  upgma_init_best<W64>(S, n, id, sz, active, best);
   __syncthreads();
   if ((threadIdx.x >> 6) == 0) {
     int32_t* dst = ml ? ml : mo;

@@ -98,29 +98,40 @@ __device__ inline WCand wc_dpp(const WCand& c) {
   return x;
 }
 
-// The key of the wave's first candidate in the merge order (all ones if no
-// lane has one), wave-uniform; all 64 lanes active.  Within each row of 16
-// lanes: lanes ^1 and ^2 of a quad, the mirrored quad of each half row, the
-// mirrored half of the row (after each stage every lane of the group holds
-// the group's first).  Across rows, by row broadcasts: lane 15 of rows 0 and
-// 2 into rows 1 and 3, then lane 31 into rows 2 and 3, which leaves the
-// wave's first in lane 63.
+// The keys of the wave's first candidates in the merge order of RB
+// independent reductions (all ones where no lane has one), wave-uniform; all
+// 64 lanes active.  Within each row of 16 lanes: lanes ^1 and ^2 of a quad,
+// the mirrored quad of each half row, the mirrored half of the row (after
+// each stage every lane of the group holds the group's first).  Across rows,
+// by row broadcasts: lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31
+// into rows 2 and 3, which leaves the wave's first in lane 63.  The RB
+// reductions advance stage by stage together, so that their dependency chains
+// overlap.
+template <int CTRL, int ROWS, bool W64, int RB>
+__device__ inline void wc_stage(WCand (&c)[RB]) {
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const WCand x = wc_dpp<CTRL, ROWS>(c[j]);
+    if (wc_better<W64>(x, c[j])) c[j] = x;
+  }
+}
+template <bool W64, int RB>
+__device__ inline void wave_first_keys(WCand (&c)[RB], uint32_t (&wk)[RB]) {
+  wc_stage<0xB1, 0xf, W64>(c);   // quad_perm [1, 0, 3, 2]
+  wc_stage<0x4E, 0xf, W64>(c);   // quad_perm [2, 3, 0, 1]
+  wc_stage<0x141, 0xf, W64>(c);  // row_half_mirror
+  wc_stage<0x140, 0xf, W64>(c);  // row_mirror
+  wc_stage<0x142, 0xa, W64>(c);  // row_bcast:15 into rows 1 and 3
+  wc_stage<0x143, 0xc, W64>(c);  // row_bcast:31 into rows 2 and 3
+#pragma unroll
+  for (int j = 0; j < RB; ++j) wk[j] = (uint32_t)__builtin_amdgcn_readlane((int)c[j].key, 63);
+}
 template <bool W64>
-__device__ inline uint32_t wave_first_key(WCand c) {
-  WCand x;
-  x = wc_dpp<0xB1>(c);  // quad_perm [1, 0, 3, 2]
-  if (wc_better<W64>(x, c)) c = x;
-  x = wc_dpp<0x4E>(c);  // quad_perm [2, 3, 0, 1]
-  if (wc_better<W64>(x, c)) c = x;
-  x = wc_dpp<0x141>(c);  // row_half_mirror
-  if (wc_better<W64>(x, c)) c = x;
-  x = wc_dpp<0x140>(c);  // row_mirror
-  if (wc_better<W64>(x, c)) c = x;
-  x = wc_dpp<0x142, 0xa>(c);  // row_bcast:15 into rows 1 and 3
-  if (wc_better<W64>(x, c)) c = x;
-  x = wc_dpp<0x143, 0xc>(c);  // row_bcast:31 into rows 2 and 3
-  if (wc_better<W64>(x, c)) c = x;
-  return (uint32_t)__builtin_amdgcn_readlane((int)c.key, 63);
+__device__ inline uint32_t wave_first_key(const WCand& c) {
+  WCand cc[1] = {c};
+  uint32_t wk[1];
+  wave_first_keys<W64, 1>(cc, wk);
+  return wk[0];
 }
 
 // Pair sums in LDS: upper triangle, a < b at a n - a (a + 1) / 2 + b - a - 1.
@@ -158,53 +169,113 @@ __device__ inline void wave_sync() {
 // The step loops take UB slots per lane at a time and load all their pair
 // sums before using any (with the sums in global memory each load is a round
 // trip: the standalone kernel uses UB = 4; the engine's tree phase, sums in
-// LDS, uses 1).  A slot that is out of range or the row itself reads a valid
-// stand-in pair whose value is ignored.
+// LDS, uses 1); the best-partner scans get the same effect from scanning
+// several rows at once.  A slot that is out of range or the row itself reads
+// a valid stand-in pair whose value is ignored.
 
 __device__ inline int other_slot(int r) { return r == 0 ? 1 : 0; }
 
-// Best partner of slot r among the active slots (whole wave; -1 if none).
-template <bool W64, int UB, typename St>
-__device__ inline int wave_best_partner(const St& S, int n, int r, const int32_t* id,
-                                        const int32_t* sz, const int32_t* active) {
+// Best partners of the slots r[0..RB) among the active slots (whole wave; -1
+// where none).  The rows share the loads of the slot arrays; their pair sums
+// are all loaded before any is used, and their reductions run together.
+template <bool W64, int RB, typename St>
+__device__ inline void wave_best_partners(const St& S, int n, const int (&r)[RB],
+                                          const int32_t* id, const int32_t* sz,
+                                          const int32_t* active, int (&out)[RB]) {
   const int lane = threadIdx.x & 63;
-  WCand c = wc_none();
-  int cb = -1;
-  const uint32_t sr = (uint32_t)sz[r];
-  const int ir = id[r];
-  for (int b0 = lane; b0 < n; b0 += 64 * UB) {
-    uint64_t sv[UB];
+  WCand c[RB];
+  int cb[RB], ir[RB];
+  uint32_t sr[RB];
 #pragma unroll
-    for (int u = 0; u < UB; ++u) {
-      const int b = b0 + 64 * u;
-      sv[u] = S.get(r, (b < n && b != r) ? b : other_slot(r));
-    }
+  for (int j = 0; j < RB; ++j) {
+    c[j] = wc_none();
+    cb[j] = -1;
+    sr[j] = (uint32_t)sz[r[j]];
+    ir[j] = id[r[j]];
+  }
+  for (int b = lane; b < n; b += 64) {
+    uint64_t sv[RB];
 #pragma unroll
-    for (int u = 0; u < UB; ++u) {
-      const int b = b0 + 64 * u;
-      if (b >= n || b == r || !active[b]) continue;
+    for (int j = 0; j < RB; ++j) sv[j] = S.get(r[j], b != r[j] ? b : other_slot(r[j]));
+    const bool on = active[b] != 0;
+    const uint32_t zb = (uint32_t)sz[b];
+    const int ib = id[b];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      if (!on || b == r[j]) continue;
       WCand x;
-      x.s = sv[u];
-      x.p = sr * (uint32_t)sz[b];
-      x.key = pair_key16(ir, id[b]);
-      if (wc_better<W64>(x, c)) {
-        c = x;
-        cb = b;
+      x.s = sv[j];
+      x.p = sr[j] * zb;
+      x.key = pair_key16(ir[j], ib);
+      if (wc_better<W64>(x, c[j])) {
+        c[j] = x;
+        cb[j] = b;
       }
     }
   }
-  const int src = winner_lane(c.key, wave_first_key<W64>(c));
-  return src < 0 ? -1 : __builtin_amdgcn_readlane(cb, src);
+  uint32_t mine[RB], wk[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) mine[j] = c[j].key;
+  wave_first_keys<W64, RB>(c, wk);
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const int src = winner_lane(mine[j], wk[j]);
+    out[j] = src < 0 ? -1 : __builtin_amdgcn_readlane(cb[j], src);
+  }
 }
 
-// Best partners of every slot (the whole workgroup, kUpgmaWaves waves).
-template <bool W64, int UB, typename St>
+// Rows per batch of best-partner scans.
+constexpr int kScanBatch = 4;
+
+// Best partners of the slots rows[0..m) (whole wave), written to best[] by
+// lane 0: batches of up to kScanBatch rows (a short last batch runs as 2 or
+// 1 rows).
+template <bool W64, typename St>
+__device__ inline void scan_rows(const St& S, int n, const int32_t* rows, int m,
+                                 const int32_t* id, const int32_t* sz, const int32_t* active,
+                                 int32_t* best) {
+  const int lane = threadIdx.x & 63;
+  int t = 0;
+  for (; t + kScanBatch <= m; t += kScanBatch) {
+    int rr[kScanBatch], bb[kScanBatch];
+#pragma unroll
+    for (int j = 0; j < kScanBatch; ++j) rr[j] = rows[t + j];
+    wave_best_partners<W64, kScanBatch>(S, n, rr, id, sz, active, bb);
+    if (lane == 0)
+#pragma unroll
+      for (int j = 0; j < kScanBatch; ++j) best[rr[j]] = bb[j];
+  }
+  if (m - t >= 2) {
+    int rr[2] = {rows[t], rows[t + 1]}, bb[2];
+    wave_best_partners<W64, 2>(S, n, rr, id, sz, active, bb);
+    if (lane == 0) {
+      best[rr[0]] = bb[0];
+      best[rr[1]] = bb[1];
+    }
+    t += 2;
+  }
+  if (t < m) {
+    int rr[1] = {rows[t]}, bb[1];
+    wave_best_partners<W64, 1>(S, n, rr, id, sz, active, bb);
+    if (lane == 0) best[rr[0]] = bb[0];
+  }
+}
+
+// Best partners of every slot (the whole workgroup, kUpgmaWaves waves; wave w
+// scans the slots w, w + kUpgmaWaves, ..., kScanBatch at a time).
+template <bool W64, typename St>
 __device__ inline void upgma_init_best(const St& S, int n, const int32_t* id, const int32_t* sz,
                                        const int32_t* active, int32_t* best) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int r = wave; r < n; r += kUpgmaWaves) {
-    const int b = wave_best_partner<W64, UB>(S, n, r, id, sz, active);
-    if (lane == 0) best[r] = b;
+  const int wave = threadIdx.x >> 6;
+  const int m = wave < n ? (n - wave + kUpgmaWaves - 1) / kUpgmaWaves : 0;
+  for (int t = 0; t < m; t += kScanBatch) {
+    const int k = min(kScanBatch, m - t);
+    int rr[kScanBatch], bb[kScanBatch];
+#pragma unroll
+    for (int j = 0; j < kScanBatch; ++j) rr[j] = wave + kUpgmaWaves * (t + min(j, k - 1));
+    wave_best_partners<W64, kScanBatch>(S, n, rr, id, sz, active, bb);
+    if ((threadIdx.x & 63) == 0)
+      for (int j = 0; j < k; ++j) best[rr[j]] = bb[j];
   }
 }
 
@@ -326,11 +397,7 @@ __device__ bool upgma_steps(const St& S, int n, int32_t* id, int32_t* sz, int32_
       }
     }
     wave_sync();
-    for (int t = 0; t < nrec; ++t) {
-      const int r = rec[t];
-      const int b = wave_best_partner<W64, UB>(S, n, r, id, sz, active);
-      if (lane == 0) best[r] = b;
-    }
+    scan_rows<W64>(S, n, rec, nrec, id, sz, active, best);
     wave_sync();
   }
   return true;
