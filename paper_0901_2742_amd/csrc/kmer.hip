@@ -157,9 +157,22 @@ __device__ inline void hist_clear(uint16_t* hist, int kspace) {
   for (int t = threadIdx.x; t < (kspace + 1) / 2; t += blockDim.x) h32[t] = 0;
 }
 
+// Sum over the wave (all 64 lanes active), wave-uniform: prefix sums within
+// each row of 16 lanes by DPP row shifts (lanes past a row's start read 0),
+// then lane 15 of rows 0 and 2 into rows 1 and 3 and lane 31 into rows 2 and
+// 3 by row broadcasts, which leaves the total in lane 63.
+template <int CTRL, int ROWS = 0xf>
+__device__ inline int32_t dpp_in(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, true);
+}
 __device__ inline int32_t wave_sum32(int32_t v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_in<0x111>(v);  // row_shr:1
+  v += dpp_in<0x112>(v);  // row_shr:2
+  v += dpp_in<0x114>(v);  // row_shr:4
+  v += dpp_in<0x118>(v);  // row_shr:8
+  v += dpp_in<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_in<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // c between the histogram's row and NC column sequences cs[0..NC) (wave-wide;
@@ -204,7 +217,32 @@ __device__ inline void wave_common_n(const uint16_t* hist, const KmerLists& kl, 
 }
 
 // columns per wave pass in the pair-sum kernels
-constexpr int kPairCols = 4;
+constexpr int kPairCols = 8;
+
+// The NC column results of a pass (wave-uniform) one per lane, so that their
+// quotients are computed side by side: lane q < NC takes column q's count,
+// sequence and position (the other lanes: sequence -1).
+template <int NC>
+__device__ inline void lane_column(const int32_t* cc, const int* cs, int lane, int32_t& c, int& j,
+                                   int& q_of_lane) {
+  c = 0;
+  j = -1;
+  q_of_lane = 0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+    if (lane == q) {
+      c = cc[q];
+      j = cs[q];
+      q_of_lane = q;
+    }
+}
+
+// Sum over the wave of a 64-bit value (once per workgroup).
+__device__ inline uint64_t wave_sum_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1)
+    v += (uint64_t)__shfl_xor((unsigned long long)v, o, 64);
+  return v;
+}
 
 __device__ inline int64_t seq_len(const KmerLists& kl, int i) {
   return kl.seq_off[i + 1] - kl.seq_off[i];
@@ -245,11 +283,12 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_chunk_kernel(KmerLists kl
 #pragma unroll
     for (int q = 0; q < kPairCols; ++q) cs[q] = j + q * nw < hi ? j + q * nw : -1;
     wave_common_n<kPairCols>(hist, kl, cs, cc);
-#pragma unroll
-    for (int q = 0; q < kPairCols; ++q)
-      if (cs[q] >= 0) part += fhat_of(cc[q], Lr, seq_len(kl, cs[q]), k);
+    int32_t cl;
+    int jl, ql;
+    lane_column<kPairCols>(cc, cs, threadIdx.x & 63, cl, jl, ql);
+    if (jl >= 0) part += fhat_of(cl, Lr, seq_len(kl, jl), k);
   }
-  uint64_t s = block_sum_waves(part, red);
+  uint64_t s = block_sum_waves(wave_sum_u64(part), red);
   if (threadIdx.x == 0) out[r] = s;
 }
 
@@ -295,11 +334,12 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl,
         }
     int32_t cc[kPairCols];
     wave_common_n<kPairCols>(hist, kl, cs, cc);
-#pragma unroll
-    for (int q = 0; q < kPairCols; ++q)
-      if (cs[q] >= 0) part += fhat_of(cc[q], Lr, seq_len(kl, cs[q]), k);
+    int32_t cl;
+    int jl, ql;
+    lane_column<kPairCols>(cc, cs, threadIdx.x & 63, cl, jl, ql);
+    if (jl >= 0) part += fhat_of(cl, Lr, seq_len(kl, jl), k);
   }
-  uint64_t s = block_sum_waves(part, red);
+  uint64_t s = block_sum_waves(wave_sum_u64(part), red);
   if (threadIdx.x == 0) out[r] = s;
 }
 
@@ -338,10 +378,10 @@ __global__ __launch_bounds__(kPairThreads) void fmatrix_kernel(KmerLists kl,
 #pragma unroll
     for (int q = 0; q < kPairCols; ++q) cs[q] = b + q * nw < ng ? ids[g0 + b + q * nw] : -1;
     wave_common_n<kPairCols>(hist, kl, cs, cc);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-      for (int q = 0; q < kPairCols; ++q)
-        if (cs[q] >= 0) Frow[b + q * nw] = fhat_of(cc[q], Lr, seq_len(kl, cs[q]), k);
+    int32_t cl;
+    int jl, ql;
+    lane_column<kPairCols>(cc, cs, threadIdx.x & 63, cl, jl, ql);
+    if (jl >= 0) Frow[b + ql * nw] = fhat_of(cl, Lr, seq_len(kl, jl), k);
   }
 }
 
