@@ -127,6 +127,10 @@ void launch_kmer_lists(const uint8_t* codes, const int64_t* offsets, int n, int 
 // (64 consecutive entries per load) and sums min(count, H[tau]).
 
 constexpr int kPairThreads = 256;
+// Workgroups of the pair kernels whose histogram leaves room for only one
+// workgroup per CU (above 64 KB: 4^8 k-mers) take four times the waves, so
+// that more column lists are in flight against the one histogram.
+constexpr int kPairThreadsMax = 1024;
 
 // F = floor(c 2^31 / d), d = min(Li, Lj) - k + 1.  The numerator is below
 // 2^44 (c <= d <= 8192), so the double quotient is within one of the floor
@@ -260,11 +264,11 @@ __device__ inline uint64_t block_sum_waves(uint64_t v, uint64_t* red) {
 }
 
 // K_loc(r) = sum over j in chunk(r) of F(r, j)
-__global__ __launch_bounds__(kPairThreads) void rowsum_chunk_kernel(KmerLists kl, int n, int p,
+__global__ __launch_bounds__(kPairThreadsMax) void rowsum_chunk_kernel(KmerLists kl, int n, int p,
                                                                      int k, int kspace,
                                                                      uint64_t* __restrict__ out) {
   extern __shared__ uint16_t hist[];
-  __shared__ uint64_t red[kPairThreads / 64];
+  __shared__ uint64_t red[kPairThreadsMax / 64];
   const int r = blockIdx.x;
   int c = (int)(((int64_t)r * p) / n);
   while (c + 1 <= p && (((int64_t)(c + 1) * n) / p) <= r) ++c;
@@ -294,13 +298,13 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_chunk_kernel(KmerLists kl
 
 // out(r) = sum over the listed columns of F(r, col); cols == nullptr lists
 // all n sequences.  A listed id outside [0, n) is reported and skipped.
-__global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl, int n,
+__global__ __launch_bounds__(kPairThreadsMax) void rowsum_list_kernel(KmerLists kl, int n,
                                                                     const int32_t* __restrict__ cols,
                                                                     int ncols, int k, int kspace,
                                                                     uint64_t* __restrict__ out,
                                                                     DevStatus* st) {
   extern __shared__ uint16_t hist[];
-  __shared__ uint64_t red[kPairThreads / 64];
+  __shared__ uint64_t red[kPairThreadsMax / 64];
   const int r = blockIdx.x;
   hist_clear(hist, kspace);
   __syncthreads();
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(kPairThreads) void rowsum_list_kernel(KmerLists kl,
 // F rows inside groups: row index g_row in [0, total_rows) of the ids array;
 // its group's members are ids[group_off[g] .. group_off[g+1]); the group's
 // matrix starts at fm_off[g] (n_g x n_g, row-major).
-__global__ __launch_bounds__(kPairThreads) void fmatrix_kernel(KmerLists kl,
+__global__ __launch_bounds__(kPairThreadsMax) void fmatrix_kernel(KmerLists kl,
                                                                 const int32_t* __restrict__ group_off,
                                                                 const int32_t* __restrict__ ids,
                                                                 int ngroups,
@@ -387,6 +391,10 @@ __global__ __launch_bounds__(kPairThreads) void fmatrix_kernel(KmerLists kl,
 
 static size_t hist_bytes(int kspace) { return (size_t)((kspace + 1) / 2) * 4; }
 
+static int pair_threads(int kspace) {
+  return hist_bytes(kspace) > 64 * 1024 ? kPairThreadsMax : kPairThreads;
+}
+
 // Histograms above 64 KB (4^8 k-mers) need the larger dynamic-LDS limit.
 static void allow_lds(const void* fn, size_t bytes) {
   if (bytes > 64 * 1024)
@@ -397,14 +405,14 @@ void launch_rowsum_chunk(const KmerLists& kl, int n, int p, int k, int kspace, u
                          hipStream_t stream) {
   if (n <= 0) return;
   allow_lds((const void*)rowsum_chunk_kernel, hist_bytes(kspace));
-  rowsum_chunk_kernel<<<n, kPairThreads, hist_bytes(kspace), stream>>>(kl, n, p, k, kspace, out);
+  rowsum_chunk_kernel<<<n, pair_threads(kspace), hist_bytes(kspace), stream>>>(kl, n, p, k, kspace, out);
 }
 
 void launch_rowsum_list(const KmerLists& kl, int n, const int32_t* cols, int ncols, int k,
                         int kspace, uint64_t* out, DevStatus* st, hipStream_t stream) {
   if (n <= 0) return;
   allow_lds((const void*)rowsum_list_kernel, hist_bytes(kspace));
-  rowsum_list_kernel<<<n, kPairThreads, hist_bytes(kspace), stream>>>(kl, n, cols, ncols, k,
+  rowsum_list_kernel<<<n, pair_threads(kspace), hist_bytes(kspace), stream>>>(kl, n, cols, ncols, k,
                                                                       kspace, out, st);
 }
 
@@ -413,7 +421,7 @@ void launch_fmatrix_groups(const KmerLists& kl, const int32_t* group_off, const 
                            int kspace, uint32_t* F, hipStream_t stream) {
   if (total_rows <= 0) return;
   allow_lds((const void*)fmatrix_kernel, hist_bytes(kspace));
-  fmatrix_kernel<<<(unsigned)total_rows, kPairThreads, hist_bytes(kspace), stream>>>(
+  fmatrix_kernel<<<(unsigned)total_rows, pair_threads(kspace), hist_bytes(kspace), stream>>>(
       kl, group_off, ids, ngroups, fm_off, k, kspace, F);
 }
 
