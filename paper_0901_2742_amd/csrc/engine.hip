@@ -1287,13 +1287,19 @@ __device__ inline void push_job(const EngineArgs& a, int j) {
 }
 
 // A finished job releases its share of its parent's count if the parent
-// already exists; otherwise the parent's creation does it (one thread).
-__device__ inline void job_finished(const EngineArgs& a, int job) {
+// already exists; otherwise the parent's creation does it (one thread).  If
+// this release makes the parent ready and `keep` is set, the parent is
+// returned for the caller to run next instead of being queued (else -1).
+__device__ inline int job_finished(const EngineArgs& a, int job, bool keep) {
   const int old = atomicCAS(&a.job_link[job], 0, 1);
-  if (old != 2) return;
+  if (old != 2) return -1;
   __threadfence();
   const int nx = __hip_atomic_load(&a.job_next[job], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (atomicSub(&a.job_pending[nx], 1) == 1) push_job(a, nx);
+  if (atomicSub(&a.job_pending[nx], 1) == 1) {
+    if (keep) return nx;
+    push_job(a, nx);
+  }
+  return -1;
 }
 
 // Creates the job of merge `step` of group g (cluster ids ia < ib, leaves
@@ -1449,18 +1455,29 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
     }
   }
   uint64_t tk0 = 0, tk1 = 0, tk2 = 0, tk3 = 0, tk35 = 0;  // phase timestamps (thread 0)
+  // (thread 0) a merge that this workgroup's last job made ready: it runs
+  // next without a trip through the queue.  Only in the batched kernel, whose
+  // idle workgroups leave on the `finished` flag rather than on a count of
+  // queued jobs.
+  int keep_job = -1;
   for (;;) {
     // ---- fetch a ready job (thread 0) and describe it to the workgroup
     if (tid == 0) {
       tk0 = __builtin_amdgcn_s_memrealtime();
-      const int slot = atomicAdd(a.queue_head, 1);
-      J.slot = slot;
       J.job = -1;
       J.helper = 0;
       // the batched kernel's queue also carries helper tickets, so its slots
       // outnumber the merges: workgroups leave when every merge is done
       const int bound = MFMA ? a.queue_cap : a.njobs;
-      if (slot < bound) {
+      const int slot = keep_job >= 0 ? -1 : atomicAdd(a.queue_head, 1);
+      J.slot = slot;
+      if (keep_job >= 0) {
+        // the other child's results were released before its count was
+        // (fence, then the count); this fence orders the reads after ours
+        __threadfence();
+        J.job = keep_job;
+        keep_job = -1;
+      } else if (slot < bound) {
         const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
         bool ok = true;
         // relaxed polls (an agent-scope acquire invalidates cache lines that
@@ -1773,7 +1790,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
           r[7] = (long long)tk35;
         }
       }
-      if (tid == 0 && !a.no_push) job_finished(a, job);
+      if (tid == 0 && !a.no_push) keep_job = job_finished(a, job, MFMA);
       if constexpr (MFMA) {
         if (tid == 0 && atomicAdd(a.jobs_done, 1) == a.njobs - 1)
           __hip_atomic_store(a.finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
