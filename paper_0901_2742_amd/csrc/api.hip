@@ -698,6 +698,9 @@ struct FusedTrees {
   // upload of the matrix offsets, then the kernels that fill the matrices
   std::function<int32_t()> upload;
   std::function<void(hipStream_t)> kernels;
+  // captured into the context's one hipGraph when its arguments repeat (off
+  // for a second tree set in the same pass, which would evict the first's)
+  bool graph = true;
 };
 
 static bool graphs_enabled() {
@@ -902,7 +905,8 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     // the batched launch with its guide trees built inside has no host step
     // between setup and results: it is captured once into a hipGraph and
     // replayed while its arguments (all baked into the graph) are unchanged
-    const bool graphable = fused && !g_phase_on && !g_tuning && njobs > 0 && graphs_enabled();
+    const bool graphable =
+        fused && fused->graph && !g_phase_on && !g_tuning && njobs > 0 && graphs_enabled();
     std::vector<unsigned char> gkey;
     if (graphable) {
       EngineArgs ka = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend,
@@ -1528,28 +1532,38 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
     int32_t *nu, *ids;
     int64_t* fm0;
     uint64_t* Sw;
+    // batched mode with few enough ancestors: their guide tree is built
+    // inside the engine launch, as the buckets' trees are
+    const bool fuse_tree = prm->mode == SAD_BATCHED_MFMA && q <= engine_fused_max_group();
     Carver cv;
     cv.add(entries, (size_t)std::max<int64_t>(h_anc_off[q], 1));
     cv.add(nu, q);
     cv.add(ids, q);
     cv.add(fm0, 1);
     cv.add(F, (size_t)q * q);
-    cv.add(Sw, (size_t)q * q);
-    r = cv.carve(c);
-    if (r) return r;
-    r = reset_status(c, stream);
-    if (r) return r;
-    group_one_kernel<<<1, 1, 0, stream>>>(ga_goff, q, ga_list, q + (q - 2));
-    iota_kernel<<<(q + 255) / 256, 256, 0, stream>>>(ids, q);
-    launch_fill_i32(reinterpret_cast<int32_t*>(fm0), 0, 2, stream);
-    launch_fill_i32(reinterpret_cast<int32_t*>(ga_off0), 0, 4, stream);
-    launch_kmer_lists(anc_codes, anc_off, q, A, k, entries, nullptr, nu, c->st, stream);
-    KmerLists kl{entries, anc_off, nu, anc_off};
-    launch_fmatrix_groups(kl, ga_goff, ids, 1, q, fm0, k, kspace, F, stream);
-    launch_upgma(F, fm0, ga_goff, 1, q, Sw, ga_merges, reinterpret_cast<int32_t*>(ga_off0), c->st,
-                 stream);
-    r = finish(c, stream);
-    if (r) return r;
+    if (!fuse_tree) cv.add(Sw, (size_t)q * q);
+    // the ancestors' k-mer lists and similarity matrix (again after every
+    // carve when the engine's workspace is carved with them)
+    auto kernels = [&](hipStream_t st) {
+      group_one_kernel<<<1, 1, 0, st>>>(ga_goff, q, ga_list, q + (q - 2));
+      iota_kernel<<<(q + 255) / 256, 256, 0, st>>>(ids, q);
+      launch_fill_i32(reinterpret_cast<int32_t*>(fm0), 0, 2, st);
+      launch_fill_i32(reinterpret_cast<int32_t*>(ga_off0), 0, 4, st);
+      launch_kmer_lists(anc_codes, anc_off, q, A, k, entries, nullptr, nu, c->st, st);
+      KmerLists kl{entries, anc_off, nu, anc_off};
+      launch_fmatrix_groups(kl, ga_goff, ids, 1, q, fm0, k, kspace, F, st);
+    };
+    if (!fuse_tree) {
+      r = cv.carve(c);
+      if (r) return r;
+      r = reset_status(c, stream);
+      if (r) return r;
+      kernels(stream);
+      launch_upgma(F, fm0, ga_goff, 1, q, Sw, ga_merges, reinterpret_cast<int32_t*>(ga_off0),
+                   c->st, stream);
+      r = finish(c, stream);
+      if (r) return r;
+    }
     TreeSet ts;
     ts.ngroups = 1;
     ts.nleaves = q;
@@ -1563,8 +1577,14 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
     ts.kmer_k = k;
     EngineBuffers e{};
     TreeOutputs to{nullptr, nullptr, ga_score, ga_cells, ga_cells_tot, true};
-    Carver base;
-    r = run_trees(c, ts, ga_merges, prm, A, base, e, to, stream);
+    if (fuse_tree) {
+      FusedTrees fz{&F, &fm0, ga_merges, []() -> int32_t { return SAD_OK; }, kernels};
+      fz.graph = false;
+      r = run_trees(c, ts, ga_merges, prm, A, cv, e, to, stream, &fz);
+    } else {
+      Carver base;
+      r = run_trees(c, ts, ga_merges, prm, A, base, e, to, stream);
+    }
     if (r) return r;
     r = reset_status(c, stream);
     if (r) return r;
