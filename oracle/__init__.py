@@ -37,7 +37,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sad_oracle.c")
-_LIB = os.path.join(_HERE, "libsad_oracle.so")
+# SADREF_LIB names another build of the same source to load instead (the
+# sanitizer test runs the pin suite against an ASan/UBSan build)
+_LIB = os.environ.get("SADREF_LIB") or os.path.join(_HERE, "libsad_oracle.so")
 
 OP_M, OP_X, OP_Y = 0, 1, 2
 OK, E_INVAL, E_CAPACITY, E_OVERFLOW = 0, -1, -2, -3
@@ -51,6 +53,8 @@ class OracleError(RuntimeError):
 
 def build(force: bool = False) -> str:
     """Compiles the oracle with gcc (plain -O2, portable code)."""
+    if os.environ.get("SADREF_LIB"):
+        return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
@@ -94,12 +98,16 @@ def _declare(L):
                                 P, I32, P, P, P, P, P, P, P, P]
     L.sadref_refine_template.argtypes = [I32, I32, P, P, I32, P, P, P, P, I32, P, I32, I32, I32,
                                          P, I32, P, P, P, P, P, P, P, P]
+    L.sadref_refine_template_ops.argtypes = [I32, I32, P, P, I32, P, P, P, P, I32, P, I32, I32,
+                                             I32, P, I32, P, P, P, P, P, P, P, P, P, I64, P, P]
+    L.sadref_glue.argtypes = [I32, I32, P, P, P, P, P]
     L.sadref_refine_tree.argtypes = [I32, I32, P, P, I32, P, P, P, I32, P, I32, P, I32, I32, I32,
                                      P, P, P, P, P, P, I32, P]
     for f in ("sadref_refine_tree", "sadref_kmer_list", "sadref_kmer_rank", "sadref_rank_against", "sadref_partition",
               "sadref_upgma",
               "sadref_profile_align", "sadref_align_buckets", "sadref_consensus",
-              "sadref_refine", "sadref_refine_template"):
+              "sadref_refine", "sadref_refine_template", "sadref_refine_template_ops",
+              "sadref_glue"):
         getattr(L, f).restype = ctypes.c_int
 
 
@@ -269,11 +277,34 @@ def align_buckets(codes, offsets, A: int, bucket_off, members, k: int, S, go: in
 TEMPLATES = {"ga": 0, "ga_msa": 1}
 
 
+def glue(TW: int, ops_list, widths):
+    """Step 15 on its own: bucket op strings (one per non-empty bucket, in
+    bucket order, over M/X/Y = 0/1/2) against a template of TW columns ->
+    (list of per-bucket arrays: glued column of each bucket column, width)."""
+    q = len(ops_list)
+    ops = np.concatenate([_c(o, np.uint8) for o in ops_list]) if q else np.zeros(1, np.uint8)
+    if len(ops) == 0:
+        ops = np.zeros(1, np.uint8)
+    off = np.zeros(q + 1, np.int64)
+    off[1:] = np.cumsum([len(o) for o in ops_list])
+    wu = _c(widths, np.int32) if q else np.zeros(1, np.int32)
+    to_g = np.zeros(max(int(np.sum(widths)) if q else 0, 1), np.int32)
+    wg = np.zeros(1, np.int32)
+    _check(lib().sadref_glue(q, TW, _p(ops), _p(off), _p(wu), _p(to_g), _p(wg)), "glue")
+    out, base = [], 0
+    for w in widths:
+        out.append(to_g[base:base + w].copy())
+        base += w
+    return out, int(wg[0])
+
+
 def refine(codes, offsets, A: int, bucket_off, members, colmap_b, width_b, k: int, S,
-           go: int, ge: int, template: str = "ga"):
+           go: int, ge: int, template: str = "ga", want_ops: bool = False):
     """Steps 12-15: ancestors, GA, each bucket against the template, glue.
     template "ga": GA as a one-row profile; "ga_msa": the ancestors' alignment
-    as a profile of q rows (the paper's future-work template)."""
+    as a profile of q rows (the paper's future-work template).  want_ops: also
+    return the refinement op strings ("ops": one array per non-empty bucket)
+    and the template's width ("tmpl_width")."""
     codes, offsets = _c(codes, np.uint8), _c(offsets, np.int64)
     boff, mem, S = _c(bucket_off, np.int32), _c(members, np.int32), _c(S, np.int8)
     cb, wb = _c(colmap_b, np.int32), _c(width_b, np.int32)
@@ -290,15 +321,26 @@ def refine(codes, offsets, A: int, bucket_off, members, colmap_b, width_b, k: in
     mc = np.zeros(2 * p, np.int64)
     nm = np.zeros(1, np.int32)
     cells = np.zeros(1, np.int64)
-    st = lib().sadref_refine_template(n, A, _p(codes), _p(offsets), p, _p(boff), _p(mem), _p(cb),
-                                      _p(wb), k, _p(S), go, ge, TEMPLATES[template], _p(ga),
-                                      ga_cap, _p(ga_len), _p(cg), _p(wg), _p(ms), _p(ml), _p(mc),
-                                      _p(nm), _p(cells))
+    # the refinement op strings: each at most W_b + template width <= 2 sum W
+    ops_cap = max(4 * int(wb.astype(np.int64).sum()) + 16, 16) if want_ops else 0
+    rops = np.zeros(max(ops_cap, 1), np.uint8)
+    roff = np.zeros(p + 1, np.int64)
+    tw = np.zeros(1, np.int32)
+    st = lib().sadref_refine_template_ops(
+        n, A, _p(codes), _p(offsets), p, _p(boff), _p(mem), _p(cb), _p(wb), k, _p(S), go, ge,
+        TEMPLATES[template], _p(ga), ga_cap, _p(ga_len), _p(cg), _p(wg), _p(ms), _p(ml), _p(mc),
+        _p(nm), _p(cells), _p(rops) if want_ops else None, ops_cap,
+        _p(roff) if want_ops else None, _p(tw) if want_ops else None)
     _check(st, "refine")
     m = int(nm[0])
-    return dict(ga=ga[:int(ga_len[0])].copy(), colmap=cg[:len(codes)].copy(), width=int(wg[0]),
-                merge_score=ms[:m].copy(), merge_list=ml[:2 * m].reshape(-1, 2).copy(),
-                merge_cells=mc[:m].copy(), cells=int(cells[0]))
+    out = dict(ga=ga[:int(ga_len[0])].copy(), colmap=cg[:len(codes)].copy(), width=int(wg[0]),
+               merge_score=ms[:m].copy(), merge_list=ml[:2 * m].reshape(-1, 2).copy(),
+               merge_cells=mc[:m].copy(), cells=int(cells[0]))
+    if want_ops:
+        q = int(np.count_nonzero(np.diff(boff)))
+        out["ops"] = [rops[roff[u]:roff[u + 1]].copy() for u in range(q)]
+        out["tmpl_width"] = int(tw[0])
+    return out
 
 
 def refine_tree(codes, offsets, A: int, bucket_off, members, colmap, width: int, tree, k: int,

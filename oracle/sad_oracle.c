@@ -762,20 +762,101 @@ int sadref_consensus(const uint16_t* counts, int32_t W, int32_t n, int32_t A,
   return SADREF_OK;
 }
 
+/* Glue of the refined bucket alignments (Section 2.3.3, step 15; the
+ * paper only says they are joined).  Bucket u (u = 0..q-1, non-empty buckets
+ * in bucket order) was aligned against the template of TW columns by the op
+ * string ops[ops_off[u] .. ops_off[u+1]): M pairs its next column with the
+ * next template column, X places its next column against a gap, Y places a
+ * gap against the next template column.  Layout: before template column j
+ * (j = 0..TW; slot TW follows the last column) an insert slot holds the
+ * X-columns of every bucket that fall there, bucket 0's first, each bucket's
+ * in its own order, each in a column of its own; then comes the shared column
+ * j, holding each bucket's M-column of j or a gap.  Columns that hold no
+ * residue (shared columns every bucket skips) are dropped.  Output: to_g, for
+ * bucket u at to_g[col_off[u] ..] (col_off = prefix sums of width_u), the glued
+ * column of each of its columns; *width_g. */
+int sadref_glue(int32_t q, int32_t TW, const uint8_t* ops, const int64_t* ops_off,
+                const int32_t* width_u, int32_t* to_g, int32_t* width_g) {
+  if (q < 0 || TW < 0) return SADREF_E_INVAL;
+  int64_t slots = (int64_t)TW + 1;
+  int64_t* ins = (int64_t*)calloc((size_t)(q * slots > 0 ? q * slots : 1), sizeof(int64_t));
+  char* shared_used = (char*)calloc((size_t)(TW > 0 ? TW : 1), 1);
+  int st = SADREF_OK;
+  for (int32_t u = 0; u < q && st == SADREF_OK; ++u) {
+    int32_t i = 0, j = 0;
+    for (int64_t t = ops_off[u]; t < ops_off[u + 1]; ++t) {
+      uint8_t op = ops[t];
+      if (op == SADREF_OP_X) {
+        ins[(int64_t)u * slots + j] += 1;
+        ++i;
+      } else if (op == SADREF_OP_M || op == SADREF_OP_Y) {
+        if (j >= TW) { st = SADREF_E_INVAL; break; }
+        if (op == SADREF_OP_M) { shared_used[j] = 1; ++i; }
+        ++j;
+      } else {
+        st = SADREF_E_INVAL;
+        break;
+      }
+    }
+    if (st == SADREF_OK && (i != width_u[u] || j != TW)) st = SADREF_E_INVAL;
+  }
+  /* start index of each (slot, bucket) block and each kept shared column */
+  int64_t* blk = (int64_t*)malloc(sizeof(int64_t) * (size_t)(q * slots > 0 ? q * slots : 1));
+  int64_t* shared_at = (int64_t*)malloc(sizeof(int64_t) * (size_t)(TW > 0 ? TW : 1));
+  int64_t pos = 0;
+  if (st == SADREF_OK) {
+    for (int64_t j = 0; j < slots; ++j) {
+      for (int32_t u = 0; u < q; ++u) {
+        blk[(int64_t)u * slots + j] = pos;
+        pos += ins[(int64_t)u * slots + j];
+      }
+      if (j < TW) {
+        shared_at[j] = shared_used[j] ? pos : -1;
+        if (shared_used[j]) ++pos;
+      }
+    }
+    *width_g = (int32_t)pos;
+    int64_t base = 0;
+    for (int32_t u = 0; u < q; ++u) {
+      int32_t i = 0, j = 0;
+      int64_t k_in = 0;
+      for (int64_t t = ops_off[u]; t < ops_off[u + 1]; ++t) {
+        uint8_t op = ops[t];
+        if (op == SADREF_OP_X) {
+          to_g[base + i++] = (int32_t)(blk[(int64_t)u * slots + j] + k_in);
+          ++k_in;
+        } else {
+          if (op == SADREF_OP_M) to_g[base + i++] = (int32_t)shared_at[j];
+          ++j;
+          k_in = 0;
+        }
+      }
+      base += width_u[u];
+    }
+  }
+  free(ins);
+  free(shared_used);
+  free(blk);
+  free(shared_at);
+  return st;
+}
+
 /* Refinement with a choice of template (Section 2.3.3, steps 12-15):
  * tmpl 0 aligns every bucket with GA as a one-row profile (the consensus of
  * the ancestors' alignment); tmpl 1 aligns every bucket with the ancestors'
  * alignment itself, a profile of q rows (the richer template the paper leaves
  * to future work).  With one non-empty bucket both are the bucket's own
  * ancestor as one row. */
-int sadref_refine_template(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
-                           int32_t p, const int32_t* bucket_off, const int32_t* members,
-                           const int32_t* colmap_b, const int32_t* width_b,
-                           int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge, int32_t tmpl,
-                           uint8_t* ga, int32_t ga_cap, int32_t* ga_len,
-                           int32_t* colmap_g, int32_t* width_g,
-                           int64_t* merge_score_g, int32_t* merge_list_g, int64_t* merge_cells_g,
-                           int32_t* n_merges_g, int64_t* cells) {
+int sadref_refine_template_ops(int32_t n, int32_t A, const uint8_t* codes,
+                               const int64_t* offsets, int32_t p, const int32_t* bucket_off,
+                               const int32_t* members, const int32_t* colmap_b,
+                               const int32_t* width_b, int32_t kmer_k, const int8_t* S,
+                               int32_t go, int32_t ge, int32_t tmpl, uint8_t* ga, int32_t ga_cap,
+                               int32_t* ga_len, int32_t* colmap_g, int32_t* width_g,
+                               int64_t* merge_score_g, int32_t* merge_list_g,
+                               int64_t* merge_cells_g, int32_t* n_merges_g, int64_t* cells,
+                               uint8_t* rf_ops, int64_t rf_ops_cap, int64_t* rf_ops_off,
+                               int32_t* tmpl_width) {
   int st = validate_seqs(n, A, codes, offsets, kmer_k);
   if (st) return st;
   if (p < 1 || go < ge || ge < 0 || tmpl < 0 || tmpl > 1) return SADREF_E_INVAL;
@@ -883,67 +964,50 @@ int sadref_refine_template(int32_t n, int32_t A, const uint8_t* codes, const int
     }
   }
 
-  /* glue: before template column j (and after the last one) an insert slot
-   * holds the bucket columns aligned to gaps there -- bucket by bucket, each in
-   * its own order -- then comes the shared column j; all-gap columns are
-   * dropped */
+  /* the refinement op strings, for callers that check the glue */
+  if (st == SADREF_OK && rf_ops_off) {
+    int64_t tot = 0;
+    for (int32_t u = 0; u < q; ++u) {
+      rf_ops_off[u] = tot;
+      if (rf_ops && tot + bnops[u] <= rf_ops_cap) memcpy(rf_ops + tot, bops[u], (size_t)bnops[u]);
+      tot += bnops[u];
+    }
+    rf_ops_off[q] = tot;
+    if (tmpl_width) *tmpl_width = TW;
+    if (rf_ops && tot > rf_ops_cap) st = SADREF_E_CAPACITY;
+  }
+
+  /* glue: the bucket columns' places in the joined alignment */
   if (st == SADREF_OK) {
-    int64_t slots = (int64_t)TW + 1;
-    int64_t* ins = (int64_t*)calloc((size_t)(q * slots > 0 ? q * slots : 1), sizeof(int64_t));
-    char* shared_used = (char*)calloc((size_t)(TW > 0 ? TW : 1), 1);
+    int64_t* ooff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(q + 1));
+    int32_t* wu = (int32_t*)malloc(sizeof(int32_t) * (size_t)(q > 0 ? q : 1));
+    int64_t tot_ops = 0, tot_w = 0;
     for (int32_t u = 0; u < q; ++u) {
-      int32_t j = 0;
-      for (int32_t t = 0; t < bnops[u]; ++t) {
-        if (bops[u][t] == SADREF_OP_X) ins[(int64_t)u * slots + j] += 1;
-        else {
-          if (bops[u][t] == SADREF_OP_M) shared_used[j] = 1;
-          ++j;
-        }
-      }
+      ooff[u] = tot_ops;
+      tot_ops += bnops[u];
+      wu[u] = width_b[nonempty[u]];
+      tot_w += wu[u];
     }
-    /* start index of each (slot, bucket) block and each kept shared column */
-    int64_t* blk = (int64_t*)malloc(sizeof(int64_t) * (size_t)(q * slots > 0 ? q * slots : 1));
-    int64_t* shared_at = (int64_t*)malloc(sizeof(int64_t) * (size_t)(TW > 0 ? TW : 1));
-    int64_t pos = 0;
-    for (int64_t j = 0; j < slots; ++j) {
-      for (int32_t u = 0; u < q; ++u) {
-        blk[(int64_t)u * slots + j] = pos;
-        pos += ins[(int64_t)u * slots + j];
-      }
-      if (j < TW) {
-        shared_at[j] = shared_used[j] ? pos : -1;
-        if (shared_used[j]) ++pos;
-      }
-    }
-    *width_g = (int32_t)pos;
-    for (int32_t u = 0; u < q; ++u) {
+    ooff[q] = tot_ops;
+    uint8_t* allops = (uint8_t*)malloc((size_t)(tot_ops > 0 ? tot_ops : 1));
+    for (int32_t u = 0; u < q; ++u) memcpy(allops + ooff[u], bops[u], (size_t)bnops[u]);
+    int32_t* to_g = (int32_t*)malloc(sizeof(int32_t) * (size_t)(tot_w > 0 ? tot_w : 1));
+    st = sadref_glue(q, TW, allops, ooff, wu, to_g, width_g);
+    int64_t base = 0;
+    for (int32_t u = 0; u < q && st == SADREF_OK; ++u) {
       int32_t b = nonempty[u];
-      int32_t W = width_b[b];
-      int32_t* to_g = (int32_t*)malloc(sizeof(int32_t) * (size_t)(W > 0 ? W : 1));
-      int32_t i = 0, j = 0;
-      int64_t k_in = 0;
-      for (int32_t t = 0; t < bnops[u]; ++t) {
-        uint8_t op = bops[u][t];
-        if (op == SADREF_OP_X) {
-          to_g[i++] = (int32_t)(blk[(int64_t)u * slots + j] + k_in);
-          ++k_in;
-        } else {
-          if (op == SADREF_OP_M) to_g[i++] = (int32_t)shared_at[j];
-          ++j;
-          k_in = 0;
-        }
-      }
       int32_t lo = bucket_off[b], nb = bucket_off[b + 1] - lo;
       for (int32_t a = 0; a < nb; ++a) {
         int32_t id = members[lo + a];
-        for (int64_t r = offsets[id]; r < offsets[id + 1]; ++r) colmap_g[r] = to_g[colmap_b[r]];
+        for (int64_t r = offsets[id]; r < offsets[id + 1]; ++r)
+          colmap_g[r] = to_g[base + colmap_b[r]];
       }
-      free(to_g);
+      base += wu[u];
     }
-    free(ins);
-    free(shared_used);
-    free(blk);
-    free(shared_at);
+    free(ooff);
+    free(wu);
+    free(allops);
+    free(to_g);
   }
   *n_merges_g = nm + q;
 
@@ -961,6 +1025,20 @@ int sadref_refine_template(int32_t n, int32_t A, const uint8_t* codes, const int
   free(GA);
   free(nonempty);
   return st;
+}
+
+int sadref_refine_template(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
+                           int32_t p, const int32_t* bucket_off, const int32_t* members,
+                           const int32_t* colmap_b, const int32_t* width_b,
+                           int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge, int32_t tmpl,
+                           uint8_t* ga, int32_t ga_cap, int32_t* ga_len,
+                           int32_t* colmap_g, int32_t* width_g,
+                           int64_t* merge_score_g, int32_t* merge_list_g, int64_t* merge_cells_g,
+                           int32_t* n_merges_g, int64_t* cells) {
+  return sadref_refine_template_ops(n, A, codes, offsets, p, bucket_off, members, colmap_b,
+                                    width_b, kmer_k, S, go, ge, tmpl, ga, ga_cap, ga_len,
+                                    colmap_g, width_g, merge_score_g, merge_list_g,
+                                    merge_cells_g, n_merges_g, cells, NULL, 0, NULL, NULL);
 }
 
 int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,

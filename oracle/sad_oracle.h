@@ -113,6 +113,26 @@ int sadref_refine_template(int32_t n, int32_t A, const uint8_t* codes, const int
                            int32_t* colmap_g, int32_t* width_g,
                            int64_t* merge_score_g, int32_t* merge_list_g, int64_t* merge_cells_g,
                            int32_t* n_merges_g, int64_t* cells);
+/* sadref_refine_template that also returns the refinement op strings:
+ * bucket u's (u-th non-empty bucket) ops at rf_ops[rf_ops_off[u] ..
+ * rf_ops_off[u+1]) (rf_ops_off has q + 1 entries; SADREF_E_CAPACITY when
+ * rf_ops_cap is too small) and the template's width in *tmpl_width. */
+int sadref_refine_template_ops(int32_t n, int32_t A, const uint8_t* codes,
+                               const int64_t* offsets, int32_t p, const int32_t* bucket_off,
+                               const int32_t* members, const int32_t* colmap_b,
+                               const int32_t* width_b, int32_t kmer_k, const int8_t* S,
+                               int32_t go, int32_t ge, int32_t tmpl, uint8_t* ga, int32_t ga_cap,
+                               int32_t* ga_len, int32_t* colmap_g, int32_t* width_g,
+                               int64_t* merge_score_g, int32_t* merge_list_g,
+                               int64_t* merge_cells_g, int32_t* n_merges_g, int64_t* cells,
+                               uint8_t* rf_ops, int64_t rf_ops_cap, int64_t* rf_ops_off,
+                               int32_t* tmpl_width);
+/* The glue of step 15 on its own: q refined bucket alignments given as op
+ * strings (M, X, Y) against a template of TW columns -> the glued column of
+ * every bucket column (to_g, buckets one after another) and the glued width.
+ * SADREF_E_INVAL when an op string does not span its bucket and the template. */
+int sadref_glue(int32_t q, int32_t TW, const uint8_t* ops, const int64_t* ops_off,
+                const int32_t* width_u, int32_t* to_g, int32_t* width_g);
 int sadref_refine(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
                   int32_t p, const int32_t* bucket_off, const int32_t* members,
                   const int32_t* colmap_b, const int32_t* width_b,

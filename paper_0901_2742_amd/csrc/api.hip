@@ -919,7 +919,8 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                                  (uintptr_t)out.d_cells, (uintptr_t)out.d_cells_total,
                                  (uintptr_t)e.prof_pool, (uintptr_t)c->st,
                                  (uintptr_t)N, (uintptr_t)ts.ngroups, (uintptr_t)ts.total_len,
-                                 (uintptr_t)A, (uintptr_t)e.nwg, (uintptr_t)stream};
+                                 (uintptr_t)A, (uintptr_t)e.nwg, (uintptr_t)stream,
+                                 (uintptr_t)ts.kmer_k, (uintptr_t)ts.max_len};
       gkey.resize(sizeof(ka) + sizeof(extra));
       std::memcpy(gkey.data(), &ka, sizeof(ka));
       std::memcpy(gkey.data() + sizeof(ka), extra, sizeof(extra));
@@ -1284,13 +1285,20 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
                             const int32_t* d_members, const sad_params* prm, sad_msa* out,
                             int32_t* grid_out, int32_t* fuse_out, hipStream_t stream) {
   if (!prm || !out || !seqs) return fail(SAD_E_INVAL, "null argument");
-  if (!d_bucket_off) return fail(SAD_E_INVAL, "null device array");
+  int32_t r = check_seqs(seqs, prm->kmer_k);
+  if (r) return r;
+  r = check_params(prm, seqs->alphabet, true);
+  if (r) return r;
+  if (!d_bucket_off || !d_members) return fail(SAD_E_INVAL, "null device array");
   DeviceCtx* c = nullptr;
-  int32_t r = get_ctx(&c);
+  r = get_ctx(&c);
   if (r) return r;
   std::vector<int32_t> off;
-  r = d2h(c, d_bucket_off, (size_t)prm->p + 1, off, stream);
+  r = validate_read(c, seqs, prm->kmer_k, stream, d_bucket_off, (size_t)prm->p + 1, off);
   if (r) return r;
+  if (off[0] != 0 || off[prm->p] != seqs->n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
+  for (int b = 0; b < prm->p; ++b)
+    if (off[b + 1] < off[b]) return fail(SAD_E_INVAL, "bucket offsets must be non-decreasing");
   int max_n = 0;
   for (int b = 0; b < prm->p; ++b) max_n = std::max(max_n, off[b + 1] - off[b]);
   const TuneKey key{seqs->alphabet, seqs->n, prm->p, (int)prm->mode, max_n, seqs->total_len};

@@ -101,3 +101,31 @@ def test_autotune_keeps_results(setup, mode):
     check_align(torch, al, ref, s, w.p)
     al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm)
     check_align(torch, al, ref, s, w.p)
+
+
+def test_graph_key_follows_kmer_length(setup):
+    """A captured launch bakes the k-mer length into its similarity kernels: a
+    call with another k on the same buffers must not replay it.  k alternates
+    3, 2, 3, 3 (the last call a replay of the re-captured k = 3 launch), each
+    call checked against the oracle on the same buckets."""
+    B, torch, s, w, ref, seqs, _, part = setup
+    boff = part["bucket_off"].cpu().numpy()
+    mem = part["members"].cpu().numpy()
+    refs = {}
+    for k in (3, 2):
+        refs[k] = oracle.align_buckets(s.codes, s.offsets, s.alphabet, boff, mem, k, w.subst(),
+                                       w.gap_open, w.gap_extend)
+    assert not np.array_equal(refs[3]["merge_list"], refs[2]["merge_list"])
+    out = None
+    B.sad_profile_graphs(reset=True)
+    for rep, k in enumerate((3, 3, 2, 3, 3, 2, 2)):
+        _say(f"case graph key k={k} call {rep}")
+        prm = B.Params(k, w.p, w.subst(), w.gap_open, w.gap_extend, w.s_max, B.SAD_BATCHED_MFMA)
+        if out is not None:
+            for t in out.values():
+                if torch.is_tensor(t):
+                    t.fill_(-7)
+        out = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm, out)
+        check_align(torch, out, {"align": refs[k]}, s, w.p)
+    captured, replayed = B.sad_profile_graphs(reset=True)
+    assert replayed >= 1

@@ -78,3 +78,33 @@ def test_bad_matrix_rejected():
     m[0, 1] = 3
     with pytest.raises(ValueError):
         validate_matrix(m)
+
+
+def test_inputs_match_frozen_manifest():
+    """Every workload regenerates byte for byte as frozen in
+    tests/data/manifest.json (codes, offsets and homology ids)."""
+    import hashlib
+    import json
+    import os
+    from workloads import CONFIGS, make_inputs
+    with open(os.path.join(os.path.dirname(__file__), "data", "manifest.json")) as fh:
+        man = json.load(fh)["workloads"]
+    assert set(man) == set(CONFIGS)
+    for name, exp in man.items():
+        s = make_inputs(name)
+        assert s.n == exp["n"] and int(s.offsets[-1]) == exp["residues"], name
+        assert s.sha256() == exp["sha256"], name
+        h = hashlib.sha256(np.ascontiguousarray(s.homology, dtype=np.int64).tobytes())
+        assert h.hexdigest() == exp["homology_sha256"], name
+    make_inputs.cache_clear()
+
+
+def test_parallel_generation_is_identical():
+    from workloads import generate
+    kw = dict(seed=77, n=600, alphabet=20, n_families=12,
+              root_len={"kind": "normal", "mean": 120, "sd": 30, "lo": 40, "hi": 200},
+              p_sub=0.1, p_indel=0.02, min_len=3, zipf=1.2)
+    a = generate(**kw, workers=1)
+    b = generate(**kw, workers=4)
+    assert a.sha256() == b.sha256()
+    assert np.array_equal(a.homology, b.homology) and np.array_equal(a.family, b.family)

@@ -188,17 +188,46 @@ def family_sizes(n_total: int, n_fam: int, zipf: float | None, min_size: int = 2
     return base + floor_
 
 
+def _family_job(args):
+    """One family from its own stream (a worker's unit of work)."""
+    seed, f, root_len, size, alphabet, p_sub, p_indel, min_len = args
+    frng = SplitMix64(seed).split(1000 + f)
+    return evolve_family(frng, root_len, size, alphabet, p_sub, p_indel, min_len, f)
+
+
+def default_workers() -> int:
+    """Worker processes for generating large sets: the host's cores, at most 16
+    (SAD_GEN_WORKERS overrides; 1 generates in this process)."""
+    import os
+    v = os.environ.get("SAD_GEN_WORKERS")
+    if v:
+        return max(1, int(v))
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def generate(seed: int, n: int, alphabet: int, n_families: int, root_len: dict,
-             p_sub: float, p_indel: float, min_len: int, zipf: float | None = None) -> SeqSet:
-    """Generates a shuffled family-structured SeqSet (see module docstring)."""
+             p_sub: float, p_indel: float, min_len: int, zipf: float | None = None,
+             workers: int | None = None) -> SeqSet:
+    """Generates a shuffled family-structured SeqSet (see module docstring).
+    Every family draws from a stream of its own, so the result does not depend
+    on ``workers`` (families are evolved in that many forked processes when the
+    set is large; None: default_workers())."""
     rng = SplitMix64(seed)
     sizes = family_sizes(n, n_families, zipf)
     rl = root_lengths(rng.split(1), n_families, root_len)
+    jobs = [(seed, f, int(rl[f]), int(sizes[f]), alphabet, p_sub, p_indel, min_len)
+            for f in range(n_families)]
+    if workers is None:
+        workers = default_workers() if n >= 10000 and n_families > 1 else 1
+    workers = min(workers, n_families)
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            fam_out = pool.map(_family_job, jobs, chunksize=max(1, n_families // (4 * workers)))
+    else:
+        fam_out = [_family_job(j) for j in jobs]
     seqs, homs, fams = [], [], []
-    for f in range(n_families):
-        frng = rng.split(1000 + f)
-        s, h = evolve_family(frng, int(rl[f]), int(sizes[f]), alphabet, p_sub, p_indel,
-                             min_len, f)
+    for f, (s, h) in enumerate(fam_out):
         seqs.extend(s)
         homs.extend(h)
         fams.extend([f] * len(s))
