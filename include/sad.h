@@ -137,6 +137,25 @@ int32_t sad_partition(const sad_seqs* seqs, const uint64_t* d_key, const sad_par
                       int32_t* d_bucket_off, int32_t* d_members, hipStream_t stream);
 
 /*
+ * sad_partition without allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, checks and outputs as sad_partition
+ * (bit-identical results); its scratch is a static device array of 32 MiB per
+ * device (enough for 200000 ids in 1024 buckets), held from the library's
+ * load until the process ends.  SAD_E_CAPACITY when the partition needs more
+ * (about 4n + 24 p(p-1) + 4 p ceil(n/256) bytes).  The call only enqueues
+ * kernels on `stream` and returns without synchronising (launch failures are
+ * SAD_E_DEVICE); it calls no allocator.  Every call on one device shares the
+ * one scratch array: calls that overlap in time on a device (different
+ * streams, or host threads) race and must be serialised by the caller, e.g.
+ * by issuing them on one stream.
+ */
+int32_t sad_partition_noalloc(const sad_seqs* seqs, const uint64_t* d_key,
+                              const sad_params* prm, uint64_t* d_pivot_key, int32_t* d_pivot_id,
+                              int32_t* d_bucket, int32_t* d_bucket_off, int32_t* d_members,
+                              hipStream_t stream);
+
+/*
  * Stage 3 -- independent alignment of every bucket (Section 2.3.3, step 11; the
  * sequential aligner is k-mer similarity + UPGMA + progressive profile-profile
  * alignment):

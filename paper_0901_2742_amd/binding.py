@@ -26,7 +26,7 @@ SAD_PLAIN = 0
 SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
-EXPORTS = ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets", "sad_refine", "sad_refine_template", "sad_refine_tree", "sad_tune",
+EXPORTS = ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_partition_noalloc", "sad_align_buckets", "sad_refine", "sad_refine_template", "sad_refine_tree", "sad_tune",
            "sad_quality",
            "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs", "sad_profile_graphs",
            "sad_last_error",
@@ -74,11 +74,13 @@ def lib():
         L.sad_kmer_rank.argtypes = [P, P, P, P, I32, P, P]
         L.sad_rank_against.argtypes = [P, I32, P, I32, P, P]
         L.sad_partition.argtypes = [P, P, P, P, P, P, P, P, P]
+        L.sad_partition_noalloc.argtypes = [P, P, P, P, P, P, P, P, P]
         L.sad_align_buckets.argtypes = [P, P, P, P, P, P]
         L.sad_refine.argtypes = [P, P, P, P, P, P, I32, P, P, P, P]
         L.sad_refine_template.argtypes = [P, P, P, P, P, I32, P, I32, P, P, P, P]
         L.sad_refine_tree.argtypes = [P, P, P, P, P, I32, P, P, P, P, I32, P]
-        for f in ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_align_buckets",
+        for f in ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_partition_noalloc",
+                  "sad_align_buckets",
                   "sad_refine", "sad_refine_template", "sad_refine_tree"):
             getattr(L, f).restype = I32
         L.sad_profile_enable.argtypes = [I32]
@@ -198,9 +200,11 @@ def sad_rank_against(seqs: DeviceSeqs, kmer_k: int, samples: torch.Tensor | None
     return key[:seqs.n]
 
 
-def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params, bufs: dict | None = None):
+def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params, bufs: dict | None = None,
+                  noalloc: bool = False):
     """Stage 2: pivots and buckets.  Returns a dict of device tensors; `bufs`
-    (a dict, filled on first use) keeps the buffers across calls."""
+    (a dict, filled on first use) keeps the buffers across calls.  noalloc:
+    call sad_partition_noalloc (static device scratch, no synchronisation)."""
     dev = key.device
     n, p = seqs.n, prm.p
     if bufs is None:
@@ -212,11 +216,12 @@ def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params, bufs: dict |
                     bucket_off=torch.empty(p + 1, dtype=torch.int32, device=dev),
                     members=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
     s, pp = seqs.c_struct(), prm.c_struct()
-    code = lib().sad_partition(ctypes.byref(s), _ptr(key), ctypes.byref(pp),
-                               _ptr(bufs["pivot_key"]), _ptr(bufs["pivot_id"]),
-                               _ptr(bufs["bucket"]), _ptr(bufs["bucket_off"]),
-                               _ptr(bufs["members"]), _stream())
-    _check(code, "sad_partition")
+    name = "sad_partition_noalloc" if noalloc else "sad_partition"
+    code = getattr(lib(), name)(ctypes.byref(s), _ptr(key), ctypes.byref(pp),
+                                _ptr(bufs["pivot_key"]), _ptr(bufs["pivot_id"]),
+                                _ptr(bufs["bucket"]), _ptr(bufs["bucket_off"]),
+                                _ptr(bufs["members"]), _stream())
+    _check(code, name)
     return dict(pivot_key=bufs["pivot_key"][:p - 1], pivot_id=bufs["pivot_id"][:p - 1],
                 bucket=bufs["bucket"][:n], bucket_off=bufs["bucket_off"],
                 members=bufs["members"][:n])

@@ -109,6 +109,8 @@ static int32_t fail(int32_t code, const std::string& msg) {
   return code;
 }
 
+int32_t report_error(int32_t code, const std::string& msg) { return fail(code, msg); }
+
 #define HIPCHK(expr)                                                                 \
   do {                                                                               \
     hipError_t e_ = (expr);                                                          \
@@ -1166,25 +1168,19 @@ extern "C" int32_t sad_partition(const sad_seqs* seqs, const uint64_t* d_key, co
   DeviceCtx* c = nullptr;
   r = get_ctx(&c);
   if (r) return r;
-  const int ny = p * (p - 1);
-  const int nblk = (n + 255) / 256;
-  int32_t *sorted, *Yi, *Ysi, *blk, *total;
-  uint64_t *Yk, *Ysk;
+  // one block of scratch, laid out as the static-scratch variant lays it out
+  const size_t need = partition_scratch(n, p, nullptr, nullptr);
+  char* base = nullptr;
   Carver cv;
-  cv.add(sorted, std::max(n, 1));
-  cv.add(Yk, std::max(ny, 1));
-  cv.add(Yi, std::max(ny, 1));
-  cv.add(Ysk, std::max(ny, 1));
-  cv.add(Ysi, std::max(ny, 1));
-  cv.add(blk, (size_t)std::max(nblk, 1) * p);
-  cv.add(total, p);
+  cv.add(base, need);
   r = cv.carve(c);
   if (r) return r;
+  PartitionScratch ps{};
+  partition_scratch(n, p, base, &ps);
   r = reset_status(c, stream);
   if (r) return r;
-  launch_chunk_sort(d_key, n, p, sorted, stream);
-  launch_partition(d_key, n, p, sorted, Yk, Yi, Ysk, Ysi, d_pivot_key, d_pivot_id, d_bucket, blk,
-                   total, d_bucket_off, d_members, stream);
+  launch_partition_keys(d_key, n, p, ps, d_pivot_key, d_pivot_id, d_bucket, d_bucket_off,
+                        d_members, stream);
   return finish(c, stream);
 }
 

@@ -2,6 +2,8 @@
 // composite keys (K_i, i), a stable merge of the p sorted runs into Y, the
 // pivots Y_{p/2 + (t-1)p}, bucket ids by binary search over the pivots, and a
 // stable scatter of ids into buckets.
+#include <algorithm>
+
 #include "sad_internal.h"
 
 namespace sad {
@@ -142,13 +144,54 @@ void launch_partition(const uint64_t* key, int n, int p, const int32_t* sorted, 
                                                           pivot_id);
   }
   const int nblk = (n + kScatterBlock - 1) / kScatterBlock;
-  hipMemsetAsync(blk_cnt, 0, sizeof(int32_t) * (size_t)nblk * p, stream);
+  // cleared by a kernel (no memset node when a caller captures the launches)
+  launch_fill_i32(blk_cnt, 0, (int64_t)nblk * p, stream);
   bucket_kernel<<<nblk, kScatterBlock, 0, stream>>>(key, n, p, pivot_key, pivot_id, bucket,
                                                     blk_cnt);
   bucket_scan_blocks_kernel<<<(p + 255) / 256, 256, 0, stream>>>(blk_cnt, nblk, p, total);
   bucket_offsets_kernel<<<1, 1, 0, stream>>>(total, p, bucket_off);
   bucket_scatter_kernel<<<nblk, kScatterBlock, 0, stream>>>(bucket, n, p, blk_cnt, bucket_off,
                                                             members);
+}
+
+// Scratch of the partition of n ids into p buckets: the chunk order, the
+// p(p-1) regular samples and their sorted copy, per-block bucket counts and
+// bucket totals, each 256-byte aligned.  Returns the bytes; carves them from
+// base when it is not null.
+size_t partition_scratch(int n, int p, char* base, PartitionScratch* ps) {
+  const size_t ny = (size_t)p * (size_t)(p - 1);
+  const size_t nblk = ((size_t)n + kScatterBlock - 1) / kScatterBlock;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base ? base + off : nullptr;
+    off += (std::max(bytes, (size_t)1) + 255) & ~(size_t)255;
+    return q;
+  };
+  char* sorted = take(sizeof(int32_t) * (size_t)n);
+  char* yk = take(sizeof(uint64_t) * ny);
+  char* yi = take(sizeof(int32_t) * ny);
+  char* ysk = take(sizeof(uint64_t) * ny);
+  char* ysi = take(sizeof(int32_t) * ny);
+  char* blk = take(sizeof(int32_t) * nblk * (size_t)p);
+  char* total = take(sizeof(int32_t) * (size_t)p);
+  if (base && ps) {
+    ps->sorted = reinterpret_cast<int32_t*>(sorted);
+    ps->Yk = reinterpret_cast<uint64_t*>(yk);
+    ps->Yi = reinterpret_cast<int32_t*>(yi);
+    ps->Ysk = reinterpret_cast<uint64_t*>(ysk);
+    ps->Ysi = reinterpret_cast<int32_t*>(ysi);
+    ps->blk = reinterpret_cast<int32_t*>(blk);
+    ps->total = reinterpret_cast<int32_t*>(total);
+  }
+  return off;
+}
+
+void launch_partition_keys(const uint64_t* key, int n, int p, const PartitionScratch& ps,
+                           uint64_t* pivot_key, int32_t* pivot_id, int32_t* bucket,
+                           int32_t* bucket_off, int32_t* members, hipStream_t stream) {
+  launch_chunk_sort(key, n, p, ps.sorted, stream);
+  launch_partition(key, n, p, ps.sorted, ps.Yk, ps.Yi, ps.Ysk, ps.Ysi, pivot_key, pivot_id,
+                   bucket, ps.blk, ps.total, bucket_off, members, stream);
 }
 
 }  // namespace sad

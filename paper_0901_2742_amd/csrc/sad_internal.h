@@ -110,6 +110,20 @@ void launch_partition(const uint64_t* key, int n, int p, const int32_t* sorted,
                       uint64_t* pivot_key, int32_t* pivot_id, int32_t* bucket,
                       int32_t* blk_cnt, int32_t* total, int32_t* bucket_off, int32_t* members,
                       hipStream_t stream);
+struct PartitionScratch {
+  int32_t* sorted;          // [n] ids in (key, id) order within each chunk
+  uint64_t *Yk, *Ysk;       // [p (p - 1)] regular samples, then sorted
+  int32_t *Yi, *Ysi;
+  int32_t* blk;             // [blocks x p] per-block bucket counts
+  int32_t* total;           // [p]
+};
+size_t partition_scratch(int n, int p, char* base, PartitionScratch* ps);
+// chunk sort + partition of n ids with keys `key` into p buckets
+void launch_partition_keys(const uint64_t* key, int n, int p, const PartitionScratch& ps,
+                           uint64_t* pivot_key, int32_t* pivot_id, int32_t* bucket,
+                           int32_t* bucket_off, int32_t* members, hipStream_t stream);
+// records a failure for sad_last_error() and returns code (api.hip)
+int32_t report_error(int32_t code, const std::string& msg);
 
 // upgma.hip: one workgroup per group; F given per group at fm_off (n_g x n_g).
 // alignment quality against homology classes (quality.hip): sums[0] aligned
