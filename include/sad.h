@@ -15,10 +15,20 @@
  *  - Pointers named d_* are device pointers (HBM of the current HIP device);
  *    everything else is host memory.  All arrays are owned by the caller; the
  *    library never frees or keeps them.  Inputs are read-only.
- *  - The library allocates its own transient device workspace (grown on
- *    demand, kept per device until sad_release()).
+ *  - Device workspace of the four stage calls is caller-owned: each call takes
+ *    (d_ws, ws_bytes), a 256-byte aligned device block that it uses only
+ *    while it runs (nothing in it survives the call), sized by the call's
+ *    sad_*_workspace query.  A block that turns out too small gives
+ *    SAD_E_CAPACITY, and sad_workspace_needed() then returns a size that
+ *    suffices.  d_ws = NULL (ws_bytes = 0) lets the library use its own
+ *    per-device workspace instead (grown on demand, kept until sad_release());
+ *    the other calls always do.  Besides workspaces the library keeps, per
+ *    device, a status word, pinned host staging, the alignment engine's
+ *    boundary-row areas (zeroed once; tags in them must only grow) and the
+ *    autotuner's cache, for the life of the process.
  *  - Work is enqueued on `stream`; each call synchronises that stream before
- *    it returns so that it can report device-side errors in its status.
+ *    it returns so that it can report device-side errors in its status
+ *    (except sad_partition_noalloc).
  *  - Residue codes are 0..A-1 (A = 20 proteins, A = 4 DNA).  A k-mer tau of
  *    a sequence x at position t is sum_u x[t+u] * A^(k-1-u); A^k <= 65536.
  *  - Limits: sequence length <= 8192; profile width <= 4096 columns; at most
@@ -105,7 +115,10 @@ typedef struct sad_msa {
  */
 int32_t sad_kmer_rank(const sad_seqs* seqs, const sad_params* prm, uint64_t* d_key,
                       int32_t* d_sample_ids, int32_t sample_cap, int32_t* n_samples,
-                      hipStream_t stream);
+                      void* d_ws, size_t ws_bytes, hipStream_t stream);
+/* Workspace of sad_kmer_rank (exact): k-mer lists of every sequence, local
+ * ranks and the chunk order; about 4 total_len + 16 n bytes. */
+int32_t sad_kmer_rank_workspace(const sad_seqs* seqs, const sad_params* prm, size_t* ws_bytes);
 
 /*
  * Rank against a given sample (Section 2.3.1, Table 1): d_key[i] = sum over
@@ -134,7 +147,12 @@ int32_t sad_rank_against(const sad_seqs* seqs, int32_t kmer_k, const int32_t* d_
  */
 int32_t sad_partition(const sad_seqs* seqs, const uint64_t* d_key, const sad_params* prm,
                       uint64_t* d_pivot_key, int32_t* d_pivot_id, int32_t* d_bucket,
-                      int32_t* d_bucket_off, int32_t* d_members, hipStream_t stream);
+                      int32_t* d_bucket_off, int32_t* d_members, void* d_ws, size_t ws_bytes,
+                      hipStream_t stream);
+/* Workspace of sad_partition (exact): the chunk order, the p(p-1) regular
+ * samples and their sorted copy, per-block bucket counts; about
+ * 4n + 24 p(p-1) + 4 p ceil(n/256) bytes. */
+int32_t sad_partition_workspace(const sad_seqs* seqs, const sad_params* prm, size_t* ws_bytes);
 
 /*
  * sad_partition without allocation, for callers that cannot allocate device
@@ -178,7 +196,18 @@ int32_t sad_partition_noalloc(const sad_seqs* seqs, const uint64_t* d_key,
  */
 int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_bucket_off,
                           const int32_t* d_members, const sad_params* prm, sad_msa* out,
-                          hipStream_t stream);
+                          void* d_ws, size_t ws_bytes, hipStream_t stream);
+/* Workspace of sad_align_buckets that suffices for any input with these
+ * buckets, under any schedule (reads the p+1 offsets, synchronising
+ * `stream`): k-mer lists, the bucket similarity matrices and UPGMA sums
+ * (12 sum n_b^2 bytes), and the alignment engine sized for the worst case:
+ * profile pools for every merge of W1 + W2 <= min(8192, (leaves below) *
+ * max_len) columns, tie bytes and boundary rows for 4096-column profiles per
+ * persistent workgroup.  Typical inputs use a small part of it; the engine's
+ * pools take whatever space the other buffers leave, so a smaller block
+ * often suffices (else SAD_E_CAPACITY, see sad_workspace_needed). */
+int32_t sad_align_buckets_workspace(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                                    const sad_params* prm, size_t* ws_bytes, hipStream_t stream);
 
 /*
  * Stage 4 -- global ancestor, ancestor-constrained refinement and glue
@@ -200,7 +229,17 @@ int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_bucket_off,
 int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off, const int32_t* d_members,
                    const sad_msa* buckets, const sad_params* prm, uint8_t* d_ga,
                    int32_t ga_cap, int32_t* ga_len, sad_msa* global_out, int32_t* n_steps,
-                   hipStream_t stream);
+                   void* d_ws, size_t ws_bytes, hipStream_t stream);
+/* Workspace of sad_refine and sad_refine_template (either template) that
+ * suffices for these stage-3 results (reads the p+1 offsets and p widths of
+ * `buckets`, synchronising `stream`): bucket profiles, ancestors, GA and the
+ * refinement's op strings and glue tables for a template of up to
+ * min(4096, sum of widths) columns, then the larger of the ancestors' stage
+ * (similarity matrix, guide tree, engine at its worst-case size) and the
+ * refinement engine. */
+int32_t sad_refine_workspace(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                             const sad_msa* buckets, const sad_params* prm, size_t* ws_bytes,
+                             hipStream_t stream);
 
 /*
  * Stage 4 with a choice of template.  SAD_TEMPLATE_GA is sad_refine.
@@ -218,7 +257,7 @@ int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bucket_off,
                             const int32_t* d_members, const sad_msa* buckets,
                             const sad_params* prm, int32_t tmpl, uint8_t* d_ga, int32_t ga_cap,
                             int32_t* ga_len, sad_msa* global_out, int32_t* n_steps,
-                            hipStream_t stream);
+                            void* d_ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Tree-dependent refinement of the glued alignment (the refinement of the
@@ -313,6 +352,11 @@ int32_t sad_profile_jobs(int64_t* out, int64_t cap, int64_t* njobs);
 
 /* Graph captures and replays of sad_align_buckets since the last reset. */
 int32_t sad_profile_graphs(int64_t* captured, int64_t* replayed, int32_t reset);
+
+/* After a stage call on this thread returned SAD_E_CAPACITY because its
+ * caller workspace was too small: a workspace size that suffices for the
+ * same call (0 otherwise). */
+size_t sad_workspace_needed(void);
 
 /* Message for the calling thread's last non-OK status (static storage). */
 const char* sad_last_error(void);

@@ -26,7 +26,9 @@ SAD_PLAIN = 0
 SAD_BATCHED_MFMA = 1
 
 # the functions include/sad.h declares
-EXPORTS = ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_partition_noalloc", "sad_align_buckets", "sad_refine", "sad_refine_template", "sad_refine_tree", "sad_tune",
+EXPORTS = ("sad_kmer_rank", "sad_kmer_rank_workspace", "sad_rank_against", "sad_partition",
+           "sad_partition_workspace", "sad_partition_noalloc", "sad_align_buckets_workspace",
+           "sad_refine_workspace", "sad_workspace_needed", "sad_align_buckets", "sad_refine", "sad_refine_template", "sad_refine_tree", "sad_tune",
            "sad_quality",
            "sad_profile_enable", "sad_profile_read", "sad_profile_phases", "sad_profile_jobs", "sad_profile_graphs",
            "sad_last_error",
@@ -71,13 +73,23 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         I32 = ctypes.c_int32
-        L.sad_kmer_rank.argtypes = [P, P, P, P, I32, P, P]
+        SZ = ctypes.c_size_t
+        L.sad_kmer_rank.argtypes = [P, P, P, P, I32, P, P, SZ, P]
         L.sad_rank_against.argtypes = [P, I32, P, I32, P, P]
-        L.sad_partition.argtypes = [P, P, P, P, P, P, P, P, P]
+        L.sad_partition.argtypes = [P, P, P, P, P, P, P, P, P, SZ, P]
         L.sad_partition_noalloc.argtypes = [P, P, P, P, P, P, P, P, P]
-        L.sad_align_buckets.argtypes = [P, P, P, P, P, P]
-        L.sad_refine.argtypes = [P, P, P, P, P, P, I32, P, P, P, P]
-        L.sad_refine_template.argtypes = [P, P, P, P, P, I32, P, I32, P, P, P, P]
+        L.sad_align_buckets.argtypes = [P, P, P, P, P, P, SZ, P]
+        L.sad_refine.argtypes = [P, P, P, P, P, P, I32, P, P, P, P, SZ, P]
+        L.sad_refine_template.argtypes = [P, P, P, P, P, I32, P, I32, P, P, P, P, SZ, P]
+        L.sad_kmer_rank_workspace.argtypes = [P, P, P]
+        L.sad_partition_workspace.argtypes = [P, P, P]
+        L.sad_align_buckets_workspace.argtypes = [P, P, P, P, P]
+        L.sad_refine_workspace.argtypes = [P, P, P, P, P, P]
+        for f in ("sad_kmer_rank_workspace", "sad_partition_workspace",
+                  "sad_align_buckets_workspace", "sad_refine_workspace"):
+            getattr(L, f).restype = I32
+        L.sad_workspace_needed.argtypes = []
+        L.sad_workspace_needed.restype = SZ
         L.sad_refine_tree.argtypes = [P, P, P, P, P, I32, P, P, P, P, I32, P]
         for f in ("sad_kmer_rank", "sad_rank_against", "sad_partition", "sad_partition_noalloc",
                   "sad_align_buckets",
@@ -115,6 +127,63 @@ def _stream():
 def _check(code: int, call: str):
     if code != SAD_OK:
         raise SadError(code, call, lib().sad_last_error().decode(errors="replace"))
+
+
+# Device workspace of the four stage calls: caller-owned (a torch uint8
+# tensor per device, grown on demand and shared by the calls, which run one
+# after another on the current stream).  ws="library" passes NULL, letting the
+# library use its own workspace; a tensor is used as given.
+_WS: dict = {}
+
+
+def _ws_tensor(dev, nbytes: int) -> torch.Tensor:
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    t = _WS.get(idx)
+    if t is None or t.numel() < nbytes:
+        _WS.pop(idx, None)
+        # whole 2 MiB pages; torch's blocks are 512-byte aligned
+        size = max((nbytes + (2 << 20) - 1) // (2 << 20) * (2 << 20), 2 << 20)
+        t = torch.empty(size, dtype=torch.uint8, device=dev)
+        _WS[idx] = t
+    return t
+
+
+def release_workspace() -> None:
+    """Drops the binding's cached workspaces."""
+    _WS.clear()
+
+
+def _query(fn, *args, stream: bool = False) -> int:
+    """Calls a workspace query: (args..., size_t* ws_bytes[, stream])."""
+    n = ctypes.c_size_t(0)
+    tail = (ctypes.byref(n), _stream()) if stream else (ctypes.byref(n),)
+    _check(getattr(lib(), fn)(*args, *tail), fn)
+    return n.value
+
+
+def _with_ws(name: str, dev, ws, query, call):
+    """Runs call(ptr, nbytes) with the workspace choice `ws`; with the
+    binding's own workspace, sizes it by `query()` on first use and grows it
+    to sad_workspace_needed() after a capacity failure."""
+    if isinstance(ws, str):
+        if ws != "library":
+            raise ValueError("ws must be a tensor, None or 'library'")
+        code = call(None, 0)
+    elif ws is not None:
+        if ws.dtype != torch.uint8 or not ws.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor")
+        code = call(_ptr(ws), ws.numel())
+    else:
+        idx = dev.index if dev.index is not None else torch.cuda.current_device()
+        t = _WS.get(idx)
+        if t is None:
+            t = _ws_tensor(dev, query())
+        code = call(_ptr(t), t.numel())
+        need = lib().sad_workspace_needed()
+        if code == SAD_E_CAPACITY and need > t.numel():
+            t = _ws_tensor(dev, need)
+            code = call(_ptr(t), t.numel())
+    _check(code, name)
 
 
 @dataclasses.dataclass
@@ -160,10 +229,37 @@ class Params:
                          self.gap_extend, self.mode)
 
 
-def sad_kmer_rank(seqs: DeviceSeqs, prm: Params, out: dict | None = None):
+def sad_kmer_rank_workspace(seqs: DeviceSeqs, prm: Params) -> int:
+    s, p = seqs.c_struct(), prm.c_struct()
+    return _query("sad_kmer_rank_workspace", ctypes.byref(s), ctypes.byref(p))
+
+
+def sad_partition_workspace(seqs: DeviceSeqs, prm: Params) -> int:
+    s, p = seqs.c_struct(), prm.c_struct()
+    return _query("sad_partition_workspace", ctypes.byref(s), ctypes.byref(p))
+
+
+def sad_align_buckets_workspace(seqs: DeviceSeqs, bucket_off: torch.Tensor, prm: Params) -> int:
+    s, p = seqs.c_struct(), prm.c_struct()
+    return _query("sad_align_buckets_workspace", ctypes.byref(s), _ptr(bucket_off),
+                  ctypes.byref(p), stream=True)
+
+
+def sad_refine_workspace(seqs: DeviceSeqs, bucket_off: torch.Tensor, buckets: dict,
+                         prm: Params) -> int:
+    s, p, mb = seqs.c_struct(), prm.c_struct(), _msa_struct(buckets)
+    return _query("sad_refine_workspace", ctypes.byref(s), _ptr(bucket_off), ctypes.byref(mb),
+                  ctypes.byref(p), stream=True)
+
+
+def sad_workspace_needed() -> int:
+    return int(lib().sad_workspace_needed())
+
+
+def sad_kmer_rank(seqs: DeviceSeqs, prm: Params, out: dict | None = None, ws=None):
     """Stage 1: globalised k-mer rank.  Returns (key[n] uint64 as int64 tensor,
     sample_ids int32 tensor).  `out` (a dict, filled on first use) keeps the
-    output buffers across calls."""
+    output buffers across calls; `ws` chooses the workspace (see _with_ws)."""
     dev = seqs.codes.device
     cap = max(prm.s_max, prm.p) + prm.p
     if out is None:
@@ -174,9 +270,10 @@ def sad_kmer_rank(seqs: DeviceSeqs, prm: Params, out: dict | None = None):
     key, sid = out["key"], out["sid"]
     ns = ctypes.c_int32(0)
     s, p = seqs.c_struct(), prm.c_struct()
-    code = lib().sad_kmer_rank(ctypes.byref(s), ctypes.byref(p), _ptr(key), _ptr(sid), cap,
-                               ctypes.byref(ns), _stream())
-    _check(code, "sad_kmer_rank")
+    _with_ws("sad_kmer_rank", dev, ws, lambda: sad_kmer_rank_workspace(seqs, prm),
+             lambda w, nb: lib().sad_kmer_rank(ctypes.byref(s), ctypes.byref(p), _ptr(key),
+                                               _ptr(sid), cap, ctypes.byref(ns), w, nb,
+                                               _stream()))
     return key[:seqs.n], sid[:ns.value]
 
 
@@ -201,7 +298,7 @@ def sad_rank_against(seqs: DeviceSeqs, kmer_k: int, samples: torch.Tensor | None
 
 
 def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params, bufs: dict | None = None,
-                  noalloc: bool = False):
+                  noalloc: bool = False, ws=None):
     """Stage 2: pivots and buckets.  Returns a dict of device tensors; `bufs`
     (a dict, filled on first use) keeps the buffers across calls.  noalloc:
     call sad_partition_noalloc (static device scratch, no synchronisation)."""
@@ -216,12 +313,14 @@ def sad_partition(seqs: DeviceSeqs, key: torch.Tensor, prm: Params, bufs: dict |
                     bucket_off=torch.empty(p + 1, dtype=torch.int32, device=dev),
                     members=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
     s, pp = seqs.c_struct(), prm.c_struct()
-    name = "sad_partition_noalloc" if noalloc else "sad_partition"
-    code = getattr(lib(), name)(ctypes.byref(s), _ptr(key), ctypes.byref(pp),
-                                _ptr(bufs["pivot_key"]), _ptr(bufs["pivot_id"]),
-                                _ptr(bufs["bucket"]), _ptr(bufs["bucket_off"]),
-                                _ptr(bufs["members"]), _stream())
-    _check(code, name)
+    args = (ctypes.byref(s), _ptr(key), ctypes.byref(pp), _ptr(bufs["pivot_key"]),
+            _ptr(bufs["pivot_id"]), _ptr(bufs["bucket"]), _ptr(bufs["bucket_off"]),
+            _ptr(bufs["members"]))
+    if noalloc:
+        _check(lib().sad_partition_noalloc(*args, _stream()), "sad_partition_noalloc")
+    else:
+        _with_ws("sad_partition", dev, ws, lambda: sad_partition_workspace(seqs, prm),
+                 lambda w, nb: lib().sad_partition(*args, w, nb, _stream()))
     return dict(pivot_key=bufs["pivot_key"][:p - 1], pivot_id=bufs["pivot_id"][:p - 1],
                 bucket=bufs["bucket"][:n], bucket_off=bufs["bucket_off"],
                 members=bufs["members"][:n])
@@ -246,15 +345,17 @@ def _msa_struct(m: dict) -> SadMsa:
 
 
 def sad_align_buckets(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor,
-                      prm: Params, out: dict | None = None):
+                      prm: Params, out: dict | None = None, ws=None):
     """Stage 3: align every bucket.  Returns a dict of device tensors."""
     dev = seqs.codes.device
     if out is None:
         out = _msa_tensors(seqs.total_len, prm.p, seqs.n, dev)
     s, pp, m = seqs.c_struct(), prm.c_struct(), _msa_struct(out)
-    code = lib().sad_align_buckets(ctypes.byref(s), _ptr(bucket_off), _ptr(members),
-                                   ctypes.byref(pp), ctypes.byref(m), _stream())
-    _check(code, "sad_align_buckets")
+    _with_ws("sad_align_buckets", dev, ws,
+             lambda: sad_align_buckets_workspace(seqs, bucket_off, prm),
+             lambda w, nb: lib().sad_align_buckets(ctypes.byref(s), _ptr(bucket_off),
+                                                   _ptr(members), ctypes.byref(pp),
+                                                   ctypes.byref(m), w, nb, _stream()))
     return out
 
 
@@ -265,7 +366,7 @@ TEMPLATES = {"ga": SAD_TEMPLATE_GA, "ga_msa": SAD_TEMPLATE_GA_MSA}
 
 def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, buckets: dict,
                prm: Params, out: dict | None = None, ga_cap: int | None = None,
-               template: str = "ga"):
+               template: str = "ga", ws=None):
     """Stage 4: global ancestor, refinement and glue.  Returns a dict of device
     tensors plus ``ga_len`` and ``n_steps``.  template "ga" (sad_refine: GA as
     one row) or "ga_msa" (sad_refine_template: the ancestors' alignment)."""
@@ -284,17 +385,19 @@ def sad_refine(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor
     nst = ctypes.c_int32(0)
     s, pp = seqs.c_struct(), prm.c_struct()
     mb, mg = _msa_struct(buckets), _msa_struct(out)
+    query = lambda: sad_refine_workspace(seqs, bucket_off, buckets, prm)  # noqa: E731
     if template == "ga":
-        code = lib().sad_refine(ctypes.byref(s), _ptr(bucket_off), _ptr(members),
-                                ctypes.byref(mb), ctypes.byref(pp), _ptr(ga), ga_cap,
-                                ctypes.byref(gl), ctypes.byref(mg), ctypes.byref(nst), _stream())
-        _check(code, "sad_refine")
+        _with_ws("sad_refine", dev, ws, query,
+                 lambda w, nb: lib().sad_refine(ctypes.byref(s), _ptr(bucket_off), _ptr(members),
+                                                ctypes.byref(mb), ctypes.byref(pp), _ptr(ga),
+                                                ga_cap, ctypes.byref(gl), ctypes.byref(mg),
+                                                ctypes.byref(nst), w, nb, _stream()))
     else:
-        code = lib().sad_refine_template(ctypes.byref(s), _ptr(bucket_off), _ptr(members),
-                                         ctypes.byref(mb), ctypes.byref(pp), TEMPLATES[template],
-                                         _ptr(ga), ga_cap, ctypes.byref(gl), ctypes.byref(mg),
-                                         ctypes.byref(nst), _stream())
-        _check(code, "sad_refine_template")
+        _with_ws("sad_refine_template", dev, ws, query,
+                 lambda w, nb: lib().sad_refine_template(
+                     ctypes.byref(s), _ptr(bucket_off), _ptr(members), ctypes.byref(mb),
+                     ctypes.byref(pp), TEMPLATES[template], _ptr(ga), ga_cap, ctypes.byref(gl),
+                     ctypes.byref(mg), ctypes.byref(nst), w, nb, _stream()))
     out["ga_len"] = gl.value
     out["n_steps"] = nst.value
     return out

@@ -48,6 +48,36 @@ static std::mutex g_mu;
 static std::vector<DeviceCtx> g_ctx;
 static thread_local std::string g_err;
 
+// Caller-owned device workspace of the running call (null: the library's own
+// arenas).  Buffers that live across the engine runs of one call take the
+// first `keep` bytes, per-step buffers the rest.
+struct CallWs {
+  char* base = nullptr;
+  size_t bytes = 0;
+  size_t keep = 0;
+  size_t bound = 0;  // a size that suffices for this call, once known
+};
+static thread_local CallWs* g_ws = nullptr;
+static thread_local size_t g_ws_needed = 0;  // sad_workspace_needed()
+
+// Installs the caller's workspace for the duration of one call.
+struct WsScope {
+  CallWs w;
+  CallWs* prev;
+  WsScope(void* base, size_t bytes) : prev(g_ws) {
+    if (base) {
+      w.base = static_cast<char*>(base);
+      w.bytes = bytes;
+      g_ws = &w;
+    } else {
+      g_ws = nullptr;
+    }
+  }
+  ~WsScope() { g_ws = prev; }
+  WsScope(const WsScope&) = delete;
+  WsScope& operator=(const WsScope&) = delete;
+};
+
 // engine-kernel timing (sad_profile_enable / sad_profile_read)
 static bool g_prof_on = false;   // engine kernel timing (HIP events)
 static bool g_phase_on = false;  // per-phase ticks and per-job records
@@ -195,9 +225,42 @@ struct Carver {
     }
     return SAD_OK;
   }
-  int32_t carve(DeviceCtx* c) { return carve_into(&c->arena, &c->cap); }
-  int32_t carve_keep(DeviceCtx* c) { return carve_into(&c->keep, &c->keep_cap); }
+  // Fixed region [base, base + cap) of a caller workspace, with `others`
+  // bytes of the workspace outside it: no growth; a shortfall is
+  // SAD_E_CAPACITY, and sad_workspace_needed() reports others + the region's
+  // need.
+  int32_t carve_fixed(char* base, size_t cap, size_t others) {
+    const size_t need = total();
+    if (need > cap) {
+      g_ws_needed = std::max(g_ws_needed, std::max(others + need, g_ws ? g_ws->bound : 0));
+      return fail(SAD_E_CAPACITY, "caller workspace too small: " +
+                                      std::to_string(others + need) + " bytes needed");
+    }
+    size_t off = 0;
+    for (auto& r : reqs) {
+      *r.ptr = base + off;
+      off += (r.bytes + 255) & ~size_t(255);
+    }
+    return SAD_OK;
+  }
+  int32_t carve(DeviceCtx* c) {
+    if (g_ws) return carve_fixed(g_ws->base + g_ws->keep, g_ws->bytes - g_ws->keep, g_ws->keep);
+    return carve_into(&c->arena, &c->cap);
+  }
+  int32_t carve_keep(DeviceCtx* c) {
+    if (g_ws) return carve_fixed(g_ws->base, g_ws->keep, g_ws->bytes - g_ws->keep);
+    return carve_into(&c->keep, &c->keep_cap);
+  }
 };
+
+// Checks a caller workspace argument and installs nothing (WsScope does).
+static int32_t check_ws(void* d_ws, size_t ws_bytes) {
+  g_ws_needed = 0;
+  if (d_ws && (reinterpret_cast<uintptr_t>(d_ws) & 255))
+    return fail(SAD_E_INVAL, "workspace must be 256-byte aligned");
+  if (!d_ws && ws_bytes) return fail(SAD_E_INVAL, "null workspace with a nonzero size");
+  return SAD_OK;
+}
 
 static const char* where_name(int32_t w) {
   switch (w) {
@@ -467,6 +530,49 @@ static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, in
   cv.add(e.up_pool, (size_t)up_cap);
   cv.add(e.tb, (size_t)e.nwg * (size_t)e.tb_words);
   cv.add(e.bnd, (size_t)e.nwg * (size_t)e.link_words);
+}
+
+// Largest persistent grid any schedule launches (plain mode tunes up to 3
+// workgroups per CU; SAD_ENGINE_WGS_PER_CU raises the default).
+static int max_grid(uint32_t mode) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return std::max(engine_workgroups(), mode == SAD_PLAIN ? 3 * cus : cus);
+}
+
+// Columns the profile pools of a set of trees can take: the leaves' own
+// columns, then per internal node W1 + W2 <= 2 kMaxWidth columns (a wider
+// child fails its merge before the parent allocates).  The t-th largest
+// internal node of a tree with m leaves has at most m - t + 1 leaves (the
+// internal nodes with at least s leaves form a subtree of at most m - s + 1
+// nodes), so it holds at most (m - t + 1) max_len columns.
+static int64_t pool_cols_bound(const std::vector<int32_t>& goff, int max_len, int64_t total_len) {
+  int64_t cols = total_len + 4096;
+  for (size_t g = 0; g + 1 < goff.size(); ++g) {
+    const int m = goff[g + 1] - goff[g];
+    for (int t = 2; t <= m; ++t) cols += std::min<int64_t>(2 * kMaxWidth, (int64_t)t * max_len);
+  }
+  return cols;
+}
+
+// Engine workspace (after the buffers in `base`) that suffices for any
+// alignment of the groups of leaves in goff: the pool bound above, tie-byte
+// scratch and boundary rows for kMaxWidth-column profiles in 64-bit values,
+// the largest grid.
+static size_t engine_bound_bytes(const Carver& base, const std::vector<int32_t>& goff,
+                                 int max_len, int64_t total_len, int A, uint32_t mode) {
+  const int N = goff.empty() ? 0 : goff.back();
+  int njobs = 0;
+  for (size_t g = 0; g + 1 < goff.size(); ++g) njobs += std::max(0, goff[g + 1] - goff[g] - 1);
+  const int64_t cols = pool_cols_bound(goff, max_len, total_len);
+  Carver cv = base;
+  EngineBuffers e{};
+  plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, cols * A, cols, kMaxWidth, true,
+              max_grid(mode));
+  return cv.total();
 }
 
 // Boundary rows of cooperative merges cross workgroups (and L2 slices), so
@@ -869,6 +975,26 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     // reaches 2^29 (n1 + n2 at most the largest group)
     const double g2 = std::floor(max_group / 2.0) * std::ceil(max_group / 2.0);
     const bool wide_links = (2.0 * wcap + 2.0) * g2 * unit >= (double)(1 << 29);
+    if (g_ws) {
+      // caller workspace: the profile pools take all the space the other
+      // buffers leave, so a pool shortfall means the workspace is too small
+      Carver probe = base_cv;
+      EngineBuffers pe{};
+      plan_engine(probe, pe, 2 * std::max(N, 1), std::max(N, 1), njobs, 0, 0, wcap, wide_links,
+                  grid);
+      const size_t avail = g_ws->bytes - g_ws->keep, fixed = probe.total() + 512;
+      const int64_t cols = fixed < avail ? (int64_t)((avail - fixed) / (2 * A + 4)) : 0;
+      if (cols <= ts.total_len) {
+        g_ws_needed = std::max(g_ws_needed,
+                               g_ws->keep + engine_bound_bytes(base_cv, ts.h_group_off,
+                                                               ts.max_len, ts.total_len, A,
+                                                               prm->mode));
+        return fail(SAD_E_CAPACITY, "caller workspace too small for the alignment engine: " +
+                                        std::to_string(g_ws_needed) + " bytes suffice");
+      }
+      prof_cap = cols * A;
+      up_cap = cols;
+    }
     plan_engine(cv, e, 2 * std::max(N, 1), std::max(N, 1), njobs, prof_cap, up_cap, wcap,
                 wide_links, grid);
     int32_t r = cv.carve(c);
@@ -1014,6 +1140,14 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
         (d.where == W_ENGINE_POOL ||
          ((d.where == W_ENGINE_TB || d.where == W_ENGINE_LINK) && wcap < kMaxWidth))) {
       if (d.where == W_ENGINE_POOL) {
+        if (g_ws) {
+          g_ws_needed = std::max(g_ws_needed,
+                                 g_ws->keep + engine_bound_bytes(base_cv, ts.h_group_off,
+                                                                 ts.max_len, ts.total_len, A,
+                                                                 prm->mode));
+          return fail(SAD_E_CAPACITY, "caller workspace too small for the profile pools: " +
+                                          std::to_string(g_ws_needed) + " bytes suffice");
+        }
         prof_cap *= 2;
         up_cap *= 2;
       } else {
@@ -1079,11 +1213,40 @@ static Schedule schedule_for(const TuneKey& k) {
 
 using namespace sad;
 
+namespace sad {
+struct KmerRankBufs {
+  uint32_t* entries;
+  int32_t *nu, *sorted;
+  uint64_t* kloc;
+};
+static void plan_kmer_rank(Carver& cv, KmerRankBufs& b, int n, int64_t total_len) {
+  cv.add(b.entries, (size_t)std::max<int64_t>(total_len, 1));
+  cv.add(b.nu, std::max(n, 1));
+  cv.add(b.kloc, std::max(n, 1));
+  cv.add(b.sorted, std::max(n, 1));
+}
+}  // namespace sad
+
+extern "C" int32_t sad_kmer_rank_workspace(const sad_seqs* seqs, const sad_params* prm,
+                                           size_t* ws_bytes) {
+  if (!prm || !ws_bytes) return fail(SAD_E_INVAL, "null argument");
+  int32_t r = check_seqs(seqs, prm->kmer_k);
+  if (r) return r;
+  Carver cv;
+  KmerRankBufs b{};
+  plan_kmer_rank(cv, b, seqs->n, seqs->total_len);
+  *ws_bytes = cv.total();
+  return SAD_OK;
+}
+
 extern "C" int32_t sad_kmer_rank(const sad_seqs* seqs, const sad_params* prm, uint64_t* d_key,
                                  int32_t* d_sample_ids, int32_t sample_cap, int32_t* n_samples,
-                                 hipStream_t stream) {
+                                 void* d_ws, size_t ws_bytes, hipStream_t stream) {
   if (!prm) return fail(SAD_E_INVAL, "null params");
-  int32_t r = check_seqs(seqs, prm->kmer_k);
+  int32_t r = check_ws(d_ws, ws_bytes);
+  if (r) return r;
+  WsScope wss(d_ws, ws_bytes);
+  r = check_seqs(seqs, prm->kmer_k);
   if (r) return r;
   r = check_params(prm, seqs->alphabet, false);
   if (r) return r;
@@ -1103,16 +1266,14 @@ extern "C" int32_t sad_kmer_rank(const sad_seqs* seqs, const sad_params* prm, ui
   r = validate_on_device(c, seqs, k, stream);
   if (r) return r;
   const int kspace = (int)kmer_space(A, k);
-  uint32_t* entries;
-  int32_t *nu, *sorted;
-  uint64_t* kloc;
   Carver cv;
-  cv.add(entries, (size_t)std::max<int64_t>(seqs->total_len, 1));
-  cv.add(nu, std::max(n, 1));
-  cv.add(kloc, std::max(n, 1));
-  cv.add(sorted, std::max(n, 1));
+  KmerRankBufs b{};
+  plan_kmer_rank(cv, b, n, seqs->total_len);
   r = cv.carve(c);
   if (r) return r;
+  uint32_t* entries = b.entries;
+  int32_t *nu = b.nu, *sorted = b.sorted;
+  uint64_t* kloc = b.kloc;
   r = reset_status(c, stream);
   if (r) return r;
   launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st, stream);
@@ -1155,11 +1316,28 @@ extern "C" int32_t sad_rank_against(const sad_seqs* seqs, int32_t kmer_k,
   return finish(c, stream);
 }
 
+extern "C" int32_t sad_partition_workspace(const sad_seqs* seqs, const sad_params* prm,
+                                           size_t* ws_bytes) {
+  if (!seqs || !prm || !ws_bytes) return fail(SAD_E_INVAL, "null argument");
+  int32_t r = check_params(prm, seqs->alphabet, false);
+  if (r) return r;
+  if (seqs->n < 2 * prm->p) return fail(SAD_E_INVAL, "need N >= 2p");
+  char* base = nullptr;
+  Carver cv;
+  cv.add(base, partition_scratch(seqs->n, prm->p, nullptr, nullptr));
+  *ws_bytes = cv.total();
+  return SAD_OK;
+}
+
 extern "C" int32_t sad_partition(const sad_seqs* seqs, const uint64_t* d_key, const sad_params* prm,
                                  uint64_t* d_pivot_key, int32_t* d_pivot_id, int32_t* d_bucket,
-                                 int32_t* d_bucket_off, int32_t* d_members, hipStream_t stream) {
+                                 int32_t* d_bucket_off, int32_t* d_members, void* d_ws,
+                                 size_t ws_bytes, hipStream_t stream) {
   if (!seqs || !prm) return fail(SAD_E_INVAL, "null argument");
-  int32_t r = check_params(prm, seqs->alphabet, false);
+  int32_t r = check_ws(d_ws, ws_bytes);
+  if (r) return r;
+  WsScope wss(d_ws, ws_bytes);
+  r = check_params(prm, seqs->alphabet, false);
   if (r) return r;
   const int n = seqs->n, p = prm->p;
   if (n < 2 * p) return fail(SAD_E_INVAL, "need N >= 2p");
@@ -1184,11 +1362,83 @@ extern "C" int32_t sad_partition(const sad_seqs* seqs, const uint64_t* d_key, co
   return finish(c, stream);
 }
 
+namespace sad {
+// k-mer lists, bucket similarity matrices and (trees by a separate kernel)
+// the UPGMA pair sums of the bucket alignment
+struct AlignBufs {
+  uint32_t *entries, *F;
+  int32_t* nu;
+  int64_t* d_fm_off;
+  uint64_t* Sw;
+};
+static void plan_align(Carver& cv, AlignBufs& b, int n, int p, int64_t total_len,
+                       int64_t fm_total, bool with_sums) {
+  cv.add(b.entries, (size_t)std::max<int64_t>(total_len, 1));
+  cv.add(b.nu, std::max(n, 1));
+  cv.add(b.d_fm_off, std::max(p, 1));
+  cv.add(b.F, (size_t)std::max<int64_t>(fm_total, 1));
+  if (with_sums) cv.add(b.Sw, (size_t)std::max<int64_t>(fm_total, 1));
+}
+
+// Checks the bucket offsets read from the device; sums of squared sizes and
+// the largest bucket.
+static int32_t bucket_shape(const std::vector<int32_t>& off, int n, int p, int64_t* fm_total,
+                            int* max_n) {
+  if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
+  *fm_total = 0;
+  *max_n = 0;
+  for (int b = 0; b < p; ++b) {
+    const int nb = off[b + 1] - off[b];
+    if (nb < 0) return fail(SAD_E_INVAL, "bucket offsets must be non-decreasing");
+    *fm_total += (int64_t)nb * nb;
+    *max_n = std::max(*max_n, nb);
+  }
+  return SAD_OK;
+}
+
+// Workspace that suffices for sad_align_buckets on these buckets under any
+// schedule (trees inside the launch or by a separate kernel, any grid).
+static size_t align_bound(const sad_seqs* seqs, const std::vector<int32_t>& off, int p,
+                          int64_t fm_total, int A, uint32_t mode) {
+  Carver base;
+  AlignBufs b{};
+  plan_align(base, b, seqs->n, p, seqs->total_len, fm_total, true);
+  return engine_bound_bytes(base, off, seqs->max_len, seqs->total_len, A, mode);
+}
+}  // namespace sad
+
+extern "C" int32_t sad_align_buckets_workspace(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                                               const sad_params* prm, size_t* ws_bytes,
+                                               hipStream_t stream) {
+  if (!prm || !ws_bytes) return fail(SAD_E_INVAL, "null argument");
+  int32_t r = check_seqs(seqs, prm->kmer_k);
+  if (r) return r;
+  r = check_params(prm, seqs->alphabet, false);
+  if (r) return r;
+  if (!d_bucket_off) return fail(SAD_E_INVAL, "null device array");
+  DeviceCtx* c = nullptr;
+  r = get_ctx(&c);
+  if (r) return r;
+  std::vector<int32_t> off;
+  r = reset_status(c, stream);
+  if (!r) r = finish_read(c, stream, d_bucket_off, (size_t)prm->p + 1, off);
+  if (r) return r;
+  int64_t fm_total = 0;
+  int max_n = 0;
+  r = bucket_shape(off, seqs->n, prm->p, &fm_total, &max_n);
+  if (r) return r;
+  *ws_bytes = align_bound(seqs, off, prm->p, fm_total, seqs->alphabet, prm->mode);
+  return SAD_OK;
+}
+
 extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_bucket_off,
                                      const int32_t* d_members, const sad_params* prm, sad_msa* out,
-                                     hipStream_t stream) {
+                                     void* d_ws, size_t ws_bytes, hipStream_t stream) {
   if (!prm || !out) return fail(SAD_E_INVAL, "null argument");
-  int32_t r = check_seqs(seqs, prm->kmer_k);
+  int32_t r = check_ws(d_ws, ws_bytes);
+  if (r) return r;
+  WsScope wss(d_ws, ws_bytes);
+  r = check_seqs(seqs, prm->kmer_k);
   if (r) return r;
   r = check_params(prm, seqs->alphabet, true);
   if (r) return r;
@@ -1202,34 +1452,34 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   std::vector<int32_t> off;
   r = validate_read(c, seqs, k, stream, d_bucket_off, (size_t)p + 1, off);
   if (r) return r;
-  if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
   int64_t fm_total = 0;
   int max_n = 0;
+  r = bucket_shape(off, n, p, &fm_total, &max_n);
+  if (r) return r;
   std::vector<int64_t> fm_off(p);
-  for (int b = 0; b < p; ++b) {
-    int nb = off[b + 1] - off[b];
-    if (nb < 0) return fail(SAD_E_INVAL, "bucket offsets must be non-decreasing");
-    fm_off[b] = fm_total;
-    fm_total += (int64_t)nb * nb;
-    max_n = std::max(max_n, nb);
+  {
+    int64_t acc = 0;
+    for (int b = 0; b < p; ++b) {
+      const int64_t nb = off[b + 1] - off[b];
+      fm_off[b] = acc;
+      acc += nb * nb;
+    }
   }
   if (max_n > kMaxGroup) return fail(SAD_E_CAPACITY, "bucket larger than the library limit");
+  if (g_ws) g_ws->bound = align_bound(seqs, off, p, fm_total, A, prm->mode);
   const int kspace = (int)kmer_space(A, k);
-  uint32_t *entries, *F;
-  int32_t* nu;
-  int64_t* d_fm_off;
-  uint64_t* Sw;
   // batched mode with small enough buckets: the guide trees are built inside
   // the engine launch, which starts aligning each merge as soon as it is known
   const Schedule sched = schedule_for(TuneKey{A, n, p, (int)prm->mode, max_n, seqs->total_len});
   const bool fuse = prm->mode == SAD_BATCHED_MFMA && max_n <= engine_fused_max_group() &&
                     sched.fuse != 0;
   Carver cv;
-  cv.add(entries, (size_t)std::max<int64_t>(seqs->total_len, 1));
-  cv.add(nu, std::max(n, 1));
-  cv.add(d_fm_off, std::max(p, 1));
-  cv.add(F, (size_t)std::max<int64_t>(fm_total, 1));
-  if (!fuse) cv.add(Sw, (size_t)std::max<int64_t>(fm_total, 1));
+  AlignBufs ab{};
+  plan_align(cv, ab, n, p, seqs->total_len, fm_total, !fuse);
+  uint32_t *&entries = ab.entries, *&F = ab.F;
+  int32_t*& nu = ab.nu;
+  int64_t*& d_fm_off = ab.d_fm_off;
+  uint64_t*& Sw = ab.Sw;
   // k-mer lists and per-bucket similarity matrices into the carved buffers
   auto upload = [&]() -> int32_t { return h2d(fm_off, d_fm_off, stream); };
   auto kernels = [&](hipStream_t st) {
@@ -1321,7 +1571,7 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
     for (int rep = 0; rep < 4 && r == SAD_OK; ++rep) {
       float t = 0.0f;
       if (hipEventRecord(e0, stream) != hipSuccess) r = fail(SAD_E_DEVICE, "event record");
-      if (!r) r = sad_align_buckets(seqs, d_bucket_off, d_members, prm, out, stream);
+      if (!r) r = sad_align_buckets(seqs, d_bucket_off, d_members, prm, out, nullptr, 0, stream);
       if (!r && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                  hipEventElapsedTime(&t, e0, e1) != hipSuccess))
         r = fail(SAD_E_DEVICE, "event timing");
@@ -1389,6 +1639,100 @@ __global__ void refine_results_kernel(int q, const int64_t* __restrict__ ga_scor
   *total = tot;
 }
 
+// Buffers of the refinement that live across its engine runs: bucket
+// profiles, ancestors, the ancestors' guide tree and GA (plan_refine_keep),
+// then the refinement's op strings and the glue's slot tables once the
+// template's width TL is known (plan_refine_keep2, carved with the same
+// prefix so the earlier buffers keep their addresses).
+struct RefineKeep {
+  int32_t *d_uidx, *d_bucket_of_u, *d_width_u, *d_rows_u, *anc_len, *cons_list, *ga_goff,
+      *ga_merges, *ga_list, *ga_len_d, *to_g, *tl_d, *cnode_W, *cnode_n;
+  int64_t *d_wo, *anc_off, *stage_off, *ga_score, *ga_cells, *ga_cells_tot, *ga_off0,
+      *cnode_prof;
+  uint32_t* cnt32;
+  uint16_t *prof16, *tmpl16;
+  uint8_t *anc_stage, *anc_codes, *ga_stage;
+  // second part
+  uint8_t* rf_ops;
+  int64_t* rf_ops_off;
+  int32_t *ins, *used, *slot_total, *slot_start, *shared_at;
+};
+
+static void plan_refine_keep(Carver& kv, RefineKeep& K, int p, int q, int64_t Wt1, int A,
+                             bool msa_tmpl) {
+  kv.add(K.d_uidx, p);
+  kv.add(K.d_bucket_of_u, q);
+  kv.add(K.d_width_u, q);
+  kv.add(K.d_rows_u, q);
+  kv.add(K.d_wo, q + 1);
+  kv.add(K.cnt32, (size_t)Wt1 * A);
+  kv.add(K.prof16, (size_t)Wt1 * A);
+  kv.add(K.cnode_W, q);
+  kv.add(K.cnode_n, q);
+  kv.add(K.cnode_prof, q);
+  kv.add(K.cons_list, q);
+  kv.add(K.anc_stage, (size_t)Wt1);
+  kv.add(K.anc_len, q);
+  kv.add(K.anc_off, q + 1);
+  kv.add(K.stage_off, q + 1);
+  kv.add(K.anc_codes, (size_t)Wt1);
+  kv.add(K.ga_goff, 2);
+  kv.add(K.ga_list, 1);
+  kv.add(K.ga_merges, 2 * std::max(q, 1));
+  kv.add(K.ga_score, std::max(q, 1));
+  kv.add(K.ga_cells, std::max(q, 1));
+  kv.add(K.ga_cells_tot, 1);
+  kv.add(K.ga_stage, (size_t)Wt1 + 1);
+  kv.add(K.ga_len_d, 1);
+  kv.add(K.ga_off0, 2);
+  kv.add(K.to_g, (size_t)Wt1);
+  kv.add(K.tmpl16, msa_tmpl ? (size_t)Wt1 * A : 1);
+  kv.add(K.tl_d, 1);
+}
+
+static void plan_refine_keep2(Carver& kv, RefineKeep& K, int q, int TL, int64_t ops_tot) {
+  kv.add(K.rf_ops, (size_t)std::max<int64_t>(ops_tot, 1));
+  kv.add(K.rf_ops_off, q + 1);
+  kv.add(K.ins, (size_t)q * (TL + 1));
+  kv.add(K.used, std::max(TL, 1));
+  kv.add(K.slot_total, TL + 1);
+  kv.add(K.slot_start, TL + 1);
+  kv.add(K.shared_at, std::max(TL, 1));
+}
+
+// Workspace that suffices for a refinement of q non-empty buckets of Wtot
+// columns in all (widest maxW) after `keep` bytes of stage buffers: the
+// larger of the ancestors' stage (k-mer lists, similarity matrix and UPGMA
+// sums of q ancestors no longer than their buckets' widths, then their tree's
+// engine) and the refinement engine (q bucket-vs-template merges with a
+// template of up to min(kMaxWidth, Wtot) columns).
+static size_t refine_bound_bytes(size_t keep, int q, int64_t Wtot, int maxW, int A,
+                                 uint32_t mode) {
+  const int64_t Wt1 = std::max<int64_t>(Wtot, 1);
+  size_t arena = 0;
+  if (q > 1) {
+    uint32_t *entries, *F;
+    int32_t *nu, *ids;
+    int64_t* fm0;
+    uint64_t* Sw;
+    Carver base;
+    base.add(entries, (size_t)Wt1);
+    base.add(nu, q);
+    base.add(ids, q);
+    base.add(fm0, 1);
+    base.add(F, (size_t)q * q);
+    base.add(Sw, (size_t)q * q);
+    arena = engine_bound_bytes(base, std::vector<int32_t>{0, q}, maxW, Wtot, A, mode);
+  }
+  const int64_t tl = std::min<int64_t>(kMaxWidth, Wt1);
+  const int64_t ops = Wtot + (int64_t)q * tl;
+  Carver cv;
+  EngineBuffers e{};
+  plan_engine(cv, e, 2 * q + 1, q, q, (Wtot + tl) * A + (ops + 1) * A, Wtot + tl + ops + 1,
+              (int)std::max<int64_t>(64, std::max<int64_t>(maxW, tl)), true, max_grid(mode));
+  return keep + std::max(arena, cv.total());
+}
+
 __global__ void init_refine_ctl_kernel(unsigned long long* tops, unsigned long long prof0,
                                        unsigned long long up0, int32_t* qctl) {
   tops[0] = prof0;
@@ -1403,11 +1747,15 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
                                        const int32_t* d_members, const sad_msa* buckets,
                                        const sad_params* prm, int32_t tmpl, uint8_t* d_ga,
                                        int32_t ga_cap, int32_t* ga_len, sad_msa* gout,
-                                       int32_t* n_steps, hipStream_t stream) {
+                                       int32_t* n_steps, void* d_ws, size_t ws_bytes,
+                                       hipStream_t stream) {
   if (!prm || !buckets || !gout || !ga_len || !n_steps) return fail(SAD_E_INVAL, "null argument");
   if (tmpl != SAD_TEMPLATE_GA && tmpl != SAD_TEMPLATE_GA_MSA)
     return fail(SAD_E_INVAL, "unknown refinement template");
-  int32_t r = check_seqs(seqs, prm->kmer_k);
+  int32_t r = check_ws(d_ws, ws_bytes);
+  if (r) return r;
+  WsScope wss(d_ws, ws_bytes);
+  r = check_seqs(seqs, prm->kmer_k);
   if (r) return r;
   r = check_params(prm, seqs->alphabet, true);
   if (r) return r;
@@ -1449,50 +1797,42 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
   if (q > kMaxGroup) return fail(SAD_E_CAPACITY, "too many buckets for the ancestor tree");
 
   // ---- stage buffers that live across the engine runs
-  int32_t *d_uidx, *d_bucket_of_u, *d_width_u, *d_rows_u, *anc_len, *cons_list, *ga_goff,
-      *ga_merges, *ga_list, *ga_len_d, *ins, *used, *slot_total, *slot_start, *shared_at, *to_g;
-  int64_t *d_wo, *anc_off, *stage_off, *ga_score, *ga_cells, *ga_cells_tot, *rf_ops_off, *ga_off0;
-  uint32_t* cnt32;
-  uint16_t *prof16, *tmpl16;
-  int32_t* tl_d;
-  uint8_t *anc_stage, *anc_codes, *ga_stage, *rf_ops;
-  int32_t* cnode_W;
-  int32_t* cnode_n;
-  int64_t* cnode_prof;
   const int64_t Wt1 = std::max<int64_t>(Wtot, 1);
-  Carver kv;
-  kv.add(d_uidx, p);
-  kv.add(d_bucket_of_u, q);
-  kv.add(d_width_u, q);
-  kv.add(d_rows_u, q);
-  kv.add(d_wo, q + 1);
-  kv.add(cnt32, (size_t)Wt1 * A);
-  kv.add(prof16, (size_t)Wt1 * A);
-  kv.add(cnode_W, q);
-  kv.add(cnode_n, q);
-  kv.add(cnode_prof, q);
-  kv.add(cons_list, q);
-  kv.add(anc_stage, (size_t)Wt1);
-  kv.add(anc_len, q);
-  kv.add(anc_off, q + 1);
-  kv.add(stage_off, q + 1);
-  kv.add(anc_codes, (size_t)Wt1);
-  kv.add(ga_goff, 2);
-  kv.add(ga_list, 1);
-  kv.add(ga_merges, 2 * std::max(q, 1));
-  kv.add(ga_score, std::max(q, 1));
-  kv.add(ga_cells, std::max(q, 1));
-  kv.add(ga_cells_tot, 1);
-  kv.add(ga_stage, (size_t)Wt1 + 1);
-  kv.add(ga_len_d, 1);
-  kv.add(ga_off0, 2);
-  kv.add(to_g, (size_t)Wt1);
   // the ancestors' alignment as a template (at most as wide as all ancestors)
   const bool msa_tmpl = tmpl == SAD_TEMPLATE_GA_MSA && q > 1;
-  kv.add(tmpl16, msa_tmpl ? (size_t)Wt1 * A : 1);
-  kv.add(tl_d, 1);
+  RefineKeep K{};
+  Carver kv;
+  plan_refine_keep(kv, K, p, q, Wt1, A, msa_tmpl);
+  if (g_ws) {
+    // caller workspace: the front holds these buffers and the refinement's
+    // (sized for the widest template the library accepts), the rest is for
+    // the engine runs
+    RefineKeep K2{};
+    Carver kb = kv;
+    const int tl_max = (int)std::min<int64_t>(kMaxWidth, Wt1);
+    plan_refine_keep2(kb, K2, q, tl_max, Wtot + (int64_t)q * tl_max);
+    g_ws->keep = kb.total();
+    g_ws->bound = refine_bound_bytes(kb.total(), q, Wtot, maxW, A, prm->mode);
+    if (g_ws->keep > g_ws->bytes) {
+      g_ws_needed = g_ws->bound;
+      return fail(SAD_E_CAPACITY, "caller workspace too small for the refinement: " +
+                                      std::to_string(g_ws_needed) + " bytes suffice");
+    }
+  }
   r = kv.carve_keep(c);
   if (r) return r;
+  int32_t *d_uidx = K.d_uidx, *d_bucket_of_u = K.d_bucket_of_u, *d_width_u = K.d_width_u,
+          *d_rows_u = K.d_rows_u;
+  int64_t* d_wo = K.d_wo;
+  uint32_t* cnt32 = K.cnt32;
+  uint16_t *prof16 = K.prof16, *tmpl16 = K.tmpl16;
+  int32_t *cnode_W = K.cnode_W, *cnode_n = K.cnode_n, *cons_list = K.cons_list,
+          *anc_len = K.anc_len, *ga_goff = K.ga_goff, *ga_list = K.ga_list,
+          *ga_merges = K.ga_merges, *ga_len_d = K.ga_len_d, *to_g = K.to_g, *tl_d = K.tl_d;
+  int64_t *cnode_prof = K.cnode_prof, *anc_off = K.anc_off, *stage_off = K.stage_off,
+          *ga_score = K.ga_score, *ga_cells = K.ga_cells, *ga_cells_tot = K.ga_cells_tot,
+          *ga_off0 = K.ga_off0;
+  uint8_t *anc_stage = K.anc_stage, *anc_codes = K.anc_codes, *ga_stage = K.ga_stage;
   r = h2d(uidx, d_uidx, stream);
   if (!r) r = h2d(bucket_of_u, d_bucket_of_u, stream);
   if (!r) r = h2d(width_u, d_width_u, stream);
@@ -1630,17 +1970,15 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
     ops_tot += width_u[u] + TL;
   }
   ops_off[q] = ops_tot;
+  uint8_t* rf_ops;
+  int64_t* rf_ops_off;
+  int32_t *ins, *used, *slot_total, *slot_start, *shared_at;
   {
     Carver kv2 = kv;
-    kv2.add(rf_ops, (size_t)std::max<int64_t>(ops_tot, 1));
-    kv2.add(rf_ops_off, q + 1);
-    kv2.add(ins, (size_t)q * (TL + 1));
-    kv2.add(used, std::max(TL, 1));
-    kv2.add(slot_total, TL + 1);
-    kv2.add(slot_start, TL + 1);
-    kv2.add(shared_at, std::max(TL, 1));
+    RefineKeep K2{};
+    plan_refine_keep2(kv2, K2, q, TL, ops_tot);
     // same prefix as kv: earlier buffers keep their addresses and contents
-    if (kv2.total() > c->keep_cap) {
+    if (!g_ws && kv2.total() > c->keep_cap) {
       // grow while preserving: copy the prefix out through the work arena
       size_t keep_bytes = kv.total();
       char* tmp = nullptr;
@@ -1659,6 +1997,13 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
       r = kv2.carve_keep(c);
       if (r) return r;
     }
+    rf_ops = K2.rf_ops;
+    rf_ops_off = K2.rf_ops_off;
+    ins = K2.ins;
+    used = K2.used;
+    slot_total = K2.slot_total;
+    slot_start = K2.slot_start;
+    shared_at = K2.shared_at;
   }
   r = h2d(ops_off, rf_ops_off, stream);
   if (r) return r;
@@ -1920,11 +2265,56 @@ extern "C" int32_t sad_refine_tree(const sad_seqs* seqs, const int32_t* d_bucket
 extern "C" int32_t sad_refine(const sad_seqs* seqs, const int32_t* d_bucket_off,
                               const int32_t* d_members, const sad_msa* buckets,
                               const sad_params* prm, uint8_t* d_ga, int32_t ga_cap,
-                              int32_t* ga_len, sad_msa* gout, int32_t* n_steps,
-                              hipStream_t stream) {
+                              int32_t* ga_len, sad_msa* gout, int32_t* n_steps, void* d_ws,
+                              size_t ws_bytes, hipStream_t stream) {
   return sad_refine_template(seqs, d_bucket_off, d_members, buckets, prm, SAD_TEMPLATE_GA, d_ga,
-                             ga_cap, ga_len, gout, n_steps, stream);
+                             ga_cap, ga_len, gout, n_steps, d_ws, ws_bytes, stream);
 }
+
+extern "C" int32_t sad_refine_workspace(const sad_seqs* seqs, const int32_t* d_bucket_off,
+                                        const sad_msa* buckets, const sad_params* prm,
+                                        size_t* ws_bytes, hipStream_t stream) {
+  if (!prm || !buckets || !ws_bytes) return fail(SAD_E_INVAL, "null argument");
+  int32_t r = check_seqs(seqs, prm->kmer_k);
+  if (r) return r;
+  r = check_params(prm, seqs->alphabet, false);
+  if (r) return r;
+  if (!d_bucket_off || !buckets->d_width) return fail(SAD_E_INVAL, "null device array");
+  const int n = seqs->n, p = prm->p, A = seqs->alphabet;
+  DeviceCtx* c = nullptr;
+  r = get_ctx(&c);
+  if (r) return r;
+  std::vector<int32_t> off, wid;
+  r = reset_status(c, stream);
+  if (!r)
+    r = finish_read(c, stream, d_bucket_off, (size_t)p + 1, off, (const int32_t*)buckets->d_width,
+                    (size_t)p, &wid);
+  if (r) return r;
+  if (off[0] != 0 || off[p] != n) return fail(SAD_E_INVAL, "bucket offsets must span 0..N");
+  int q = 0, maxW = 0;
+  int64_t Wtot = 0;
+  for (int b = 0; b < p; ++b) {
+    const int nb = off[b + 1] - off[b];
+    if (nb < 0) return fail(SAD_E_INVAL, "bucket offsets must be non-decreasing");
+    if (nb == 0) continue;
+    if (wid[b] < 0 || wid[b] > kMaxWidth) return fail(SAD_E_INVAL, "bucket width out of range");
+    ++q;
+    Wtot += wid[b];
+    maxW = std::max(maxW, wid[b]);
+  }
+  if (q == 0) return fail(SAD_E_INVAL, "no sequences");
+  // either template: the q-row template's buffer included
+  const int64_t Wt1 = std::max<int64_t>(Wtot, 1);
+  const int tl_max = (int)std::min<int64_t>(kMaxWidth, Wt1);
+  RefineKeep K{};
+  Carver kb;
+  plan_refine_keep(kb, K, p, q, Wt1, A, q > 1);
+  plan_refine_keep2(kb, K, q, tl_max, Wtot + (int64_t)q * tl_max);
+  *ws_bytes = refine_bound_bytes(kb.total(), q, Wtot, maxW, A, prm->mode);
+  return SAD_OK;
+}
+
+extern "C" size_t sad_workspace_needed(void) { return g_ws_needed; }
 
 extern "C" int32_t sad_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_mu);

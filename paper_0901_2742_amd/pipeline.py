@@ -13,19 +13,22 @@ def to_device(codes, offsets, alphabet: int) -> B.DeviceSeqs:
 
 
 def run_device(seqs: B.DeviceSeqs, prm: B.Params, bufs: dict | None = None,
-               template: str = "ga") -> dict:
+               template: str = "ga", ws=None) -> dict:
     """All four stages; results stay on the device.  `bufs` (a dict, filled on
     first use) keeps every output buffer across calls, so repeated passes over
     the same input reuse them (and the library can replay its captured launch).
-    template: the refinement template ("ga" or "ga_msa")."""
+    template: the refinement template ("ga" or "ga_msa").  ws: the stages'
+    device workspace (None: the binding's own caller-owned tensor, "library":
+    the library's, or a uint8 tensor)."""
     if bufs is None:
         bufs = {}
-    key, samples = B.sad_kmer_rank(seqs, prm, bufs.setdefault("rank", {}))
-    part = B.sad_partition(seqs, key, prm, bufs.setdefault("part", {}))
-    al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm, bufs.get("align"))
+    key, samples = B.sad_kmer_rank(seqs, prm, bufs.setdefault("rank", {}), ws=ws)
+    part = B.sad_partition(seqs, key, prm, bufs.setdefault("part", {}), ws=ws)
+    al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm, bufs.get("align"),
+                             ws=ws)
     bufs["align"] = al
     rf = B.sad_refine(seqs, part["bucket_off"], part["members"], al, prm, bufs.get("refine"),
-                      template=template)
+                      template=template, ws=ws)
     bufs["refine"] = rf
     return dict(key=key, samples=samples, part=part, align=al, refine=rf)
 
@@ -55,8 +58,8 @@ def to_host(res: dict, n: int, p: int, total_len: int) -> dict:
     )
 
 
-def run(codes, offsets, alphabet: int, prm: B.Params, template: str = "ga") -> dict:
+def run(codes, offsets, alphabet: int, prm: B.Params, template: str = "ga", ws=None) -> dict:
     seqs = to_device(codes, offsets, alphabet)
-    res = run_device(seqs, prm, template=template)
+    res = run_device(seqs, prm, template=template, ws=ws)
     torch.cuda.synchronize()
     return to_host(res, seqs.n, prm.p, seqs.total_len)

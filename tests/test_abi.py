@@ -50,3 +50,36 @@ def test_product_path_does_not_touch_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "sad_oracle" not in text and "sadref_" not in text, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsad.so not built")
+def test_host_only_workspace_queries():
+    """The rank and partition workspace queries are host arithmetic (no device
+    call): exact sizes of 256-byte aligned buffers plus 256 bytes of slack,
+    and the same input checks as the calls."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_0901_2742_amd import binding as B
+
+    def up(x):
+        return (max(x, 1) + 255) // 256 * 256
+
+    L = B.lib()
+    n, total, p = 2000, 646_000, 16
+    seqs = B.SadSeqs(n, 20, 1, 1, total, 600)   # device pointers are never read
+    prm = B.SadParams(3, p, 1024, 1, 10, 1, 1)
+    got = ctypes.c_size_t(0)
+    assert L.sad_kmer_rank_workspace(ctypes.byref(seqs), ctypes.byref(prm),
+                                     ctypes.byref(got)) == B.SAD_OK
+    assert got.value == up(4 * total) + up(4 * n) + up(8 * n) + up(4 * n) + 256
+    assert L.sad_partition_workspace(ctypes.byref(seqs), ctypes.byref(prm),
+                                     ctypes.byref(got)) == B.SAD_OK
+    ny, nblk = p * (p - 1), (n + 255) // 256
+    part = up(4 * n) + 2 * up(8 * ny) + 2 * up(4 * ny) + up(4 * nblk * p) + up(4 * p)
+    assert got.value == up(part) + 256
+    bad = B.SadParams(3, 1001, 1024, 1, 10, 1, 1)   # N < 2p
+    assert L.sad_partition_workspace(ctypes.byref(seqs), ctypes.byref(bad),
+                                     ctypes.byref(got)) == B.SAD_E_INVAL
+    short = B.SadSeqs(n, 20, 1, 1, total, 2)        # sequences shorter than k
+    assert L.sad_kmer_rank_workspace(ctypes.byref(short), ctypes.byref(prm),
+                                     ctypes.byref(got)) == B.SAD_E_INVAL

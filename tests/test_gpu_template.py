@@ -87,5 +87,5 @@ def test_msa_template_bad_kind(hip):
                                        B._ptr(res["part"]["members"]), ctypes.byref(mb),
                                        ctypes.byref(pp), 7, B._ptr(out["ga"]), out["ga"].numel(),
                                        ctypes.byref(gl), ctypes.byref(mg), ctypes.byref(nst),
-                                       B._stream())
+                                       None, 0, B._stream())
     assert code == B.SAD_E_INVAL
