@@ -103,6 +103,34 @@ def test_autotune_keeps_results(setup, mode):
     check_align(torch, al, ref, s, w.p)
 
 
+def tuner_candidates(torch, mode):
+    """The schedules sad_tune measures: batched, a grid of 1, 3/4 or 1/2
+    workgroup per CU with the guide trees inside the launch or by a separate
+    kernel; plain, 1-3 workgroups per CU."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    if mode == 1:
+        return [(cus * den // 4, fuse) for fuse in (1, 0) for den in (4, 3, 2)]
+    return [(cus * per, 0) for per in (1, 2, 3)]
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_every_tuner_candidate_matches_the_oracle(setup, monkeypatch, mode):
+    """Each schedule the autotuner can pick, imposed with SAD_SCHEDULE, gives
+    the oracle's bucket alignment (results never depend on the schedule)."""
+    B, torch, s, w, ref, seqs, _, part = setup
+    prm = B.Params(w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, w.s_max, mode)
+    out = None
+    for grid, fuse in tuner_candidates(torch, mode):
+        _say(f"case tuner candidate mode={mode} grid={grid} fuse={fuse}")
+        monkeypatch.setenv("SAD_SCHEDULE", f"{grid},{fuse}")
+        if out is not None:
+            for t in out.values():
+                if torch.is_tensor(t):
+                    t.fill_(-7)
+        out = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm, out)
+        check_align(torch, out, ref, s, w.p)
+
+
 def test_graph_key_follows_kmer_length(setup):
     """A captured launch bakes the k-mer length into its similarity kernels: a
     call with another k on the same buffers must not replay it.  k alternates

@@ -184,3 +184,26 @@ def test_error_paths(hip):
     with pytest.raises(B.SadError) as e:
         B.sad_kmer_rank(seqs, B.Params(4, 4, protein_matrix(), 10, 1))    # 20^4 > 2^16
     assert e.value.code == B.SAD_E_INVAL
+
+
+def test_prot2000_extreme_bucket_counts(hip):
+    """The bucket-count sweep's extremes, bit-exact in full: p = 1 (one bucket
+    of 2000 proteins, its guide tree by the standalone kernel) and p = 256
+    (buckets of about 8, k_s = 4 samples per chunk, 256 ancestors)."""
+    from concurrent.futures import ThreadPoolExecutor
+    B, pipeline = hip
+    w = CONFIGS["prot2000"]
+    s = make_inputs("prot2000")
+
+    def ref(p):   # the oracle's C code runs outside the interpreter lock
+        return oracle.run_pipeline(s.codes, s.offsets, s.alphabet, w.kmer_k, p, w.subst(),
+                                   w.gap_open, w.gap_extend, w.s_max)
+
+    with ThreadPoolExecutor(2) as ex:
+        refs = dict(zip((1, 256), ex.map(ref, (1, 256))))
+    for p in (1, 256):
+        for mode in (1, 0):
+            _say(f"case prot2000 p={p} mode={mode}")
+            prm = B.Params(w.kmer_k, p, w.subst(), w.gap_open, w.gap_extend, w.s_max, mode)
+            got = pipeline.run(s.codes, s.offsets, s.alphabet, prm)
+            compare(got, refs[p], f"prot2000 p={p} mode={mode}")
