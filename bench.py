@@ -9,7 +9,11 @@ the inputs already resident in HBM.  Prints one JSON line:
   seq_per_s  sequences aligned per second (same step time)
   roofline   the alignment engine kernel (DP + traceback + merge) against the
              int32 vector-ALU peak, timed with HIP events on its own stream
-  cpu_baseline  the CPU oracle on the same workload (single thread)
+  cpu_baseline  the CPU oracle on the same workload (all host threads; one
+             thread beside it)
+  workloads  the other workloads (64 proteins, 20000 proteins, 50000 DNA
+             sequences, 200000 proteins): batched and plain pass times,
+             GCUPS, the engine's roofline, the oracle on a sample
 """
 from __future__ import annotations
 
@@ -39,6 +43,8 @@ def parse():
     ap.add_argument("--workload", default="prot2000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the default schedule without autotuning first (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the q-row template and tree-refinement figures (profiling runs)")
     ap.add_argument("--sweep-p", default="", metavar="P1,P2,...",
@@ -53,6 +59,11 @@ def parse():
                          "(p (p - 1) samples at most), their statistics and histograms")
     ap.add_argument("--rank-p", type=int, default=16,
                     help="bucket count p of the globalised rank in --rank-study")
+    ap.add_argument("--workloads", default="prot64,prot20k,dna50k,prot200k",
+                    help="other workloads timed beside the benchmark line (batched and plain "
+                         "pass times, GCUPS, engine roofline, the oracle on a sample); "
+                         "empty to skip")
+    ap.add_argument("--workload-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a buffer of this many MiB once (a kernel "
                          "of known traffic for scaling hardware byte counters)")
@@ -147,6 +158,123 @@ def extras(out, args, B, pipeline, torch, seqs, prm, s, w, res, quality):
                                   "accepted": acc_t, "width": w_t,
                                   "quality": quality(cm_t.cpu().numpy())}
     out["tree_refine"] = tr
+
+
+def host_threads() -> int:
+    """Host cores this process may use (affinity, capped by OMP_NUM_THREADS
+    when set: the GPU machines give one GPU's process a share of the host)."""
+    n = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(n, 1)
+
+
+def oracle_sample(s, w, host, threads):
+    """The oracle on a bounded sample of a large workload, all host threads:
+    the rank keys of 256 sequences against the library's samples, and the
+    alignment of 16 whole buckets (spread over the bucket order)."""
+    import numpy as np
+
+    import oracle
+    oracle.set_threads(threads)
+    try:
+        rng = np.random.default_rng(3)
+        rows = np.sort(rng.choice(s.n, 256, replace=False)).astype(np.int32)
+        t0 = time.perf_counter()
+        kref = oracle.rank_against(s.codes, s.offsets, s.alphabet, w.kmer_k,
+                                   samples=host["samples"], rows=rows)
+        t_rank = time.perf_counter() - t0
+        boff, mem = host["part"]["bucket_off"], host["part"]["members"]
+        pick = np.linspace(0, w.p - 1, 16).round().astype(int)
+        ids = np.concatenate([mem[boff[b]:boff[b + 1]] for b in pick])
+        sizes = [boff[b + 1] - boff[b] for b in pick]
+        sub = s.subset(ids)
+        sboff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+        t0 = time.perf_counter()
+        ra = oracle.align_buckets(sub.codes, sub.offsets, s.alphabet, sboff,
+                                  np.arange(len(ids), dtype=np.int32), w.kmer_k, w.subst(),
+                                  w.gap_open, w.gap_extend)
+        t_al = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
+    same = bool(np.array_equal(kref, host["key"][rows]))
+    gcm = np.concatenate([host["align"]["colmap"][s.offsets[i]:s.offsets[i + 1]] for i in ids])
+    same = same and bool(np.array_equal(gcm, ra["colmap"]))
+    return {"value": round(ra["cells"] / t_al / 1e9, 5), "unit": "GCUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"alignment of 16 whole buckets ({int(ra['cells'])} DP cells, "
+                      f"{t_al:.2f} s) and rank keys of 256 sequences ({t_rank:.2f} s)",
+            "bit_exact_vs_library": same}
+
+
+def workload_figures(name, args, B, pipeline, torch, threads):
+    """Batched and plain pass times of one workload (each mode autotuned
+    first), GCUPS, sequences/s, the engine kernel against the int32 peak,
+    the caller workspace the pass used, and the oracle on a sample."""
+    import numpy as np
+
+    from workloads import make_inputs, workload
+    w = workload(name)
+    t0 = time.perf_counter()
+    s = make_inputs(name)
+    gen_s = time.perf_counter() - t0
+    seqs = pipeline.to_device(s.codes, s.offsets, s.alphabet)
+    out = {"n": s.n, "alphabet": s.alphabet, "mean_len": round(float(s.lengths.mean()), 1),
+           "buckets": w.p, "kmer_k": w.kmer_k, "gaps": f"{w.gap_open}/{w.gap_extend}",
+           "input_generation_s": round(gen_s, 1)}
+    hosts = {}
+    for mode, label in ((B.SAD_BATCHED_MFMA, "batched"), (B.SAD_PLAIN, "plain")):
+        print(f"workload {name}: {label}", file=sys.stderr, flush=True)
+        prm = B.Params(w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, w.s_max, mode)
+        key0, _ = B.sad_kmer_rank(seqs, prm)
+        part0 = B.sad_partition(seqs, key0, prm)
+        tuned = B.sad_tune(seqs, part0["bucket_off"], part0["members"], prm)
+        B.sad_profile_graphs(reset=True)
+        res, ms, eng_ms, launches = timed_steps(pipeline.run_device, seqs, prm,
+                                                args.workload_steps, 1, B, torch)
+        graphs = B.sad_profile_graphs(reset=True)
+        host = pipeline.to_host(res, s.n, w.p, seqs.total_len)
+        hosts[label] = host
+        cells = host["align"]["cells"] + host["refine"]["cells"]
+        eng_pass = eng_ms / args.workload_steps
+        achieved = cells * OPS_PER_CELL / (eng_pass / 1e3) / 1e12 if eng_pass > 0 else 0.0
+        out[label] = {"ms_per_pass": round(ms, 3),
+                      "value": round(cells / (ms / 1e3) / 1e9, 3), "unit": "GCUPS",
+                      "seq_per_s": round(s.n / (ms / 1e3), 1), "dp_cells_per_pass": cells,
+                      "engine_ms_per_pass": round(eng_pass, 3),
+                      "engine_launches_per_pass": launches // args.workload_steps,
+                      "roofline": {"bound": "alu", "achieved": round(achieved, 4),
+                                   "peak": round(INT32_PEAK_TOPS, 2), "unit": "TOP/s (int32)",
+                                   "frac": round(achieved / INT32_PEAK_TOPS, 5)},
+                      "schedule": {"engine_workgroups": tuned[0],
+                                   "trees_in_launch": bool(tuned[1]),
+                                   "graph_replays": graphs[1]}}
+    out["same_result"] = bool(
+        all(np.array_equal(hosts["batched"][st]["colmap"], hosts["plain"][st]["colmap"])
+            for st in ("align", "refine")))
+    out["workspace_bytes"] = int(max(t.numel() for t in B._WS.values())) if B._WS else 0
+    if name == "prot64":
+        import oracle
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        ref = oracle.run_pipeline(s.codes, s.offsets, s.alphabet, w.kmer_k, w.p, w.subst(),
+                                  w.gap_open, w.gap_extend, w.s_max)
+        dt = time.perf_counter() - t0
+        oracle.set_threads(1)
+        rc = ref["align"]["cells"] + ref["refine"]["cells"]
+        out["cpu_baseline"] = {"value": round(rc / dt / 1e9, 5), "unit": "GCUPS",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"full pipeline, {dt:.2f} s",
+                               "bit_exact_vs_library": bool(
+                                   np.array_equal(ref["refine"]["colmap"],
+                                                  hosts["batched"]["refine"]["colmap"]))}
+    else:
+        out["cpu_baseline"] = oracle_sample(s, w, hosts["batched"], threads)
+    del seqs, hosts
+    B.release_workspace()
+    torch.cuda.empty_cache()
+    return out
 
 
 def rank_study(args, B, pipeline, torch):
@@ -248,7 +376,8 @@ def main():
     # the process), then time the pipeline with it
     key0, _ = B.sad_kmer_rank(seqs, prm)
     part0 = B.sad_partition(seqs, key0, prm)
-    tuned = B.sad_tune(seqs, part0["bucket_off"], part0["members"], prm)
+    tuned = (0, -1) if args.no_tune else B.sad_tune(seqs, part0["bucket_off"],
+                                                    part0["members"], prm)
     B.sad_profile_graphs(reset=True)
     res, ms, eng_ms, launches = timed_steps(pipeline.run_device, seqs, prm, args.steps,
                                             args.warmup, B, torch)
@@ -275,7 +404,8 @@ def main():
         "data": "synthetic (seeded family-structured proteins)",
         "config": {"workload": w.name, "n": s.n, "mean_len": round(float(s.lengths.mean()), 1),
                    "buckets": w.p, "kmer_k": w.kmer_k, "gaps": f"{w.gap_open}/{w.gap_extend}",
-                   "matrix": "seeded 20x20 integer stand-in (BLOSUM62 range)",
+                   "matrix": ("seeded 20x20 integer stand-in (BLOSUM62 range)"
+                              if s.alphabet == 20 else "+2/-3 (DNA)"),
                    "parallelism": "single GPU"},
         "seq_per_s": round(seq_s, 2),
         "dp_cells_per_step": cells,
@@ -304,12 +434,20 @@ def main():
                         "ms_per_step": round(ms_p, 3), "engine_workgroups": tuned_p[0],
                         "same_result": bool(np.array_equal(host_p["refine"]["colmap"],
                                                            host["refine"]["colmap"]))}
+    threads = host_threads()
     if not args.no_cpu_baseline:
         import oracle
+        # one thread, then every host core this process may use
+        t = time.perf_counter()
+        ref1 = oracle.run_pipeline(s.codes, s.offsets, s.alphabet, w.kmer_k, w.p, S, w.gap_open,
+                                   w.gap_extend, w.s_max)
+        dt1 = time.perf_counter() - t
+        oracle.set_threads(threads)
         t = time.perf_counter()
         ref = oracle.run_pipeline(s.codes, s.offsets, s.alphabet, w.kmer_k, w.p, S, w.gap_open,
                                   w.gap_extend, w.s_max)
         dt = time.perf_counter() - t
+        oracle.set_threads(1)
         ref_cells = ref["align"]["cells"] + ref["refine"]["cells"]
         exact = (np.array_equal(ref["key"], host["key"])
                  and np.array_equal(ref["part"]["members"], host["part"]["members"])
@@ -318,13 +456,24 @@ def main():
                                     host["align"]["merge_score"][:s.n])
                  and np.array_equal(ref["refine"]["ga"], host["refine"]["ga"])
                  and np.array_equal(ref["refine"]["colmap"], host["refine"]["colmap"])
-                 and ref_cells == cells)
+                 and ref_cells == cells
+                 and np.array_equal(ref1["refine"]["colmap"], ref["refine"]["colmap"]))
         out["cpu_baseline"] = {"value": round(ref_cells / dt / 1e9, 5), "unit": "GCUPS",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"full {w.name} pipeline (all four stages), one run, "
-                                         f"one thread, {dt:.2f} s",
-                               "seq_per_s": round(s.n / dt, 2)}
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"full {w.name} pipeline (all four stages), one run on "
+                                         f"{threads} threads ({dt:.2f} s) and one on one thread "
+                                         f"({dt1:.2f} s)",
+                               "seq_per_s": round(s.n / dt, 2),
+                               "single_thread": {"value": round(ref_cells / dt1 / 1e9, 5),
+                                                 "unit": "GCUPS", "seconds": round(dt1, 2),
+                                                 "seq_per_s": round(s.n / dt1, 2)}}
         out["bit_exact_vs_oracle"] = bool(exact)
+    if args.workloads:
+        # the other workloads: parity cases of the test suite, timed here so
+        # that the engine's roofline is reported where it is throughput-bound
+        out["workloads"] = {}
+        for name in [x for x in args.workloads.split(",") if x]:
+            out["workloads"][name] = workload_figures(name, args, B, pipeline, torch, threads)
     print(json.dumps(out), flush=True)
 
 

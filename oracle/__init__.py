@@ -57,7 +57,7 @@ def build(force: bool = False) -> str:
         return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall",
                                "-Wno-unused-function", _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
@@ -81,6 +81,8 @@ I32, I64 = ctypes.c_int32, ctypes.c_int64
 
 
 def _declare(L):
+    L.sadref_set_threads.argtypes = [I32]
+    L.sadref_set_threads.restype = None
     L.sadref_kmer_list.argtypes = [P, I64, ctypes.c_int, ctypes.c_int, P, P, P]
     L.sadref_common_kmers.argtypes = [P, I64, P, I64, ctypes.c_int, ctypes.c_int]
     L.sadref_common_kmers.restype = I64
@@ -152,6 +154,12 @@ def fhat(xi, xj, A: int, k: int) -> int:
 # --------------------------------------------------------------------------
 # rank and partition
 # --------------------------------------------------------------------------
+
+def set_threads(threads: int) -> None:
+    """Threads of the oracle's loops over independent items (1: the calling
+    thread only, the default); results do not depend on it."""
+    lib().sadref_set_threads(int(threads))
+
 
 def kmer_rank(codes, offsets, A: int, k: int, p: int, s_max: int = 1024):
     codes, offsets = _c(codes, np.uint8), _c(offsets, np.int64)

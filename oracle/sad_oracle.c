@@ -2,16 +2,66 @@
  * CPU oracle for the Sample-Align-D data-parallel core (Saeed & Khokhar,
  * arXiv 0901.2742).  TEST INFRASTRUCTURE ONLY -- see sad_oracle.h.
  *
- * Plain, single-threaded C.  Each function follows one step of the method in
- * the order the paper states it; where the paper leaves a choice open, the
- * reading used is stated next to the code.  All arithmetic is integer: scores
- * in int64, k-mer similarities as exact rationals c/d turned into the fixed
- * point floor(c * 2^31 / d).
+ * Plain C.  Each function follows one step of the method in the order the
+ * paper states it; where the paper leaves a choice open, the reading used is
+ * stated next to the code.  All arithmetic is integer: scores in int64, k-mer
+ * similarities as exact rationals c/d turned into the fixed point
+ * floor(c * 2^31 / d).  Single-threaded by default; sadref_set_threads(t)
+ * spreads loops over independent items (sequences, chunks, buckets, the
+ * refinement alignments) over t threads, each item computed exactly as in
+ * the single-threaded loop and written to its own outputs.
  */
 #include "sad_oracle.h"
 
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* loops over independent items                                        */
+/* ------------------------------------------------------------------ */
+
+static int g_threads = 1;
+
+void sadref_set_threads(int32_t threads) { g_threads = threads < 1 ? 1 : threads; }
+
+typedef void (*item_fn)(void* ctx, int64_t i);
+
+typedef struct {
+  item_fn fn;
+  void* ctx;
+  int64_t n;
+  int64_t next; /* next unclaimed item, taken with an atomic add */
+} item_loop_t;
+
+static void* item_worker(void* arg) {
+  item_loop_t* L = (item_loop_t*)arg;
+  for (;;) {
+    int64_t i = __atomic_fetch_add(&L->next, 1, __ATOMIC_RELAXED);
+    if (i >= L->n) break;
+    L->fn(L->ctx, i);
+  }
+  return NULL;
+}
+
+/* fn(ctx, i) for i = 0..n-1, on up to g_threads threads (the caller's one
+ * included); items must not write to shared state. */
+static void for_items(int64_t n, item_fn fn, void* ctx) {
+  int64_t t = g_threads < n ? g_threads : n;
+  if (t <= 1) {
+    for (int64_t i = 0; i < n; ++i) fn(ctx, i);
+    return;
+  }
+  item_loop_t L = {fn, ctx, n, 0};
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)(t - 1));
+  int64_t started = 0;
+  for (int64_t k = 0; k < t - 1; ++k)
+    if (pthread_create(&th[k], NULL, item_worker, &L) == 0) started = k + 1;
+    else break;
+  item_worker(&L);
+  for (int64_t k = 0; k < started; ++k) pthread_join(th[k], NULL);
+  free(th);
+}
 
 #define NEG_INF (INT64_MIN / 4)
 
@@ -175,6 +225,69 @@ static int32_t chunk_lo(int32_t n, int32_t p, int32_t c) {
 /* Step 1: local rank, samples, globalised rank (Sections 2, 2.3.1)     */
 /* ------------------------------------------------------------------ */
 
+typedef struct {
+  kmer_list_t* kl;
+  const uint8_t* codes;
+  const int64_t* offsets;
+  int A, k;
+} lists_ctx_t;
+
+static void list_item(void* ctx, int64_t i) {
+  lists_ctx_t* c = (lists_ctx_t*)ctx;
+  build_list(&c->kl[i], c->codes + c->offsets[i], c->offsets[i + 1] - c->offsets[i], c->A, c->k);
+}
+
+static void build_lists(kmer_list_t* kl, int32_t n, const uint8_t* codes, const int64_t* offsets,
+                        int A, int k) {
+  lists_ctx_t c = {kl, codes, offsets, A, k};
+  for_items(n, list_item, &c);
+}
+
+/* one chunk c: local ranks over the chunk, its order by (rank, id), its ks
+ * samples (buf[lo..hi) is the chunk's own part of the buffer) */
+typedef struct {
+  const kmer_list_t* kl;
+  ckey_t* buf;
+  int32_t* sample_ids;
+  int32_t n, p, ks, k;
+} local_ctx_t;
+
+static void local_chunk(void* ctx, int64_t c64) {
+  local_ctx_t* L = (local_ctx_t*)ctx;
+  const int32_t c = (int32_t)c64;
+  int32_t lo = chunk_lo(L->n, L->p, c), hi = chunk_lo(L->n, L->p, c + 1), w = hi - lo;
+  ckey_t* b = L->buf + lo;
+  for (int32_t i = lo; i < hi; ++i) {
+    uint64_t s = 0;
+    for (int32_t j = lo; j < hi; ++j) s += fhat_lists(&L->kl[i], &L->kl[j], L->k);
+    b[i - lo].key = s;
+    b[i - lo].id = i;
+  }
+  qsort(b, (size_t)w, sizeof(ckey_t), cmp_ckey);
+  for (int32_t t = 1; t <= L->ks; ++t)
+    L->sample_ids[c * L->ks + (t - 1)] = b[((int64_t)t * w) / (L->ks + 1)].id;
+}
+
+/* one row t: key[t] = sum over the samples s of F(row, s); samples == NULL
+ * means all sequences 0..ns-1, rows == NULL row t itself */
+typedef struct {
+  const kmer_list_t* kl;
+  const int32_t* samples;
+  int32_t ns;
+  const int32_t* rows;
+  uint64_t* key;
+  int k;
+} against_ctx_t;
+
+static void against_row(void* ctx, int64_t t) {
+  against_ctx_t* G = (against_ctx_t*)ctx;
+  const int32_t i = G->rows ? G->rows[t] : (int32_t)t;
+  uint64_t sum = 0;
+  for (int32_t u = 0; u < G->ns; ++u)
+    sum += fhat_lists(&G->kl[i], &G->kl[G->samples ? G->samples[u] : u], G->k);
+  G->key[t] = sum;
+}
+
 int sadref_kmer_rank(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
                      int32_t kmer_k, int32_t p, int32_t s_max,
                      uint64_t* key, int32_t* sample_ids, int32_t sample_cap,
@@ -184,8 +297,7 @@ int sadref_kmer_rank(int32_t n, int32_t A, const uint8_t* codes, const int64_t* 
   if (p < 1 || s_max < 1 || n < 2 * p) return SADREF_E_INVAL;
 
   kmer_list_t* kl = (kmer_list_t*)malloc(sizeof(kmer_list_t) * (size_t)(n > 0 ? n : 1));
-  for (int32_t i = 0; i < n; ++i)
-    build_list(&kl[i], codes + offsets[i], offsets[i + 1] - offsets[i], A, kmer_k);
+  build_lists(kl, n, codes, offsets, A, kmer_k);
 
   /* samples per processor: k = p - 1 as in Section 2.3.2, capped so that the
    * whole sample stays within s_max and each chunk keeps a non-sampled item */
@@ -211,26 +323,13 @@ int sadref_kmer_rank(int32_t n, int32_t A, const uint8_t* codes, const int64_t* 
    * F(i, j); the chunk is sorted by (K_loc, i) and ks evenly spaced items are
    * sampled at positions floor(t w / (ks + 1)), t = 1..ks */
   ckey_t* buf = (ckey_t*)malloc(sizeof(ckey_t) * (size_t)(n > 0 ? n : 1));
-  for (int32_t c = 0; c < p; ++c) {
-    int32_t lo = chunk_lo(n, p, c), hi = chunk_lo(n, p, c + 1), w = hi - lo;
-    for (int32_t i = lo; i < hi; ++i) {
-      uint64_t s = 0;
-      for (int32_t j = lo; j < hi; ++j) s += fhat_lists(&kl[i], &kl[j], kmer_k);
-      buf[i - lo].key = s;
-      buf[i - lo].id = i;
-    }
-    qsort(buf, (size_t)w, sizeof(ckey_t), cmp_ckey);
-    for (int32_t t = 1; t <= ks; ++t)
-      sample_ids[c * ks + (t - 1)] = buf[((int64_t)t * w) / (ks + 1)].id;
-  }
+  local_ctx_t lc = {kl, buf, sample_ids, n, p, ks, kmer_k};
+  for_items(p, local_chunk, &lc);
 
   /* globalised rank: every sequence against all k*p samples (self included
    * when the sequence is itself a sample) */
-  for (int32_t i = 0; i < n; ++i) {
-    uint64_t s = 0;
-    for (int32_t t = 0; t < S; ++t) s += fhat_lists(&kl[i], &kl[sample_ids[t]], kmer_k);
-    key[i] = s;
-  }
+  against_ctx_t gc = {kl, sample_ids, S, NULL, key, kmer_k};
+  for_items(n, against_row, &gc);
 
   free(buf);
   for (int32_t i = 0; i < n; ++i) free_list(&kl[i]);
@@ -260,15 +359,9 @@ int sadref_rank_against(int32_t n, int32_t A, const uint8_t* codes, const int64_
   for (int32_t t = 0; rows && t < nrows; ++t)
     if (rows[t] < 0 || rows[t] >= n) return SADREF_E_INVAL;
   kmer_list_t* kl = (kmer_list_t*)malloc(sizeof(kmer_list_t) * (size_t)(n > 0 ? n : 1));
-  for (int32_t i = 0; i < n; ++i)
-    build_list(&kl[i], codes + offsets[i], offsets[i + 1] - offsets[i], A, kmer_k);
-  for (int32_t t = 0; t < nrows; ++t) {
-    const int32_t i = rows ? rows[t] : t;
-    uint64_t sum = 0;
-    for (int32_t u = 0; u < n_samples; ++u)
-      sum += fhat_lists(&kl[i], &kl[samples ? samples[u] : u], kmer_k);
-    key[t] = sum;
-  }
+  build_lists(kl, n, codes, offsets, A, kmer_k);
+  against_ctx_t gc = {kl, samples, n_samples, rows, key, kmer_k};
+  for_items(nrows, against_row, &gc);
   for (int32_t i = 0; i < n; ++i) free_list(&kl[i]);
   free(kl);
   return SADREF_OK;
@@ -689,6 +782,64 @@ static int32_t root_column(const node_t* nodes, int32_t a, int32_t r) {
   return c;
 }
 
+/* one bucket's progressive alignment and its column map; ops (when given)
+ * are appended at *ops_pos, so buckets with ops run one after another */
+typedef struct {
+  int32_t A, kmer_k, go, ge;
+  const uint8_t* codes;
+  const int64_t* offsets;
+  const int32_t *bucket_off, *members;
+  const int8_t* S;
+  int32_t *colmap, *width, *merge_list;
+  int64_t *merge_score, *merge_cells;
+  uint8_t* ops;
+  int64_t ops_cap;
+  int64_t* ops_off;
+  int64_t* ops_pos;
+  int* status; /* per bucket */
+} bucket_ctx_t;
+
+static void align_one_bucket(void* ctx, int64_t b64) {
+  bucket_ctx_t* B = (bucket_ctx_t*)ctx;
+  const int32_t b = (int32_t)b64;
+  int32_t lo = B->bucket_off[b], nb = B->bucket_off[b + 1] - lo;
+  B->status[b] = SADREF_OK;
+  if (nb <= 0) {
+    B->width[b] = 0;
+    if (nb < 0) B->status[b] = SADREF_E_INVAL;
+    return;
+  }
+  const uint8_t** seq = (const uint8_t**)malloc(sizeof(uint8_t*) * (size_t)nb);
+  int64_t* len = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
+  for (int32_t a = 0; a < nb; ++a) {
+    int32_t id = B->members[lo + a];
+    seq[a] = B->codes + B->offsets[id];
+    len[a] = B->offsets[id + 1] - B->offsets[id];
+  }
+  node_t* nodes = (node_t*)calloc((size_t)(2 * nb - 1), sizeof(node_t));
+  int st = progressive(nb, seq, len, B->A, B->kmer_k, B->S, B->go, B->ge, nodes,
+                       B->merge_list + 2 * (int64_t)lo, B->merge_score + lo,
+                       B->merge_cells + lo, B->ops, B->ops_cap,
+                       B->ops ? B->ops_off + lo : NULL, B->ops_pos);
+  /* the bucket's last slot holds no merge: its offset closes the previous
+   * op string, so merge t always ends at ops_off[t + 1] */
+  if (B->ops && st == SADREF_OK) B->ops_off[lo + nb - 1] = *B->ops_pos;
+  if (st == SADREF_OK) {
+    int32_t root = 2 * nb - 2;
+    B->width[b] = nodes[root].W;
+    for (int32_t a = 0; a < nb; ++a) {
+      int32_t id = B->members[lo + a];
+      for (int64_t r = 0; r < len[a]; ++r)
+        B->colmap[B->offsets[id] + r] = root_column(nodes, a, (int32_t)r);
+    }
+  }
+  B->status[b] = st;
+  free_nodes(nodes, 2 * nb - 1);
+  free(nodes);
+  free(seq);
+  free(len);
+}
+
 int sadref_align_buckets(int32_t n, int32_t A, const uint8_t* codes, const int64_t* offsets,
                          int32_t p, const int32_t* bucket_off, const int32_t* members,
                          int32_t kmer_k, const int8_t* S, int32_t go, int32_t ge,
@@ -699,45 +850,29 @@ int sadref_align_buckets(int32_t n, int32_t A, const uint8_t* codes, const int64
   if (st) return st;
   if (p < 1 || go < ge || ge < 0) return SADREF_E_INVAL;
   if (bucket_off[0] != 0 || bucket_off[p] != n) return SADREF_E_INVAL;
+  for (int32_t b = 0; b < p; ++b)
+    if (bucket_off[b + 1] < bucket_off[b]) return SADREF_E_INVAL;
   *cells = 0;
   int64_t ops_pos = 0;
-  for (int32_t b = 0; b < p && st == SADREF_OK; ++b) {
-    int32_t lo = bucket_off[b], nb = bucket_off[b + 1] - lo;
-    if (nb < 0) return SADREF_E_INVAL;
-    if (nb == 0) {
-      width[b] = 0;
-      continue;
+  int* status = (int*)calloc((size_t)p, sizeof(int));
+  bucket_ctx_t bc = {A, kmer_k, go, ge, codes, offsets, bucket_off, members, S, colmap, width,
+                     merge_list, merge_score, merge_cells, ops, ops_cap, ops_off, &ops_pos,
+                     status};
+  if (ops) {
+    /* op strings are appended bucket by bucket: in order, up to the first
+     * failure */
+    for (int32_t b = 0; b < p && st == SADREF_OK; ++b) {
+      align_one_bucket(&bc, b);
+      st = status[b];
     }
-    const uint8_t** seq = (const uint8_t**)malloc(sizeof(uint8_t*) * (size_t)nb);
-    int64_t* len = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
-    for (int32_t a = 0; a < nb; ++a) {
-      int32_t id = members[lo + a];
-      seq[a] = codes + offsets[id];
-      len[a] = offsets[id + 1] - offsets[id];
-    }
-    node_t* nodes = (node_t*)calloc((size_t)(2 * nb - 1), sizeof(node_t));
-    st = progressive(nb, seq, len, A, kmer_k, S, go, ge, nodes, merge_list + 2 * (int64_t)lo,
-                     merge_score + lo, merge_cells + lo, ops, ops_cap,
-                     ops ? ops_off + lo : NULL, &ops_pos);
-    /* the bucket's last slot holds no merge: its offset closes the previous
-     * op string, so merge t always ends at ops_off[t + 1] */
-    if (ops && st == SADREF_OK) ops_off[lo + nb - 1] = ops_pos;
-    if (st == SADREF_OK) {
-      int32_t root = 2 * nb - 2;
-      width[b] = nodes[root].W;
-      for (int32_t t = 0; t < nb - 1; ++t) *cells += merge_cells[lo + t];
-      for (int32_t a = 0; a < nb; ++a) {
-        int32_t id = members[lo + a];
-        for (int64_t r = 0; r < len[a]; ++r)
-          colmap[offsets[id] + r] = root_column(nodes, a, (int32_t)r);
-      }
-    }
-    free_nodes(nodes, 2 * nb - 1);
-    free(nodes);
-    free(seq);
-    free(len);
+  } else {
+    for_items(p, align_one_bucket, &bc);
+    for (int32_t b = 0; b < p && st == SADREF_OK; ++b) st = status[b];
   }
+  for (int32_t b = 0; b < p && st == SADREF_OK; ++b)
+    for (int32_t t = bucket_off[b]; t < bucket_off[b + 1] - 1; ++t) *cells += merge_cells[t];
   if (ops && st == SADREF_OK) ops_off[n] = ops_pos;
+  free(status);
   return st;
 }
 
@@ -847,6 +982,36 @@ int sadref_glue(int32_t q, int32_t TW, const uint8_t* ops, const int64_t* ops_of
  * alignment itself, a profile of q rows (the richer template the paper leaves
  * to future work).  With one non-empty bucket both are the bucket's own
  * ancestor as one row. */
+/* refinement alignment u: bucket u's profile against the template */
+typedef struct {
+  const int32_t *nonempty, *width_b, *bucket_off;
+  uint16_t* const* prof;
+  const uint16_t* tprof;
+  int32_t TW, tn, A;
+  const int8_t* S;
+  int32_t go, ge;
+  uint8_t** bops;
+  int32_t* bnops;
+  int64_t *score, *cells;
+  int32_t* list;
+  int* status;
+} refine_ctx_t;
+
+static void refine_one_bucket(void* ctx, int64_t u64) {
+  refine_ctx_t* R = (refine_ctx_t*)ctx;
+  const int32_t u = (int32_t)u64;
+  int32_t b = R->nonempty[u];
+  int32_t W = R->width_b[b], nb = R->bucket_off[b + 1] - R->bucket_off[b];
+  R->bops[u] = (uint8_t*)malloc((size_t)(W + R->TW > 0 ? W + R->TW : 1));
+  int64_t sc = 0;
+  R->status[u] = sadref_profile_align(R->prof[b], W, nb, R->tprof, R->TW, R->tn, R->A, R->S,
+                                      R->go, R->ge, R->bops[u], &R->bnops[u], &sc);
+  R->score[u] = sc;
+  R->cells[u] = (int64_t)W * R->TW;
+  R->list[2 * u] = b;
+  R->list[2 * u + 1] = -1;
+}
+
 int sadref_refine_template_ops(int32_t n, int32_t A, const uint8_t* codes,
                                const int64_t* offsets, int32_t p, const int32_t* bucket_off,
                                const int32_t* members, const int32_t* colmap_b,
@@ -949,19 +1114,16 @@ int sadref_refine_template_ops(int32_t n, int32_t A, const uint8_t* codes,
     for (int32_t c = 0; c < GL; ++c) tprof[(size_t)c * A + GA[c]] = 1;
   }
   if (st == SADREF_OK) {
+    int* rst = (int*)calloc((size_t)(q > 0 ? q : 1), sizeof(int));
+    refine_ctx_t rc = {nonempty, width_b, bucket_off, prof, tprof, TW, tn, A, S, go, ge, bops,
+                       bnops, merge_score_g + nm, merge_cells_g + nm, merge_list_g + 2 * nm,
+                       rst};
+    for_items(q, refine_one_bucket, &rc);
     for (int32_t u = 0; u < q && st == SADREF_OK; ++u) {
-      int32_t b = nonempty[u];
-      int32_t W = width_b[b], nb = bucket_off[b + 1] - bucket_off[b];
-      bops[u] = (uint8_t*)malloc((size_t)(W + TW > 0 ? W + TW : 1));
-      int64_t sc = 0;
-      st = sadref_profile_align(prof[b], W, nb, tprof, TW, tn, A, S, go, ge, bops[u],
-                                &bnops[u], &sc);
-      merge_score_g[nm + u] = sc;
-      merge_cells_g[nm + u] = (int64_t)W * TW;
-      merge_list_g[2 * (nm + u)] = b;
-      merge_list_g[2 * (nm + u) + 1] = -1;
-      *cells += (int64_t)W * TW;
+      st = rst[u];
+      if (st == SADREF_OK) *cells += merge_cells_g[nm + u];
     }
+    free(rst);
   }
 
   /* the refinement op strings, for callers that check the glue */

@@ -34,6 +34,11 @@ enum { SADREF_OP_M = 0, SADREF_OP_X = 1, SADREF_OP_Y = 2 };
 /* Sorted unique k-mer list of one sequence (Section 2, k-mer counts nx(tau)).
  * taus/counts must hold L-k+1 entries; returns the number of unique k-mers in
  * *n_unique.  tau = sum_u x[t+u] * A^(k-1-u). */
+/* Threads for the loops over independent items (sequences, chunks,
+ * buckets, refinement alignments); 1 (the default) runs everything on the
+ * calling thread.  Results do not depend on it. */
+void sadref_set_threads(int32_t threads);
+
 int sadref_kmer_list(const uint8_t* x, int64_t L, int A, int k,
                      int32_t* taus, int32_t* counts, int64_t* n_unique);
 

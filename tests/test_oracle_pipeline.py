@@ -148,3 +148,29 @@ def test_small_merges_are_optimal(oracle_lib):
         C2 = np.eye(4, dtype=np.int64)[x2]
         score, _ = brute_best(C1, 1, C2, 1, S, 5, 2)
         assert score == al["merge_score"][boff[b]]
+
+
+@pytest.mark.parametrize("name,p", [("prot64", 4), ("prot64", 7)])
+def test_threads_do_not_change_results(oracle_lib, name, p):
+    """The oracle's loops over sequences, chunks, buckets and refinement
+    alignments give the same outputs on 4 threads as on one."""
+    s = make_inputs(name)
+    S = protein_matrix()
+    outs = []
+    try:
+        for t in (1, 4):
+            oracle.set_threads(t)
+            outs.append(oracle.run_pipeline(s.codes, s.offsets, s.alphabet, 3, p, S, 10, 1))
+            outs[-1]["rank_all"] = oracle.rank_against(s.codes, s.offsets, s.alphabet, 3)
+    finally:
+        oracle.set_threads(1)
+    a, b = outs
+
+    def same(x, y):
+        if isinstance(x, dict):
+            assert x.keys() == y.keys()
+            for k in x:
+                same(x[k], y[k])
+        else:
+            assert np.array_equal(np.asarray(x), np.asarray(y))
+    same(a, b)

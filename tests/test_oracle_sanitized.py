@@ -28,7 +28,7 @@ def test_oracle_pins_under_sanitizers(tmp_path):
     if not asan or not ubsan:
         pytest.skip("sanitizer runtimes not available")
     lib = str(tmp_path / "libsad_oracle_san.so")
-    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared",
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-pthread",
                            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                            "-fno-omit-frame-pointer", os.path.join(ROOT, "oracle", "sad_oracle.c"),
                            "-o", lib])
