@@ -80,10 +80,60 @@ __global__ __launch_bounds__(kUpgmaThreads) void upgma_kernel(
   }
 }
 
+// Large groups: one workgroup of kUpgmaWideThreads per group, pair sums in
+// the global n x n work array, the steps split over all its waves.
+__global__ __launch_bounds__(kUpgmaWideThreads) void upgma_wide_kernel(
+    const uint32_t* __restrict__ F, const int64_t* __restrict__ fm_off,
+    const int32_t* __restrict__ group_off, uint64_t* __restrict__ Sw,
+    int32_t* __restrict__ merges_out, const int32_t* __restrict__ merge_base, DevStatus* st) {
+  extern __shared__ int32_t shw[];
+  __shared__ WideScratch ws;
+  const int g = blockIdx.x;
+  const int n = group_off[g + 1] - group_off[g];
+  if (n <= 1) return;
+  int32_t* id = shw;
+  int32_t* sz = shw + n;
+  int32_t* active = shw + 2 * n;
+  int32_t* best = shw + 3 * n;
+  int32_t* rec = shw + 4 * n;
+  const uint32_t* Fg = F + fm_off[g];
+  int32_t* mo = merges_out + 2 * (int64_t)merge_base[g];
+  const int tid = threadIdx.x;
+  for (int a = tid; a < n; a += kUpgmaWideThreads) {
+    id[a] = a;
+    sz[a] = 1;
+    active[a] = 1;
+  }
+  const FullS S{Sw + fm_off[g], n};
+  for (int64_t q = tid; q < (int64_t)n * n; q += kUpgmaWideThreads) S.t[q] = Fg[q];
+  __syncthreads();
+  auto rec_merge = [&](int step, int ia, int ib) {
+    mo[2 * step] = ia;
+    mo[2 * step + 1] = ib;
+  };
+  if (n <= kUpgmaW64MaxN) {
+    wide_init_best<true>(S, n, id, sz, active, best, &ws);
+    upgma_steps_wide<true>(S, n, id, sz, active, best, rec, &ws, g, st, rec_merge);
+  } else {
+    wide_init_best<false>(S, n, id, sz, active, best, &ws);
+    upgma_steps_wide<false>(S, n, id, sz, active, best, rec, &ws, g, st, rec_merge);
+  }
+}
+
 void launch_upgma(const uint32_t* F, const int64_t* fm_off, const int32_t* group_off,
                   int ngroups, int max_n, uint64_t* Swork, int32_t* merges_out,
                   const int32_t* merge_base, DevStatus* st, hipStream_t stream) {
   if (ngroups <= 0 || max_n <= 1) return;
+  if (max_n >= kUpgmaWideMinN) {
+    // a large group: its O(n) step phases on a workgroup of 16 waves
+    const size_t lds = (size_t)5 * max_n * sizeof(int32_t);
+    if (lds > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)upgma_wide_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    upgma_wide_kernel<<<ngroups, kUpgmaWideThreads, lds, stream>>>(F, fm_off, group_off, Swork,
+                                                                   merges_out, merge_base, st);
+    return;
+  }
   // groups up to lds_n keep their sums in LDS; the per-cluster arrays take
   // 5 max(n) words either way
   const int lds_n = std::min(max_n, kUpgmaLdsN);

@@ -404,3 +404,211 @@ __device__ bool upgma_steps(const St& S, int n, int32_t* id, int32_t* sz, int32_
 }
 
 }  // namespace sad
+
+namespace sad {
+
+// ---------------------------------------------------------------- wide steps
+// The same steps for large groups, run by every wave of a workgroup of
+// kUpgmaWideThreads threads: each phase of a step (the first of the best
+// pairs, the union's sums, the comparisons with the union, the rescans) is
+// split over all threads, with workgroup barriers between the phases; rescans
+// take 4 rows at a time, each row scanned by the whole workgroup.  A wave's
+// winner is reduced across the waves through LDS with the same order, so the
+// merges are those of upgma_steps.
+constexpr int kUpgmaWideThreads = 1024;
+constexpr int kUpgmaWideWaves = kUpgmaWideThreads / 64;
+constexpr int kUpgmaWideMinN = 257;   // smaller groups keep the one-wave steps
+
+// Per-wave winners of up to 4 reductions, in LDS.
+struct WideScratch {
+  uint64_t s[4][kUpgmaWideWaves];
+  uint32_t p[4][kUpgmaWideWaves];
+  uint32_t key[4][kUpgmaWideWaves];
+  int32_t arg[4][kUpgmaWideWaves];
+  int32_t nrec;
+};
+
+// The workgroup's first candidate of RB reductions: every wave reduces its
+// lanes' candidates c[j] (argument a[j]), lane 0 of each wave publishes, and
+// after a barrier every wave reduces the published ones; out[j] is the
+// winner's argument (-1 if no candidate).  Ends with a barrier.
+template <bool W64, int RB>
+__device__ inline void wg_first(WCand (&c)[RB], const int (&a)[RB], WideScratch* ws,
+                                int (&out)[RB]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t mine[RB], wk[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) mine[j] = c[j].key;
+  wave_first_keys<W64, RB>(c, wk);
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const int src = winner_lane(mine[j], wk[j]);
+    // the winner's fields are read from the lane that holds it (after the
+    // reduction every lane of row 3 holds the first's fields; lane 63 does)
+    const uint64_t s = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c[j].s, 63) |
+                       ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(c[j].s >> 32), 63)
+                        << 32);
+    const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)c[j].p, 63);
+    const int arg = src < 0 ? -1 : __builtin_amdgcn_readlane(a[j], src);
+    if (lane == 0) {
+      ws->s[j][wave] = src < 0 ? 0 : s;
+      ws->p[j][wave] = src < 0 ? 1u : p;
+      ws->key[j][wave] = wk[j];
+      ws->arg[j][wave] = arg;
+    }
+  }
+  __syncthreads();
+  WCand d[RB];
+  int da[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const bool on = lane < kUpgmaWideWaves;
+    d[j].s = on ? ws->s[j][lane] : 0;
+    d[j].p = on ? ws->p[j][lane] : 1u;
+    d[j].key = on ? ws->key[j][lane] : ~0u;
+    da[j] = on ? ws->arg[j][lane] : -1;
+    mine[j] = d[j].key;
+  }
+  wave_first_keys<W64, RB>(d, wk);
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const int src = winner_lane(mine[j], wk[j]);
+    out[j] = src < 0 ? -1 : __builtin_amdgcn_readlane(da[j], src);
+  }
+  __syncthreads();
+}
+
+// Best partners of the rows r[0..RB) among the active slots, the whole
+// workgroup scanning each row (-1 where none).
+template <bool W64, int RB, typename St>
+__device__ inline void wg_best_partners(const St& S, int n, const int (&r)[RB], const int32_t* id,
+                                        const int32_t* sz, const int32_t* active,
+                                        WideScratch* ws, int (&out)[RB]) {
+  WCand c[RB];
+  int cb[RB], ir[RB];
+  uint32_t sr[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    c[j] = wc_none();
+    cb[j] = -1;
+    sr[j] = (uint32_t)sz[r[j]];
+    ir[j] = id[r[j]];
+  }
+  for (int b = threadIdx.x; b < n; b += kUpgmaWideThreads) {
+    uint64_t sv[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) sv[j] = S.get(r[j], b != r[j] ? b : other_slot(r[j]));
+    const bool on = active[b] != 0;
+    const uint32_t zb = (uint32_t)sz[b];
+    const int ib = id[b];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      if (!on || b == r[j]) continue;
+      WCand x;
+      x.s = sv[j];
+      x.p = sr[j] * zb;
+      x.key = pair_key16(ir[j], ib);
+      if (wc_better<W64>(x, c[j])) {
+        c[j] = x;
+        cb[j] = b;
+      }
+    }
+  }
+  wg_first<W64, RB>(c, cb, ws, out);
+}
+
+// Best partners of every slot (the whole workgroup, 4 rows at a time).
+template <bool W64, typename St>
+__device__ inline void wide_init_best(const St& S, int n, const int32_t* id, const int32_t* sz,
+                                      const int32_t* active, int32_t* best, WideScratch* ws) {
+  for (int t = 0; t < n; t += 4) {
+    const int k = min(4, n - t);
+    int rr[4], bb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rr[j] = t + min(j, k - 1);
+    wg_best_partners<W64, 4>(S, n, rr, id, sz, active, ws, bb);
+    if (threadIdx.x == 0)
+      for (int j = 0; j < k; ++j) best[rr[j]] = bb[j];
+  }
+  __syncthreads();
+}
+
+// The n - 1 merge steps on the whole workgroup (after wide_init_best).
+// on_merge(step, min id, max id) runs on thread 0.  Returns false (after
+// raising an error) if a step finds no pair; every thread returns the same.
+template <bool W64, typename St, typename OnMerge>
+__device__ bool upgma_steps_wide(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
+                                 int32_t* best, int32_t* rec, WideScratch* ws, int g,
+                                 DevStatus* st, OnMerge&& on_merge) {
+  const int tid = threadIdx.x;
+  for (int step = 0; step < n - 1; ++step) {
+    // the first of the clusters' best pairs
+    WCand c[1] = {wc_none()};
+    int cab[1] = {0};
+    for (int r = tid; r < n; r += kUpgmaWideThreads) {
+      const int b = active[r] ? best[r] : -1;
+      if (b < 0) continue;
+      WCand x;
+      x.s = S.get(r, b);
+      x.p = (uint32_t)sz[r] * (uint32_t)sz[b];
+      x.key = pair_key16(id[r], id[b]);
+      if (wc_better<W64>(x, c[0])) {
+        c[0] = x;
+        cab[0] = min(r, b) | (max(r, b) << 16);
+      }
+    }
+    int win[1];
+    wg_first<W64, 1>(c, cab, ws, win);
+    if (win[0] < 0) {
+      if (tid == 0) raise_error(st, SAD_E_INVAL, g, W_UPGMA);
+      return false;
+    }
+    const int ba = win[0] & 0xffff, bb = win[0] >> 16;
+    if (tid == 0) on_merge(step, min(id[ba], id[bb]), max(id[ba], id[bb]));
+    // S(new, c) = S(a, c) + S(b, c) for the remaining active clusters
+    for (int q = tid; q < n; q += kUpgmaWideThreads)
+      if (active[q] && q != ba && q != bb) S.set(ba, q, S.get(ba, q) + S.get(bb, q));
+    __syncthreads();
+    if (tid == 0) {
+      sz[ba] += sz[bb];
+      id[ba] = n + step;
+      active[bb] = 0;
+      ws->nrec = 0;
+    }
+    __syncthreads();
+    if (step == n - 2) break;
+    // clusters that pointed at a merged cluster are listed for a rescan, the
+    // others compare their best with the union
+    for (int q = tid; q < n; q += kUpgmaWideThreads) {
+      if (!active[q]) continue;
+      const int b = best[q];
+      if (q == ba || b == ba || b == bb) {
+        rec[atomicAdd(&ws->nrec, 1)] = q;
+        continue;
+      }
+      WCand cur, uni;
+      cur.s = S.get(q, b);
+      cur.p = (uint32_t)sz[q] * (uint32_t)sz[b];
+      cur.key = pair_key16(id[q], id[b]);
+      uni.s = S.get(q, ba);
+      uni.p = (uint32_t)sz[q] * (uint32_t)sz[ba];
+      uni.key = pair_key16(id[q], id[ba]);
+      if (wc_better<W64>(uni, cur)) best[q] = ba;
+    }
+    __syncthreads();
+    const int m = ws->nrec;
+    for (int t = 0; t < m; t += 4) {
+      const int k = min(4, m - t);
+      int rr[4], bb4[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rr[j] = rec[t + min(j, k - 1)];
+      wg_best_partners<W64, 4>(S, n, rr, id, sz, active, ws, bb4);
+      if (tid == 0)
+        for (int j = 0; j < k; ++j) best[rr[j]] = bb4[j];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+}  // namespace sad
