@@ -1502,7 +1502,7 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
     launch_fill_i32(reinterpret_cast<int32_t*>(out->d_merge_cells), 0, 2 * (int64_t)n, st);
     launch_kmer_lists(seqs->d_codes, seqs->d_offsets, n, A, k, entries, nullptr, nu, c->st, st);
     KmerLists kl{entries, seqs->d_offsets, nu, seqs->d_offsets};
-    launch_fmatrix_groups(kl, d_bucket_off, d_members, p, n, d_fm_off, k, kspace, F, st);
+    launch_fmatrix_groups(kl, d_bucket_off, d_members, p, max_n, d_fm_off, k, kspace, F, st);
   };
   TreeSet ts;
   ts.ngroups = p;

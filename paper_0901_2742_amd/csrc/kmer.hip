@@ -263,93 +263,289 @@ __device__ inline uint64_t block_sum_waves(uint64_t v, uint64_t* red) {
   return s;
 }
 
-// K_loc(r) = sum over j in chunk(r) of F(r, j)
+// ------------------------------------------------------------------ row groups
+// A workgroup takes kRowGroup consecutive rows that share their column set
+// (rows of one chunk, of the listed rows, of one group).  Their counts go to
+// one histogram as 4-bit fields (row g in bits 4g..4g+3 of the k-mer's 16-bit
+// word): each streamed column entry then serves every row of the group.  A
+// count above 15 (the field's range) anywhere in the group sends the group
+// down the one-row path instead (a full 16-bit count per k-mer, one row at a
+// time), so the sums are exact either way.
+constexpr int kRowGroup = 4;
+
+// Loads the lists of rows[0..kRowGroup) (-1: none) as 4-bit fields; sets
+// *over if a count does not fit.  hist and *over must be zero.
+__device__ __forceinline__ void hist_load_packed(uint16_t* hist, const KmerLists& kl,
+                                        const int* rows, int32_t* over) {
+  uint32_t* h32 = reinterpret_cast<uint32_t*>(hist);
+#pragma unroll
+  for (int g = 0; g < kRowGroup; ++g) {
+    if (rows[g] < 0) continue;
+    const uint32_t* e = kl.entries + kl.off[rows[g]];
+    const int nr = kl.nu[rows[g]];
+    for (int t = threadIdx.x; t < nr; t += blockDim.x) {
+      const uint32_t v = e[t], tau = v >> 16, cnt = v & 0xffffu;
+      if (cnt > 15u) *over = 1;
+      else if (cnt) atomicOr(&h32[tau >> 1], cnt << (4 * g + 16 * (tau & 1u)));
+    }
+  }
+}
+
+// c between every row of the packed histogram and NC column sequences
+// cs[0..NC) (wave-wide; cs[q] < 0: none): res[q][g] for row g.  The loads are
+// those of wave_common_n; each entry adds min(count, field g) for every g.
+template <int NC>
+__device__ __forceinline__ void wave_common_packed(const uint16_t* hist, const KmerLists& kl, const int* cs,
+                                          int32_t (&res)[NC][kRowGroup]) {
+  const uint32_t* e[NC];
+  int nl[NC];
+  int nmax = 0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    e[q] = kl.entries + kl.off[cs[q] >= 0 ? cs[q] : cs[0]];
+    nl[q] = cs[q] >= 0 ? kl.nu[cs[q]] : 0;
+    nmax = nl[q] > nmax ? nl[q] : nmax;
+  }
+  const int lane = threadIdx.x & 63;
+  int32_t acc[NC][kRowGroup];
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+#pragma unroll
+    for (int g = 0; g < kRowGroup; ++g) acc[q][g] = 0;
+  for (int t0 = 0; t0 < nmax; t0 += 256) {
+    uint32_t v[NC][4];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + 64 * u + lane;
+        v[q][u] = t < nl[q] ? e[q][t] : 0u;
+      }
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t h = hist[v[q][u] >> 16], k = v[q][u] & 0xffffu;
+#pragma unroll
+        for (int g = 0; g < kRowGroup; ++g) {
+          const uint32_t f = (h >> (4 * g)) & 15u;
+          acc[q][g] += (int32_t)(k < f ? k : f);
+        }
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+#pragma unroll
+    for (int g = 0; g < kRowGroup; ++g) res[q][g] = wave_sum32(acc[q][g]);
+}
+
+// The NC x kRowGroup results of a packed pass one per lane: lane q
+// kRowGroup + g takes column q's count for row g (lanes past them: column -1).
+template <int NC>
+__device__ __forceinline__ void lane_pair(const int32_t (&cc)[NC][kRowGroup], const int* cs, int lane,
+                                 int32_t& c, int& j, int& q_of_lane) {
+  c = 0;
+  j = -1;
+  q_of_lane = 0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+#pragma unroll
+    for (int g = 0; g < kRowGroup; ++g)
+      if (lane == q * kRowGroup + g) {
+        c = cc[q][g];
+        j = cs[q];
+        q_of_lane = q;
+      }
+}
+
+// Per-row sums of the workgroup's lanes (row g = lane % kRowGroup, lanes
+// below NC kRowGroup): thread 0 gets sums[g].
+__device__ __forceinline__ void block_sum_rows(uint64_t part, uint64_t* red, uint64_t* sums) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int g = 0; g < kRowGroup; ++g) {
+    const uint64_t v = wave_sum_u64((lane % kRowGroup) == g ? part : 0ull);
+    if (lane == 0) red[g * (kPairThreadsMax / 64) + w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int g = 0; g < kRowGroup; ++g) {
+      uint64_t t = 0;
+      for (int q = 0; q < nw; ++q) t += red[g * (kPairThreadsMax / 64) + q];
+      sums[g] = t;
+    }
+}
+
+// Column passes of the group's rows over the columns col(x), x in [0, ncol)
+// (col(x) < 0: skip).  packed: all rows at once against the 4-bit histogram,
+// cb(x, g, c) for every column and row with its count c; otherwise only row
+// `one` against the 16-bit histogram, cb(x, one, c).  cb runs on the lane that
+// holds the result.
+template <typename Col, typename Cb>
+__device__ __forceinline__ void column_passes(const uint16_t* hist, const KmerLists& kl, int ncol, bool packed,
+                                     int one, Col&& col, Cb&& cb) {
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  for (int x0 = wave; x0 < ncol; x0 += kPairCols * nw) {
+    int cs[kPairCols], xs[kPairCols];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < kPairCols; ++q) {
+      const int x = x0 + q * nw;
+      xs[q] = x;
+      cs[q] = x < ncol ? col(x) : -1;
+      any = any || cs[q] >= 0;
+    }
+    if (!any) continue;
+    // the first column must be valid (it names the stand-in list)
+    if (cs[0] < 0)
+#pragma unroll
+      for (int q = 1; q < kPairCols; ++q)
+        if (cs[0] < 0 && cs[q] >= 0) {
+          cs[0] = cs[q];
+          xs[0] = xs[q];
+          cs[q] = -1;
+        }
+    int32_t cl;
+    int jl, ql;
+    if (packed) {
+      int32_t cc[kPairCols][kRowGroup];
+      wave_common_packed<kPairCols>(hist, kl, cs, cc);
+      lane_pair<kPairCols>(cc, cs, lane, cl, jl, ql);
+    } else {
+      int32_t cc[kPairCols];
+      wave_common_n<kPairCols>(hist, kl, cs, cc);
+      lane_column<kPairCols>(cc, cs, lane, cl, jl, ql);
+    }
+    int xl = xs[0];
+#pragma unroll
+    for (int q = 0; q < kPairCols; ++q)
+      if (q == ql) xl = xs[q];
+    if (jl >= 0) cb(xl, packed ? lane % kRowGroup : one, jl, cl);
+  }
+}
+
+// The shared body of the pair kernels: rows[0..kRowGroup) (-1: none) against
+// the columns col(x); cb(x, g, column sequence, c) on the lane holding each
+// result (g = the row's index in rows); done(g) by every thread after the
+// columns of row g (one-row path) or of all rows (packed, g = -1).  Clears
+// and loads the histogram.
+template <typename Col, typename Cb, typename Done>
+__device__ __forceinline__ void pair_rows(uint16_t* hist, int kspace, const KmerLists& kl,
+                                 const int* rows, int ncol, int32_t* over, Col&& col,
+                                 Cb&& cb, Done&& done) {
+  hist_clear(hist, kspace);
+  if (threadIdx.x == 0) *over = 0;
+  __syncthreads();
+  hist_load_packed(hist, kl, rows, over);
+  __syncthreads();
+  if (!*over) {
+    // lanes of absent rows (a group's last rows) produce no result
+    column_passes(hist, kl, ncol, true, -1, col, [&](int x, int g, int j, int32_t c) {
+      if (rows[g] >= 0) cb(x, g, j, c);
+    });
+    done(-1);
+    return;
+  }
+  for (int g = 0; g < kRowGroup; ++g) {
+    const int rg = rows[g];
+    if (rg < 0) continue;
+    __syncthreads();
+    hist_clear(hist, kspace);
+    __syncthreads();
+    hist_load(hist, kl, rg);
+    __syncthreads();
+    column_passes(hist, kl, ncol, false, g, col, cb);
+    done(g);
+  }
+}
+
+// Row sums of the pair kernels: the packed path's per-row lanes, or one row's
+// lanes; thread 0 writes out[rows[g]].  Resets part.
+__device__ __forceinline__ void store_row_sums(int g, uint64_t& part, uint64_t* red, uint64_t* sums,
+                                      const int* rows, uint64_t* out) {
+  if (g < 0) {
+    block_sum_rows(part, red, sums);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int q = 0; q < kRowGroup; ++q)
+        if (rows[q] >= 0) out[rows[q]] = sums[q];
+  } else {
+    const uint64_t s = block_sum_waves(wave_sum_u64(part), red);
+    if (threadIdx.x == 0) out[rows[g]] = s;
+  }
+  part = 0;
+  __syncthreads();
+}
+
+// K_loc(r) = sum over j in chunk(r) of F(r, j).  Workgroup (x, c) runs rows
+// 4x .. 4x + 3 of chunk c.
 __global__ __launch_bounds__(kPairThreadsMax) void rowsum_chunk_kernel(KmerLists kl, int n, int p,
                                                                      int k, int kspace,
                                                                      uint64_t* __restrict__ out) {
   extern __shared__ uint16_t hist[];
-  __shared__ uint64_t red[kPairThreadsMax / 64];
-  const int r = blockIdx.x;
-  int c = (int)(((int64_t)r * p) / n);
-  while (c + 1 <= p && (((int64_t)(c + 1) * n) / p) <= r) ++c;
-  while ((((int64_t)c * n) / p) > r) --c;
+  __shared__ uint64_t red[kRowGroup * (kPairThreadsMax / 64)];
+  __shared__ uint64_t sums[kRowGroup];
+  __shared__ int32_t over;
+  const int c = blockIdx.y;
   const int lo = (int)(((int64_t)c * n) / p), hi = (int)(((int64_t)(c + 1) * n) / p);
-  hist_clear(hist, kspace);
-  __syncthreads();
-  hist_load(hist, kl, r);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int64_t Lr = seq_len(kl, r);
-  uint64_t part = 0;
-  for (int j = lo + wave; j < hi; j += kPairCols * nw) {
-    int cs[kPairCols];
-    int32_t cc[kPairCols];
-#pragma unroll
-    for (int q = 0; q < kPairCols; ++q) cs[q] = j + q * nw < hi ? j + q * nw : -1;
-    wave_common_n<kPairCols>(hist, kl, cs, cc);
-    int32_t cl;
-    int jl, ql;
-    lane_column<kPairCols>(cc, cs, threadIdx.x & 63, cl, jl, ql);
-    if (jl >= 0) part += fhat_of(cl, Lr, seq_len(kl, jl), k);
+  const int r = lo + kRowGroup * (int)blockIdx.x;
+  if (r >= hi) return;
+  // the group's rows and lengths in LDS (read with lane-dependent indices)
+  __shared__ int rows[kRowGroup];
+  __shared__ int64_t Lr[kRowGroup];
+  if (threadIdx.x < kRowGroup) {
+    const int g = threadIdx.x;
+    rows[g] = r + g < hi ? r + g : -1;
+    Lr[g] = rows[g] >= 0 ? seq_len(kl, rows[g]) : 0;
   }
-  uint64_t s = block_sum_waves(wave_sum_u64(part), red);
-  if (threadIdx.x == 0) out[r] = s;
+  __syncthreads();
+  uint64_t part = 0;
+  pair_rows(hist, kspace, kl, rows, hi - lo, &over, [&](int x) { return lo + x; },
+            [&](int, int g, int j, int32_t cnt) {
+              part += fhat_of(cnt, Lr[g], seq_len(kl, j), k);
+            },
+            [&](int g) { store_row_sums(g, part, red, sums, rows, out); });
 }
 
 // out(r) = sum over the listed columns of F(r, col); cols == nullptr lists
 // all n sequences.  A listed id outside [0, n) is reported and skipped.
+// Workgroup b runs rows 4b .. 4b + 3.
 __global__ __launch_bounds__(kPairThreadsMax) void rowsum_list_kernel(KmerLists kl, int n,
                                                                     const int32_t* __restrict__ cols,
                                                                     int ncols, int k, int kspace,
                                                                     uint64_t* __restrict__ out,
                                                                     DevStatus* st) {
   extern __shared__ uint16_t hist[];
-  __shared__ uint64_t red[kPairThreadsMax / 64];
-  const int r = blockIdx.x;
-  hist_clear(hist, kspace);
-  __syncthreads();
-  hist_load(hist, kl, r);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int64_t Lr = seq_len(kl, r);
-  uint64_t part = 0;
-  for (int q0 = wave; q0 < ncols; q0 += kPairCols * nw) {
-    int cs[kPairCols];
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < kPairCols; ++q) {
-      const int qq = q0 + q * nw;
-      int j = qq < ncols ? (cols ? cols[qq] : qq) : -1;
-      if (qq < ncols && (j < 0 || j >= n)) {
-        if (r == 0 && (threadIdx.x & 63) == 0) raise_error(st, SAD_E_INVAL, qq, W_RANK);
-        j = -1;
-      }
-      cs[q] = j;
-      any = any || j >= 0;
-    }
-    if (!any) continue;
-    // the first listed column must be valid (it names the stand-in list)
-    if (cs[0] < 0)
-#pragma unroll
-      for (int q = 1; q < kPairCols; ++q)
-        if (cs[0] < 0 && cs[q] >= 0) {
-          cs[0] = cs[q];
-          cs[q] = -1;
-        }
-    int32_t cc[kPairCols];
-    wave_common_n<kPairCols>(hist, kl, cs, cc);
-    int32_t cl;
-    int jl, ql;
-    lane_column<kPairCols>(cc, cs, threadIdx.x & 63, cl, jl, ql);
-    if (jl >= 0) part += fhat_of(cl, Lr, seq_len(kl, jl), k);
+  __shared__ uint64_t red[kRowGroup * (kPairThreadsMax / 64)];
+  __shared__ uint64_t sums[kRowGroup];
+  __shared__ int32_t over;
+  const int r = kRowGroup * (int)blockIdx.x;
+  __shared__ int rows[kRowGroup];
+  __shared__ int64_t Lr[kRowGroup];
+  if (threadIdx.x < kRowGroup) {
+    const int g = threadIdx.x;
+    rows[g] = r + g < n ? r + g : -1;
+    Lr[g] = rows[g] >= 0 ? seq_len(kl, rows[g]) : 0;
   }
-  uint64_t s = block_sum_waves(wave_sum_u64(part), red);
-  if (threadIdx.x == 0) out[r] = s;
+  __syncthreads();
+  uint64_t part = 0;
+  pair_rows(hist, kspace, kl, rows, ncols, &over,
+            [&](int x) {
+              const int j = cols ? cols[x] : x;
+              if (j < 0 || j >= n) {
+                if (r == 0 && (threadIdx.x & 63) == 0) raise_error(st, SAD_E_INVAL, x, W_RANK);
+                return -1;
+              }
+              return j;
+            },
+            [&](int, int g, int j, int32_t cnt) {
+              part += fhat_of(cnt, Lr[g], seq_len(kl, j), k);
+            },
+            [&](int g) { store_row_sums(g, part, red, sums, rows, out); });
 }
 
-// F rows inside groups: row index g_row in [0, total_rows) of the ids array;
-// its group's members are ids[group_off[g] .. group_off[g+1]); the group's
-// matrix starts at fm_off[g] (n_g x n_g, row-major).
+// F rows inside groups: group g's members are ids[group_off[g] ..
+// group_off[g+1]); its matrix starts at fm_off[g] (n_g x n_g, row-major).
+// Workgroup (x, g) writes the rows of members 4x .. 4x + 3 of group g.
 __global__ __launch_bounds__(kPairThreadsMax) void fmatrix_kernel(KmerLists kl,
                                                                 const int32_t* __restrict__ group_off,
                                                                 const int32_t* __restrict__ ids,
@@ -358,35 +554,26 @@ __global__ __launch_bounds__(kPairThreadsMax) void fmatrix_kernel(KmerLists kl,
                                                                 int k, int kspace,
                                                                 uint32_t* __restrict__ F) {
   extern __shared__ uint16_t hist[];
-  const int row = blockIdx.x;
-  int lo = 0, hi = ngroups;  // find g with group_off[g] <= row < group_off[g+1]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (group_off[mid] <= row) lo = mid;
-    else hi = mid;
-  }
-  const int g = lo;
+  __shared__ int32_t over;
+  const int g = blockIdx.y;
   const int g0 = group_off[g], ng = group_off[g + 1] - g0;
-  const int a = row - g0;
-  const int r = ids[row];
-  hist_clear(hist, kspace);
-  __syncthreads();
-  hist_load(hist, kl, r);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int64_t Lr = seq_len(kl, r);
-  uint32_t* Frow = F + fm_off[g] + (int64_t)a * ng;
-  for (int b = wave; b < ng; b += kPairCols * nw) {
-    int cs[kPairCols];
-    int32_t cc[kPairCols];
-#pragma unroll
-    for (int q = 0; q < kPairCols; ++q) cs[q] = b + q * nw < ng ? ids[g0 + b + q * nw] : -1;
-    wave_common_n<kPairCols>(hist, kl, cs, cc);
-    int32_t cl;
-    int jl, ql;
-    lane_column<kPairCols>(cc, cs, threadIdx.x & 63, cl, jl, ql);
-    if (jl >= 0) Frow[b + ql * nw] = fhat_of(cl, Lr, seq_len(kl, jl), k);
+  const int a = kRowGroup * (int)blockIdx.x;
+  if (a >= ng) return;
+  const int row = g0 + a;
+  __shared__ int rows[kRowGroup];
+  __shared__ int64_t Lr[kRowGroup];
+  if (threadIdx.x < kRowGroup) {
+    const int q = threadIdx.x;
+    rows[q] = a + q < ng ? ids[row + q] : -1;
+    Lr[q] = rows[q] >= 0 ? seq_len(kl, rows[q]) : 0;
   }
+  __syncthreads();
+  uint32_t* Fg = F + fm_off[g] + (int64_t)a * ng;
+  pair_rows(hist, kspace, kl, rows, ng, &over, [&](int x) { return ids[g0 + x]; },
+            [&](int x, int q, int j, int32_t cnt) {
+              Fg[(int64_t)q * ng + x] = fhat_of(cnt, Lr[q], seq_len(kl, j), k);
+            },
+            [&](int) {});
 }
 
 static size_t hist_bytes(int kspace) { return (size_t)((kspace + 1) / 2) * 4; }
@@ -405,23 +592,27 @@ void launch_rowsum_chunk(const KmerLists& kl, int n, int p, int k, int kspace, u
                          hipStream_t stream) {
   if (n <= 0) return;
   allow_lds((const void*)rowsum_chunk_kernel, hist_bytes(kspace));
-  rowsum_chunk_kernel<<<n, pair_threads(kspace), hist_bytes(kspace), stream>>>(kl, n, p, k, kspace, out);
+  const int wmax = (n + p - 1) / p;  // largest chunk
+  const dim3 grid((wmax + kRowGroup - 1) / kRowGroup, p);
+  rowsum_chunk_kernel<<<grid, pair_threads(kspace), hist_bytes(kspace), stream>>>(kl, n, p, k,
+                                                                                kspace, out);
 }
 
 void launch_rowsum_list(const KmerLists& kl, int n, const int32_t* cols, int ncols, int k,
                         int kspace, uint64_t* out, DevStatus* st, hipStream_t stream) {
   if (n <= 0) return;
   allow_lds((const void*)rowsum_list_kernel, hist_bytes(kspace));
-  rowsum_list_kernel<<<n, pair_threads(kspace), hist_bytes(kspace), stream>>>(kl, n, cols, ncols, k,
-                                                                      kspace, out, st);
+  rowsum_list_kernel<<<(n + kRowGroup - 1) / kRowGroup, pair_threads(kspace), hist_bytes(kspace),
+                       stream>>>(kl, n, cols, ncols, k, kspace, out, st);
 }
 
 void launch_fmatrix_groups(const KmerLists& kl, const int32_t* group_off, const int32_t* ids,
-                           int ngroups, int64_t total_rows, const int64_t* fm_off, int k,
-                           int kspace, uint32_t* F, hipStream_t stream) {
-  if (total_rows <= 0) return;
+                           int ngroups, int max_group, const int64_t* fm_off, int k, int kspace,
+                           uint32_t* F, hipStream_t stream) {
+  if (ngroups <= 0 || max_group <= 0) return;
   allow_lds((const void*)fmatrix_kernel, hist_bytes(kspace));
-  fmatrix_kernel<<<(unsigned)total_rows, pair_threads(kspace), hist_bytes(kspace), stream>>>(
+  const dim3 grid((max_group + kRowGroup - 1) / kRowGroup, ngroups);
+  fmatrix_kernel<<<grid, pair_threads(kspace), hist_bytes(kspace), stream>>>(
       kl, group_off, ids, ngroups, fm_off, k, kspace, F);
 }
 

@@ -97,9 +97,10 @@ void launch_rowsum_chunk(const KmerLists& kl, int n, int p, int k, int kspace,
                          uint64_t* out, hipStream_t stream);
 void launch_rowsum_list(const KmerLists& kl, int n, const int32_t* cols, int ncols, int k,
                         int kspace, uint64_t* out, DevStatus* st, hipStream_t stream);
+// (max_group: the largest group; every group's n_g x n_g matrix is written)
 void launch_fmatrix_groups(const KmerLists& kl, const int32_t* group_off, const int32_t* ids,
-                           int ngroups, int64_t total_rows, const int64_t* fm_off, int k,
-                           int kspace, uint32_t* F, hipStream_t stream);
+                           int ngroups, int max_group, const int64_t* fm_off, int k, int kspace,
+                           uint32_t* F, hipStream_t stream);
 void launch_chunk_sort(const uint64_t* key, int n, int p, int32_t* sorted, hipStream_t stream);
 void launch_pick_samples(const int32_t* sorted, int n, int p, int ks, int32_t* sample_ids,
                          hipStream_t stream);
