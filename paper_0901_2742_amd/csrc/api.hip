@@ -802,6 +802,7 @@ struct FusedTrees {
   uint32_t* const* F;            // carved with the caller's buffers (base carver)
   int64_t* const* d_fm_off;
   int32_t* d_merges;
+  uint64_t* const* Sw;           // pair sums of groups too large for LDS (or null)
   // after each carve (a regrown workspace loses earlier contents): host
   // upload of the matrix offsets, then the kernels that fill the matrices
   std::function<int32_t()> upload;
@@ -1048,7 +1049,8 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                                  (uintptr_t)e.prof_pool, (uintptr_t)c->st,
                                  (uintptr_t)N, (uintptr_t)ts.ngroups, (uintptr_t)ts.total_len,
                                  (uintptr_t)A, (uintptr_t)e.nwg, (uintptr_t)stream,
-                                 (uintptr_t)ts.kmer_k, (uintptr_t)ts.max_len};
+                                 (uintptr_t)ts.kmer_k, (uintptr_t)ts.max_len,
+                                 (uintptr_t)(fused->Sw ? *fused->Sw : nullptr)};
       gkey.resize(sizeof(ka) + sizeof(extra));
       std::memcpy(gkey.data(), &ka, sizeof(ka));
       std::memcpy(gkey.data() + sizeof(ka), extra, sizeof(extra));
@@ -1086,6 +1088,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     if (fused) {
       a.up_F = *fused->F;
       a.up_fm_off = *fused->d_fm_off;
+      a.up_Sw = fused->Sw ? *fused->Sw : nullptr;
       a.up_group_off = ts.d_group_off;
       a.up_ngroups = ts.ngroups;
       a.up_N = N;
@@ -1489,7 +1492,9 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
                     sched.fuse != 0;
   Carver cv;
   AlignBufs ab{};
-  plan_align(cv, ab, n, p, seqs->total_len, fm_total, !fuse);
+  // pair sums in HBM: guide trees by the separate kernel, or built in the
+  // launch for groups too large for LDS
+  plan_align(cv, ab, n, p, seqs->total_len, fm_total, !fuse || max_n > engine_fused_lds_group());
   uint32_t *&entries = ab.entries, *&F = ab.F;
   int32_t*& nu = ab.nu;
   int64_t*& d_fm_off = ab.d_fm_off;
@@ -1521,7 +1526,8 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   if (fuse) {
     // the similarity matrices stay alive under the engine's workspace, which
     // is carved after them on every attempt
-    const FusedTrees fz{&F, &d_fm_off, out->d_merge_list, upload, kernels};
+    const FusedTrees fz{&F, &d_fm_off, out->d_merge_list,
+                        max_n > engine_fused_lds_group() ? &Sw : nullptr, upload, kernels};
     return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz, sched.grid);
   }
   r = cv.carve(c);
@@ -1899,7 +1905,7 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
     cv.add(ids, q);
     cv.add(fm0, 1);
     cv.add(F, (size_t)q * q);
-    if (!fuse_tree) cv.add(Sw, (size_t)q * q);
+    if (!fuse_tree || q > engine_fused_lds_group()) cv.add(Sw, (size_t)q * q);
     // the ancestors' k-mer lists and similarity matrix (again after every
     // carve when the engine's workspace is carved with them)
     auto kernels = [&](hipStream_t st) {
@@ -1936,7 +1942,8 @@ extern "C" int32_t sad_refine_template(const sad_seqs* seqs, const int32_t* d_bu
     EngineBuffers e{};
     TreeOutputs to{nullptr, nullptr, ga_score, ga_cells, ga_cells_tot, true};
     if (fuse_tree) {
-      FusedTrees fz{&F, &fm0, ga_merges, []() -> int32_t { return SAD_OK; }, kernels};
+      FusedTrees fz{&F, &fm0, ga_merges, q > engine_fused_lds_group() ? &Sw : nullptr,
+                    []() -> int32_t { return SAD_OK; }, kernels};
       fz.graph = false;
       r = run_trees(c, ts, ga_merges, prm, A, cv, e, to, stream, &fz);
     } else {

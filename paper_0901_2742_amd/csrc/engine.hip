@@ -1329,44 +1329,27 @@ __device__ inline void create_job(const EngineArgs& a, int g0, int n, int step, 
   if (atomicSub(&a.job_pending[s], 1) == 1) push_job(a, s);
 }
 
-// Largest group whose guide tree is built inside the engine: the triangle of
-// 64-bit pair sums must fit in the score ring's LDS and the five cluster
-// arrays in the traceback staging block.
-constexpr int kFusedMaxN = 182;
+// Groups up to kFusedLdsN keep the triangle of 64-bit pair sums in the score
+// ring's LDS and the five cluster arrays in the traceback staging block;
+// larger ones, up to kFusedMaxN, keep the sums in their n x n area of the
+// global work array (a.up_Sw at the group's matrix offset) and the cluster
+// arrays in the ring.  The merge list (2 (n - 1) ints) fits the op buffer.
+constexpr int kFusedLdsN = 182;
+constexpr int kFusedMaxN = 600;
+static_assert(kFusedMaxN <= kUpgmaW64MaxN, "in-launch trees compare 64-bit cross products");
 
-// UPGMA of group g by the whole workgroup, pair sums in LDS (ring), cluster
-// arrays in tbst.
-__device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t* tbst,
-                           int32_t* mlist, int32_t* mcount) {
-  const int g0 = a.up_group_off[g], n = a.up_group_off[g + 1] - g0;
-  if (n <= 1) return;
+// The steps of the tree of group g on wave 0, the jobs of its merges made by
+// wave 1 as they are decided (see fused_tree).
+template <bool W64, int UB, typename St>
+__device__ void fused_tree_steps(const EngineArgs& a, int g, int g0, int n, const St& S, int32_t* id,
+                                 int32_t* sz, int32_t* active, int32_t* best, int32_t* rec,
+                                 int32_t* mlist, int32_t* mcount) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  uint64_t* tri = reinterpret_cast<uint64_t*>(ring);
-  int32_t* id = reinterpret_cast<int32_t*>(tbst);
-  int32_t* sz = id + n;
-  int32_t* active = id + 2 * n;
-  int32_t* best = id + 3 * n;
-  int32_t* rec = id + 4 * n;
-  for (int x = tid; x < n; x += kThreads) {
-    id[x] = x;
-    sz[x] = 1;
-    active[x] = 1;
-  }
-  const uint32_t* Fg = a.up_F + a.up_fm_off[g];
-  for (int64_t q = tid; q < (int64_t)n * n; q += kThreads) {
-    const int x = (int)(q / n), y = (int)(q % n);
-    if (x < y) tri[x * n - x * (x + 1) / 2 + y - x - 1] = Fg[q];
-  }
-  if (tid == 0) *mcount = 0;
-  __threadfence_block();
-  __syncthreads();
-  // (groups here are below kUpgmaW64MaxN: 64-bit cross products are exact)
-  const TriS S{tri, n};
-  upgma_init_best<true>(S, n, id, sz, active, best);
+  upgma_init_best<W64>(S, n, id, sz, active, best);
   __syncthreads();
   if (wave == 0) {
     // the merge steps; each decided merge is listed for wave 1
-    const bool ok = upgma_steps<true, 1>(
+    const bool ok = upgma_steps<W64, UB>(
         S, n, id, sz, active, best, rec, g, a.st,
         [&](int step, int ia, int ib) {
           mlist[2 * step] = ia;
@@ -1407,6 +1390,47 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
   __syncthreads();
 }
 
+// UPGMA of group g by the whole workgroup.
+__device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t* tbst,
+                           int32_t* mlist, int32_t* mcount) {
+  const int g0 = a.up_group_off[g], n = a.up_group_off[g + 1] - g0;
+  if (n <= 1) return;
+  const int tid = threadIdx.x;
+  const bool in_lds = n <= kFusedLdsN;
+  int32_t* id = reinterpret_cast<int32_t*>(in_lds ? tbst : ring);
+  int32_t* sz = id + n;
+  int32_t* active = id + 2 * n;
+  int32_t* best = id + 3 * n;
+  int32_t* rec = id + 4 * n;
+  for (int x = tid; x < n; x += kThreads) {
+    id[x] = x;
+    sz[x] = 1;
+    active[x] = 1;
+  }
+  const uint32_t* Fg = a.up_F + a.up_fm_off[g];
+  if (tid == 0) *mcount = 0;
+  if (!in_lds) {
+    // sums in the group's area of the global work array (both halves)
+    const FullS S{a.up_Sw + a.up_fm_off[g], n};
+    for (int64_t q = tid; q < (int64_t)n * n; q += kThreads) S.t[q] = Fg[q];
+    __threadfence_block();
+    __syncthreads();
+    // (kFusedMaxN <= kUpgmaW64MaxN: 64-bit cross products are exact)
+    fused_tree_steps<true, 1>(a, g, g0, n, S, id, sz, active, best, rec, mlist, mcount);
+    return;
+  }
+  uint64_t* tri = reinterpret_cast<uint64_t*>(ring);
+  for (int64_t q = tid; q < (int64_t)n * n; q += kThreads) {
+    const int x = (int)(q / n), y = (int)(q % n);
+    if (x < y) tri[x * n - x * (x + 1) / 2 + y - x - 1] = Fg[q];
+  }
+  __threadfence_block();
+  __syncthreads();
+  // (groups here are below kUpgmaW64MaxN: 64-bit cross products are exact)
+  fused_tree_steps<true, 1>(a, g, g0, n, TriS{tri, n}, id, sz, active, best, rec, mlist, mcount);
+}
+
+
 // ---------------------------------------------------------------- kernel
 template <int A, bool MFMA>
 __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
@@ -1437,9 +1461,10 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
 
   if constexpr (MFMA) {
     static_assert(kUpgmaThreads == kThreads, "tree phase uses the engine's workgroup shape");
-    static_assert(5 * kFusedMaxN <= kStageT4 * 64, "cluster arrays fit the staging block");
-    static_assert((int64_t)kFusedMaxN * (kFusedMaxN - 1) / 2 * 8 <=
+    static_assert(5 * kFusedLdsN <= kStageT4 * 64, "cluster arrays fit the staging block");
+    static_assert((int64_t)kFusedLdsN * (kFusedLdsN - 1) / 2 * 8 <=
                       (int64_t)kWaves * kRingWords * 4, "pair sums fit the score ring");
+    static_assert(5 * kFusedMaxN <= kWaves * kRingWords, "cluster arrays fit the score ring");
     // guide trees first; their merges become jobs for the other workgroups
     static_assert(2 * (kFusedMaxN - 1) * 4 <= 2 * kMaxWidth, "merge list fits the ops buffer");
     __shared__ int32_t umcount, ugrp;
@@ -1801,6 +1826,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
 }
 
 int engine_fused_max_group() { return kFusedMaxN; }
+int engine_fused_lds_group() { return kFusedLdsN; }
 
 int engine_workgroups() {
   int per_cu = kEngineWGPerCU;

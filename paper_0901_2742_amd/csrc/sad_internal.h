@@ -194,6 +194,7 @@ struct EngineArgs {
   // up_N + slot.
   const uint32_t* up_F;
   const int64_t* up_fm_off;
+  uint64_t* up_Sw;        // pair sums of groups above the in-LDS size (F's offsets)
   const int32_t* up_group_off;
   int32_t up_ngroups, up_N;
   int32_t* up_merges;
@@ -236,6 +237,7 @@ void launch_make_leaves(const uint8_t* codes, const int64_t* offsets, const int3
                         uint16_t* prof_pool, int64_t total_len, hipStream_t stream);
 // Jobs from UPGMA merge lists (one group per bucket, slots = member positions).
 int engine_fused_max_group();  // largest group the engine builds its guide tree for
+int engine_fused_lds_group();  // largest such group whose pair sums stay in LDS
 void launch_make_jobs(const int32_t* merges, const int32_t* group_off, int ngroups, int nslots,
                       int32_t internal_base, int32_t* node_parent, int32_t* job_a, int32_t* job_b,
                       int32_t* job_out, int32_t* job_next, int32_t* job_pending, int32_t* job_link,

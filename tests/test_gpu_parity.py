@@ -207,3 +207,36 @@ def test_prot2000_extreme_bucket_counts(hip):
             prm = B.Params(w.kmer_k, p, w.subst(), w.gap_open, w.gap_extend, w.s_max, mode)
             got = pipeline.run(s.codes, s.offsets, s.alphabet, prm)
             compare(got, refs[p], f"prot2000 p={p} mode={mode}")
+
+
+@pytest.mark.parametrize("alphabet", [4, 20])
+def test_repeat_rich_sequences(hip, alphabet):
+    """Sequences with k-mers repeated more than 15 times (homopolymer and
+    short tandem-repeat runs) next to ordinary ones: the pair kernels' row
+    groups that hold such a row take the one-row path with full 16-bit
+    counts; keys, samples, buckets and the bucket similarity matrices (through
+    the guide trees and alignments) must still be the oracle's."""
+    from workloads.synth import SeqSet
+    B, pipeline = hip
+    _say(f"case repeat-rich A={alphabet}")
+    k = 8 if alphabet == 4 else 3
+    s = generate(1500 + alphabet, 48, alphabet, 3, {"kind": "uniform_int", "lo": 90, "hi": 140},
+                 0.1, 0.02, k)
+    rng = np.random.default_rng(alphabet)
+    codes = [s.codes[s.offsets[i]:s.offsets[i + 1]].copy() for i in range(s.n)]
+    for t, i in enumerate(rng.choice(s.n, 9, replace=False)):
+        x = codes[i]
+        at = int(rng.integers(0, len(x) - 40))
+        if t % 3 == 0:
+            x[at:at + 40] = 0                                  # homopolymer: one k-mer 40 - k + 1 times
+        elif t % 3 == 1:
+            x[at:at + 40] = np.tile(np.array([1, 2], np.uint8), 20)   # period-2 repeat
+        else:
+            x[at:at + 40] = np.tile(np.array([3, 1, 2], np.uint8), 14)[:40]
+    offs = np.zeros(s.n + 1, np.int64)
+    offs[1:] = np.cumsum([len(x) for x in codes])
+    rs = SeqSet(alphabet, np.concatenate(codes).astype(np.uint8), offs, s.family, s.homology)
+    S = dna_matrix() if alphabet == 4 else protein_matrix()
+    for mode in (1, 0):
+        got, ref = run_both(B, pipeline, rs, k, 4, S, 10, 1, mode)
+        compare(got, ref, f"repeat-rich A={alphabet} mode {mode}")
