@@ -249,6 +249,7 @@ def workload_figures(name, args, B, pipeline, torch, threads):
                                    "frac": round(achieved / INT32_PEAK_TOPS, 5)},
                       "schedule": {"engine_workgroups": tuned[0],
                                    "trees_in_launch": bool(tuned[1]),
+                                   "cooperative_merges": bool(tuned[2]),
                                    "graph_replays": graphs[1]}}
     out["same_result"] = bool(
         all(np.array_equal(hosts["batched"][st]["colmap"], hosts["plain"][st]["colmap"])
@@ -376,7 +377,7 @@ def main():
     # the process), then time the pipeline with it
     key0, _ = B.sad_kmer_rank(seqs, prm)
     part0 = B.sad_partition(seqs, key0, prm)
-    tuned = (0, -1) if args.no_tune else B.sad_tune(seqs, part0["bucket_off"],
+    tuned = (0, -1, 1) if args.no_tune else B.sad_tune(seqs, part0["bucket_off"],
                                                     part0["members"], prm)
     B.sad_profile_graphs(reset=True)
     res, ms, eng_ms, launches = timed_steps(pipeline.run_device, seqs, prm, args.steps,
@@ -412,6 +413,7 @@ def main():
         "quality": qual,
         "mode": "batched",
         "schedule": {"engine_workgroups": tuned[0], "trees_in_launch": bool(tuned[1]),
+                     "cooperative_merges": bool(tuned[2]),
                      "graph_captures": graphs[0], "graph_replays": graphs[1]},
         "engine_kernel": {"ms_total": round(eng_ms, 3), "launches": launches,
                           "avg_launch_ms": round(eng_ms / max(launches, 1), 4),

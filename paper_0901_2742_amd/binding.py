@@ -103,7 +103,7 @@ def lib():
         L.sad_profile_phases.restype = I32
         L.sad_profile_jobs.argtypes = [P, ctypes.c_int64, P]
         L.sad_profile_jobs.restype = I32
-        L.sad_tune.argtypes = [P, P, P, P, P, P, P, P]
+        L.sad_tune.argtypes = [P, P, P, P, P, P, P, P, P]
         L.sad_tune.restype = I32
         L.sad_profile_graphs.argtypes = [P, P, I32]
         L.sad_profile_graphs.restype = I32
@@ -451,16 +451,17 @@ def sad_profile_phases(reset: bool = False):
 def sad_tune(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, prm: Params,
              out: dict | None = None):
     """Autotunes the schedule of sad_align_buckets for these buckets (cached for
-    later calls with the same workload shape).  Returns (grid, fuse)."""
+    later calls with the same workload shape).  Returns (grid, fuse, coop)."""
     dev = seqs.codes.device
     if out is None:
         out = _msa_tensors(seqs.total_len, prm.p, seqs.n, dev)
     s, pp, m = seqs.c_struct(), prm.c_struct(), _msa_struct(out)
-    g, f = ctypes.c_int32(0), ctypes.c_int32(0)
+    g, f, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
     code = lib().sad_tune(ctypes.byref(s), _ptr(bucket_off), _ptr(members), ctypes.byref(pp),
-                          ctypes.byref(m), ctypes.byref(g), ctypes.byref(f), _stream())
+                          ctypes.byref(m), ctypes.byref(g), ctypes.byref(f), ctypes.byref(c),
+                          _stream())
     _check(code, "sad_tune")
-    return g.value, f.value
+    return g.value, f.value, c.value
 
 
 def sad_profile_graphs(reset: bool = False):

@@ -651,7 +651,8 @@ static int32_t* tag_rows(int nwg) {
 }
 
 static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const int8_t* S, int go,
-                              int ge, uint32_t mode, uint8_t* ops_out, DevStatus* st) {
+                              int ge, uint32_t mode, uint8_t* ops_out, DevStatus* st,
+                              bool coop = true) {
   EngineArgs a{};
   a.node_W = e.node_W;
   a.node_n = e.node_n;
@@ -691,7 +692,7 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
   a.coop_words_per_wg = kCoopWordsPerWG;
   a.coop_wgs = 0;
   if (mode == SAD_BATCHED_MFMA) {
-    a.coop_buf = coop_buffer(&a.coop_wgs);
+    a.coop_buf = coop ? coop_buffer(&a.coop_wgs) : nullptr;
     if (!a.coop_buf) a.coop_wgs = 0;
     a.trow = tag_rows(e.nwg);  // null: the launch is refused
     a.trow_words_per_wg = kTagRowWordsPerWG;
@@ -956,7 +957,7 @@ static int32_t plan_priority(const TreeSet& ts, const int32_t* d_merges, const E
 static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
                          const sad_params* prm, int A, Carver& base_cv, EngineBuffers& e,
                          const TreeOutputs& out, hipStream_t stream,
-                         const FusedTrees* fused = nullptr, int grid = 0) {
+                         const FusedTrees* fused = nullptr, int grid = 0, bool coop = true) {
   const int N = ts.nleaves;
   int njobs = 0;
   for (int g = 0; g < ts.ngroups; ++g)
@@ -1039,7 +1040,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     std::vector<unsigned char> gkey;
     if (graphable) {
       EngineArgs ka = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend,
-                                  prm->mode, nullptr, c->st);
+                                  prm->mode, nullptr, c->st, coop);
       const uintptr_t extra[] = {(uintptr_t)ts.d_codes, (uintptr_t)ts.d_offsets,
                                  (uintptr_t)ts.d_ids, (uintptr_t)ts.d_group_off,
                                  (uintptr_t)*fused->F, (uintptr_t)*fused->d_fm_off,
@@ -1083,7 +1084,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                        e.job_b, e.job_out, e.job_next, e.job_pending, e.job_link, e.queue,
                        e.queue_flag, e.qctl + 1, stream);
     EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
-                               nullptr, c->st);
+                               nullptr, c->st, coop);
     if (prm->mode == SAD_BATCHED_MFMA && !a.trow) return SAD_E_DEVICE;
     if (fused) {
       a.up_F = *fused->F;
@@ -1188,6 +1189,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
 struct Schedule {
   int grid = 0;
   int fuse = -1;
+  int coop = 1;  // cooperative merges (batched mode): a merge's strip groups spread over idle workgroups
 };
 
 struct TuneKey {
@@ -1203,15 +1205,17 @@ static std::mutex g_tune_mu;
 static std::map<TuneKey, Schedule> g_tune;
 static thread_local const Schedule* g_forced = nullptr;  // set while sad_tune measures
 
-// SAD_SCHEDULE=grid,fuse (e.g. "192,1") imposes one schedule on every call,
-// for tests that compare each autotuner candidate with the oracle.
+// SAD_SCHEDULE=grid,fuse[,coop] (e.g. "192,1,0") imposes one schedule on every
+// call, for tests that compare each autotuner candidate with the oracle.
 static bool schedule_from_env(Schedule* out) {
   const char* v = getenv("SAD_SCHEDULE");
-  int grid = 0, fuse = -1;
-  if (!v || sscanf(v, "%d,%d", &grid, &fuse) != 2 || grid < 0 || fuse < -1 || fuse > 1)
-    return false;
+  int grid = 0, fuse = -1, coop = 1;
+  if (!v) return false;
+  const int got = sscanf(v, "%d,%d,%d", &grid, &fuse, &coop);
+  if (got < 2 || grid < 0 || fuse < -1 || fuse > 1 || coop < 0 || coop > 1) return false;
   out->grid = grid;
   out->fuse = fuse;
+  out->coop = coop;
   return true;
 }
 
@@ -1528,7 +1532,8 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
     // is carved after them on every attempt
     const FusedTrees fz{&F, &d_fm_off, out->d_merge_list,
                         max_n > engine_fused_lds_group() ? &Sw : nullptr, upload, kernels};
-    return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz, sched.grid);
+    return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz, sched.grid,
+                     sched.coop != 0);
   }
   r = cv.carve(c);
   if (r) return r;
@@ -1544,12 +1549,14 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   // the engine's workspace follows the k-mer/UPGMA buffers (merge lists are
   // in the caller's array, so those buffers are no longer needed)
   Carver base;
-  return run_trees(c, ts, out->d_merge_list, prm, A, base, e, to, stream, nullptr, sched.grid);
+  return run_trees(c, ts, out->d_merge_list, prm, A, base, e, to, stream, nullptr, sched.grid,
+                   sched.coop != 0);
 }
 
 extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
                             const int32_t* d_members, const sad_params* prm, sad_msa* out,
-                            int32_t* grid_out, int32_t* fuse_out, hipStream_t stream) {
+                            int32_t* grid_out, int32_t* fuse_out, int32_t* coop_out,
+                            hipStream_t stream) {
   if (!prm || !out || !seqs) return fail(SAD_E_INVAL, "null argument");
   int32_t r = check_seqs(seqs, prm->kmer_k);
   if (r) return r;
@@ -1572,10 +1579,11 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
   std::vector<Schedule> cand;
   if (prm->mode == SAD_BATCHED_MFMA) {
     // one workgroup per CU fits (LDS); try smaller grids and both tree modes
-    for (int fuse : {1, 0})
-      for (int den : {4, 3, 2}) cand.push_back(Schedule{cus * den / 4, fuse});
+    for (int coop : {1, 0})
+      for (int fuse : {1, 0})
+        for (int den : {4, 3, 2}) cand.push_back(Schedule{cus * den / 4, fuse, coop});
   } else {
-    for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, 0});
+    for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, 0, 0});
   }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1614,6 +1622,7 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
   }
   if (grid_out) *grid_out = best.grid;
   if (fuse_out) *fuse_out = best.fuse;
+  if (coop_out) *coop_out = best.coop;
   return SAD_OK;
 }
 
