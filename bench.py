@@ -250,6 +250,7 @@ def workload_figures(name, args, B, pipeline, torch, threads):
                       "schedule": {"engine_workgroups": tuned[0],
                                    "trees_in_launch": bool(tuned[1]),
                                    "cooperative_merges": bool(tuned[2]),
+                                   "mfma_scores": bool(tuned[3]),
                                    "graph_replays": graphs[1]}}
     out["same_result"] = bool(
         all(np.array_equal(hosts["batched"][st]["colmap"], hosts["plain"][st]["colmap"])
@@ -377,7 +378,7 @@ def main():
     # the process), then time the pipeline with it
     key0, _ = B.sad_kmer_rank(seqs, prm)
     part0 = B.sad_partition(seqs, key0, prm)
-    tuned = (0, -1, 1) if args.no_tune else B.sad_tune(seqs, part0["bucket_off"],
+    tuned = (0, -1, 1, 1) if args.no_tune else B.sad_tune(seqs, part0["bucket_off"],
                                                     part0["members"], prm)
     B.sad_profile_graphs(reset=True)
     res, ms, eng_ms, launches = timed_steps(pipeline.run_device, seqs, prm, args.steps,
@@ -413,7 +414,7 @@ def main():
         "quality": qual,
         "mode": "batched",
         "schedule": {"engine_workgroups": tuned[0], "trees_in_launch": bool(tuned[1]),
-                     "cooperative_merges": bool(tuned[2]),
+                     "cooperative_merges": bool(tuned[2]), "mfma_scores": bool(tuned[3]),
                      "graph_captures": graphs[0], "graph_replays": graphs[1]},
         "engine_kernel": {"ms_total": round(eng_ms, 3), "launches": launches,
                           "avg_launch_ms": round(eng_ms / max(launches, 1), 4),

@@ -292,22 +292,26 @@ int32_t sad_refine_tree(const sad_seqs* seqs, const int32_t* d_bucket_off,
 /* Autotuner for sad_align_buckets (batching of the bucket merges, Section
  * 2.3.3 step 11).  Runs the call on the given buckets under each candidate
  * schedule, once to warm up and three times timed (the fastest counts), with
- * HIP events on `stream`: batched mode: persistent grid of 1, 3/4 or 1/2
- * workgroup per CU; guide trees built inside the engine launch (buckets of up
- * to 600 members) or by a separate kernel; cooperative merges (a merge's
- * 4-strip groups spread over idle workgroups) on or off -- 12 schedules;
- * plain mode: 1, 2 or 3 workgroups per CU for the per-level launches.  The
- * fastest is kept in a process-wide cache keyed by (alphabet, n, p, mode,
- * largest bucket, total length) and used by later sad_align_buckets calls
- * with that key; results never depend on the schedule.  `out` receives the
- * last run's (identical) results.  *grid_out = chosen workgroup count (0 =
- * default), *fuse_out = 1 trees in the launch, 0 separate, *coop_out = 1
- * cooperative merges (any of them may be NULL).  The environment variable
- * SAD_SCHEDULE="grid,fuse[,coop]" imposes one schedule on every call instead
- * (for tests that check each candidate). */
+ * HIP events on `stream`.  Batched mode, one persistent launch over every
+ * bucket's merge DAG: column scores as int8 MFMA tiles with a grid of 1, 3/4
+ * or 1/2 workgroup per CU, guide trees built inside the launch (buckets of up
+ * to 600 members) or by a separate kernel, and cooperative merges (a merge's
+ * 4-strip groups spread over idle workgroups) on or off -- 12 schedules; or
+ * column scores as vector-ALU dot products (the plain kernel, whose registers
+ * and LDS allow several workgroups per CU) with 1, 2 or 3 workgroups per CU
+ * -- 3 schedules.  Plain mode: 1, 2 or 3 workgroups per CU for the per-level
+ * launches.  The fastest is kept in a process-wide cache keyed by (alphabet,
+ * n, p, mode, largest bucket, total length) and used by later
+ * sad_align_buckets calls with that key; results never depend on the
+ * schedule.  `out` receives the last run's (identical) results.  *grid_out =
+ * chosen workgroup count (0 = default), *fuse_out = 1 trees in the launch, 0
+ * separate, *flags_out: bit 0 cooperative merges, bit 1 MFMA column scores
+ * (any of them may be NULL).  The environment variable
+ * SAD_SCHEDULE="grid,fuse[,coop[,mfma]]" imposes one schedule on every call
+ * instead (for tests that check each candidate). */
 int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off, const int32_t* d_members,
                  const sad_params* prm, sad_msa* out, int32_t* grid_out, int32_t* fuse_out,
-                 int32_t* coop_out, hipStream_t stream);
+                 int32_t* flags_out, hipStream_t stream);
 
 /* Kernel timing for measurement tools.  on & 1: every launch of the
  * alignment engine kernel (the DP + traceback + merge kernel that dominates

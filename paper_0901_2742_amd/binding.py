@@ -451,7 +451,9 @@ def sad_profile_phases(reset: bool = False):
 def sad_tune(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, prm: Params,
              out: dict | None = None):
     """Autotunes the schedule of sad_align_buckets for these buckets (cached for
-    later calls with the same workload shape).  Returns (grid, fuse, coop)."""
+    later calls with the same workload shape).  Returns (grid, fuse, coop,
+    mfma): workgroups, trees in the launch, cooperative merges, MFMA column
+    scores."""
     dev = seqs.codes.device
     if out is None:
         out = _msa_tensors(seqs.total_len, prm.p, seqs.n, dev)
@@ -461,7 +463,7 @@ def sad_tune(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, 
                           ctypes.byref(m), ctypes.byref(g), ctypes.byref(f), ctypes.byref(c),
                           _stream())
     _check(code, "sad_tune")
-    return g.value, f.value, c.value
+    return g.value, f.value, c.value & 1, (c.value >> 1) & 1
 
 
 def sad_profile_graphs(reset: bool = False):

@@ -532,15 +532,16 @@ static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, in
   cv.add(e.bnd, (size_t)e.nwg * (size_t)e.link_words);
 }
 
-// Largest persistent grid any schedule launches (plain mode tunes up to 3
-// workgroups per CU; SAD_ENGINE_WGS_PER_CU raises the default).
+// Largest persistent grid any schedule launches (up to 3 workgroups per CU;
+// SAD_ENGINE_WGS_PER_CU raises the default).
 static int max_grid(uint32_t mode) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)
     cus = 256;
-  return std::max(engine_workgroups(), mode == SAD_PLAIN ? 3 * cus : cus);
+  (void)mode;  // plain launches and the batched mode's vector-ALU schedules reach 3 per CU
+  return std::max(engine_workgroups(), 3 * cus);
 }
 
 // Columns the profile pools of a set of trees can take: the leaves' own
@@ -957,7 +958,8 @@ static int32_t plan_priority(const TreeSet& ts, const int32_t* d_merges, const E
 static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
                          const sad_params* prm, int A, Carver& base_cv, EngineBuffers& e,
                          const TreeOutputs& out, hipStream_t stream,
-                         const FusedTrees* fused = nullptr, int grid = 0, bool coop = true) {
+                         const FusedTrees* fused = nullptr, int grid = 0, bool coop = true,
+                         bool valu_scores = false) {
   const int N = ts.nleaves;
   int njobs = 0;
   for (int g = 0; g < ts.ngroups; ++g)
@@ -1083,9 +1085,12 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
       launch_make_jobs(d_merges, ts.d_group_off, ts.ngroups, N, N, e.node_parent, e.job_a,
                        e.job_b, e.job_out, e.job_next, e.job_pending, e.job_link, e.queue,
                        e.queue_flag, e.qctl + 1, stream);
-    EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, prm->mode,
+    // batched mode with vector-ALU scores: the plain kernel as one persistent
+    // launch over the whole merge DAG (no cooperative merges, no in-launch trees)
+    const uint32_t kmode = valu_scores ? SAD_PLAIN : prm->mode;
+    EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, kmode,
                                nullptr, c->st, coop);
-    if (prm->mode == SAD_BATCHED_MFMA && !a.trow) return SAD_E_DEVICE;
+    if (kmode == SAD_BATCHED_MFMA && !a.trow) return SAD_E_DEVICE;
     if (fused) {
       a.up_F = *fused->F;
       a.up_fm_off = *fused->d_fm_off;
@@ -1190,6 +1195,7 @@ struct Schedule {
   int grid = 0;
   int fuse = -1;
   int coop = 1;  // cooperative merges (batched mode): a merge's strip groups spread over idle workgroups
+  int mfma = 1;  // batched mode: column scores as int8 MFMA tiles (1) or vector-ALU dot products (0)
 };
 
 struct TuneKey {
@@ -1205,17 +1211,21 @@ static std::mutex g_tune_mu;
 static std::map<TuneKey, Schedule> g_tune;
 static thread_local const Schedule* g_forced = nullptr;  // set while sad_tune measures
 
-// SAD_SCHEDULE=grid,fuse[,coop] (e.g. "192,1,0") imposes one schedule on every
-// call, for tests that compare each autotuner candidate with the oracle.
+// SAD_SCHEDULE=grid,fuse[,coop[,mfma]] (e.g. "192,1,0") imposes one schedule
+// on every call, for tests that compare each autotuner candidate with the
+// oracle.
 static bool schedule_from_env(Schedule* out) {
   const char* v = getenv("SAD_SCHEDULE");
-  int grid = 0, fuse = -1, coop = 1;
+  int grid = 0, fuse = -1, coop = 1, mfma = 1;
   if (!v) return false;
-  const int got = sscanf(v, "%d,%d,%d", &grid, &fuse, &coop);
-  if (got < 2 || grid < 0 || fuse < -1 || fuse > 1 || coop < 0 || coop > 1) return false;
+  const int got = sscanf(v, "%d,%d,%d,%d", &grid, &fuse, &coop, &mfma);
+  if (got < 2 || grid < 0 || fuse < -1 || fuse > 1 || coop < 0 || coop > 1 || mfma < 0 ||
+      mfma > 1)
+    return false;
   out->grid = grid;
   out->fuse = fuse;
   out->coop = coop;
+  out->mfma = mfma;
   return true;
 }
 
@@ -1492,8 +1502,9 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   // batched mode with small enough buckets: the guide trees are built inside
   // the engine launch, which starts aligning each merge as soon as it is known
   const Schedule sched = schedule_for(TuneKey{A, n, p, (int)prm->mode, max_n, seqs->total_len});
+  const bool valu = prm->mode == SAD_BATCHED_MFMA && sched.mfma == 0;
   const bool fuse = prm->mode == SAD_BATCHED_MFMA && max_n <= engine_fused_max_group() &&
-                    sched.fuse != 0;
+                    sched.fuse != 0 && !valu;
   Carver cv;
   AlignBufs ab{};
   // pair sums in HBM: guide trees by the separate kernel, or built in the
@@ -1533,7 +1544,7 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
     const FusedTrees fz{&F, &d_fm_off, out->d_merge_list,
                         max_n > engine_fused_lds_group() ? &Sw : nullptr, upload, kernels};
     return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz, sched.grid,
-                     sched.coop != 0);
+                     sched.coop != 0, valu);
   }
   r = cv.carve(c);
   if (r) return r;
@@ -1550,12 +1561,12 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   // in the caller's array, so those buffers are no longer needed)
   Carver base;
   return run_trees(c, ts, out->d_merge_list, prm, A, base, e, to, stream, nullptr, sched.grid,
-                   sched.coop != 0);
+                   sched.coop != 0 && !valu, valu);
 }
 
 extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
                             const int32_t* d_members, const sad_params* prm, sad_msa* out,
-                            int32_t* grid_out, int32_t* fuse_out, int32_t* coop_out,
+                            int32_t* grid_out, int32_t* fuse_out, int32_t* flags_out,
                             hipStream_t stream) {
   if (!prm || !out || !seqs) return fail(SAD_E_INVAL, "null argument");
   int32_t r = check_seqs(seqs, prm->kmer_k);
@@ -1581,9 +1592,12 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
     // one workgroup per CU fits (LDS); try smaller grids and both tree modes
     for (int coop : {1, 0})
       for (int fuse : {1, 0})
-        for (int den : {4, 3, 2}) cand.push_back(Schedule{cus * den / 4, fuse, coop});
+        for (int den : {4, 3, 2}) cand.push_back(Schedule{cus * den / 4, fuse, coop, 1});
+    // the same persistent DAG launch with vector-ALU scores (the plain kernel,
+    // whose registers and LDS leave room for several workgroups per CU)
+    for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, 0, 0, 0});
   } else {
-    for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, 0, 0});
+    for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, 0, 0, 0});
   }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1622,7 +1636,7 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
   }
   if (grid_out) *grid_out = best.grid;
   if (fuse_out) *fuse_out = best.fuse;
-  if (coop_out) *coop_out = best.coop;
+  if (flags_out) *flags_out = (best.coop ? 1 : 0) | (best.mfma ? 2 : 0);
   return SAD_OK;
 }
 
