@@ -24,7 +24,7 @@ __global__ void y_pick_kernel(const uint64_t* __restrict__ key, const int32_t* _
   Yi[q] = id;
 }
 
-// number of entries of run [r0, r0 + len) strictly below (k, i) / at most (k, i)
+// number of entries of run [r0, r0 + len) strictly below (k, i)
 __device__ inline int run_lower(const uint64_t* Yk, const int32_t* Yi, int r0, int len, uint64_t k,
                                 int32_t i) {
   int lo = 0, hi = len;
@@ -35,34 +35,28 @@ __device__ inline int run_lower(const uint64_t* Yk, const int32_t* Yi, int r0, i
   }
   return lo;
 }
-__device__ inline int run_upper(const uint64_t* Yk, const int32_t* Yi, int r0, int len, uint64_t k,
-                                int32_t i) {
-  int lo = 0, hi = len;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (!ck_less(k, i, Yk[r0 + mid], Yi[r0 + mid])) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
 
-// Stable rank of each Y entry among all runs (equal entries ordered by run,
-// then position), scattered into sorted order.
-__global__ void y_merge_kernel(const uint64_t* __restrict__ Yk, const int32_t* __restrict__ Yi,
-                               int p, uint64_t* __restrict__ Sk, int32_t* __restrict__ Si) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int len = p - 1;
-  if (q >= p * len) return;
-  const int c = q / len, pos = q % len;
-  const uint64_t k = Yk[q];
-  const int32_t i = Yi[q];
-  int rank = pos;
-  for (int r = 0; r < p; ++r) {
-    if (r == c) continue;
-    rank += (r < c) ? run_upper(Yk, Yi, r * len, len, k, i) : run_lower(Yk, Yi, r * len, len, k, i);
-  }
-  Sk[rank] = k;
-  Si[rank] = i;
+// One round of the pairwise merge of Y's sorted runs of `len` entries (the
+// last may be shorter): runs 2m and 2m + 1 merge into one.  Entry x of run j
+// lands at the start of its pair plus its index in its run plus the number of
+// entries of the partner run below it (an entry without a partner run keeps
+// its place).  The composite keys (K_i, i) are distinct, so after the last
+// round the entries are in (K, i) order, whatever the merge order.
+__global__ void y_merge_round_kernel(const uint64_t* __restrict__ Ik,
+                                     const int32_t* __restrict__ Ii, int ny, int len,
+                                     uint64_t* __restrict__ Ok, int32_t* __restrict__ Oi) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= ny) return;
+  const int j = x / len;
+  const int start = j * len;
+  const int ps = (j ^ 1) * len;  // partner run
+  const uint64_t k = Ik[x];
+  const int32_t i = Ii[x];
+  int below = 0;
+  if (ps < ny) below = run_lower(Ik, Ii, ps, min(len, ny - ps), k, i);
+  const int to = (j & ~1) * len + (x - start) + below;
+  Ok[to] = k;
+  Oi[to] = i;
 }
 
 __global__ void pivot_kernel(const uint64_t* __restrict__ Sk, const int32_t* __restrict__ Si, int p,
@@ -139,9 +133,16 @@ void launch_partition(const uint64_t* key, int n, int p, const int32_t* sorted, 
   const int ny = p * (p - 1);
   if (ny > 0) {
     y_pick_kernel<<<(ny + 255) / 256, 256, 0, stream>>>(key, sorted, n, p, Ykey, Yid);
-    y_merge_kernel<<<(ny + 255) / 256, 256, 0, stream>>>(Ykey, Yid, p, Ysorted_key, Ysorted_id);
-    pivot_kernel<<<(p - 1 + 255) / 256, 256, 0, stream>>>(Ysorted_key, Ysorted_id, p, pivot_key,
-                                                          pivot_id);
+    // the p runs (each chunk's picks, in its order) merged pairwise, ping-pong
+    // between the two buffers
+    uint64_t *ik = Ykey, *ok = Ysorted_key;
+    int32_t *ii = Yid, *oi = Ysorted_id;
+    for (int len = p - 1; len < ny; len *= 2) {
+      y_merge_round_kernel<<<(ny + 255) / 256, 256, 0, stream>>>(ik, ii, ny, len, ok, oi);
+      std::swap(ik, ok);
+      std::swap(ii, oi);
+    }
+    pivot_kernel<<<(p - 1 + 255) / 256, 256, 0, stream>>>(ik, ii, p, pivot_key, pivot_id);
   }
   const int nblk = (n + kScatterBlock - 1) / kScatterBlock;
   // cleared by a kernel (no memset node when a caller captures the launches)
