@@ -80,44 +80,62 @@ __global__ __launch_bounds__(kUpgmaThreads) void upgma_kernel(
   }
 }
 
+// Sw <- F widened to 64 bits, group by group (the two share their layout):
+// blockIdx.y is the group, the blocks along x stride over its n^2 entries.
+__global__ void widen_sums_kernel(const uint32_t* __restrict__ F,
+                                  const int64_t* __restrict__ fm_off,
+                                  const int32_t* __restrict__ group_off, uint64_t* __restrict__ Sw) {
+  const int g = blockIdx.y;
+  const int64_t n = group_off[g + 1] - group_off[g];
+  if (n <= 1) return;
+  const int64_t m = n * n, o = fm_off[g];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += stride)
+    Sw[o + q] = F[o + q];
+}
+
 // Large groups: one workgroup of kUpgmaWideThreads per group, pair sums in
-// the global n x n work array, the steps split over all its waves.
+// the global n x n work array, the steps split over all its waves.  LDS: id,
+// size (0 = inactive), best partner, rescan list (4 n words) and, up to
+// kUpgmaWideLdsN members, the best pair sums (n 64-bit words; larger groups
+// keep them on the array's diagonal).
 __global__ __launch_bounds__(kUpgmaWideThreads) void upgma_wide_kernel(
-    const uint32_t* __restrict__ F, const int64_t* __restrict__ fm_off,
+    const int64_t* __restrict__ fm_off,
     const int32_t* __restrict__ group_off, uint64_t* __restrict__ Sw,
     int32_t* __restrict__ merges_out, const int32_t* __restrict__ merge_base, DevStatus* st) {
-  extern __shared__ int32_t shw[];
+  extern __shared__ uint64_t shw[];
   __shared__ WideScratch ws;
   const int g = blockIdx.x;
   const int n = group_off[g + 1] - group_off[g];
   if (n <= 1) return;
-  int32_t* id = shw;
-  int32_t* sz = shw + n;
-  int32_t* active = shw + 2 * n;
-  int32_t* best = shw + 3 * n;
-  int32_t* rec = shw + 4 * n;
-  const uint32_t* Fg = F + fm_off[g];
+  const bool lds_best = n <= kUpgmaWideLdsN;
+  int32_t* id = reinterpret_cast<int32_t*>(shw + (lds_best ? n : 0));
+  int32_t* sz = id + n;
+  int32_t* best = id + 2 * n;
+  int32_t* rec = id + 3 * n;
   int32_t* mo = merges_out + 2 * (int64_t)merge_base[g];
   const int tid = threadIdx.x;
   for (int a = tid; a < n; a += kUpgmaWideThreads) {
     id[a] = a;
     sz[a] = 1;
-    active[a] = 1;
   }
+  // (the sums were widened from F by widen_sums_kernel)
   const FullS S{Sw + fm_off[g], n};
-  for (int64_t q = tid; q < (int64_t)n * n; q += kUpgmaWideThreads) S.t[q] = Fg[q];
   __syncthreads();
   auto rec_merge = [&](int step, int ia, int ib) {
     mo[2 * step] = ia;
     mo[2 * step + 1] = ib;
   };
-  if (n <= kUpgmaW64MaxN) {
-    wide_init_best<true>(S, n, id, sz, active, best, &ws);
-    upgma_steps_wide<true>(S, n, id, sz, active, best, rec, &ws, g, st, rec_merge);
-  } else {
-    wide_init_best<false>(S, n, id, sz, active, best, &ws);
-    upgma_steps_wide<false>(S, n, id, sz, active, best, rec, &ws, g, st, rec_merge);
-  }
+  if (n <= kUpgmaW64MaxN)
+    upgma_steps_wide<true, true>(S, n, id, sz, best, LdsBest{shw}, rec, &ws, g, st, rec_merge);
+  else if (lds_best)
+    upgma_steps_wide<false, true>(S, n, id, sz, best, LdsBest{shw}, rec, &ws, g, st, rec_merge);
+  else if (n <= kUpgmaRow64MaxN)
+    upgma_steps_wide<false, true>(S, n, id, sz, best, DiagBest{S.t, n}, rec, &ws, g, st,
+                                  rec_merge);
+  else
+    upgma_steps_wide<false, false>(S, n, id, sz, best, DiagBest{S.t, n}, rec, &ws, g, st,
+                                   rec_merge);
 }
 
 void launch_upgma(const uint32_t* F, const int64_t* fm_off, const int32_t* group_off,
@@ -126,11 +144,14 @@ void launch_upgma(const uint32_t* F, const int64_t* fm_off, const int32_t* group
   if (ngroups <= 0 || max_n <= 1) return;
   if (max_n >= kUpgmaWideMinN) {
     // a large group: its O(n) step phases on a workgroup of 16 waves
-    const size_t lds = (size_t)5 * max_n * sizeof(int32_t);
+    const size_t lds = (size_t)max_n * (4 * sizeof(int32_t) +
+                                        (max_n <= kUpgmaWideLdsN ? sizeof(uint64_t) : 0));
     if (lds > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)upgma_wide_kernel,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    upgma_wide_kernel<<<ngroups, kUpgmaWideThreads, lds, stream>>>(F, fm_off, group_off, Swork,
+    const int bx = (int)std::min<int64_t>(64, ((int64_t)max_n * max_n + 255) / 256);
+    widen_sums_kernel<<<dim3(bx, ngroups), 256, 0, stream>>>(F, fm_off, group_off, Swork);
+    upgma_wide_kernel<<<ngroups, kUpgmaWideThreads, lds, stream>>>(fm_off, group_off, Swork,
                                                                    merges_out, merge_base, st);
     return;
   }

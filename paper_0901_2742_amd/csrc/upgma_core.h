@@ -408,33 +408,60 @@ __device__ bool upgma_steps(const St& S, int n, int32_t* id, int32_t* sz, int32_
 namespace sad {
 
 // ---------------------------------------------------------------- wide steps
-// The same steps for large groups, run by every wave of a workgroup of
-// kUpgmaWideThreads threads: each phase of a step (the first of the best
-// pairs, the union's sums, the comparisons with the union, the rescans) is
-// split over all threads, with workgroup barriers between the phases; rescans
-// take 4 rows at a time, each row scanned by the whole workgroup.  A wave's
-// winner is reduced across the waves through LDS with the same order, so the
-// merges are those of upgma_steps.
-constexpr int kUpgmaWideThreads = 1024;
+// The same steps for large groups, run by a workgroup of kUpgmaWideThreads
+// threads (one wave per SIMD), with each cluster's best pair sum cached
+// (bs[r] = S(r, best[r]); in LDS up to kUpgmaWideLdsN members).  A step: the
+// first of the best pairs (a reduction over the workgroup: a thread's own
+// candidates in registers, then DPP across the wave, then across the waves
+// through LDS); one pass over the clusters that forms the union's sums and
+// compares each cluster's best with the union; the union's size and id; the
+// rescans of the clusters that pointed at a merged one, spread over the
+// waves, each row scanned by one wave.  Every reduction keeps the order of
+// upgma_steps, so the merges are the same.
+constexpr int kUpgmaWideThreads = 256;
 constexpr int kUpgmaWideWaves = kUpgmaWideThreads / 64;
-constexpr int kUpgmaWideMinN = 257;   // smaller groups keep the one-wave steps
+constexpr int kUpgmaWideMinN = 257;    // smaller groups keep the one-wave steps
+constexpr int kUpgmaWideLdsN = 4096;   // larger groups keep the best sums in HBM
+constexpr int kWideRB = 2;             // rows per wave and rescan batch
+// Comparisons within one row r (its rescans, its best against the union)
+// share the factor |r| in both cross products, so they compare s |b'| with
+// s' |b|: s <= 2^31 |r| |b| and |r| + |b| + |b'| <= n give products of at most
+// 2^31 (n / 3)^3, below 2^64 while n < 6144.
+constexpr int kUpgmaRow64MaxN = 6143;
 
-// Per-wave winners of up to 4 reductions, in LDS.
+// Where the best pair sums live: LDS, or the unused diagonal of the n x n
+// pair-sum array.
+struct LdsBest {
+  uint64_t* b;
+  __device__ uint64_t get(int r) const { return b[r]; }
+  __device__ void set(int r, uint64_t v) const { b[r] = v; }
+};
+struct DiagBest {
+  uint64_t* t;
+  int n;
+  __device__ uint64_t get(int r) const { return t[(int64_t)r * (n + 1)]; }
+  __device__ void set(int r, uint64_t v) const { t[(int64_t)r * (n + 1)] = v; }
+};
+
+// Per-wave winners of the workgroup reductions (one at a time), in LDS.
 struct WideScratch {
-  uint64_t s[4][kUpgmaWideWaves];
-  uint32_t p[4][kUpgmaWideWaves];
-  uint32_t key[4][kUpgmaWideWaves];
-  int32_t arg[4][kUpgmaWideWaves];
+  uint64_t s[1][kUpgmaWideWaves];
+  uint32_t p[1][kUpgmaWideWaves];
+  uint32_t key[1][kUpgmaWideWaves];
+  int32_t arg[1][kUpgmaWideWaves];
   int32_t nrec;
 };
 
 // The workgroup's first candidate of RB reductions: every wave reduces its
 // lanes' candidates c[j] (argument a[j]), lane 0 of each wave publishes, and
-// after a barrier every wave reduces the published ones; out[j] is the
-// winner's argument (-1 if no candidate).  Ends with a barrier.
+// after a barrier every thread compares the published ones in turn; out[j] is the
+// winner's argument (-1 if no candidate) and outs[j] its sum.  The caller
+// places a barrier before the next call (the published winners are read until
+// then).
 template <bool W64, int RB>
 __device__ inline void wg_first(WCand (&c)[RB], const int (&a)[RB], WideScratch* ws,
-                                int (&out)[RB]) {
+                                int (&out)[RB], uint64_t (&outs)[RB]) {
+  static_assert(RB == 1, "one workgroup reduction at a time");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t mine[RB], wk[RB];
 #pragma unroll
@@ -443,8 +470,7 @@ __device__ inline void wg_first(WCand (&c)[RB], const int (&a)[RB], WideScratch*
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
     const int src = winner_lane(mine[j], wk[j]);
-    // the winner's fields are read from the lane that holds it (after the
-    // reduction every lane of row 3 holds the first's fields; lane 63 does)
+    // after the reduction lane 63 holds the wave's first candidate
     const uint64_t s = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c[j].s, 63) |
                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(c[j].s >> 32), 63)
                         << 32);
@@ -458,98 +484,141 @@ __device__ inline void wg_first(WCand (&c)[RB], const int (&a)[RB], WideScratch*
     }
   }
   __syncthreads();
-  WCand d[RB];
-  int da[RB];
+  // the waves' winners in wave order (a pair published twice carries the
+  // same argument either time)
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
-    const bool on = lane < kUpgmaWideWaves;
-    d[j].s = on ? ws->s[j][lane] : 0;
-    d[j].p = on ? ws->p[j][lane] : 1u;
-    d[j].key = on ? ws->key[j][lane] : ~0u;
-    da[j] = on ? ws->arg[j][lane] : -1;
-    mine[j] = d[j].key;
-  }
-  wave_first_keys<W64, RB>(d, wk);
+    WCand d;
+    d.s = ws->s[j][0];
+    d.p = ws->p[j][0];
+    d.key = ws->key[j][0];
+    int da = ws->arg[j][0];
 #pragma unroll
-  for (int j = 0; j < RB; ++j) {
-    const int src = winner_lane(mine[j], wk[j]);
-    out[j] = src < 0 ? -1 : __builtin_amdgcn_readlane(da[j], src);
+    for (int w = 1; w < kUpgmaWideWaves; ++w) {
+      WCand x;
+      x.s = ws->s[j][w];
+      x.p = ws->p[j][w];
+      x.key = ws->key[j][w];
+      if (wc_better<W64>(x, d)) {
+        d = x;
+        da = ws->arg[j][w];
+      }
+    }
+    out[j] = d.key == ~0u ? -1 : da;
+    outs[j] = d.s;
   }
-  __syncthreads();
 }
 
-// Best partners of the rows r[0..RB) among the active slots, the whole
-// workgroup scanning each row (-1 where none).
-template <bool W64, int RB, typename St>
-__device__ inline void wg_best_partners(const St& S, int n, const int (&r)[RB], const int32_t* id,
-                                        const int32_t* sz, const int32_t* active,
-                                        WideScratch* ws, int (&out)[RB]) {
+// Best partners of the rows r[0..RB) among the active slots (sz > 0), one
+// wave scanning them all (kWideU slots per lane at a time, their sums loaded
+// before any is compared; a candidate's p is the partner's size alone, R64
+// when 64-bit products are exact); out[j] is the partner (-1 if none),
+// outs[j] its pair sum, both wave-uniform.
+constexpr int kWideU = 16;
+template <bool R64, int RB, typename St>
+__device__ inline void wave_rescan(const St& S, int n, const int (&r)[RB], const int32_t* id,
+                                   const int32_t* sz, int (&out)[RB], uint64_t (&outs)[RB]) {
+  const int lane = threadIdx.x & 63;
   WCand c[RB];
   int cb[RB], ir[RB];
-  uint32_t sr[RB];
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
     c[j] = wc_none();
     cb[j] = -1;
-    sr[j] = (uint32_t)sz[r[j]];
     ir[j] = id[r[j]];
   }
-  for (int b = threadIdx.x; b < n; b += kUpgmaWideThreads) {
-    uint64_t sv[RB];
+  for (int b0 = lane; b0 < n; b0 += 64 * kWideU) {
+    uint64_t sv[kWideU][RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) sv[j] = S.get(r[j], b != r[j] ? b : other_slot(r[j]));
-    const bool on = active[b] != 0;
-    const uint32_t zb = (uint32_t)sz[b];
-    const int ib = id[b];
+    for (int u = 0; u < kWideU; ++u) {
+      const int b = min(b0 + 64 * u, n - 1);
 #pragma unroll
-    for (int j = 0; j < RB; ++j) {
-      if (!on || b == r[j]) continue;
-      WCand x;
-      x.s = sv[j];
-      x.p = sr[j] * zb;
-      x.key = pair_key16(ir[j], ib);
-      if (wc_better<W64>(x, c[j])) {
-        c[j] = x;
-        cb[j] = b;
+      for (int j = 0; j < RB; ++j) sv[u][j] = S.get(r[j], b != r[j] ? b : other_slot(r[j]));
+    }
+#pragma unroll
+    for (int u = 0; u < kWideU; ++u) {
+      const int b = b0 + 64 * u;
+      const uint32_t zb = b < n ? (uint32_t)sz[b] : 0u;
+      const int ib = b < n ? id[b] : 0;
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        if (zb == 0 || b == r[j]) continue;
+        WCand x;
+        x.s = sv[u][j];
+        x.p = zb;
+        x.key = pair_key16(ir[j], ib);
+        if (wc_better<R64>(x, c[j])) {
+          c[j] = x;
+          cb[j] = b;
+        }
       }
     }
   }
-  wg_first<W64, RB>(c, cb, ws, out);
+  uint32_t mine[RB], wk[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) mine[j] = c[j].key;
+  wave_first_keys<R64, RB>(c, wk);
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const int src = winner_lane(mine[j], wk[j]);
+    out[j] = src < 0 ? -1 : __builtin_amdgcn_readlane(cb[j], src);
+    // after the reduction lane 63 holds the first candidate
+    outs[j] = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c[j].s, 63) |
+              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(c[j].s >> 32), 63) << 32);
+  }
 }
 
-// Best partners of every slot (the whole workgroup, 4 rows at a time).
-template <bool W64, typename St>
-__device__ inline void wide_init_best(const St& S, int n, const int32_t* id, const int32_t* sz,
-                                      const int32_t* active, int32_t* best, WideScratch* ws) {
-  for (int t = 0; t < n; t += 4) {
-    const int k = min(4, n - t);
-    int rr[4], bb[4];
+// Rescans of the rows rows[0..m) (m the same in every thread): wave w takes
+// the rows w, w + kUpgmaWideWaves, ..., kWideRB at a time, and its lane 0
+// stores their best[] and bs[].  Ends with a barrier.
+template <bool R64, typename St, typename BS>
+__device__ inline void wide_rescan_rows(const St& S, int n, const int32_t* rows, int m,
+                                        const int32_t* id, const int32_t* sz, int32_t* best,
+                                        const BS& bs) {
+  constexpr int RB = kWideRB;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mine = m > wave ? (m - wave + kUpgmaWideWaves - 1) / kUpgmaWideWaves : 0;
+  for (int t = 0; t < mine; t += RB) {
+    const int k = min(RB, mine - t);
+    int rr[RB], out[RB];
+    uint64_t outs[RB];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) rr[j] = t + min(j, k - 1);
-    wg_best_partners<W64, 4>(S, n, rr, id, sz, active, ws, bb);
-    if (threadIdx.x == 0)
-      for (int j = 0; j < k; ++j) best[rr[j]] = bb[j];
+    for (int j = 0; j < RB; ++j) rr[j] = rows[wave + kUpgmaWideWaves * (t + min(j, k - 1))];
+    wave_rescan<R64, RB>(S, n, rr, id, sz, out, outs);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+        if (j < k) {
+          best[rr[j]] = out[j];
+          bs.set(rr[j], outs[j]);
+        }
+    }
   }
   __syncthreads();
 }
 
-// The n - 1 merge steps on the whole workgroup (after wide_init_best).
-// on_merge(step, min id, max id) runs on thread 0.  Returns false (after
-// raising an error) if a step finds no pair; every thread returns the same.
-template <bool W64, typename St, typename OnMerge>
-__device__ bool upgma_steps_wide(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
-                                 int32_t* best, int32_t* rec, WideScratch* ws, int g,
+// The n - 1 merge steps on the whole workgroup.  sz[r] == 0 marks an
+// inactive slot.  on_merge(step, min id, max id) runs on thread 0.  Returns
+// false (after raising an error) if a step finds no pair; every thread
+// returns the same.  rec: scratch of n slots.
+template <bool W64, bool R64, typename St, typename BS, typename OnMerge>
+__device__ bool upgma_steps_wide(const St& S, int n, int32_t* id, int32_t* sz, int32_t* best,
+                                 const BS& bs, int32_t* rec, WideScratch* ws, int g,
                                  DevStatus* st, OnMerge&& on_merge) {
   const int tid = threadIdx.x;
+  // every cluster's best partner and pair sum
+  for (int r = tid; r < n; r += kUpgmaWideThreads) rec[r] = r;
+  __syncthreads();
+  wide_rescan_rows<R64>(S, n, rec, n, id, sz, best, bs);
   for (int step = 0; step < n - 1; ++step) {
-    // the first of the clusters' best pairs
+    // the first of the clusters' best pairs (cached sums)
     WCand c[1] = {wc_none()};
     int cab[1] = {0};
     for (int r = tid; r < n; r += kUpgmaWideThreads) {
-      const int b = active[r] ? best[r] : -1;
+      const int b = sz[r] ? best[r] : -1;
       if (b < 0) continue;
       WCand x;
-      x.s = S.get(r, b);
+      x.s = bs.get(r);
       x.p = (uint32_t)sz[r] * (uint32_t)sz[b];
       x.key = pair_key16(id[r], id[b]);
       if (wc_better<W64>(x, c[0])) {
@@ -558,55 +627,54 @@ __device__ bool upgma_steps_wide(const St& S, int n, int32_t* id, int32_t* sz, i
       }
     }
     int win[1];
-    wg_first<W64, 1>(c, cab, ws, win);
+    uint64_t wins[1];
+    wg_first<W64, 1>(c, cab, ws, win, wins);
     if (win[0] < 0) {
       if (tid == 0) raise_error(st, SAD_E_INVAL, g, W_UPGMA);
       return false;
     }
     const int ba = win[0] & 0xffff, bb = win[0] >> 16;
-    if (tid == 0) on_merge(step, min(id[ba], id[bb]), max(id[ba], id[bb]));
-    // S(new, c) = S(a, c) + S(b, c) for the remaining active clusters
-    for (int q = tid; q < n; q += kUpgmaWideThreads)
-      if (active[q] && q != ba && q != bb) S.set(ba, q, S.get(ba, q) + S.get(bb, q));
-    __syncthreads();
+    const uint32_t szu = (uint32_t)(sz[ba] + sz[bb]);
+    const int idu = n + step;
     if (tid == 0) {
-      sz[ba] += sz[bb];
-      id[ba] = n + step;
-      active[bb] = 0;
-      ws->nrec = 0;
+      on_merge(step, min(id[ba], id[bb]), max(id[ba], id[bb]));
+      rec[0] = ba;  // the union's own row is rescanned
+      ws->nrec = 1;
     }
     __syncthreads();
-    if (step == n - 2) break;
-    // clusters that pointed at a merged cluster are listed for a rescan, the
-    // others compare their best with the union
+    // the union's sums S(new, q) = S(a, q) + S(b, q); each other cluster
+    // compares its best pair with the union, or is listed for a rescan if its
+    // best partner was a merged cluster
     for (int q = tid; q < n; q += kUpgmaWideThreads) {
-      if (!active[q]) continue;
+      if (!sz[q] || q == ba || q == bb) continue;
+      const uint64_t v = S.get(ba, q) + S.get(bb, q);
+      S.set(ba, q, v);
       const int b = best[q];
-      if (q == ba || b == ba || b == bb) {
+      if (b == ba || b == bb) {
         rec[atomicAdd(&ws->nrec, 1)] = q;
         continue;
       }
       WCand cur, uni;
-      cur.s = S.get(q, b);
-      cur.p = (uint32_t)sz[q] * (uint32_t)sz[b];
+      cur.s = bs.get(q);
+      cur.p = (uint32_t)sz[b];  // (the common factor |q| dropped)
       cur.key = pair_key16(id[q], id[b]);
-      uni.s = S.get(q, ba);
-      uni.p = (uint32_t)sz[q] * (uint32_t)sz[ba];
-      uni.key = pair_key16(id[q], id[ba]);
-      if (wc_better<W64>(uni, cur)) best[q] = ba;
+      uni.s = v;
+      uni.p = szu;
+      uni.key = pair_key16(id[q], idu);
+      if (wc_better<R64>(uni, cur)) {
+        best[q] = ba;
+        bs.set(q, v);
+      }
     }
     __syncthreads();
-    const int m = ws->nrec;
-    for (int t = 0; t < m; t += 4) {
-      const int k = min(4, m - t);
-      int rr[4], bb4[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) rr[j] = rec[t + min(j, k - 1)];
-      wg_best_partners<W64, 4>(S, n, rr, id, sz, active, ws, bb4);
-      if (tid == 0)
-        for (int j = 0; j < k; ++j) best[rr[j]] = bb4[j];
+    if (tid == 0) {
+      sz[ba] = (int32_t)szu;
+      id[ba] = idu;
+      sz[bb] = 0;
     }
     __syncthreads();
+    if (step == n - 2) break;
+    wide_rescan_rows<R64>(S, n, rec, ws->nrec, id, sz, best, bs);
   }
   return true;
 }
