@@ -34,8 +34,12 @@ typedef struct {
   int64_t next; /* next unclaimed item, taken with an atomic add */
 } item_loop_t;
 
+/* set while a thread runs items: loops nested in an item run on its thread */
+static __thread int t_in_items = 0;
+
 static void* item_worker(void* arg) {
   item_loop_t* L = (item_loop_t*)arg;
+  t_in_items = 1;
   for (;;) {
     int64_t i = __atomic_fetch_add(&L->next, 1, __ATOMIC_RELAXED);
     if (i >= L->n) break;
@@ -48,7 +52,7 @@ static void* item_worker(void* arg) {
  * included); items must not write to shared state. */
 static void for_items(int64_t n, item_fn fn, void* ctx) {
   int64_t t = g_threads < n ? g_threads : n;
-  if (t <= 1) {
+  if (t <= 1 || t_in_items) {
     for (int64_t i = 0; i < n; ++i) fn(ctx, i);
     return;
   }
@@ -59,6 +63,7 @@ static void for_items(int64_t n, item_fn fn, void* ctx) {
     if (pthread_create(&th[k], NULL, item_worker, &L) == 0) started = k + 1;
     else break;
   item_worker(&L);
+  t_in_items = 0;
   for (int64_t k = 0; k < started; ++k) pthread_join(th[k], NULL);
   free(th);
 }
@@ -429,6 +434,51 @@ int sadref_partition(int32_t n, const uint64_t* key, int32_t p,
 /* Pick the active pair with the largest average similarity
  * S_AB / (|A| |B|); compared exactly by cross-multiplication in 128 bits;
  * ties go to the lexicographically smallest (min id, max id). */
+typedef struct {
+  const uint64_t* S;
+  const int32_t* id;
+  const int64_t* sz;
+  const char* active;
+  int32_t n, parts;
+  int32_t* part_a;
+  int32_t* part_b;
+} upgma_scan_t;
+
+/* pair (a, b) comes before pair (c, d) in the merge order */
+static int pair_before(const upgma_scan_t* U, int32_t a, int32_t b, int32_t c, int32_t d) {
+  const int32_t n = U->n;
+  unsigned __int128 lhs = (unsigned __int128)U->S[(size_t)a * n + b] *
+                          (unsigned __int128)(U->sz[c] * U->sz[d]);
+  unsigned __int128 rhs = (unsigned __int128)U->S[(size_t)c * n + d] *
+                          (unsigned __int128)(U->sz[a] * U->sz[b]);
+  if (lhs != rhs) return lhs > rhs;
+  int32_t lo1 = U->id[a] < U->id[b] ? U->id[a] : U->id[b];
+  int32_t hi1 = U->id[a] < U->id[b] ? U->id[b] : U->id[a];
+  int32_t lo2 = U->id[c] < U->id[d] ? U->id[c] : U->id[d];
+  int32_t hi2 = U->id[c] < U->id[d] ? U->id[d] : U->id[c];
+  return lo1 < lo2 || (lo1 == lo2 && hi1 < hi2);
+}
+
+/* the first active pair (a, b), a < b, among the rows a = part, part +
+ * parts, ... (the order is strict, so splitting the rows cannot change the
+ * overall first) */
+static void upgma_scan_part(void* ctx, int64_t part) {
+  upgma_scan_t* U = (upgma_scan_t*)ctx;
+  int32_t ba = -1, bb = -1;
+  for (int32_t a = (int32_t)part; a < U->n; a += U->parts) {
+    if (!U->active[a]) continue;
+    for (int32_t b = a + 1; b < U->n; ++b) {
+      if (!U->active[b]) continue;
+      if (ba < 0 || pair_before(U, a, b, ba, bb)) {
+        ba = a;
+        bb = b;
+      }
+    }
+  }
+  U->part_a[part] = ba;
+  U->part_b[part] = bb;
+}
+
 int sadref_upgma(int32_t n, const uint32_t* F, int32_t* merges) {
   if (n <= 1) return SADREF_OK;
   uint64_t* S = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n * (size_t)n);
@@ -441,31 +491,20 @@ int sadref_upgma(int32_t n, const uint32_t* F, int32_t* merges) {
     sz[a] = 1;
     active[a] = 1;
   }
+  const int32_t max_parts = g_threads > 1 ? 4 * g_threads : 1;
+  int32_t* part_a = (int32_t*)malloc(sizeof(int32_t) * (size_t)max_parts);
+  int32_t* part_b = (int32_t*)malloc(sizeof(int32_t) * (size_t)max_parts);
+  upgma_scan_t U = {S, id, sz, active, n, 1, part_a, part_b};
   for (int32_t step = 0; step < n - 1; ++step) {
+    /* rows split over threads while enough clusters remain */
+    U.parts = n - step >= 256 ? max_parts : 1;
+    for_items(U.parts, upgma_scan_part, &U);
     int32_t ba = -1, bb = -1;
-    for (int32_t a = 0; a < n; ++a) {
-      if (!active[a]) continue;
-      for (int32_t b = a + 1; b < n; ++b) {
-        if (!active[b]) continue;
-        if (ba < 0) {
-          ba = a;
-          bb = b;
-          continue;
-        }
-        unsigned __int128 lhs = (unsigned __int128)S[(size_t)a * n + b] *
-                                (unsigned __int128)(sz[ba] * sz[bb]);
-        unsigned __int128 rhs = (unsigned __int128)S[(size_t)ba * n + bb] *
-                                (unsigned __int128)(sz[a] * sz[b]);
-        int better = lhs > rhs;
-        if (lhs == rhs) {
-          int32_t lo1 = id[a] < id[b] ? id[a] : id[b], hi1 = id[a] < id[b] ? id[b] : id[a];
-          int32_t lo2 = id[ba] < id[bb] ? id[ba] : id[bb], hi2 = id[ba] < id[bb] ? id[bb] : id[ba];
-          better = lo1 < lo2 || (lo1 == lo2 && hi1 < hi2);
-        }
-        if (better) {
-          ba = a;
-          bb = b;
-        }
+    for (int32_t t = 0; t < U.parts; ++t) {
+      if (part_a[t] < 0) continue;
+      if (ba < 0 || pair_before(&U, part_a[t], part_b[t], ba, bb)) {
+        ba = part_a[t];
+        bb = part_b[t];
       }
     }
     int32_t ia = id[ba], ib = id[bb];
@@ -486,6 +525,8 @@ int sadref_upgma(int32_t n, const uint32_t* F, int32_t* merges) {
   free(id);
   free(sz);
   free(active);
+  free(part_a);
+  free(part_b);
   return SADREF_OK;
 }
 
