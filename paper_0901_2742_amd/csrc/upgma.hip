@@ -144,8 +144,11 @@ void launch_upgma(const uint32_t* F, const int64_t* fm_off, const int32_t* group
   if (ngroups <= 0 || max_n <= 1) return;
   if (max_n >= kUpgmaWideMinN) {
     // a large group: its O(n) step phases on a workgroup of 16 waves
-    const size_t lds = (size_t)max_n * (4 * sizeof(int32_t) +
-                                        (max_n <= kUpgmaWideLdsN ? sizeof(uint64_t) : 0));
+    // (a group of up to kUpgmaWideLdsN members also keeps its best sums in
+    // LDS, whatever the largest group's size)
+    const size_t lds = std::max((size_t)max_n * 4 * sizeof(int32_t),
+                                (size_t)std::min(max_n, kUpgmaWideLdsN) *
+                                    (4 * sizeof(int32_t) + sizeof(uint64_t)));
     if (lds > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)upgma_wide_kernel,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -5,6 +5,7 @@ buckets, per-merge scores/cells/merge lists, column maps, widths, the global
 ancestor and the glued column map.  Inputs are the seeded workloads (full size
 for the two smaller ones) plus small edge cases (p = 1, empty buckets,
 DNA with k = 8, tiny buckets)."""
+import os
 import sys
 
 import numpy as np
@@ -141,6 +142,22 @@ def test_large_bucket(hip, mode):
     s = generate(6007, 700, 20, 2, {"kind": "uniform_int", "lo": 24, "hi": 40}, 0.1, 0.02, 3)
     got, ref = run_both(B, pipeline, s, 3, 1, protein_matrix(), 40, 2, mode)
     compare(got, ref, f"large bucket mode {mode}")
+
+
+def test_bucket_of_4200(hip):
+    """One bucket of 4200 short DNA sequences (p = 1): a guide tree above 4096
+    members, whose clusters keep their best pair sums in HBM rather than LDS,
+    and 4199 progressive merges, all bit-exact.  The oracle's pair scans run
+    on up to 16 host threads (about 20-40 s)."""
+    B, pipeline = hip
+    _say("case bucket of 4200")
+    s = generate(7331, 4200, 4, 6, {"kind": "uniform_int", "lo": 20, "hi": 32}, 0.1, 0.02, 4)
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    try:
+        got, ref = run_both(B, pipeline, s, 4, 1, dna_matrix(), 6, 1, 1)
+    finally:
+        oracle.set_threads(1)
+    compare(got, ref, "bucket of 4200")
 
 
 @pytest.mark.parametrize("mode", [1, 0])
