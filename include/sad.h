@@ -299,7 +299,8 @@ int32_t sad_refine_tree(const sad_seqs* seqs, const int32_t* d_bucket_off,
  * 4-strip groups spread over idle workgroups) on or off -- 12 schedules; or
  * column scores as vector-ALU dot products (the plain kernel, whose registers
  * and LDS allow several workgroups per CU) with 1, 2 or 3 workgroups per CU
- * -- 3 schedules.  Plain mode: 1, 2 or 3 workgroups per CU for the per-level
+ * and the guide trees inside the launch or separate -- 6 schedules.  Plain
+ * mode: 1, 2 or 3 workgroups per CU for the per-level
  * launches.  The fastest is kept in a process-wide cache keyed by (alphabet,
  * n, p, mode, largest bucket, total length) and used by later
  * sad_align_buckets calls with that key; results never depend on the

@@ -1039,10 +1039,13 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     // replayed while its arguments (all baked into the graph) are unchanged
     const bool graphable =
         fused && fused->graph && !g_phase_on && !g_tuning && njobs > 0 && graphs_enabled();
+    // batched mode with vector-ALU scores: the plain kernel as one persistent
+    // launch over the whole merge DAG (no cooperative merges)
+    const uint32_t kmode = valu_scores ? SAD_PLAIN : prm->mode;
     std::vector<unsigned char> gkey;
     if (graphable) {
       EngineArgs ka = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend,
-                                  prm->mode, nullptr, c->st, coop);
+                                  kmode, nullptr, c->st, coop);
       const uintptr_t extra[] = {(uintptr_t)ts.d_codes, (uintptr_t)ts.d_offsets,
                                  (uintptr_t)ts.d_ids, (uintptr_t)ts.d_group_off,
                                  (uintptr_t)*fused->F, (uintptr_t)*fused->d_fm_off,
@@ -1085,9 +1088,6 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
       launch_make_jobs(d_merges, ts.d_group_off, ts.ngroups, N, N, e.node_parent, e.job_a,
                        e.job_b, e.job_out, e.job_next, e.job_pending, e.job_link, e.queue,
                        e.queue_flag, e.qctl + 1, stream);
-    // batched mode with vector-ALU scores: the plain kernel as one persistent
-    // launch over the whole merge DAG (no cooperative merges, no in-launch trees)
-    const uint32_t kmode = valu_scores ? SAD_PLAIN : prm->mode;
     EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, kmode,
                                nullptr, c->st, coop);
     if (kmode == SAD_BATCHED_MFMA && !a.trow) return SAD_E_DEVICE;
@@ -1504,12 +1504,14 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   const Schedule sched = schedule_for(TuneKey{A, n, p, (int)prm->mode, max_n, seqs->total_len});
   const bool valu = prm->mode == SAD_BATCHED_MFMA && sched.mfma == 0;
   const bool fuse = prm->mode == SAD_BATCHED_MFMA && max_n <= engine_fused_max_group() &&
-                    sched.fuse != 0 && !valu;
+                    sched.fuse != 0;
+  // pair sums in HBM: guide trees by the separate kernel, or built in the
+  // launch for groups too large for the MFMA kernel's LDS (every group of the
+  // vector-ALU kernel)
+  const bool sums_in_hbm = !fuse || valu || max_n > engine_fused_lds_group();
   Carver cv;
   AlignBufs ab{};
-  // pair sums in HBM: guide trees by the separate kernel, or built in the
-  // launch for groups too large for LDS
-  plan_align(cv, ab, n, p, seqs->total_len, fm_total, !fuse || max_n > engine_fused_lds_group());
+  plan_align(cv, ab, n, p, seqs->total_len, fm_total, sums_in_hbm);
   uint32_t *&entries = ab.entries, *&F = ab.F;
   int32_t*& nu = ab.nu;
   int64_t*& d_fm_off = ab.d_fm_off;
@@ -1541,10 +1543,10 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   if (fuse) {
     // the similarity matrices stay alive under the engine's workspace, which
     // is carved after them on every attempt
-    const FusedTrees fz{&F, &d_fm_off, out->d_merge_list,
-                        max_n > engine_fused_lds_group() ? &Sw : nullptr, upload, kernels};
+    const FusedTrees fz{&F, &d_fm_off, out->d_merge_list, sums_in_hbm ? &Sw : nullptr, upload,
+                        kernels};
     return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz, sched.grid,
-                     sched.coop != 0, valu);
+                     sched.coop != 0 && !valu, valu);
   }
   r = cv.carve(c);
   if (r) return r;
@@ -1595,7 +1597,8 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
         for (int den : {4, 3, 2}) cand.push_back(Schedule{cus * den / 4, fuse, coop, 1});
     // the same persistent DAG launch with vector-ALU scores (the plain kernel,
     // whose registers and LDS leave room for several workgroups per CU)
-    for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, 0, 0, 0});
+    for (int fuse : {1, 0})
+      for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, fuse, 0, 0});
   } else {
     for (int per_cu : {1, 2, 3}) cand.push_back(Schedule{cus * per_cu, 0, 0, 0});
   }
@@ -1621,6 +1624,9 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
     }
     g_forced = nullptr;
     if (r) break;
+    if (log_enabled())
+      fprintf(stderr, "[sad] tune: grid %d fuse %d coop %d mfma %d: %.3f ms\n", sc.grid, sc.fuse,
+              sc.coop, sc.mfma, ms);
     if (best_ms == 0.0f || ms < best_ms) {
       best_ms = ms;
       best = sc;

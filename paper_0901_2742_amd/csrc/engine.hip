@@ -27,6 +27,7 @@
 // maps (node column -> parent column) are W int32 in another.  Internal nodes
 // are bump-allocated with W1 + W2 columns.
 #include <cstdlib>
+#include <type_traits>
 
 #include "sad_internal.h"
 #include "upgma_core.h"
@@ -1329,33 +1330,42 @@ __device__ inline void create_job(const EngineArgs& a, int g0, int n, int step, 
   if (atomicSub(&a.job_pending[s], 1) == 1) push_job(a, s);
 }
 
-// Groups up to kFusedLdsN keep the triangle of 64-bit pair sums in the score
-// ring's LDS and the five cluster arrays in the traceback staging block;
-// larger ones, up to kFusedMaxN, keep the sums in their n x n area of the
-// global work array (a.up_Sw at the group's matrix offset) and the cluster
-// arrays in the ring.  The merge list (2 (n - 1) ints) fits the op buffer.
+// In the MFMA kernel, groups up to kFusedLdsN keep the triangle of 64-bit pair
+// sums in the score ring's LDS and the five cluster arrays in the traceback
+// staging block; larger ones, up to kFusedMaxN, and every group of the
+// vector-ALU kernel (whose ring is too small for the triangle) keep the sums
+// in their n x n area of the global work array (a.up_Sw at the group's matrix
+// offset), the cluster arrays and each cluster's best pair sum in `big` (the
+// MFMA kernel's ring, or an LDS block of their own).  The merge list
+// (2 (n - 1) ints) fits the op buffer.
 constexpr int kFusedLdsN = 182;
 constexpr int kFusedMaxN = 600;
 static_assert(kFusedMaxN <= kUpgmaW64MaxN, "in-launch trees compare 64-bit cross products");
 
 // The steps of the tree of group g on wave 0, the jobs of its merges made by
-// wave 1 as they are decided (see fused_tree).
-template <bool W64, int UB, typename St>
+// wave 1 as they are decided (see fused_tree).  Sums in LDS (TriS): the
+// one-wave steps; in HBM (FullS, bsum non-null): the steps with cached best
+// sums.
+template <typename St>
 __device__ void fused_tree_steps(const EngineArgs& a, int g, int g0, int n, const St& S, int32_t* id,
                                  int32_t* sz, int32_t* active, int32_t* best, int32_t* rec,
-                                 int32_t* mlist, int32_t* mcount) {
+                                 uint64_t* bsum, int32_t* mlist, int32_t* mcount) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  upgma_init_best<W64>(S, n, id, sz, active, best);
+  // (kFusedMaxN <= kUpgmaW64MaxN: 64-bit cross products are exact)
+  upgma_init_best<true>(S, n, id, sz, active, best);
   __syncthreads();
   if (wave == 0) {
     // the merge steps; each decided merge is listed for wave 1
-    const bool ok = upgma_steps<W64, UB>(
-        S, n, id, sz, active, best, rec, g, a.st,
-        [&](int step, int ia, int ib) {
-          mlist[2 * step] = ia;
-          mlist[2 * step + 1] = ib;
-          __hip_atomic_store(mcount, step + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        });
+    auto listed = [&](int step, int ia, int ib) {
+      mlist[2 * step] = ia;
+      mlist[2 * step + 1] = ib;
+      __hip_atomic_store(mcount, step + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    bool ok;
+    if constexpr (std::is_same<St, FullS>::value)
+      ok = upgma_steps_hbm<true, 4>(S, n, id, sz, active, best, bsum, rec, g, a.st, listed);
+    else
+      ok = upgma_steps<true, 1>(S, n, id, sz, active, best, rec, g, a.st, listed);
     if (!ok && lane == 0)
       __hip_atomic_store(mcount, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   } else if (wave == 1) {
@@ -1391,17 +1401,20 @@ __device__ void fused_tree_steps(const EngineArgs& a, int g, int g0, int n, cons
 }
 
 // UPGMA of group g by the whole workgroup.
+template <bool MFMA>
 __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t* tbst,
-                           int32_t* mlist, int32_t* mcount) {
+                           int32_t* big, int32_t* mlist, int32_t* mcount) {
   const int g0 = a.up_group_off[g], n = a.up_group_off[g + 1] - g0;
   if (n <= 1) return;
   const int tid = threadIdx.x;
-  const bool in_lds = n <= kFusedLdsN;
-  int32_t* id = reinterpret_cast<int32_t*>(in_lds ? tbst : ring);
+  const bool in_lds = MFMA && n <= kFusedLdsN;
+  int32_t* id = in_lds ? reinterpret_cast<int32_t*>(tbst) : big;
   int32_t* sz = id + n;
   int32_t* active = id + 2 * n;
   int32_t* best = id + 3 * n;
   int32_t* rec = id + 4 * n;
+  // the best pair sums of the HBM branch, 8-byte aligned after the arrays
+  uint64_t* bsum = reinterpret_cast<uint64_t*>(big + ((5 * n + 1) & ~1));
   for (int x = tid; x < n; x += kThreads) {
     id[x] = x;
     sz[x] = 1;
@@ -1415,10 +1428,10 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
     for (int64_t q = tid; q < (int64_t)n * n; q += kThreads) S.t[q] = Fg[q];
     __threadfence_block();
     __syncthreads();
-    // (kFusedMaxN <= kUpgmaW64MaxN: 64-bit cross products are exact)
-    fused_tree_steps<true, 1>(a, g, g0, n, S, id, sz, active, best, rec, mlist, mcount);
+    fused_tree_steps(a, g, g0, n, S, id, sz, active, best, rec, bsum, mlist, mcount);
     return;
   }
+  if constexpr (!MFMA) return;  // (every group of this kernel takes the branch above)
   uint64_t* tri = reinterpret_cast<uint64_t*>(ring);
   for (int64_t q = tid; q < (int64_t)n * n; q += kThreads) {
     const int x = (int)(q / n), y = (int)(q % n);
@@ -1426,8 +1439,7 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
   }
   __threadfence_block();
   __syncthreads();
-  // (groups here are below kUpgmaW64MaxN: 64-bit cross products are exact)
-  fused_tree_steps<true, 1>(a, g, g0, n, TriS{tri, n}, id, sz, active, best, rec, mlist, mcount);
+  fused_tree_steps(a, g, g0, n, TriS{tri, n}, id, sz, active, best, rec, nullptr, mlist, mcount);
 }
 
 
@@ -1460,23 +1472,27 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   __syncthreads();
 
   if constexpr (MFMA) {
-    static_assert(kUpgmaThreads == kThreads, "tree phase uses the engine's workgroup shape");
     static_assert(5 * kFusedLdsN <= kStageT4 * 64, "cluster arrays fit the staging block");
     static_assert((int64_t)kFusedLdsN * (kFusedLdsN - 1) / 2 * 8 <=
                       (int64_t)kWaves * kRingWords * 4, "pair sums fit the score ring");
-    static_assert(5 * kFusedMaxN <= kWaves * kRingWords, "cluster arrays fit the score ring");
-    // guide trees first; their merges become jobs for the other workgroups
-    static_assert(2 * (kFusedMaxN - 1) * 4 <= 2 * kMaxWidth, "merge list fits the ops buffer");
-    __shared__ int32_t umcount, ugrp;
-    if (a.up_ngroups > 0) {
-      for (;;) {
-        if (tid == 0) ugrp = atomicAdd(a.up_next, 1);
-        __syncthreads();
-        const int g = ugrp;
-        __syncthreads();
-        if (g >= a.up_ngroups) break;
-        fused_tree(a, g, ring, tbst, reinterpret_cast<int32_t*>(ops), &umcount);
-      }
+    static_assert(7 * kFusedMaxN + 2 <= kWaves * kRingWords,
+                  "cluster arrays and best sums fit the score ring");
+  }
+  static_assert(kUpgmaThreads == kThreads, "tree phase uses the engine's workgroup shape");
+  static_assert(2 * (kFusedMaxN - 1) * 4 <= 2 * kMaxWidth, "merge list fits the ops buffer");
+  // the vector-ALU kernel's cluster arrays and best sums of an in-launch tree
+  __shared__ __attribute__((aligned(8))) int32_t tree_arrays[MFMA ? 1 : 7 * kFusedMaxN + 2];
+  __shared__ int32_t umcount, ugrp;
+  // guide trees first; their merges become jobs for the other workgroups
+  if (a.up_ngroups > 0) {
+    int32_t* big = MFMA ? reinterpret_cast<int32_t*>(ring) : tree_arrays;
+    for (;;) {
+      if (tid == 0) ugrp = atomicAdd(a.up_next, 1);
+      __syncthreads();
+      const int g = ugrp;
+      __syncthreads();
+      if (g >= a.up_ngroups) break;
+      fused_tree<MFMA>(a, g, ring, tbst, big, reinterpret_cast<int32_t*>(ops), &umcount);
     }
   }
   uint64_t tk0 = 0, tk1 = 0, tk2 = 0, tk3 = 0, tk35 = 0;  // phase timestamps (thread 0)

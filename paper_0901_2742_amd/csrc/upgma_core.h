@@ -679,4 +679,119 @@ __device__ bool upgma_steps_wide(const St& S, int n, int32_t* id, int32_t* sz, i
   return true;
 }
 
+// ---------------------------------------------------------------- one wave, sums in HBM
+// The steps on one wave for a group whose pair sums live in the global work
+// array (below kUpgmaRow64MaxN members): each cluster's best pair sum cached
+// in LDS (bsum), the union's sums formed and compared with every cluster's
+// best in one pass (QC slots per lane at a time, their loads first), then the
+// rescans of the union and of the clusters that pointed at a merged one, two
+// rows at a time.  A merged-away slot gets size 0 besides active = 0 (the
+// rescans skip slots of size 0).  Comparisons within a row drop the row's own
+// size (exact in 64 bits below kUpgmaRow64MaxN members).  Called by one wave
+// after upgma_init_best; the merges are those of upgma_steps.
+template <bool W64, int QC, typename OnMerge>
+__device__ bool upgma_steps_hbm(const FullS& S, int n, int32_t* id, int32_t* sz, int32_t* active,
+                                int32_t* best, uint64_t* bsum, int32_t* rec, int g,
+                                DevStatus* st, OnMerge&& on_merge) {
+  // (callers hold groups below kUpgmaRow64MaxN: row comparisons in 64 bits)
+  const int lane = threadIdx.x & 63;
+  for (int r = lane; r < n; r += 64) bsum[r] = S.get(r, best[r]);
+  wave_sync();
+  for (int step = 0; step < n - 1; ++step) {
+    // the first of the clusters' best pairs (LDS only)
+    WCand c = wc_none();
+    uint32_t cab = 0;
+    for (int r = lane; r < n; r += 64) {
+      if (!active[r]) continue;
+      const int b = best[r];
+      WCand x;
+      x.s = bsum[r];
+      x.p = (uint32_t)sz[r] * (uint32_t)sz[b];
+      x.key = pair_key16(id[r], id[b]);
+      if (wc_better<W64>(x, c)) {
+        c = x;
+        cab = (uint32_t)min(r, b) | ((uint32_t)max(r, b) << 16);
+      }
+    }
+    const int src = winner_lane(c.key, wave_first_key<W64>(c));
+    if (src < 0) {
+      if (lane == 0) raise_error(st, SAD_E_INVAL, g, W_UPGMA);
+      return false;
+    }
+    const uint32_t ab = (uint32_t)__builtin_amdgcn_readlane((int)cab, src);
+    const int ba = (int)(ab & 0xffffu), bb = (int)(ab >> 16);
+    const uint32_t szu = (uint32_t)(sz[ba] + sz[bb]);
+    const int idu = n + step;
+    if (lane == 0) on_merge(step, min(id[ba], id[bb]), max(id[ba], id[bb]));
+    // S(new, q) = S(a, q) + S(b, q), QC slots per lane at a time with their
+    // loads first; each other cluster compares its best with the union or is
+    // listed for a rescan
+    if (lane == 0) rec[0] = ba;
+    int nrec = 1;
+    for (int q0 = lane; q0 < 64 * ((n + 63) / 64); q0 += 64 * QC) {
+      uint64_t va[QC], vb[QC];
+      bool on[QC];
+#pragma unroll
+      for (int u = 0; u < QC; ++u) {
+        const int q = q0 + 64 * u;
+        on[u] = q < n && active[q] && q != ba && q != bb;
+        va[u] = on[u] ? S.get(ba, q) : 0;
+        vb[u] = on[u] ? S.get(bb, q) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < QC; ++u) {
+        const int q = q0 + 64 * u;
+        bool again = false;
+        if (on[u]) {
+          const uint64_t v = va[u] + vb[u];
+          S.set(ba, q, v);
+          const int b = best[q];
+          again = b == ba || b == bb;
+          if (!again) {
+            WCand cur, uni;
+            cur.s = bsum[q];
+            cur.p = (uint32_t)sz[b];  // (the common factor |q| dropped)
+            cur.key = pair_key16(id[q], id[b]);
+            uni.s = v;
+            uni.p = szu;
+            uni.key = pair_key16(id[q], idu);
+            if (wc_better<true>(uni, cur)) {
+              best[q] = ba;
+              bsum[q] = v;
+            }
+          }
+        }
+        const uint64_t m = __ballot(again);
+        if (again) rec[nrec + (int)__popcll(m & ((1ull << lane) - 1ull))] = q;
+        nrec += (int)__popcll(m);
+      }
+    }
+    wave_sync();
+    if (lane == 0) {
+      sz[ba] = (int32_t)szu;
+      id[ba] = idu;
+      active[bb] = 0;
+      sz[bb] = 0;
+    }
+    wave_sync();
+    if (step == n - 2) break;
+    for (int t = 0; t < nrec; t += 2) {
+      const int k = min(2, nrec - t);
+      int rr[2] = {rec[t], rec[t + k - 1]}, out[2];
+      uint64_t outs[2];
+      wave_rescan<true, 2>(S, n, rr, id, sz, out, outs);
+      if (lane == 0) {
+        best[rr[0]] = out[0];
+        bsum[rr[0]] = outs[0];
+        if (k == 2) {
+          best[rr[1]] = out[1];
+          bsum[rr[1]] = outs[1];
+        }
+      }
+    }
+    wave_sync();
+  }
+  return true;
+}
+
 }  // namespace sad

@@ -90,6 +90,37 @@ def test_graphs_disabled_same_results(setup, monkeypatch):
     check_align(torch, al, ref, s, w.p)
 
 
+def test_valu_trees_in_launch_large_buckets(setup, monkeypatch):
+    """Vector-ALU column scores with the guide trees built inside the launch
+    (pair sums in HBM) on buckets above the MFMA kernel's LDS limit of 182
+    members: prot2000 in 8 buckets of 232-262; the eager call, the one that
+    captures the launch and a replay, each against the oracle."""
+    B, torch, s, w, _, seqs, _, _ = setup
+    p = 8
+    _say("case vector-ALU schedule, trees in the launch, 8 buckets")
+    ref = oracle.run_pipeline(s.codes, s.offsets, s.alphabet, w.kmer_k, p, w.subst(),
+                              w.gap_open, w.gap_extend, w.s_max)
+    prm = B.Params(w.kmer_k, p, w.subst(), w.gap_open, w.gap_extend, w.s_max,
+                   B.SAD_BATCHED_MFMA)
+    key, _ = B.sad_kmer_rank(seqs, prm)
+    part = B.sad_partition(seqs, key, prm)
+    sizes = np.diff(part["bucket_off"].cpu().numpy())
+    assert 182 < sizes.max() <= 600
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    monkeypatch.setenv("SAD_SCHEDULE", f"{2 * cus},1,0,0")
+    B.sad_profile_graphs(reset=True)
+    out = None
+    for rep in range(3):
+        if out is not None:
+            for t in out.values():
+                if torch.is_tensor(t):
+                    t.fill_(-7)
+        out = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm, out)
+        check_align(torch, out, ref, s, p)
+    captured, replayed = B.sad_profile_graphs(reset=True)
+    assert captured == 1 and replayed == 1
+
+
 @pytest.mark.parametrize("mode", [1, 0])
 def test_autotune_keeps_results(setup, mode):
     B, torch, s, w, ref, seqs, _, part = setup
@@ -107,11 +138,13 @@ def tuner_candidates(torch, mode):
     """The schedules sad_tune measures: batched, a grid of 1, 3/4 or 1/2
     workgroup per CU, the guide trees inside the launch or by a separate
     kernel, cooperative merges on or off, or vector-ALU scores with 1-3
-    workgroups per CU; plain, 1-3 workgroups per CU."""
+    workgroups per CU and the trees inside the launch or separate; plain, 1-3
+    workgroups per CU."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     if mode == 1:
         return ([(cus * den // 4, fuse, coop, 1) for coop in (1, 0) for fuse in (1, 0)
-                 for den in (4, 3, 2)] + [(cus * per, 0, 0, 0) for per in (1, 2, 3)])
+                 for den in (4, 3, 2)] +
+                [(cus * per, fuse, 0, 0) for fuse in (1, 0) for per in (1, 2, 3)])
     return [(cus * per, 0, 0, 0) for per in (1, 2, 3)]
 
 
