@@ -474,6 +474,7 @@ struct EngineBuffers {
   int64_t* coop_score;
   int64_t *job_score, *job_cells, *job_ops_off;
   int32_t *queue, *queue_flag, *qctl;
+  int32_t *prio, *prio_cnt;  // job priority scratch (batched launches with separate trees)
   unsigned long long* tops;
   uint16_t* prof_pool;
   int32_t* up_pool;
@@ -525,6 +526,8 @@ static void plan_engine(Carver& cv, EngineBuffers& e, int nnodes, int nslots, in
   cv.add(e.queue, (size_t)std::max(njobs, 1) * (1 + kMaxHelpers));
   cv.add(e.queue_flag, (size_t)std::max(njobs, 1) * (1 + kMaxHelpers));
   cv.add(e.qctl, 8);
+  cv.add(e.prio, nslots);
+  cv.add(e.prio_cnt, kPrioBins);
   cv.add(e.tops, 2);
   cv.add(e.prof_pool, (size_t)prof_cap);
   cv.add(e.up_pool, (size_t)up_cap);
@@ -907,54 +910,6 @@ static int32_t plan_levels(DeviceCtx* c, const TreeSet& ts, const int32_t* d_mer
   return SAD_OK;
 }
 
-// Order of the initially ready jobs (leaf-leaf merges) for the persistent
-// launch: longest estimated remaining path to the tree root first, so the
-// chains that bound the launch start before short ones.  A job's estimate is
-// W1 W2 DP cells plus per-op and per-job terms, with node widths estimated as
-// the larger child's width (leaves: sequence lengths).
-static int32_t plan_priority(const TreeSet& ts, const int32_t* d_merges, const EngineBuffers& e,
-                             hipStream_t stream) {
-  const int N = ts.nleaves;
-  std::vector<int32_t> merges(2 * (size_t)N), len(N);
-  HIPCHK(hipMemcpyAsync(merges.data(), d_merges, merges.size() * sizeof(int32_t),
-                        hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipMemcpyAsync(len.data(), e.node_W, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToHost,
-                        stream));
-  HIPCHK(hipStreamSynchronize(stream));
-  std::vector<double> cost(N, 0.0), path(N, 0.0);
-  std::vector<int32_t> width(N, 0), parent(N, -1), ready;
-  for (int g = 0; g < ts.ngroups; ++g) {
-    const int g0 = ts.h_group_off[g], ng = ts.h_group_off[g + 1] - g0;
-    for (int t = 0; t + 1 < ng; ++t) {
-      int w[2];
-      bool leaves = true;
-      for (int q = 0; q < 2; ++q) {
-        const int x = merges[2 * (size_t)(g0 + t) + q];
-        if (x < 0 || x >= 2 * ng - 1) return fail(SAD_E_INVAL, "malformed guide tree");
-        if (x < ng) {
-          w[q] = len[g0 + x];
-        } else {
-          w[q] = width[g0 + (x - ng)];
-          parent[g0 + (x - ng)] = g0 + t;
-          leaves = false;
-        }
-      }
-      width[g0 + t] = std::max(w[0], w[1]);
-      cost[g0 + t] = (double)w[0] * w[1] + 64.0 * (w[0] + w[1]) + 16384.0;
-      if (leaves) ready.push_back(g0 + t);
-    }
-    // parents come after their children in merge order
-    for (int t = ng - 2; t >= 0; --t) {
-      const int j = g0 + t;
-      path[j] = cost[j] + (parent[j] >= 0 ? path[parent[j]] : 0.0);
-    }
-  }
-  std::stable_sort(ready.begin(), ready.end(),
-                   [&](int a, int b) { return path[a] > path[b]; });
-  // queued through the pinned upload area: no wait here
-  return h2d(ready, e.queue, stream);
-}
-
 static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merges,
                          const sad_params* prm, int A, Carver& base_cv, EngineBuffers& e,
                          const TreeOutputs& out, hipStream_t stream,
@@ -1110,8 +1065,9 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
       r = plan_levels(c, ts, d_merges, e, njobs, &lvl_off, stream);
       if (r) return r;
     } else if (njobs > 0 && !fused) {
-      r = plan_priority(ts, d_merges, e, stream);
-      if (r) return r;
+      // the ready jobs, longest estimated path to the root first
+      launch_job_priorities(d_merges, ts.d_group_off, ts.ngroups, max_group, std::max(N, 1),
+                            e.node_W, e.prio, e.prio_cnt, e.queue, c->st, stream);
     }
     EngineTimer timer(stream);
     if (lvl_off.empty()) {

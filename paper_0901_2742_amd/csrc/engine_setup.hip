@@ -195,4 +195,137 @@ void launch_job_results(const int32_t* job_a, const int64_t* job_score, const in
       reinterpret_cast<unsigned long long*>(cells_total));
 }
 
+// ---------------------------------------------------------------- job priorities
+// Order of the initially ready jobs (leaf-leaf merges) of the persistent
+// launch: the longest estimated remaining path to the tree root first, so
+// that the chains that bound the launch start before short ones.  A job's
+// estimate is W1 W2 DP cells plus per-column and per-job terms, with a node's
+// width estimated as its wider child's (leaves: sequence lengths); its path
+// adds the estimates of its ancestors.  The order only schedules the work:
+// results never depend on it.  Ready jobs are placed by a counting sort on
+// the path's log2 in steps of 1/128 (kPrioBins bins; ties in any order).
+
+// One workgroup per group: the group's leaf widths and its merges (a chunk at
+// a time) are staged in LDS, where the first thread walks the merges in order
+// (each internal node's width, parent and path estimate, kept as float: the
+// bins need far less precision); then prio[s] = the bin of ready job s
+// (highest path first), -1 for the group's other jobs.
+constexpr int kPrioChunk = 1024;
+__global__ __launch_bounds__(256) void prio_paths_kernel(const int32_t* __restrict__ merges,
+                                                         const int32_t* __restrict__ group_off,
+                                                         const int32_t* __restrict__ node_W,
+                                                         int32_t* __restrict__ prio,
+                                                         DevStatus* st) {
+  extern __shared__ int32_t prio_sh[];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int g0 = group_off[g], n = group_off[g + 1] - g0;
+  if (n <= 1) return;
+  const int m = n - 1;
+  float* path = reinterpret_cast<float*>(prio_sh);
+  int32_t* width = prio_sh + m;
+  int32_t* parent = width + m;
+  int32_t* leafw = parent + m;
+  int32_t* mch = leafw + n;  // 2 kPrioChunk
+  for (int x = tid; x < n; x += blockDim.x) leafw[x] = node_W[g0 + x];
+  for (int t = tid; t < m; t += blockDim.x) parent[t] = -1;
+  for (int c0 = 0; c0 < m; c0 += kPrioChunk) {
+    const int cn = min(kPrioChunk, m - c0);
+    __syncthreads();
+    for (int q = tid; q < 2 * cn; q += blockDim.x) mch[q] = merges[2 * (int64_t)(g0 + c0) + q];
+    __syncthreads();
+    if (tid == 0) {
+      for (int t = c0; t < c0 + cn; ++t) {
+        int w[2];
+        for (int q = 0; q < 2; ++q) {
+          int x = mch[2 * (t - c0) + q];
+          if (x < 0 || x >= n + t) {  // not a leaf or an earlier cluster
+            raise_error(st, SAD_E_INVAL, g0 + t, W_ENGINE);
+            x = 0;
+          }
+          if (x < n) {
+            w[q] = leafw[x];
+          } else {
+            w[q] = width[x - n];
+            parent[x - n] = t;
+          }
+        }
+        width[t] = max(w[0], w[1]);
+        path[t] = (float)((int64_t)w[0] * w[1] + 64 * (int64_t)(w[0] + w[1]) + 16384);
+      }
+    }
+  }
+  __syncthreads();
+  // parents come after their children in merge order
+  if (tid == 0)
+    for (int t = m - 1; t >= 0; --t)
+      if (parent[t] >= 0) path[t] += path[parent[t]];
+  __syncthreads();
+  for (int t = tid; t < m; t += blockDim.x) {
+    const int la = merges[2 * (int64_t)(g0 + t)], lb = merges[2 * (int64_t)(g0 + t) + 1];
+    int bin = -1;
+    if (la >= 0 && la < n && lb >= 0 && lb < n) {
+      // path >= 2^14; bins of 1/128 octave above it, highest path in bin 0
+      const int b = (int)((__log2f(path[t]) - 14.0f) * 128.0f);
+      bin = kPrioBins - 1 - min(max(b, 0), kPrioBins - 1);
+    }
+    prio[g0 + t] = bin;
+  }
+}
+
+__global__ void prio_count_kernel(const int32_t* __restrict__ prio, int nslots,
+                                  int32_t* __restrict__ cnt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nslots && prio[s] >= 0 && prio[s] < kPrioBins) atomicAdd(&cnt[prio[s]], 1);
+}
+
+// cnt[b] <- first queue position of bin b (exclusive scan, one workgroup of
+// 1024 threads, four bins each).
+__global__ __launch_bounds__(1024) void prio_scan_kernel(int32_t* __restrict__ cnt) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  int v[4], sum = 0;
+  for (int q = 0; q < 4; ++q) {
+    v[q] = cnt[4 * t + q];
+    sum += v[q];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int add = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  int run = part[t] - sum;
+  for (int q = 0; q < 4; ++q) {
+    cnt[4 * t + q] = run;
+    run += v[q];
+  }
+}
+
+__global__ void prio_scatter_kernel(const int32_t* __restrict__ prio, int nslots,
+                                    int32_t* __restrict__ cnt, int32_t* __restrict__ queue) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nslots && prio[s] >= 0 && prio[s] < kPrioBins) queue[atomicAdd(&cnt[prio[s]], 1)] = s;
+}
+
+void launch_job_priorities(const int32_t* merges, const int32_t* group_off, int ngroups,
+                           int max_group, int nslots, const int32_t* node_W, int32_t* prio,
+                           int32_t* cnt, int32_t* queue, DevStatus* st, hipStream_t stream) {
+  if (ngroups <= 0 || nslots <= 0 || max_group <= 1) return;
+  static_assert(kPrioBins == 4 * 1024, "the scan takes four bins per thread");
+  // path, width, parent of the internal nodes, the leaf widths, a merge chunk
+  const size_t lds = ((size_t)3 * (max_group - 1) + max_group + 2 * kPrioChunk) * sizeof(int32_t);
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)prio_paths_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  launch_fill_i32(cnt, 0, kPrioBins, stream);
+  launch_fill_i32(prio, -1, nslots, stream);
+  prio_paths_kernel<<<ngroups, 256, lds, stream>>>(merges, group_off, node_W, prio, st);
+  const int blocks = (nslots + 255) / 256;
+  prio_count_kernel<<<blocks, 256, 0, stream>>>(prio, nslots, cnt);
+  prio_scan_kernel<<<1, 1024, 0, stream>>>(cnt);
+  prio_scatter_kernel<<<blocks, 256, 0, stream>>>(prio, nslots, cnt, queue);
+}
+
 }  // namespace sad

@@ -243,6 +243,13 @@ void launch_make_jobs(const int32_t* merges, const int32_t* group_off, int ngrou
                       int32_t* job_out, int32_t* job_next, int32_t* job_pending, int32_t* job_link,
                       int32_t* queue, int32_t* queue_flag, int32_t* queue_tail,
                       hipStream_t stream);
+// Reorders the ready jobs queue[0..nready) (leaf-leaf merges, as make_jobs
+// queued them) by estimated path to their tree's root, longest first.  prio:
+// nslots ints, cnt: kPrioBins ints of scratch.
+constexpr int kPrioBins = 4096;
+void launch_job_priorities(const int32_t* merges, const int32_t* group_off, int ngroups,
+                           int max_group, int nslots, const int32_t* node_W, int32_t* prio,
+                           int32_t* cnt, int32_t* queue, DevStatus* st, hipStream_t stream);
 void launch_colmap(const int64_t* offsets, const int32_t* ids, int nleaves,
                    const int32_t* node_parent, const int64_t* node_up, const int32_t* up_pool,
                    int32_t* colmap, DevStatus* st, hipStream_t stream);
