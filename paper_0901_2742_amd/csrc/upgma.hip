@@ -69,14 +69,25 @@ __global__ __launch_bounds__(kUpgmaThreads) void upgma_kernel(
     else
       upgma_run<false>(S, n, id, sz, active, best, rec, ml, mo, g, st);
   } else {
+    // sums in the global work array; each cluster's best pair sum cached in
+    // LDS after the cluster arrays (groups here are below kUpgmaWideMinN
+    // members, so 64-bit cross products are exact)
     const FullS S{Sw + fm_off[g], n};
-    for (int64_t q = tid; q < (int64_t)n * n; q += kUpgmaThreads) S.t[q] = Fg[q];
-    __threadfence_block();
+    if (lds_n > 0) {  // (with lds_n == 0 every group was widened beforehand)
+      for (int64_t q = tid; q < (int64_t)n * n; q += kUpgmaThreads) S.t[q] = Fg[q];
+      __threadfence_block();
+    }
     __syncthreads();
-    if (w64)
-      upgma_run<true>(S, n, id, sz, active, best, rec, nullptr, mo, g, st);
-    else
-      upgma_run<false>(S, n, id, sz, active, best, rec, nullptr, mo, g, st);
+    static_assert(kUpgmaWideMinN - 1 <= kUpgmaW64MaxN, "64-bit cross products");
+    uint64_t* bsum = reinterpret_cast<uint64_t*>(sh + ((5 * n + 1) & ~1));
+    upgma_init_best<true>(S, n, id, sz, active, best);
+    __syncthreads();
+    if ((tid >> 6) == 0)
+      upgma_steps_hbm<true, 4>(S, n, id, sz, active, best, bsum, rec, g, st,
+                               [&](int step, int ia, int ib) {
+                                 mo[2 * step] = ia;
+                                 mo[2 * step + 1] = ib;
+                               });
   }
 }
 
@@ -143,7 +154,7 @@ void launch_upgma(const uint32_t* F, const int64_t* fm_off, const int32_t* group
                   const int32_t* merge_base, DevStatus* st, hipStream_t stream) {
   if (ngroups <= 0 || max_n <= 1) return;
   if (max_n >= kUpgmaWideMinN) {
-    // a large group: its O(n) step phases on a workgroup of 16 waves
+    // a large group: its O(n) step phases on a workgroup of 4 waves
     // (a group of up to kUpgmaWideLdsN members also keeps its best sums in
     // LDS, whatever the largest group's size)
     const size_t lds = std::max((size_t)max_n * 4 * sizeof(int32_t),
@@ -165,11 +176,21 @@ void launch_upgma(const uint32_t* F, const int64_t* fm_off, const int32_t* group
   // (the merge lists of groups kept in LDS follow their 5 lds_n words)
   size_t lds = tri + (size_t)std::max(5 * max_n, 7 * lds_n) * sizeof(int32_t);
   int use_lds_n = lds_n;
-  if (lds > 160 * 1024 - 1024) {
-    // large groups present: all groups use the global sums
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (lds > 160 * 1024 - 1024 || ngroups > cus) {
+    // large groups present, or more groups than CUs (the LDS triangle allows
+    // one workgroup per CU, so they would take several rounds): all groups
+    // keep their sums in HBM, widened from F by one grid-wide pass
     use_lds_n = 0;
-    lds = (size_t)5 * max_n * sizeof(int32_t);
+    lds = 0;
+    const int bx = (int)std::min<int64_t>(64, ((int64_t)max_n * max_n + 255) / 256);
+    widen_sums_kernel<<<dim3(bx, ngroups), 256, 0, stream>>>(F, fm_off, group_off, Swork);
   }
+  // a group with global sums: 5 n words of cluster arrays, then n best sums
+  lds = std::max(lds, ((size_t)7 * max_n + 2) * sizeof(int32_t));
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)upgma_kernel,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
