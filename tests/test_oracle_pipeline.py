@@ -174,3 +174,25 @@ def test_threads_do_not_change_results(oracle_lib, name, p):
         else:
             assert np.array_equal(np.asarray(x), np.asarray(y))
     same(a, b)
+
+
+def test_threaded_tree_scan_keeps_the_merge_order(oracle_lib):
+    """The guide tree's pair scan split over threads (steps with 256 or more
+    clusters) gives the single-thread merges: a 400-member matrix with many
+    tied averages (values from four levels) and one of distinct values."""
+    rng = np.random.default_rng(11)
+    n = 400
+    mats = []
+    tied = (rng.integers(0, 4, (n, n)) * (1 << 29)).astype(np.uint32)
+    mats.append(np.triu(tied, 1) + np.triu(tied, 1).T)
+    dist = rng.integers(0, 1 << 31, (n, n)).astype(np.uint32)
+    mats.append(np.triu(dist, 1) + np.triu(dist, 1).T)
+    try:
+        for F in mats:
+            got = []
+            for t in (1, 5):
+                oracle.set_threads(t)
+                got.append(np.asarray(oracle.upgma(F)))
+            assert np.array_equal(got[0], got[1])
+    finally:
+        oracle.set_threads(1)
