@@ -247,18 +247,19 @@ __device__ __forceinline__ void dp_steps(int t0, int lane, int W2, T o, T e, Sco
     const T t2 = max(Xn, Yn);
     const T Hn = max(M, t2);
     const uint32_t hc = (M >= t2) ? 0u : ((Xn >= Yn) ? 1u : 2u);
-    // 0 extend only, 1 both, 2 open only (stored as sign + 1)
-    const uint32_t xc = (uint32_t)(sign3(xo - xe) + 1);
-    const uint32_t yc = (uint32_t)(sign3(yo - ye) + 1);
-    const uint32_t bits = hc | (xc << 2) | (yc << 4);
+    // tie byte hc | xc << 2 | yc << 4 with xc, yc = sign(open - extend) + 1
+    // (0 extend only, 1 both, 2 open only), accumulated as hc + 4 sign + 16
+    // sign; the + 4 + 16 of every byte is added once per word (each byte of
+    // the exact sum lies in 0..42, so none carries into the next)
+    const int32_t v = (int32_t)hc + 4 * sign3(xo - xe) + 16 * sign3(yo - ye);
     if (!MASK || (j >= 1 && j <= W2)) {
       H = Hn;
       X = Xn;
       Y = Yn;
     }
-    word |= bits << (8 * (k & 3));
+    word += (uint32_t)v << (8 * (k & 3));
     if ((k & 3) == 3) {
-      tw[k >> 2] = word;
+      tw[k >> 2] = word + 0x14141414u;
       word = 0;
     }
     oh = shl1(H, oh);
