@@ -1459,8 +1459,12 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   // the engine launch, which starts aligning each merge as soon as it is known
   const Schedule sched = schedule_for(TuneKey{A, n, p, (int)prm->mode, max_n, seqs->total_len});
   const bool valu = prm->mode == SAD_BATCHED_MFMA && sched.mfma == 0;
-  const bool fuse = prm->mode == SAD_BATCHED_MFMA && max_n <= engine_fused_max_group() &&
-                    sched.fuse != 0;
+  // (by default only while the pair sums fit the MFMA kernel's LDS: with sums
+  // in HBM the separate tree kernels are faster unless the autotuner finds
+  // otherwise)
+  const bool fuse = prm->mode == SAD_BATCHED_MFMA && sched.fuse != 0 &&
+                    max_n <= (sched.fuse == 1 ? engine_fused_max_group()
+                                              : engine_fused_lds_group());
   // pair sums in HBM: guide trees by the separate kernel, or built in the
   // launch for groups too large for the MFMA kernel's LDS (every group of the
   // vector-ALU kernel)

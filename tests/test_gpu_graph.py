@@ -90,14 +90,15 @@ def test_graphs_disabled_same_results(setup, monkeypatch):
     check_align(torch, al, ref, s, w.p)
 
 
-def test_valu_trees_in_launch_large_buckets(setup, monkeypatch):
-    """Vector-ALU column scores with the guide trees built inside the launch
-    (pair sums in HBM) on buckets above the MFMA kernel's LDS limit of 182
-    members: prot2000 in 8 buckets of 232-262; the eager call, the one that
-    captures the launch and a replay, each against the oracle."""
+@pytest.mark.parametrize("mfma", [0, 1])
+def test_trees_in_launch_large_buckets(setup, monkeypatch, mfma):
+    """The guide trees built inside the launch with their pair sums in HBM
+    (buckets above the MFMA kernel's LDS limit of 182 members: prot2000 in 8
+    buckets of 232-262), with vector-ALU or MFMA column scores; the eager call,
+    the one that captures the launch and a replay, each against the oracle."""
     B, torch, s, w, _, seqs, _, _ = setup
     p = 8
-    _say("case vector-ALU schedule, trees in the launch, 8 buckets")
+    _say(f"case trees in the launch, 8 buckets, mfma={mfma}")
     ref = oracle.run_pipeline(s.codes, s.offsets, s.alphabet, w.kmer_k, p, w.subst(),
                               w.gap_open, w.gap_extend, w.s_max)
     prm = B.Params(w.kmer_k, p, w.subst(), w.gap_open, w.gap_extend, w.s_max,
@@ -107,7 +108,7 @@ def test_valu_trees_in_launch_large_buckets(setup, monkeypatch):
     sizes = np.diff(part["bucket_off"].cpu().numpy())
     assert 182 < sizes.max() <= 600
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    monkeypatch.setenv("SAD_SCHEDULE", f"{2 * cus},1,0,0")
+    monkeypatch.setenv("SAD_SCHEDULE", f"{cus},1,1,1" if mfma else f"{2 * cus},1,0,0")
     B.sad_profile_graphs(reset=True)
     out = None
     for rep in range(3):
