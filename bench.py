@@ -163,7 +163,8 @@ def extras(out, args, B, pipeline, torch, seqs, prm, s, w, res, quality):
 
 def host_threads() -> int:
     """Host cores this process may use (affinity, capped by OMP_NUM_THREADS
-    when set: the GPU machines give one GPU's process a share of the host)."""
+    when set: a machine shared by several GPUs gives each GPU's process a
+    share of the host)."""
     n = len(os.sched_getaffinity(0))
     omp = os.environ.get("OMP_NUM_THREADS", "")
     if omp.isdigit() and int(omp) > 0:
