@@ -515,7 +515,7 @@ __device__ inline void wg_first(WCand (&c)[RB], const int (&a)[RB], WideScratch*
 // when 64-bit products are exact); out[j] is the partner (-1 if none),
 // outs[j] its pair sum, both wave-uniform.
 constexpr int kWideU = 16;
-template <bool R64, int RB, typename St>
+template <bool R64, int RB, typename St, int U = kWideU>
 __device__ inline void wave_rescan(const St& S, int n, const int (&r)[RB], const int32_t* id,
                                    const int32_t* sz, int (&out)[RB], uint64_t (&outs)[RB]) {
   const int lane = threadIdx.x & 63;
@@ -527,16 +527,16 @@ __device__ inline void wave_rescan(const St& S, int n, const int (&r)[RB], const
     cb[j] = -1;
     ir[j] = id[r[j]];
   }
-  for (int b0 = lane; b0 < n; b0 += 64 * kWideU) {
-    uint64_t sv[kWideU][RB];
+  for (int b0 = lane; b0 < n; b0 += 64 * U) {
+    uint64_t sv[U][RB];
 #pragma unroll
-    for (int u = 0; u < kWideU; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int b = min(b0 + 64 * u, n - 1);
 #pragma unroll
       for (int j = 0; j < RB; ++j) sv[u][j] = S.get(r[j], b != r[j] ? b : other_slot(r[j]));
     }
 #pragma unroll
-    for (int u = 0; u < kWideU; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int b = b0 + 64 * u;
       const uint32_t zb = b < n ? (uint32_t)sz[b] : 0u;
       const int ib = b < n ? id[b] : 0;
@@ -689,8 +689,8 @@ __device__ bool upgma_steps_wide(const St& S, int n, int32_t* id, int32_t* sz, i
 // rescans skip slots of size 0).  Comparisons within a row drop the row's own
 // size (exact in 64 bits below kUpgmaRow64MaxN members).  Called by one wave
 // after upgma_init_best; the merges are those of upgma_steps.
-template <bool W64, int QC, typename OnMerge>
-__device__ bool upgma_steps_hbm(const FullS& S, int n, int32_t* id, int32_t* sz, int32_t* active,
+template <bool W64, int QC, typename St, typename OnMerge>
+__device__ bool upgma_steps_hbm(const St& S, int n, int32_t* id, int32_t* sz, int32_t* active,
                                 int32_t* best, uint64_t* bsum, int32_t* rec, int g,
                                 DevStatus* st, OnMerge&& on_merge) {
   // (callers hold groups below kUpgmaRow64MaxN: row comparisons in 64 bits)
@@ -779,7 +779,7 @@ __device__ bool upgma_steps_hbm(const FullS& S, int n, int32_t* id, int32_t* sz,
       const int k = min(2, nrec - t);
       int rr[2] = {rec[t], rec[t + k - 1]}, out[2];
       uint64_t outs[2];
-      wave_rescan<true, 2>(S, n, rr, id, sz, out, outs);
+      wave_rescan<true, 2, St, QC>(S, n, rr, id, sz, out, outs);
       if (lane == 0) {
         best[rr[0]] = out[0];
         bsum[rr[0]] = outs[0];
