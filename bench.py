@@ -415,7 +415,10 @@ def main():
         "dp_cells_per_step": cells,
         "quality": qual,
         "mode": "batched",
-        "schedule": {"engine_workgroups": tuned[0], "trees_in_launch": bool(tuned[1]),
+        # (untuned: the library's default, trees in the launch while buckets
+        # have at most 182 members; null here)
+        "schedule": {"engine_workgroups": tuned[0],
+                     "trees_in_launch": bool(tuned[1]) if tuned[1] >= 0 else None,
                      "cooperative_merges": bool(tuned[2]), "mfma_scores": bool(tuned[3]),
                      "graph_captures": graphs[0], "graph_replays": graphs[1]},
         "engine_kernel": {"ms_total": round(eng_ms, 3), "launches": launches,
