@@ -77,6 +77,20 @@ def test_prot64_full(hip, mode):
     compare(got, ref, "prot64")
 
 
+@pytest.mark.parametrize("sched", ["0,0,1,1", "0,0,0,0"])
+@pytest.mark.parametrize("p", [3, 15])
+def test_small_sets_separate_trees(hip, monkeypatch, p, sched):
+    """Guide trees by the separate kernel (the ready merges ordered on the
+    device), MFMA or vector-ALU scores, on 30 proteins in 3 buckets and in 15
+    (two of them of a single member, so without merges)."""
+    B, pipeline = hip
+    _say(f"case small protein p={p} schedule {sched}")
+    monkeypatch.setenv("SAD_SCHEDULE", sched)
+    s = generate(4245, 30, 20, 3, {"kind": "fixed", "value": 70}, 0.15, 0.04, 3)
+    got, ref = run_both(B, pipeline, s, 3, p, protein_matrix(), 10, 1, 1)
+    compare(got, ref, f"p={p} {sched}")
+
+
 @pytest.mark.parametrize("p", [1, 2, 3, 7])
 def test_small_protein_sets(hip, p):
     B, pipeline = hip
