@@ -218,24 +218,56 @@ __device__ inline uint64_t tag_word(int32_t v, uint32_t tag) {
 }
 __device__ inline uint32_t tag_of(uint64_t w) { return (uint32_t)(w >> 32); }
 
+// The row above a strip during one chunk: H and X of the previous strip's
+// last row at the column each step's lane 0 computes.  RegRow keeps them in
+// two registers (lane m: step m's column) shifted one lane per step; LdsRow
+// reads them from the wave's LDS pairs at a wave-uniform address (a broadcast
+// read, no shifts), put there by put_row.
+template <typename T>
+struct RegRow {
+  T bhv, bxv;
+  __device__ __forceinline__ T h(int) const { return bhv; }
+  __device__ __forceinline__ T x(int) const { return bxv; }
+  __device__ __forceinline__ void next() {
+    bhv = shl1(bhv, bhv);
+    bxv = shl1(bxv, bxv);
+  }
+};
+template <typename T>
+struct LdsRow {
+  const T* p;  // step k: H at p[2 k], X at p[2 k + 1]
+  __device__ __forceinline__ T h(int k) const { return p[2 * k]; }
+  __device__ __forceinline__ T x(int k) const { return p[2 * k + 1]; }
+  __device__ __forceinline__ void next() {}
+};
+// Lane m stores the row above of step m (lanes past the chunk's steps store
+// values no step reads).  The wave's LDS operations run in order, so the
+// chunk's reads that follow see these stores, and the next chunk's stores
+// come after them.
+template <typename T>
+__device__ __forceinline__ void put_row(T* p, int lane, T h, T x) {
+  p[2 * lane] = h;
+  p[2 * lane + 1] = x;
+  __builtin_amdgcn_wave_barrier();
+}
+
 // DP steps K0..K1-1 (K0 a multiple of 4) of the 64 steps of one chunk of a
 // strip.  MASK: some cells of the chunk lie outside 1 <= j <= W2 and must
 // leave H/X/Y untouched.  score(k, j) gives s(i, j) of this lane's row at step
-// k.  bhv/bxv hold the row above the strip (lane 0 the column of the current
-// step) and shift one lane per step; oh/ox collect the strip's last row.
-template <bool MASK, int K0, int K1, typename T, typename Score>
+// k.  R gives the row above the strip at lane 0 (RegRow or LdsRow); oh/ox
+// collect the strip's last row.
+template <bool MASK, int K0, int K1, typename T, typename Score, typename Row>
 __device__ __forceinline__ void dp_steps(int t0, int lane, int W2, T o, T e, Score&& score, T& H,
-                                         T& X, T& Y, T& Hprev, T& bhv, T& bxv, T& oh, T& ox,
+                                         T& X, T& Y, T& Hprev, Row& R, T& oh, T& ox,
                                          uint32_t (&tw)[16]) {
   static_assert(K0 % 4 == 0 && K1 % 4 == 0, "tie words hold 4 steps");
   uint32_t word = 0;
 #pragma unroll
   for (int k = K0; k < K1; ++k) {
     const int j = t0 + k - lane + 1;
-    const T Hup = shr1(bhv, H);
-    const T Xup = shr1(bxv, X);
-    bhv = shl1(bhv, bhv);
-    bxv = shl1(bxv, bxv);
+    const T Hup = shr1(R.h(k), H);
+    const T Xup = shr1(R.x(k), X);
+    R.next();
     const T Hdiag = Hprev;
     Hprev = Hup;
     const T sc = (T)score(k, j);
@@ -268,11 +300,11 @@ __device__ __forceinline__ void dp_steps(int t0, int lane, int W2, T o, T e, Sco
 }
 
 // All 64 DP steps of one chunk of a strip.
-template <bool MASK, typename T, typename Score>
+template <bool MASK, typename T, typename Score, typename Row>
 __device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, T o, T e, Score&& score, T& H,
-                                         T& X, T& Y, T& Hprev, T bhv, T bxv, T& oh, T& ox,
+                                         T& X, T& Y, T& Hprev, Row R, T& oh, T& ox,
                                          uint32_t (&tw)[16]) {
-  dp_steps<MASK, 0, 64>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+  dp_steps<MASK, 0, 64>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
 }
 
 // Column score from a P2 column staged in the wave's LDS ring: packed 16-bit
@@ -322,7 +354,7 @@ struct RingScore {
 template <int A, bool PACK, typename T>
 __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                          int32_t* prog, uint32_t* tbw, int32_t* links, const int32_t* Ssh,
-                         const uint16_t* P1, const uint16_t* P2) {
+                         const uint16_t* P1, const uint16_t* P2, T* rowl) {
   constexpr int CW = ColWords<A>::value;
   const int W1 = J.W1, W2 = J.W2, nchunks = J.nchunks, nstrips = J.nstrips;
   const T o = (T)J.o, e = (T)J.e;
@@ -420,16 +452,18 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
 #pragma unroll
       for (int m = NW; m < CW; ++m) dst[m] = 0u;
     }
+    put_row(rowl, lane, bh, bx);
     __threadfence_block();
     if (c + 1 < nchunks) prefetch(c + 1, false);
     T oh = 0, ox = 0;
     const bool mask = (c == 0) || (t0 + 64 > W2);
     const RingScore<A, PACK> score{ring, Up, U};
+    const LdsRow<T> R{rowl};
     uint32_t tw[16];
     if (mask)
-      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
     else
-      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
     if (s + 1 < nstrips) {
       // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
       const int jo = t0 + lane - 62;
@@ -668,11 +702,12 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
     T oh = 0, ox = 0;
     const bool mask = (c == 0) || (t0 + 64 > W2);
     auto score = [&](int k, int) -> int32_t { return scv[k]; };
+    const RegRow<T> R{bh, bx};
     uint32_t tw[16];
     if (mask)
-      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
     else
-      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bh, bx, oh, ox, tw);
+      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
     // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
     const int jo = t0 + lane - 62;
     if (L.outH) {
@@ -729,7 +764,7 @@ __device__ inline StripLinks<T> strip_links(const EngineArgs& a, JobInfo& J, int
 template <int A>
 __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                                 uint32_t* tbw, const TagLinks& L, const int32_t* S32,
-                                const uint16_t* P1, const uint16_t* P2) {
+                                const uint16_t* P1, const uint16_t* P2, int32_t* rowl) {
   using T = int32_t;
   constexpr int KS = Tile<A>::KS;
   constexpr int CW = 32;  // steps (columns of the row above) per chunk
@@ -804,7 +839,8 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
 #pragma unroll
     for (int k = 0; k < CW; ++k) scv[k] = (int32_t)ring[lane * kScPitch + (t0 & 127) + k];
     T oh = 0, ox = 0;
-    T bhv = bh, bxv = bx;
+    put_row(rowl, lane, bh, bx);
+    LdsRow<T> R{rowl};
     const bool mask = (t0 < 63) || (t0 + CW > W2);
     auto score = [&](int k, int) -> int32_t { return scv[k]; };
     uint32_t tw[16];
@@ -813,13 +849,13 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
     // producer as closely as it can still finds it written
     constexpr int KF = CW / 2;
     if (mask) {
-      dp_steps<true, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+      dp_steps<true, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
       fetch(c + 1);
-      dp_steps<true, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+      dp_steps<true, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
     } else {
-      dp_steps<false, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+      dp_steps<false, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
       fetch(c + 1);
-      dp_steps<false, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, bhv, bxv, oh, ox, tw);
+      dp_steps<false, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
     }
     if (L.outH) {
       // lanes 64 - CW .. 63 hold the last row's values of steps t0 .. t0 + CW - 1,
@@ -885,7 +921,7 @@ __device__ inline TagLinks tag_links(const EngineArgs& a, JobInfo& J, int s, int
 template <int A>
 __device__ bool tagged_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, uint32_t* myring,
                           const int32_t* S32, const uint16_t* P1, const uint16_t* P2,
-                          int32_t* glist, int32_t* gstate) {
+                          int32_t* glist, int32_t* gstate, int32_t* rowl) {
   const int ns = J.nstrips;
   const int ngroups = (ns + kCoopGroupStrips - 1) / kCoopGroupStrips;
   uint32_t* tbw = a.tb + (int64_t)J.owner * a.tb_words_per_wg;
@@ -928,7 +964,7 @@ __device__ bool tagged_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, u
     const int s = g * kCoopGroupStrips + wave;
     if (s < ns) {
       const TagLinks L = tag_links(a, J, s, k);
-      if (!dp_strip_tagged<A>(a, J, s, lane, myring, tbw, L, S32, P1, P2)) return false;
+      if (!dp_strip_tagged<A>(a, J, s, lane, myring, tbw, L, S32, P1, P2, rowl)) return false;
       if (J.coop) {
         __builtin_amdgcn_s_waitcnt(0);
         __threadfence();
@@ -1459,6 +1495,8 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   __shared__ int32_t tbctl[5];  // strip staging: ready[2], consumed[2], fin
   __shared__ int32_t glist[kCoopMaxGroups];  // groups of a cooperative merge claimed here
   __shared__ int32_t gstate[2];              // groups claimed, no group left
+  // per wave: the row above of the current chunk, (H, X) per step
+  __shared__ __attribute__((aligned(16))) int64_t rowbuf[kWaves * 128];
   __shared__ JobInfo J;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
@@ -1470,6 +1508,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   uint32_t* tbw = a.tb + (int64_t)blockIdx.x * a.tb_words_per_wg;
   int32_t* links = a.bnd + (int64_t)blockIdx.x * a.link_words_per_wg;
   uint32_t* myring = ring + wave * kRingWords;
+  int64_t* myrow = rowbuf + wave * 128;
   __syncthreads();
 
   if constexpr (MFMA) {
@@ -1699,19 +1738,23 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
             }
           } else {
             // alone or cooperative (the tagged rows hold 32-bit values)
-            tagged_dp<A>(a, J, wave, lane, myring, S32, P1, P2, glist, gstate);
+            tagged_dp<A>(a, J, wave, lane, myring, S32, P1, P2, glist, gstate,
+                         reinterpret_cast<int32_t*>(myrow));
           }
         } else if (J.wide) {
           for (int s = wave; s < J.nstrips; s += kWaves)
-            if (!dp_strip<A, false, int64_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2))
+            if (!dp_strip<A, false, int64_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2,
+                                             myrow))
               break;
         } else if (J.packed) {
           for (int s = wave; s < J.nstrips; s += kWaves)
-            if (!dp_strip<A, true, int32_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2))
+            if (!dp_strip<A, true, int32_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2,
+                                            reinterpret_cast<int32_t*>(myrow)))
               break;
         } else {
           for (int s = wave; s < J.nstrips; s += kWaves)
-            if (!dp_strip<A, false, int32_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2))
+            if (!dp_strip<A, false, int32_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2,
+                                             reinterpret_cast<int32_t*>(myrow)))
               break;
         }
       }
