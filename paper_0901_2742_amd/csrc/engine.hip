@@ -240,6 +240,24 @@ struct LdsRow {
   __device__ __forceinline__ T x(int k) const { return p[2 * k + 1]; }
   __device__ __forceinline__ void next() {}
 };
+// The chunk's row above read from the wave's LDS pairs into registers at the
+// chunk's start, all K steps at once (the reads are in flight while the
+// chunk's scores are read; read one by one next to their steps, each exposes
+// the LDS latency to a wave that has its SIMD to itself).
+template <typename T, int K>
+struct ArrRow {
+  T hv[K], xv[K];
+  __device__ __forceinline__ void load(const T* p) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      hv[k] = p[2 * k];
+      xv[k] = p[2 * k + 1];
+    }
+  }
+  __device__ __forceinline__ T h(int k) const { return hv[k]; }
+  __device__ __forceinline__ T x(int k) const { return xv[k]; }
+  __device__ __forceinline__ void next() {}
+};
 // Lane m stores the row above of step m (lanes past the chunk's steps store
 // values no step reads).  The wave's LDS operations run in order, so the
 // chunk's reads that follow see these stores, and the next chunk's stores
@@ -251,14 +269,33 @@ __device__ __forceinline__ void put_row(T* p, int lane, T h, T x) {
   __builtin_amdgcn_wave_barrier();
 }
 
+// The strip's last row (lane 63's H and X after each step), collected for the
+// next strip by shifting it into two registers: after K steps lane 64 - K + m
+// holds step m.  (Storing each step's pair to LDS instead takes fewer
+// instructions, but the stores share the in-order LDS counter with the
+// row-above reads, and waiting for a read then waits for the stores too.)
+template <typename T>
+struct RegOut {
+  T oh = 0, ox = 0;
+  __device__ __forceinline__ void put(int, T h, T x) {
+    oh = shl1(h, oh);
+    ox = shl1(x, ox);
+  }
+};
+
 // DP steps K0..K1-1 (K0 a multiple of 4) of the 64 steps of one chunk of a
 // strip.  MASK: some cells of the chunk lie outside 1 <= j <= W2 and must
 // leave H/X/Y untouched.  score(k, j) gives s(i, j) of this lane's row at step
-// k.  R gives the row above the strip at lane 0 (RegRow or LdsRow); oh/ox
-// collect the strip's last row.
-template <bool MASK, int K0, int K1, typename T, typename Score, typename Row>
+// k.  R gives the row above the strip at lane 0 (RegRow or LdsRow); O
+// collects the strip's last row.
+// The gap states are carried plus the gap-open cost: X and Y here (and in
+// every boundary row) are X + o and Y + o, so that X's update
+// max(H_up - o, X_up - e) becomes max(H_up, X_up - e) + o, and
+// open - extend = H_up - (X_up - e) in the same terms; H = max(M, max(X, Y) - o)
+// is unchanged.  Integer identities, so every value and tie is the same.
+template <bool MASK, int K0, int K1, typename T, typename Score, typename Row, typename Out>
 __device__ __forceinline__ void dp_steps(int t0, int lane, int W2, T o, T e, Score&& score, T& H,
-                                         T& X, T& Y, T& Hprev, Row& R, T& oh, T& ox,
+                                         T& X, T& Y, T& Hprev, Row& R, Out& O,
                                          uint32_t (&tw)[16]) {
   static_assert(K0 % 4 == 0 && K1 % 4 == 0, "tie words hold 4 steps");
   uint32_t word = 0;
@@ -272,18 +309,18 @@ __device__ __forceinline__ void dp_steps(int t0, int lane, int W2, T o, T e, Sco
     Hprev = Hup;
     const T sc = (T)score(k, j);
     const T M = Hdiag + sc;
-    const T xo = Hup - o, xe = Xup - e;
-    const T Xn = max(xo, xe);
-    const T yo = H - o, ye = Y - e;
-    const T Yn = max(yo, ye);
-    const T t2 = max(Xn, Yn);
+    const T xe = Xup - e;
+    const T Xn = max(Hup, xe);
+    const T ye = Y - e;
+    const T Yn = max(H, ye);
+    const T t2 = max(Xn, Yn) - o;
     const T Hn = max(M, t2);
     const uint32_t hc = (M >= t2) ? 0u : ((Xn >= Yn) ? 1u : 2u);
     // tie byte hc | xc << 2 | yc << 4 with xc, yc = sign(open - extend) + 1
     // (0 extend only, 1 both, 2 open only), accumulated as hc + 4 sign + 16
     // sign; the + 4 + 16 of every byte is added once per word (each byte of
     // the exact sum lies in 0..42, so none carries into the next)
-    const int32_t v = (int32_t)hc + 4 * sign3(xo - xe) + 16 * sign3(yo - ye);
+    const int32_t v = (int32_t)hc + 4 * sign3(Hup - xe) + 16 * sign3(H - ye);
     if (!MASK || (j >= 1 && j <= W2)) {
       H = Hn;
       X = Xn;
@@ -294,17 +331,16 @@ __device__ __forceinline__ void dp_steps(int t0, int lane, int W2, T o, T e, Sco
       tw[k >> 2] = word + 0x14141414u;
       word = 0;
     }
-    oh = shl1(H, oh);
-    ox = shl1(X, ox);
+    O.put(k, H, X);
   }
 }
 
 // All 64 DP steps of one chunk of a strip.
-template <bool MASK, typename T, typename Score, typename Row>
+template <bool MASK, typename T, typename Score, typename Row, typename Out>
 __device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, T o, T e, Score&& score, T& H,
-                                         T& X, T& Y, T& Hprev, Row R, T& oh, T& ox,
+                                         T& X, T& Y, T& Hprev, Row R, Out& O,
                                          uint32_t (&tw)[16]) {
-  dp_steps<MASK, 0, 64>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+  dp_steps<MASK, 0, 64>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
 }
 
 // Column score from a P2 column staged in the wave's LDS ring: packed 16-bit
@@ -388,7 +424,8 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
     }
   }
   T H = -(o + (T)(ie - 1) * e);
-  T X = DpNeg<T>::value, Y = DpNeg<T>::value;
+  const T neg = DpNeg<T>::value + o;  // minus infinity of the offset gap states
+  T X = neg, Y = neg;
   T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
   uint32_t* tbs = tbw + (int64_t)s * nchunks * 16 * 64;
   // boundary rows: H and X of each strip's last row, link_stride 32-bit
@@ -403,7 +440,7 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
   // chunk (the boundary only if its producer is already far enough)
   constexpr int NW = (A + 1) / 2;
   uint32_t pcol[NW];
-  T pbh = 0, pbx = DpNeg<T>::value;
+  T pbh = 0, pbx = neg;
   bool have_link = (s == 0);
   auto prefetch = [&](int c, bool block) -> bool {
     const int jn = 64 * c + 1 + lane;
@@ -414,7 +451,7 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
     }
     if (s == 0) {
       pbh = jn <= W2 ? -(o + (T)(jn - 1) * e) : (T)0;
-      pbx = DpNeg<T>::value;
+      pbx = neg;
       have_link = true;
       return true;
     }
@@ -455,21 +492,21 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
     put_row(rowl, lane, bh, bx);
     __threadfence_block();
     if (c + 1 < nchunks) prefetch(c + 1, false);
-    T oh = 0, ox = 0;
+    RegOut<T> O;
     const bool mask = (c == 0) || (t0 + 64 > W2);
     const RingScore<A, PACK> score{ring, Up, U};
     const LdsRow<T> R{rowl};
     uint32_t tw[16];
     if (mask)
-      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
     else
-      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
     if (s + 1 < nstrips) {
       // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
       const int jo = t0 + lane - 62;
       if (jo >= 1 && jo <= W2) {
-        outH[jo] = oh;
-        outX[jo] = ox;
+        outH[jo] = O.oh;
+        outX[jo] = O.ox;
       }
       const int done = (c + 1 == nchunks) ? W2 : min(W2, t0 + 1);
       __builtin_amdgcn_s_waitcnt(0);  // the link stores have reached L2
@@ -657,18 +694,19 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
   long ua[3][2][KS];
   tile_rows<A>(ua, P1, S32, W1, s, lane);
   T H = -(o + (T)(ie - 1) * e);
-  T X = DpNeg<T>::value, Y = DpNeg<T>::value;
+  const T neg = DpNeg<T>::value + o;  // minus infinity of the offset gap states
+  T X = neg, Y = neg;
   T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
   uint32_t* tbs = tbw + (int64_t)s * nchunks * 16 * 64;
   const int ntiles = (W2 + 63) >> 6;
   uint32_t bw[2][KS][4];
-  T pbh = 0, pbx = DpNeg<T>::value;
+  T pbh = 0, pbx = neg;
   bool have_link = (s == 0);
   auto link_fetch = [&](int c, bool block) -> bool {
     const int jn = 64 * c + 1 + lane;
     if (s == 0) {
       pbh = jn <= W2 ? -(o + (T)(jn - 1) * e) : (T)0;
-      pbx = DpNeg<T>::value;
+      pbx = neg;
       have_link = true;
       return true;
     }
@@ -699,21 +737,21 @@ __device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, 
     for (int k = 0; k < 64; ++k) scv[k] = (int32_t)ring[lane * kScPitch + (t0 & 127) + k];
     if (c + 1 < ntiles) tile_load_counts<A>(bw, P2, W2, c + 1, lane);
     if (c + 1 < nchunks) link_fetch(c + 1, false);
-    T oh = 0, ox = 0;
+    RegOut<T> O;
     const bool mask = (c == 0) || (t0 + 64 > W2);
     auto score = [&](int k, int) -> int32_t { return scv[k]; };
     const RegRow<T> R{bh, bx};
     uint32_t tw[16];
     if (mask)
-      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+      dp_chunk<true>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
     else
-      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+      dp_chunk<false>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
     // lane m holds the last row's value of step t0 + m, i.e. column t0 + m - 62
     const int jo = t0 + lane - 62;
     if (L.outH) {
       if (jo >= 1 && jo <= W2) {
-        L.outH[jo] = oh;
-        L.outX[jo] = ox;
+        L.outH[jo] = O.oh;
+        L.outX[jo] = O.ox;
       }
       const int done = (c + 1 == nchunks) ? W2 : min(W2, t0 + 1);
       __builtin_amdgcn_s_waitcnt(0);  // the link stores are complete
@@ -777,7 +815,8 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
   long ua[3][2][KS];
   tile_rows<A>(ua, P1, S32, W1, s, lane);
   T H = -(o + (T)(ie - 1) * e);
-  T X = DpNeg<T>::value, Y = DpNeg<T>::value;
+  const T neg = DpNeg<T>::value + o;  // minus infinity of the offset gap states
+  T X = neg, Y = neg;
   T Hprev = (s == 0) ? (T)0 : -(o + (T)(64 * s - 1) * e);
   // tie words: the strip's block of J.nchunks x 16 x 64 words, word (t / 4, lane)
   uint32_t* tbs = tbw + (int64_t)s * J.nchunks * 16 * 64;
@@ -822,7 +861,7 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
       } while (!__all(!need || (tag_of(nh) == L.in_tag && tag_of(nx) == L.in_tag)));
     }
     bh = has_in ? (T)(int32_t)(uint32_t)nh : (jn <= W2 ? -(o + (T)(jn - 1) * e) : (T)0);
-    bx = has_in ? (T)(int32_t)(uint32_t)nx : DpNeg<T>::value;
+    bx = has_in ? (T)(int32_t)(uint32_t)nx : neg;
     return true;
   };
   tile_load_counts<A>(bw, P2, W2, 0, lane);
@@ -835,12 +874,15 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
       tile_scores<A>(ua, bw, nd_u, nd_c, ring, m, lane);
       if (m + 1 < ntiles) tile_load_counts<A>(bw, P2, W2, m + 1, lane);
     }
+    put_row(rowl, lane, bh, bx);
+    ArrRow<T, CW> R;
+    R.load(rowl);
     int32_t scv[CW];
 #pragma unroll
     for (int k = 0; k < CW; ++k) scv[k] = (int32_t)ring[lane * kScPitch + (t0 & 127) + k];
-    T oh = 0, ox = 0;
-    put_row(rowl, lane, bh, bx);
-    LdsRow<T> R{rowl};
+    // (the reads above stay ahead of the steps)
+    __builtin_amdgcn_sched_barrier(0);
+    RegOut<T> O;
     const bool mask = (t0 < 63) || (t0 + CW > W2);
     auto score = [&](int k, int) -> int32_t { return scv[k]; };
     uint32_t tw[16];
@@ -849,18 +891,19 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
     // producer as closely as it can still finds it written
     constexpr int KF = CW / 2;
     if (mask) {
-      dp_steps<true, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+      dp_steps<true, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
       fetch(c + 1);
-      dp_steps<true, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+      dp_steps<true, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
     } else {
-      dp_steps<false, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+      dp_steps<false, 0, KF>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
       fetch(c + 1);
-      dp_steps<false, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, oh, ox, tw);
+      dp_steps<false, KF, CW>(t0, lane, W2, o, e, score, H, X, Y, Hprev, R, O, tw);
     }
     if (L.outH) {
       // lanes 64 - CW .. 63 hold the last row's values of steps t0 .. t0 + CW - 1,
       // i.e. columns t0 + lane - (64 - CW) - 62
       const int jo = t0 + lane - (64 - CW) - 62;
+      const T oh = O.oh, ox = O.ox;
       if (lane >= 64 - CW && jo >= 1 && jo <= W2) {
         __hip_atomic_store(L.outH + jo, tag_word(oh, L.out_tag), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -1482,7 +1525,8 @@ __device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t*
 
 // ---------------------------------------------------------------- kernel
 template <int A, bool MFMA>
-__global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MFMA ? 1 : 2))) void
+engine_kernel(EngineArgs a) {
   constexpr int CW = ColWords<A>::value;
   constexpr int kRingWords = MFMA ? kScWords : kColRing * CW;  // per wave
   __shared__ __attribute__((aligned(16))) uint32_t ring[kWaves * kRingWords];
@@ -1495,8 +1539,11 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   __shared__ int32_t tbctl[5];  // strip staging: ready[2], consumed[2], fin
   __shared__ int32_t glist[kCoopMaxGroups];  // groups of a cooperative merge claimed here
   __shared__ int32_t gstate[2];              // groups claimed, no group left
-  // per wave: the row above of the current chunk, (H, X) per step
-  __shared__ __attribute__((aligned(16))) int64_t rowbuf[kWaves * 128];
+  // per wave: the row above of the current chunk, (H, X) per step (the MFMA
+  // kernel's 32-bit strips put 64 lanes' pairs of 32-bit values, the other
+  // kernel's strips up to 64 pairs of 64-bit values)
+  constexpr int kRowWords = MFMA ? 128 : 256;
+  __shared__ __attribute__((aligned(16))) int32_t rowbuf[kWaves * kRowWords];
   __shared__ JobInfo J;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave
@@ -1508,7 +1555,7 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
   uint32_t* tbw = a.tb + (int64_t)blockIdx.x * a.tb_words_per_wg;
   int32_t* links = a.bnd + (int64_t)blockIdx.x * a.link_words_per_wg;
   uint32_t* myring = ring + wave * kRingWords;
-  int64_t* myrow = rowbuf + wave * 128;
+  int32_t* myrow = rowbuf + wave * kRowWords;
   __syncthreads();
 
   if constexpr (MFMA) {
@@ -1738,23 +1785,22 @@ __global__ __launch_bounds__(kThreads) void engine_kernel(EngineArgs a) {
             }
           } else {
             // alone or cooperative (the tagged rows hold 32-bit values)
-            tagged_dp<A>(a, J, wave, lane, myring, S32, P1, P2, glist, gstate,
-                         reinterpret_cast<int32_t*>(myrow));
+            tagged_dp<A>(a, J, wave, lane, myring, S32, P1, P2, glist, gstate, myrow);
           }
         } else if (J.wide) {
           for (int s = wave; s < J.nstrips; s += kWaves)
             if (!dp_strip<A, false, int64_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2,
-                                             myrow))
+                                             reinterpret_cast<int64_t*>(myrow)))
               break;
         } else if (J.packed) {
           for (int s = wave; s < J.nstrips; s += kWaves)
             if (!dp_strip<A, true, int32_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2,
-                                            reinterpret_cast<int32_t*>(myrow)))
+                                            myrow))
               break;
         } else {
           for (int s = wave; s < J.nstrips; s += kWaves)
             if (!dp_strip<A, false, int32_t>(a, J, s, lane, myring, prog, tbw, links, Ssh, P1, P2,
-                                             reinterpret_cast<int32_t*>(myrow)))
+                                             myrow))
               break;
         }
       }
