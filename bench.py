@@ -253,6 +253,7 @@ def workload_figures(name, args, B, pipeline, torch, threads):
                                    "trees_in_launch": bool(tuned[1]),
                                    "cooperative_merges": bool(tuned[2]),
                                    "mfma_scores": bool(tuned[3]),
+                                   "chunk_steps": tuned[4] if tuned[3] else None,
                                    "graph_replays": graphs[1]}}
     out["same_result"] = bool(
         all(np.array_equal(hosts["batched"][st]["colmap"], hosts["plain"][st]["colmap"])
@@ -380,7 +381,7 @@ def main():
     # the process), then time the pipeline with it
     key0, _ = B.sad_kmer_rank(seqs, prm)
     part0 = B.sad_partition(seqs, key0, prm)
-    tuned = (0, -1, 1, 1) if args.no_tune else B.sad_tune(seqs, part0["bucket_off"],
+    tuned = (0, -1, 1, 1, 32) if args.no_tune else B.sad_tune(seqs, part0["bucket_off"],
                                                     part0["members"], prm)
     B.sad_profile_graphs(reset=True)
     res, ms, eng_ms, launches = timed_steps(pipeline.run_device, seqs, prm, args.steps,
@@ -420,6 +421,7 @@ def main():
         "schedule": {"engine_workgroups": tuned[0],
                      "trees_in_launch": bool(tuned[1]) if tuned[1] >= 0 else None,
                      "cooperative_merges": bool(tuned[2]), "mfma_scores": bool(tuned[3]),
+                     "chunk_steps": tuned[4] if tuned[3] else None,
                      "graph_captures": graphs[0], "graph_replays": graphs[1]},
         "engine_kernel": {"ms_total": round(eng_ms, 3), "launches": launches,
                           "avg_launch_ms": round(eng_ms / max(launches, 1), 4),

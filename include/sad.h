@@ -299,17 +299,20 @@ int32_t sad_refine_tree(const sad_seqs* seqs, const int32_t* d_bucket_off,
  * 4-strip groups spread over idle workgroups) on or off -- 12 schedules; or
  * column scores as vector-ALU dot products (the plain kernel, whose registers
  * and LDS allow several workgroups per CU) with 1, 2 or 3 workgroups per CU
- * and the guide trees inside the launch or separate -- 6 schedules.  Plain
- * mode: 1, 2 or 3 workgroups per CU for the per-level
+ * and the guide trees inside the launch or separate -- 6 schedules; then the
+ * fastest MFMA schedule once more with a shape of its DP strips changed:
+ * 16-step chunks instead of 32 (a strip trails the one above by 63 + chunk
+ * steps, and each chunk costs a boundary-row check and a tie-word store).
+ * Plain mode: 1, 2 or 3 workgroups per CU for the per-level
  * launches.  The fastest is kept in a process-wide cache keyed by (alphabet,
  * n, p, mode, largest bucket, total length) and used by later
  * sad_align_buckets calls with that key; results never depend on the
  * schedule.  `out` receives the last run's (identical) results.  *grid_out =
  * chosen workgroup count (0 = default), *fuse_out = 1 trees in the launch, 0
- * separate, *flags_out: bit 0 cooperative merges, bit 1 MFMA column scores
- * (any of them may be NULL).  The environment variable
- * SAD_SCHEDULE="grid,fuse[,coop[,mfma]]" imposes one schedule on every call
- * instead (for tests that check each candidate). */
+ * separate, *flags_out: bit 0 cooperative merges, bit 1 MFMA column scores,
+ * bit 2 16-step chunks (any of them may be NULL).  The environment variable
+ * SAD_SCHEDULE="grid,fuse[,coop[,mfma[,chunk]]]" imposes one schedule on
+ * every call instead (for tests that check each candidate). */
 int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off, const int32_t* d_members,
                  const sad_params* prm, sad_msa* out, int32_t* grid_out, int32_t* fuse_out,
                  int32_t* flags_out, hipStream_t stream);

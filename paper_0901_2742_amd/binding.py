@@ -452,8 +452,8 @@ def sad_tune(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, 
              out: dict | None = None):
     """Autotunes the schedule of sad_align_buckets for these buckets (cached for
     later calls with the same workload shape).  Returns (grid, fuse, coop,
-    mfma): workgroups, trees in the launch, cooperative merges, MFMA column
-    scores."""
+    mfma, chunk): workgroups, trees in the launch, cooperative merges, MFMA
+    column scores, steps per chunk of the MFMA kernel's DP strips."""
     dev = seqs.codes.device
     if out is None:
         out = _msa_tensors(seqs.total_len, prm.p, seqs.n, dev)
@@ -463,7 +463,7 @@ def sad_tune(seqs: DeviceSeqs, bucket_off: torch.Tensor, members: torch.Tensor, 
                           ctypes.byref(m), ctypes.byref(g), ctypes.byref(f), ctypes.byref(c),
                           _stream())
     _check(code, "sad_tune")
-    return g.value, f.value, c.value & 1, (c.value >> 1) & 1
+    return g.value, f.value, c.value & 1, (c.value >> 1) & 1, 16 if c.value & 4 else 32
 
 
 def sad_profile_graphs(reset: bool = False):

@@ -656,7 +656,7 @@ static int32_t* tag_rows(int nwg) {
 
 static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const int8_t* S, int go,
                               int ge, uint32_t mode, uint8_t* ops_out, DevStatus* st,
-                              bool coop = true) {
+                              bool coop = true, int chunk = 32) {
   EngineArgs a{};
   a.node_W = e.node_W;
   a.node_n = e.node_n;
@@ -717,6 +717,7 @@ static EngineArgs engine_args(const EngineBuffers& e, int njobs, int A, const in
   a.go = go;
   a.ge = ge;
   a.mode = mode;
+  a.chunk = chunk == 16 ? 16 : 32;
   a.st = st;
   // queue waits end after 20 s of wall clock (a malformed DAG cannot hang)
   int dev = 0, khz = 0;
@@ -914,7 +915,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                          const sad_params* prm, int A, Carver& base_cv, EngineBuffers& e,
                          const TreeOutputs& out, hipStream_t stream,
                          const FusedTrees* fused = nullptr, int grid = 0, bool coop = true,
-                         bool valu_scores = false) {
+                         bool valu_scores = false, int chunk = 32) {
   const int N = ts.nleaves;
   int njobs = 0;
   for (int g = 0; g < ts.ngroups; ++g)
@@ -1000,7 +1001,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
     std::vector<unsigned char> gkey;
     if (graphable) {
       EngineArgs ka = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend,
-                                  kmode, nullptr, c->st, coop);
+                                  kmode, nullptr, c->st, coop, chunk);
       const uintptr_t extra[] = {(uintptr_t)ts.d_codes, (uintptr_t)ts.d_offsets,
                                  (uintptr_t)ts.d_ids, (uintptr_t)ts.d_group_off,
                                  (uintptr_t)*fused->F, (uintptr_t)*fused->d_fm_off,
@@ -1044,7 +1045,7 @@ static int32_t run_trees(DeviceCtx* c, const TreeSet& ts, const int32_t* d_merge
                        e.job_b, e.job_out, e.job_next, e.job_pending, e.job_link, e.queue,
                        e.queue_flag, e.qctl + 1, stream);
     EngineArgs a = engine_args(e, njobs, A, prm->subst, prm->gap_open, prm->gap_extend, kmode,
-                               nullptr, c->st, coop);
+                               nullptr, c->st, coop, chunk);
     if (kmode == SAD_BATCHED_MFMA && !a.trow) return SAD_E_DEVICE;
     if (fused) {
       a.up_F = *fused->F;
@@ -1152,6 +1153,7 @@ struct Schedule {
   int fuse = -1;
   int coop = 1;  // cooperative merges (batched mode): a merge's strip groups spread over idle workgroups
   int mfma = 1;  // batched mode: column scores as int8 MFMA tiles (1) or vector-ALU dot products (0)
+  int chunk = 32;  // MFMA scores: steps per chunk of the 32-bit strips (32 or 16)
 };
 
 struct TuneKey {
@@ -1167,21 +1169,22 @@ static std::mutex g_tune_mu;
 static std::map<TuneKey, Schedule> g_tune;
 static thread_local const Schedule* g_forced = nullptr;  // set while sad_tune measures
 
-// SAD_SCHEDULE=grid,fuse[,coop[,mfma]] (e.g. "192,1,0") imposes one schedule
-// on every call, for tests that compare each autotuner candidate with the
-// oracle.
+// SAD_SCHEDULE=grid,fuse[,coop[,mfma[,chunk]]] (e.g. "192,1,0") imposes one
+// schedule on every call, for tests that compare each autotuner candidate with
+// the oracle.
 static bool schedule_from_env(Schedule* out) {
   const char* v = getenv("SAD_SCHEDULE");
-  int grid = 0, fuse = -1, coop = 1, mfma = 1;
+  int grid = 0, fuse = -1, coop = 1, mfma = 1, chunk = 32;
   if (!v) return false;
-  const int got = sscanf(v, "%d,%d,%d,%d", &grid, &fuse, &coop, &mfma);
+  const int got = sscanf(v, "%d,%d,%d,%d,%d", &grid, &fuse, &coop, &mfma, &chunk);
   if (got < 2 || grid < 0 || fuse < -1 || fuse > 1 || coop < 0 || coop > 1 || mfma < 0 ||
-      mfma > 1)
+      mfma > 1 || (chunk != 16 && chunk != 32))
     return false;
   out->grid = grid;
   out->fuse = fuse;
   out->coop = coop;
   out->mfma = mfma;
+  out->chunk = chunk;
   return true;
 }
 
@@ -1506,7 +1509,7 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
     const FusedTrees fz{&F, &d_fm_off, out->d_merge_list, sums_in_hbm ? &Sw : nullptr, upload,
                         kernels};
     return run_trees(c, ts, out->d_merge_list, prm, A, cv, e, to, stream, &fz, sched.grid,
-                     sched.coop != 0 && !valu, valu);
+                     sched.coop != 0 && !valu, valu, sched.chunk);
   }
   r = cv.carve(c);
   if (r) return r;
@@ -1523,7 +1526,7 @@ extern "C" int32_t sad_align_buckets(const sad_seqs* seqs, const int32_t* d_buck
   // in the caller's array, so those buffers are no longer needed)
   Carver base;
   return run_trees(c, ts, out->d_merge_list, prm, A, base, e, to, stream, nullptr, sched.grid,
-                   sched.coop != 0 && !valu, valu);
+                   sched.coop != 0 && !valu, valu, sched.chunk);
 }
 
 extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
@@ -1570,7 +1573,13 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
   // every candidate runs eagerly (no graph capture while tuning): one warm-up
   // run, then the fastest of three timed runs counts
   g_tuning = true;
-  for (const Schedule& sc : cand) {
+  // (the MFMA schedules run with 32-step chunks; the best of them is then
+  // also timed with 16-step chunks, a shape of the DP strips)
+  bool shaped = false;
+  Schedule best_mfma{};
+  float best_mfma_ms = 0.0f;
+  for (size_t ci = 0; ci < cand.size(); ++ci) {
+    const Schedule sc = cand[ci];
     g_forced = &sc;
     float ms = 0.0f;
     for (int rep = 0; rep < 4 && r == SAD_OK; ++rep) {
@@ -1585,11 +1594,21 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
     g_forced = nullptr;
     if (r) break;
     if (log_enabled())
-      fprintf(stderr, "[sad] tune: grid %d fuse %d coop %d mfma %d: %.3f ms\n", sc.grid, sc.fuse,
-              sc.coop, sc.mfma, ms);
+      fprintf(stderr, "[sad] tune: grid %d fuse %d coop %d mfma %d chunk %d: %.3f ms\n", sc.grid,
+              sc.fuse, sc.coop, sc.mfma, sc.chunk, ms);
     if (best_ms == 0.0f || ms < best_ms) {
       best_ms = ms;
       best = sc;
+    }
+    if (prm->mode == SAD_BATCHED_MFMA && sc.mfma && (best_mfma_ms == 0.0f || ms < best_mfma_ms)) {
+      best_mfma_ms = ms;
+      best_mfma = sc;
+    }
+    if (ci + 1 == cand.size() && !shaped && best_mfma_ms > 0.0f) {
+      shaped = true;
+      Schedule sh = best_mfma;
+      sh.chunk = 16;
+      cand.push_back(sh);
     }
   }
   g_tuning = false;
@@ -1602,7 +1621,8 @@ extern "C" int32_t sad_tune(const sad_seqs* seqs, const int32_t* d_bucket_off,
   }
   if (grid_out) *grid_out = best.grid;
   if (fuse_out) *fuse_out = best.fuse;
-  if (flags_out) *flags_out = (best.coop ? 1 : 0) | (best.mfma ? 2 : 0);
+  if (flags_out)
+    *flags_out = (best.coop ? 1 : 0) | (best.mfma ? 2 : 0) | (best.chunk == 16 ? 4 : 0);
   return SAD_OK;
 }
 

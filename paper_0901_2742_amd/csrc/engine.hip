@@ -682,7 +682,7 @@ __device__ inline void tile_rows(long (&ua)[3][2][Tile<A>::KS], const uint16_t* 
 // rows a chunk at a time under LDS counters.  Returns false if the job
 // aborted.
 template <int A, typename T>
-__device__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
+__device__ __forceinline__ bool dp_strip_mfma(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                               uint32_t* tbw, const StripLinks<T>& L, const int32_t* S32,
                               const uint16_t* P1, const uint16_t* P2) {
   constexpr int KS = Tile<A>::KS;
@@ -791,21 +791,25 @@ __device__ inline StripLinks<T> strip_links(const EngineArgs& a, JobInfo& J, int
 }
 
 // One strip of a 32-bit DP with MFMA tile scores and tagged boundary rows
-// (run by one wave), in chunks of 32 steps: a chunk needs 32 columns of the row
-// above, so the next strip trails this one by 63 + 32 steps rather than
-// 63 + 64.  The 64 x 64 score tile of columns 64 m + 1 .. 64 m + 64 is made at
-// the start of chunk 2 m; chunks 2 m and 2 m + 1 read only tiles m - 1 and m,
-// and tile m + 1 overwrites their ring slots only at chunk 2 m + 2.  The row
-// above is read a chunk ahead, and again until every column carries the tag;
-// the strip's last row is written at the end of each chunk with no fence, so
-// the wave never waits for its own stores.  False when the job aborted.
-template <int A>
-__device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
+// (run by one wave), in chunks of CW steps (32 or 16, a shape the autotuner
+// picks): a chunk needs CW columns of the row above, so the next strip trails
+// this one by 63 + CW steps rather than 63 + 64; shorter chunks shorten that
+// lag on chains of dependent merges and cost more per-chunk work.  The
+// 64 x 64 score tile of columns 64 m + 1 .. 64 m + 64 is made at the start of
+// chunk (64 / CW) m; the chunks of tile m read only tiles m - 1 and m, and
+// tile m + 1 overwrites their ring slots only at the chunk after them.  The
+// row above is read a chunk ahead, and again until every column carries the
+// tag; the strip's last row is written at the end of each chunk with no
+// fence, so the wave never waits for its own stores.  False when the job
+// aborted.
+template <int A, int CW>
+__device__ __forceinline__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane, uint32_t* ring,
                                 uint32_t* tbw, const TagLinks& L, const int32_t* S32,
                                 const uint16_t* P1, const uint16_t* P2, int32_t* rowl) {
   using T = int32_t;
   constexpr int KS = Tile<A>::KS;
-  constexpr int CW = 32;  // steps (columns of the row above) per chunk
+  static_assert(CW == 16 || CW == 32, "chunks of 16 or 32 steps");
+  constexpr int CPT = 64 / CW;  // chunks per score tile
   const int W1 = J.W1, W2 = J.W2;
   const int nch = (W2 + 63 + CW - 1) / CW;  // chunks of CW steps
   const int nd_u = J.nd_u, nd_c = J.nd_c;
@@ -869,8 +873,8 @@ __device__ bool dp_strip_tagged(const EngineArgs& a, JobInfo& J, int s, int lane
   if (!check(0)) return false;
   for (int c = 0; c < nch; ++c) {
     const int t0 = CW * c;
-    const int m = c >> 1;
-    if ((c & 1) == 0 && m < ntiles) {
+    const int m = c / CPT;
+    if (c % CPT == 0 && m < ntiles) {
       tile_scores<A>(ua, bw, nd_u, nd_c, ring, m, lane);
       if (m + 1 < ntiles) tile_load_counts<A>(bw, P2, W2, m + 1, lane);
     }
@@ -961,8 +965,8 @@ __device__ inline TagLinks tag_links(const EngineArgs& a, JobInfo& J, int s, int
 // groups of one workgroup overlap as the strips of one merge do, and every
 // finished strip makes its tie bytes (and H(W1, W2)) visible device-wide,
 // then counts itself.
-template <int A>
-__device__ bool tagged_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, uint32_t* myring,
+template <int A, int CW>
+__device__ __forceinline__ bool tagged_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, uint32_t* myring,
                           const int32_t* S32, const uint16_t* P1, const uint16_t* P2,
                           int32_t* glist, int32_t* gstate, int32_t* rowl) {
   const int ns = J.nstrips;
@@ -1007,7 +1011,8 @@ __device__ bool tagged_dp(const EngineArgs& a, JobInfo& J, int wave, int lane, u
     const int s = g * kCoopGroupStrips + wave;
     if (s < ns) {
       const TagLinks L = tag_links(a, J, s, k);
-      if (!dp_strip_tagged<A>(a, J, s, lane, myring, tbw, L, S32, P1, P2, rowl)) return false;
+      if (!dp_strip_tagged<A, CW>(a, J, s, lane, myring, tbw, L, S32, P1, P2, rowl))
+        return false;
       if (J.coop) {
         __builtin_amdgcn_s_waitcnt(0);
         __threadfence();
@@ -1148,7 +1153,7 @@ struct StripSource {
 
 // Helper wave of StripSource: copies strips sL, sL - 1, ... (each nchunks x
 // 4 KB, contiguous) into the two LDS buffers with direct-to-LDS loads.
-__device__ void strip_loader(const uint32_t* tbw, uint32_t* buf, int words, int sL,
+__device__ __forceinline__ void strip_loader(const uint32_t* tbw, uint32_t* buf, int words, int sL,
                              int32_t* ready, int32_t* consumed, int32_t* fin, int64_t wait_ticks,
                              DevStatus* st, int32_t* wsites, int lane) {
   for (int s = sL; s >= 0; --s) {
@@ -1312,7 +1317,7 @@ __device__ inline void merge_store(const MergeRow<A>& r, int nops, uint2* __rest
 }
 
 template <int A>
-__device__ void merge(const uint8_t* ops, int base, int nops, const uint16_t* P1,
+__device__ __forceinline__ void merge(const uint8_t* ops, int base, int nops, const uint16_t* P1,
                       const uint16_t* P2, uint16_t* Pout, int32_t* up1, int32_t* up2,
                       int32_t* gcnt) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1482,7 +1487,7 @@ __device__ void fused_tree_steps(const EngineArgs& a, int g, int g0, int n, cons
 
 // UPGMA of group g by the whole workgroup.
 template <bool MFMA>
-__device__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t* tbst,
+__device__ __forceinline__ void fused_tree(const EngineArgs& a, int g, uint32_t* ring, uint32_t* tbst,
                            int32_t* big, int32_t* mlist, int32_t* mcount) {
   const int g0 = a.up_group_off[g], n = a.up_group_off[g + 1] - g0;
   if (n <= 1) return;
@@ -1785,7 +1790,10 @@ engine_kernel(EngineArgs a) {
             }
           } else {
             // alone or cooperative (the tagged rows hold 32-bit values)
-            tagged_dp<A>(a, J, wave, lane, myring, S32, P1, P2, glist, gstate, myrow);
+            if (a.chunk == 16)
+              tagged_dp<A, 16>(a, J, wave, lane, myring, S32, P1, P2, glist, gstate, myrow);
+            else
+              tagged_dp<A, 32>(a, J, wave, lane, myring, S32, P1, P2, glist, gstate, myrow);
           }
         } else if (J.wide) {
           for (int s = wave; s < J.nstrips; s += kWaves)

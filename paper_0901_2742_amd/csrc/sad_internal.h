@@ -179,6 +179,7 @@ struct EngineArgs {
   int32_t go, ge;
   int32_t smax;           // max |S|
   uint32_t mode;
+  int32_t chunk;          // steps per chunk of the MFMA kernel's 32-bit strips: 32 or 16
   int64_t wait_ticks;     // queue wait limit in s_memrealtime ticks
   unsigned long long* phase_acc;  // optional: ticks in queue wait, DP, traceback, merge; jobs
   long long* job_rec;  // optional: per job slot W1, W2, ops and five phase timestamps (8 words)

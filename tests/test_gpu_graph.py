@@ -127,8 +127,8 @@ def test_autotune_keeps_results(setup, mode):
     B, torch, s, w, ref, seqs, _, part = setup
     _say(f"case autotune mode={mode}")
     prm = B.Params(w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, w.s_max, mode)
-    grid, fuse, coop, mfma = B.sad_tune(seqs, part["bucket_off"], part["members"], prm)
-    assert grid > 0
+    grid, fuse, coop, mfma, chunk = B.sad_tune(seqs, part["bucket_off"], part["members"], prm)
+    assert grid > 0 and chunk in (16, 32)
     al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm)
     check_align(torch, al, ref, s, w.p)
     al = B.sad_align_buckets(seqs, part["bucket_off"], part["members"], prm)
@@ -140,13 +140,14 @@ def tuner_candidates(torch, mode):
     workgroup per CU, the guide trees inside the launch or by a separate
     kernel, cooperative merges on or off, or vector-ALU scores with 1-3
     workgroups per CU and the trees inside the launch or separate; plain, 1-3
-    workgroups per CU."""
+    workgroups per CU.  The MFMA schedules with 32-step chunks (the tuner
+    times its best one with 16-step chunks as well: here every one of them)."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     if mode == 1:
-        return ([(cus * den // 4, fuse, coop, 1) for coop in (1, 0) for fuse in (1, 0)
-                 for den in (4, 3, 2)] +
-                [(cus * per, fuse, 0, 0) for fuse in (1, 0) for per in (1, 2, 3)])
-    return [(cus * per, 0, 0, 0) for per in (1, 2, 3)]
+        return ([(cus * den // 4, fuse, coop, 1, chunk) for chunk in (32, 16) for coop in (1, 0)
+                 for fuse in (1, 0) for den in (4, 3, 2)] +
+                [(cus * per, fuse, 0, 0, 32) for fuse in (1, 0) for per in (1, 2, 3)])
+    return [(cus * per, 0, 0, 0, 32) for per in (1, 2, 3)]
 
 
 @pytest.mark.parametrize("mode", [1, 0])
@@ -156,9 +157,10 @@ def test_every_tuner_candidate_matches_the_oracle(setup, monkeypatch, mode):
     B, torch, s, w, ref, seqs, _, part = setup
     prm = B.Params(w.kmer_k, w.p, w.subst(), w.gap_open, w.gap_extend, w.s_max, mode)
     out = None
-    for grid, fuse, coop, mfma in tuner_candidates(torch, mode):
-        _say(f"case tuner candidate mode={mode} grid={grid} fuse={fuse} coop={coop} mfma={mfma}")
-        monkeypatch.setenv("SAD_SCHEDULE", f"{grid},{fuse},{coop},{mfma}")
+    for grid, fuse, coop, mfma, chunk in tuner_candidates(torch, mode):
+        _say(f"case tuner candidate mode={mode} grid={grid} fuse={fuse} coop={coop} mfma={mfma} "
+             f"chunk={chunk}")
+        monkeypatch.setenv("SAD_SCHEDULE", f"{grid},{fuse},{coop},{mfma},{chunk}")
         if out is not None:
             for t in out.values():
                 if torch.is_tensor(t):

@@ -77,12 +77,13 @@ def test_prot64_full(hip, mode):
     compare(got, ref, "prot64")
 
 
-@pytest.mark.parametrize("sched", ["0,0,1,1", "0,0,0,0"])
+@pytest.mark.parametrize("sched", ["0,0,1,1", "0,0,0,0", "0,0,1,1,16", "0,1,1,1,16"])
 @pytest.mark.parametrize("p", [3, 15])
 def test_small_sets_separate_trees(hip, monkeypatch, p, sched):
     """Guide trees by the separate kernel (the ready merges ordered on the
     device), MFMA or vector-ALU scores, on 30 proteins in 3 buckets and in 15
-    (two of them of a single member, so without merges)."""
+    (two of them of a single member, so without merges); the MFMA strips also
+    in 16-step chunks, with separate trees and with the trees in the launch."""
     B, pipeline = hip
     _say(f"case small protein p={p} schedule {sched}")
     monkeypatch.setenv("SAD_SCHEDULE", sched)
@@ -100,29 +101,39 @@ def test_small_protein_sets(hip, p):
     compare(got, ref, f"p={p}")
 
 
-def test_small_dna_k8(hip):
+@pytest.mark.parametrize("sched", [None, "0,-1,1,1,16"])
+def test_small_dna_k8(hip, monkeypatch, sched):
     B, pipeline = hip
-    _say("case small dna k=8")
+    _say(f"case small dna k=8 schedule {sched}")
+    if sched:
+        monkeypatch.setenv("SAD_SCHEDULE", sched)
     s = generate(808, 40, 4, 4, {"kind": "uniform_int", "lo": 90, "hi": 140}, 0.05, 0.01, 8)
     got, ref = run_both(B, pipeline, s, 8, 4, dna_matrix(), 5, 2, 1)
     compare(got, ref, "dna")
 
 
-def test_long_sequences_multi_strip(hip):
-    """Profiles wider than several 64-row strips and the 256-column ring."""
+@pytest.mark.parametrize("sched", [None, "0,-1,1,1,16", "0,-1,0,1,16"])
+def test_long_sequences_multi_strip(hip, monkeypatch, sched):
+    """Profiles wider than several 64-row strips and the 256-column ring; the
+    MFMA strips also in 16-step chunks, with and without cooperative merges."""
     B, pipeline = hip
-    _say("case long sequences")
+    _say(f"case long sequences schedule {sched}")
+    if sched:
+        monkeypatch.setenv("SAD_SCHEDULE", sched)
     s = generate(31, 12, 20, 2, {"kind": "fixed", "value": 700}, 0.1, 0.02, 3)
     got, ref = run_both(B, pipeline, s, 3, 2, protein_matrix(), 10, 1, 1)
     compare(got, ref, "long")
 
 
-def test_gap_models(hip):
+@pytest.mark.parametrize("sched", [None, "0,-1,1,1,16"])
+def test_gap_models(hip, monkeypatch, sched):
     """o == e and free extension: many tied optima exercise the tie rule."""
     B, pipeline = hip
+    if sched:
+        monkeypatch.setenv("SAD_SCHEDULE", sched)
     s = generate(77, 16, 20, 2, {"kind": "fixed", "value": 50}, 0.3, 0.05, 3)
     for go, ge in [(3, 3), (6, 0), (0, 0)]:
-        _say(f"case gaps {go}/{ge}")
+        _say(f"case gaps {go}/{ge} schedule {sched}")
         got, ref = run_both(B, pipeline, s, 3, 2, protein_matrix(), go, ge, 1)
         compare(got, ref, f"gaps {go}/{ge}")
 
