@@ -37,6 +37,9 @@ namespace sad {
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kColRing = 128;   // staged P2 columns per wave (power of two)
+// Slots kColRing .. kColRing + 63 repeat slots 0 .. 63, so that a lane reads
+// the 64 columns of a chunk at one base plus constant offsets (no wrap).
+constexpr int kColRingPad = 64;
 constexpr int kStageT4 = 16;    // traceback staging: 16 x 64 words (64 steps of a strip)
 constexpr int kMaxStrips = kMaxWidth / 64;
 constexpr int kEngineWGPerCU = 1;
@@ -344,15 +347,17 @@ __device__ __forceinline__ void dp_chunk(int t0, int lane, int W2, T o, T e, Sco
 }
 
 // Column score from a P2 column staged in the wave's LDS ring: packed 16-bit
-// dot products (PACK) or 32-bit products.
+// dot products (PACK) or 32-bit products.  base is this lane's slot of the
+// chunk's first step (column t0 - lane + 1 at slot (t0 - lane) mod kColRing);
+// step k reads slot base + k, past kColRing in the repeated slots.
 template <int A, bool PACK>
 struct RingScore {
-  const uint32_t* ring;
+  const uint32_t* base;
   const uint32_t* Up;
   const int32_t* U;
-  __device__ __forceinline__ int32_t operator()(int, int j) const {
+  __device__ __forceinline__ int32_t operator()(int k, int) const {
     constexpr int CW = ColWords<A>::value;
-    const uint32_t* col = ring + ((j - 1) & (kColRing - 1)) * CW;
+    const uint32_t* col = base + k * CW;
     int32_t sc = 0;
     if constexpr (PACK) {
       if constexpr (A == 20) {
@@ -483,18 +488,26 @@ __device__ bool dp_strip(const EngineArgs& a, JobInfo& J, int s, int lane, uint3
     }
     const T bh = pbh, bx = pbx;
     if (jn <= W2) {
-      uint32_t* dst = ring + ((jn - 1) & (kColRing - 1)) * CW;
+      const int slot = (jn - 1) & (kColRing - 1);
+      uint32_t* dst = ring + slot * CW;
 #pragma unroll
       for (int m = 0; m < NW; ++m) dst[m] = pcol[m];
 #pragma unroll
       for (int m = NW; m < CW; ++m) dst[m] = 0u;
+      if (slot < kColRingPad) {
+        uint32_t* rep = dst + kColRing * CW;
+#pragma unroll
+        for (int m = 0; m < NW; ++m) rep[m] = pcol[m];
+#pragma unroll
+        for (int m = NW; m < CW; ++m) rep[m] = 0u;
+      }
     }
     put_row(rowl, lane, bh, bx);
     __threadfence_block();
     if (c + 1 < nchunks) prefetch(c + 1, false);
     RegOut<T> O;
     const bool mask = (c == 0) || (t0 + 64 > W2);
-    const RingScore<A, PACK> score{ring, Up, U};
+    const RingScore<A, PACK> score{ring + ((t0 - lane) & (kColRing - 1)) * CW, Up, U};
     const LdsRow<T> R{rowl};
     uint32_t tw[16];
     if (mask)
@@ -1533,7 +1546,7 @@ template <int A, bool MFMA>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MFMA ? 1 : 2))) void
 engine_kernel(EngineArgs a) {
   constexpr int CW = ColWords<A>::value;
-  constexpr int kRingWords = MFMA ? kScWords : kColRing * CW;  // per wave
+  constexpr int kRingWords = MFMA ? kScWords : (kColRing + kColRingPad) * CW;  // per wave
   __shared__ __attribute__((aligned(16))) uint32_t ring[kWaves * kRingWords];
   __shared__ int32_t S32[MFMA ? A * 32 : 1];
   __shared__ uint32_t tbst[kStageT4 * 64];
