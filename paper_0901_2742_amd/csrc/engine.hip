@@ -286,6 +286,20 @@ struct RegOut {
   }
 };
 
+template <int A, bool PACK>
+struct RingScore;
+// M = H_diag + s(i, j) of step k: the 32-bit vector-ALU strips fold H_diag
+// into their dot products; other scores are added.
+template <typename Score, typename T>
+__device__ __forceinline__ T diag_plus_score(const Score& score, int k, int j, T h) {
+  return h + (T)score(k, j);
+}
+template <int A, bool PACK>
+__device__ __forceinline__ int32_t diag_plus_score(const RingScore<A, PACK>& score, int k, int,
+                                                   int32_t h) {
+  return score.plus(k, h);
+}
+
 // DP steps K0..K1-1 (K0 a multiple of 4) of the 64 steps of one chunk of a
 // strip.  MASK: some cells of the chunk lie outside 1 <= j <= W2 and must
 // leave H/X/Y untouched.  score(k, j) gives s(i, j) of this lane's row at step
@@ -310,8 +324,7 @@ __device__ __forceinline__ void dp_steps(int t0, int lane, int W2, T o, T e, Sco
     R.next();
     const T Hdiag = Hprev;
     Hprev = Hup;
-    const T sc = (T)score(k, j);
-    const T M = Hdiag + sc;
+    const T M = diag_plus_score(score, k, j, Hdiag);
     const T xe = Xup - e;
     const T Xn = max(Hup, xe);
     const T ye = Y - e;
@@ -355,10 +368,13 @@ struct RingScore {
   const uint32_t* base;
   const uint32_t* Up;
   const int32_t* U;
-  __device__ __forceinline__ int32_t operator()(int k, int) const {
+  __device__ __forceinline__ int32_t operator()(int k, int) const { return plus(k, 0); }
+  // h + s(i, j) of step k: the dot products accumulate onto h (modulo 2^32,
+  // exact because the sum fits in 32 bits)
+  __device__ __forceinline__ int32_t plus(int k, int32_t h) const {
     constexpr int CW = ColWords<A>::value;
     const uint32_t* col = base + k * CW;
-    int32_t sc = 0;
+    int32_t sc = h;
     if constexpr (PACK) {
       if constexpr (A == 20) {
         const uint4 c0 = *reinterpret_cast<const uint4*>(col);
@@ -382,8 +398,9 @@ struct RingScore {
 #pragma unroll
       for (int m = 0; m < (A + 1) / 2; ++m) {
         const uint32_t w = col[m];
-        sc += U[2 * m] * (int32_t)(w & 0xffffu);
-        if (2 * m + 1 < A) sc += U[2 * m + 1] * (int32_t)(w >> 16);
+        sc = (int32_t)((uint32_t)sc + (uint32_t)(U[2 * m] * (int32_t)(w & 0xffffu)));
+        if (2 * m + 1 < A)
+          sc = (int32_t)((uint32_t)sc + (uint32_t)(U[2 * m + 1] * (int32_t)(w >> 16)));
       }
     }
     return sc;
